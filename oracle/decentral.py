@@ -1,0 +1,111 @@
+"""Decentralized pieces around the measurement operator, in FP64:
+filters Gamma, the pseudo-full-resolution composition of Eq. 7, the
+aggregate rho and exchanged Phi of Eqs. 5 and 7, and the final combination.
+
+Node names: ``own`` is the node doing the work (V_L or V_H), ``other`` the
+node whose filtered deconvolved residuals it receives.
+"""
+
+import numpy as np
+
+from .imaging import apply_psf
+
+
+def gamma_low(n, ell, delta, scale=1.0):
+    """Gamma_L on an n x n DFT grid in numpy FFT ordering.
+
+    Section 4.1 asks the filters to keep only their own spatial frequencies
+    and to have weights summing to one on the overlap L n H.  Reading
+    (shape parity unpinned): a radial linear ramp
+        Gamma_L(kappa) = clip((ell + delta - kappa) / (2 delta), 0, 1)
+    with kappa the radius of the DFT frequency in Fourier pixels of the
+    N x N image; for a 2N x 2N image the same physical frequency has twice
+    the index, so ``scale`` = 2 there.
+    """
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    kappa = np.sqrt(kx * kx + ky * ky) / scale
+    return np.clip((ell + delta - kappa) / (2.0 * delta), 0.0, 1.0)
+
+
+def gamma_high(n, ell, delta, scale=1.0):
+    """Gamma_H = 1 - Gamma_L, so Gamma_L + Gamma_H is the identity."""
+    return 1.0 - gamma_low(n, ell, delta, scale)
+
+
+def apply_filter(img, filt):
+    """Gamma x = Re F^-1 (Gamma . F x) on the image's own periodic grid."""
+    return np.fft.ifft2(np.fft.fft2(img) * filt).real
+
+
+def filters(n_img, ell, delta, own):
+    """(Gamma_own, Gamma_other) for an N x N image; own in {'L', 'H'}."""
+    lo = gamma_low(n_img, ell, delta)
+    return (lo, 1.0 - lo) if own == "L" else (1.0 - lo, lo)
+
+
+def psf_filters(n_img, ell, delta, own):
+    """Same as ``filters`` for the 2N x 2N PSF grid."""
+    lo = gamma_low(2 * n_img, ell, delta, scale=2.0)
+    return (lo, 1.0 - lo) if own == "L" else (1.0 - lo, lo)
+
+
+def weights_schedule(cycle, w_own, w_other):
+    """(gamma^n, mu^n) of Eq. 7.
+
+    Section 4.2 fixes gamma = 1, mu = 0 at the first major cycle and calls
+    them, afterwards, weights that re-normalise the PSF and dirty images
+    globally (each is first normalised by its local visibilities).  Reading:
+    gamma = W_own / (W_own + W_other), mu = W_other / (W_own + W_other),
+    with W the summed imaging weights of each partition (parity unpinned).
+    """
+    if cycle <= 1:
+        return 1.0, 0.0
+    tot = w_own + w_other
+    return w_own / tot, w_other / tot
+
+
+def compose_dirty(resid_own, rho_other, psf_other, ell, delta, own, gamma, mu):
+    """Eq. 7 dirty image: gamma Gamma_own i~_own + mu H_other rho_other."""
+    g_own, _ = filters(resid_own.shape[0], ell, delta, own)
+    out = gamma * apply_filter(resid_own, g_own)
+    if mu != 0.0 and rho_other is not None:
+        out = out + mu * apply_psf(psf_other, rho_other)
+    return out
+
+
+def compose_psf(psf_own, psf_other, ell, delta, own, gamma, mu):
+    """Eq. 7 PSF: gamma Gamma_own H_own + mu Gamma_other H_other (2N x 2N)."""
+    n = psf_own.shape[0] // 2
+    g_own, g_other = psf_filters(n, ell, delta, own)
+    out = gamma * apply_filter(psf_own, g_own)
+    if mu != 0.0:
+        out = out + mu * apply_filter(psf_other, g_other)
+    return out
+
+
+def exchange(delta_own, ell, delta, own):
+    """Phi sent to the other node after a major cycle (Eq. 5 and Eq. 7):
+    Gamma_own applied to the node's latest deconvolved residual."""
+    g_own, _ = filters(delta_own.shape[0], ell, delta, own)
+    return apply_filter(delta_own, g_own)
+
+
+def update_rho(rho_other, phi_received, delta_own, ell, delta, own):
+    """Aggregate update (Section 4.1): add the received Phi and subtract the
+    other node's filter applied to the local deconvolved residual,
+        rho^n = rho^{n-1} + Phi^n - Gamma_other ibar_own^n."""
+    _, g_other = filters(delta_own.shape[0], ell, delta, own)
+    prev = np.zeros_like(delta_own) if rho_other is None else rho_other
+    return prev + phi_received - apply_filter(delta_own, g_other)
+
+
+def combine(images, weights=None):
+    """Final image: weighted average of the nodes' images; the paper uses
+    equal weights 0.5 / 0.5 (Section 5.2)."""
+    if weights is None:
+        weights = [1.0 / len(images)] * len(images)
+    out = np.zeros_like(np.asarray(images[0], np.float64))
+    for w, im in zip(weights, images):
+        out = out + w * np.asarray(im, np.float64)
+    return out

@@ -1,0 +1,382 @@
+"""Pins of the FP64 oracle against mathematics (no GPU).
+
+Each test fixes the oracle to something other than itself: closed forms,
+brute force on tiny inputs, invariants that a dropped term, a wrong sign,
+a wrong index or a transposed operand would break.
+"""
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import decentral, dft, es_kernel, geometry, gridding, imaging
+
+W = 8
+BETA = es_kernel.es_beta(W)
+# measured design accuracy of the ES kernel at W = 8, beta = 2.3 W, sigma = 2
+# (relative L2, gridded operator against the direct sum): 1.4e-7.
+EPS_W8 = 5e-7
+
+
+def _uv(rng, m, n_grid, cell, frac=1.0 / 3.0):
+    du = 1.0 / (n_grid * cell)
+    u, v = rng.uniform(-frac * n_grid, frac * n_grid, (2, m)) * du
+    return u, v
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+# ---------------------------------------------------------------- ES kernel
+
+def test_es_kernel_shape():
+    z = np.linspace(-1, 1, 201)
+    phi = es_kernel.es_phi(z, BETA)
+    assert phi[100] == 1.0
+    assert np.allclose(phi, phi[::-1], rtol=1e-13, atol=0)
+    assert np.isclose(phi[0], np.exp(-BETA), rtol=1e-15)
+    assert np.all(es_kernel.es_phi(np.array([-1.01, 1.5]), BETA) == 0)
+    assert np.all(np.diff(phi[100:]) < 0)
+
+
+def test_taps_cover_support():
+    x = np.array([10.3, 10.0, 0.999999, 127.5])
+    first, w = es_kernel.taps(x, W, BETA)
+    assert list(first) == [7, 7, -3, 124]
+    # every tap is inside |c - x| <= W/2 and the excluded neighbours are outside
+    for xi, fi, wi in zip(x, first, w):
+        d = fi + np.arange(W) - xi
+        assert np.all(np.abs(d) <= W / 2)
+        assert abs(fi - 1 - xi) >= W / 2 and abs(fi + W - xi) > W / 2 - 1e-12
+        assert np.allclose(wi, es_kernel.es_phi(d / (W / 2), BETA))
+
+
+def test_correction_quadrature_converged_and_matches_adaptive():
+    n, ng = 64, 128
+    a = es_kernel.correction(n, ng, W, BETA, nodes=256)
+    b = es_kernel.correction(n, ng, W, BETA, nodes=512)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
+    for p in (-32, -7, 0, 5, 31):
+        f = lambda z: es_kernel.es_phi(np.array([z]), BETA)[0] * np.cos(np.pi * W * z * p / ng)
+        val, _ = integrate.quad(f, -1, 1, epsabs=1e-15, epsrel=1e-14, limit=200)
+        assert abs((W / 2) * val - a[p + n // 2]) < 1e-12
+
+
+def test_correction_is_transform_of_sampled_kernel():
+    # psi_hat(p) is the continuous FT of the stretched kernel; the sum of the
+    # kernel sampled at unit spacing with shift s, times exp(-2 pi i c p / Ng),
+    # approaches psi_hat(p) exp(-2 pi i s p / Ng) up to aliasing ~ the design eps.
+    n, ng = 64, 128
+    psi = es_kernel.correction(n, ng, W, BETA)
+    for s in (0.0, 0.37, 0.81):
+        c = np.arange(-W, W + 1)
+        k = es_kernel.es_phi((c - s) / (W / 2), BETA)
+        p = np.arange(n) - n // 2
+        ft = (k[None, :] * np.exp(-2j * np.pi * np.outer(p, c) / ng)).sum(1)
+        ref = psi * np.exp(-2j * np.pi * s * p / ng)
+        assert rel(ft, ref) < 1e-6
+
+
+# ---------------------------------------------------------------- FFT convention
+
+def test_centred_fft_equals_dft_matrix():
+    rng = np.random.default_rng(1)
+    for ng in (8, 16, 64):
+        x = rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng))
+        j = np.arange(ng) - ng // 2
+        f = np.exp(-2j * np.pi * np.outer(j, j) / ng)
+        assert np.allclose(gridding.centred_fft2(x), f @ x @ f.T, rtol=0, atol=1e-13 * ng * ng)
+        assert np.allclose(gridding.centred_ifft2(x), f.conj() @ x @ f.conj().T, rtol=0,
+                           atol=1e-13 * ng * ng)
+        # Parseval for the unnormalised transform
+        assert np.isclose(np.sum(np.abs(gridding.centred_fft2(x)) ** 2),
+                          ng * ng * np.sum(np.abs(x) ** 2), rtol=1e-13)
+
+
+# ---------------------------------------------------------------- operator pins
+
+def test_point_source_at_phase_centre_gives_constant_visibilities():
+    rng = np.random.default_rng(2)
+    n, cell = 64, 1e-3
+    u, v = _uv(rng, 1500, 2 * n, cell)
+    img = np.zeros((n, n))
+    img[n // 2, n // 2] = 2.5
+    v_dft = dft.forward(img, u, v, cell)
+    assert np.max(np.abs(v_dft - 2.5)) < 1e-13
+    op = imaging.Operator(u, v, cell, n, 2, W)
+    assert np.max(np.abs(op.forward(img) - 2.5)) < 2.5 * EPS_W8 * 5
+
+
+def test_shift_theorem_gridded():
+    # a point at (ix, iy) != centre, ix != iy, catches swapped axes and signs
+    rng = np.random.default_rng(3)
+    n, cell = 64, 2e-4
+    u, v = _uv(rng, 2000, 2 * n, cell)
+    ix, iy = 41, 19
+    img = np.zeros((n, n))
+    img[iy, ix] = 1.3
+    l, m = (ix - n // 2) * cell, (iy - n // 2) * cell
+    closed = 1.3 * np.exp(-2j * np.pi * (u * l + v * m))
+    assert rel(dft.forward(img, u, v, cell), closed) < 1e-13
+    op = imaging.Operator(u, v, cell, n, 2, W)
+    assert rel(op.forward(img), closed) < EPS_W8
+
+
+def test_analytic_gaussian_source():
+    # sampled circular Gaussian of sigma = 3 px: its DFT equals the continuous
+    # transform S exp(-2 pi^2 sigma_l^2 |u|^2) exp(-2 pi i u.l0) up to pixel
+    # aliasing, here below 1e-9, plus the kernel error of the gridded operator.
+    rng = np.random.default_rng(4)
+    n, cell = 64, 1e-4
+    u, v = _uv(rng, 2000, 2 * n, cell)
+    s, sig, cx, cy = 0.7, 3.0, 37, 29
+    yy, xx = np.mgrid[0:n, 0:n]
+    img = s * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * sig ** 2)) / (2 * np.pi * sig ** 2)
+    sl = sig * cell
+    l0, m0 = (cx - n // 2) * cell, (cy - n // 2) * cell
+    closed = s * np.exp(-2 * np.pi ** 2 * sl ** 2 * (u ** 2 + v ** 2)) \
+        * np.exp(-2j * np.pi * (u * l0 + v * m0))
+    assert rel(dft.forward(img, u, v, cell), closed) < 1e-8
+    op = imaging.Operator(u, v, cell, n, 2, W)
+    assert rel(op.forward(img), closed) < EPS_W8
+
+
+@pytest.mark.parametrize("which", ["dft", "gridded"])
+def test_adjoint_identity(which):
+    rng = np.random.default_rng(5)
+    n, cell = 48, 3e-4
+    u, v = _uv(rng, 1200, 2 * n, cell)
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    y = rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))
+    if which == "dft":
+        ax, ahy = dft.forward(x, u, v, cell), dft.adjoint(y, u, v, cell, n)
+    else:
+        op = imaging.Operator(u, v, cell, n, 2, W)
+        ax, ahy = op.forward(x), op.adjoint(y)
+    lhs = np.vdot(y, ax)
+    rhs = np.vdot(ahy, x)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(ax) * np.linalg.norm(y)
+
+
+def test_gridded_matches_direct_sum_to_design_accuracy():
+    rng = np.random.default_rng(6)
+    n, cell = 64, 1e-3
+    u, v = _uv(rng, 2000, 2 * n, cell)
+    x = rng.standard_normal((n, n))
+    y = rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))
+    op = imaging.Operator(u, v, cell, n, 2, W)
+    e_fwd = rel(op.forward(x), dft.forward(x, u, v, cell))
+    e_adj = rel(op.adjoint(y), dft.adjoint(y, u, v, cell, n))
+    assert e_fwd < EPS_W8 and e_adj < EPS_W8
+    # a narrower kernel is measurably worse: the error is the kernel's, not noise
+    op6 = imaging.Operator(u, v, cell, n, 2, 6)
+    assert rel(op6.forward(x), dft.forward(x, u, v, cell)) > 10 * e_fwd
+
+
+def test_hermitian_symmetry_for_real_images():
+    rng = np.random.default_rng(7)
+    n, cell = 32, 1e-3
+    u, v = _uv(rng, 500, 2 * n, cell)
+    x = rng.standard_normal((n, n))
+    op_p = imaging.Operator(u, v, cell, n, 2, W)
+    op_m = imaging.Operator(-u, -v, cell, n, 2, W)
+    # F_c at -g equals conj(F_c at g) for a real input only up to the centre
+    # shift of an even grid, so compare the direct sums exactly and the
+    # gridded operator to the kernel accuracy.
+    assert rel(dft.forward(x, -u, -v, cell), np.conj(dft.forward(x, u, v, cell))) < 1e-13
+    assert rel(op_m.forward(x), np.conj(op_p.forward(x))) < EPS_W8
+
+
+def test_psf_peak_equals_summed_weights():
+    rng = np.random.default_rng(8)
+    n, cell = 32, 1e-3
+    u, v = _uv(rng, 800, 4 * n, cell, frac=1.0 / 6.0)   # |u| within the N-grid's third
+    w = rng.uniform(0.2, 2.0, len(u))
+    # direct sum on the 2N image: value at the centre (N, N) is sum(w) exactly
+    p_dft = dft.adjoint(w, u, v, cell, 2 * n).real
+    assert abs(p_dft[n, n] - w.sum()) < 1e-12 * w.sum()
+    assert p_dft.max() <= p_dft[n, n] * (1 + 1e-12)
+    p = imaging.psf2(u, v, w, n, cell, normalise=False)
+    assert abs(p[n, n] - w.sum()) < EPS_W8 * w.sum()
+    assert np.unravel_index(np.argmax(p), p.shape) == (n, n)
+    # symmetry psf[N + d] = psf[N - d]
+    core = p[1:, 1:]
+    assert rel(core, core[::-1, ::-1]) < EPS_W8
+
+
+def test_psf_convolution_is_normal_operator():
+    # H x = Re A^H (w . A x) / sum(w): exact under the direct sum for real x
+    rng = np.random.default_rng(9)
+    n, cell = 16, 1e-3
+    u, v = _uv(rng, 400, 2 * n, cell)
+    w = rng.uniform(0.5, 1.5, len(u))
+    x = rng.standard_normal((n, n))
+    normal = (dft.adjoint(w * dft.forward(x, u, v, cell), u, v, cell, n).real) / w.sum()
+    psf_dft = dft.adjoint(w, u, v, cell, 2 * n).real / w.sum()
+    assert rel(imaging.apply_psf(psf_dft, x), normal) < 1e-12
+    # gridded PSF reproduces the same operator to the kernel accuracy
+    psf_g = imaging.psf2(u, v, w, n, cell)
+    assert rel(imaging.apply_psf(psf_g, x), normal) < 5 * EPS_W8
+
+
+def test_apply_psf_brute_force():
+    rng = np.random.default_rng(10)
+    n = 6
+    psf = rng.standard_normal((2 * n, 2 * n))
+    x = rng.standard_normal((n, n))
+    ref = np.zeros((n, n))
+    for py in range(n):
+        for px in range(n):
+            for qy in range(n):
+                for qx in range(n):
+                    ref[py, px] += psf[n + py - qy, n + px - qx] * x[qy, qx]
+    assert np.allclose(imaging.apply_psf(psf, x), ref, atol=1e-12)
+
+
+def test_residual_vanishes_for_exact_model():
+    # noise-free point sky at pixel centres: residual with the true model is
+    # at the kernel error level, the dirty image is not.
+    from paper_2507_22128_amd import synth
+    d = synth.make("tiny", with_noise=False, n_time=6)
+    u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
+    src = d["sources"]
+    pts = src["sigma_px"] == 0
+    n = d["n_img"]
+    model = np.zeros((n, n))
+    np.add.at(model, (src["iy"][pts], src["ix"][pts]), src["flux"][pts])
+    # visibilities of the point part only (the generator's Gaussians are not
+    # pixel sums), from the closed form of each point
+    l0 = (src["ix"][pts] - n // 2) * d["cell"]
+    m0 = (src["iy"][pts] - n // 2) * d["cell"]
+    vis = np.exp(-2j * np.pi * (np.outer(u, l0) + np.outer(v, m0))) @ src["flux"][pts]
+    w = imaging.uniform_weights(u, v, n, d["cell"])
+    res, pred = imaging.residual_image(u, v, vis, w, model, d["cell"])
+    dirty = imaging.dirty_image(u, v, vis, w, n, d["cell"])
+    assert rel(pred, vis) < EPS_W8
+    assert np.max(np.abs(res)) < EPS_W8 * np.max(np.abs(dirty))
+
+
+def test_residual_is_affine_in_model():
+    rng = np.random.default_rng(11)
+    n, cell = 32, 1e-3
+    u, v = _uv(rng, 600, 2 * n, cell)
+    vis = rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))
+    w = np.ones(len(u))
+    a, b = rng.standard_normal((2, n, n))
+    r0, _ = imaging.residual_image(u, v, vis, w, np.zeros((n, n)), cell)
+    ra, _ = imaging.residual_image(u, v, vis, w, a, cell)
+    rb, _ = imaging.residual_image(u, v, vis, w, b, cell)
+    rab, _ = imaging.residual_image(u, v, vis, w, a + 2 * b, cell)
+    assert rel(rab - r0, (ra - r0) + 2 * (rb - r0)) < 1e-12
+
+
+# ---------------------------------------------------------------- weighting / partition
+
+def test_uniform_weights_brute_force():
+    rng = np.random.default_rng(12)
+    n, cell = 16, 1e-2
+    u, v = _uv(rng, 700, n, cell, frac=0.45)
+    valid = rng.random(len(u)) > 0.1
+    w = imaging.uniform_weights(u, v, n, cell, valid=valid)
+    cells = []
+    for uk, vk in zip(u, v):
+        cu = int(np.floor(uk * n * cell + 0.5)) % n
+        cv = int(np.floor(vk * n * cell + 0.5)) % n
+        cells.append((cv, cu))
+    for k in range(len(u)):
+        cnt = sum(1 for j in range(len(u)) if valid[j] and cells[j] == cells[k])
+        assert w[k] == (1.0 / cnt if valid[k] else 0.0)
+    # every occupied cell sums to one
+    sums = {}
+    for k in range(len(u)):
+        if valid[k]:
+            sums[cells[k]] = sums.get(cells[k], 0.0) + w[k]
+    assert np.allclose(list(sums.values()), 1.0, rtol=1e-14)
+
+
+def test_partition_sets():
+    rng = np.random.default_rng(13)
+    n, cell = 64, 1e-3
+    u, v = _uv(rng, 1001, 2 * n, cell)
+    valid = rng.random(len(u)) > 0.05
+    low, high, ell = imaging.partition(u, v, n, cell, valid=valid)
+    rho = np.sqrt((u * n * cell) ** 2 + (v * n * cell) ** 2)
+    vr = np.sort(rho[valid])
+    assert ell == vr[(len(vr) - 1) // 2]
+    assert np.all(low <= valid) and np.all(high <= valid)
+    assert low.sum() + high.sum() - (low & high).sum() == valid.sum()
+    assert np.all(rho[low] <= ell + 1.0) and np.all(rho[high] >= ell - 1.0)
+    ring = low & high
+    assert np.all(np.abs(rho[ring] - ell) <= 1.0)
+    # explicit ell, degenerate: everything low
+    low2, high2, _ = imaging.partition(u, v, n, cell, ell=1e9, valid=valid)
+    assert low2.sum() == valid.sum() and high2.sum() == 0
+
+
+# ---------------------------------------------------------------- decentralized pieces
+
+def test_filters_partition_of_unity_and_bands():
+    n, ell, delta = 32, 6.0, 1.0
+    gl = decentral.gamma_low(n, ell, delta)
+    gh = decentral.gamma_high(n, ell, delta)
+    assert np.all(gl + gh == 1.0)
+    rng = np.random.default_rng(14)
+    x = rng.standard_normal((n, n))
+    y = rng.standard_normal((n, n))
+    # self-adjoint
+    assert abs(np.vdot(decentral.apply_filter(x, gl), y) - np.vdot(x, decentral.apply_filter(y, gl))) < 1e-12
+    # identity on kappa <= ell - delta: a cosine at radius 3 passes, at 12 is removed
+    ix = np.arange(n)
+    c3 = np.cos(2 * np.pi * 3 * ix / n)[None, :] * np.ones((n, 1))
+    c12 = np.cos(2 * np.pi * 12 * ix / n)[None, :] * np.ones((n, 1))
+    assert np.allclose(decentral.apply_filter(c3, gl), c3, atol=1e-13)
+    assert np.allclose(decentral.apply_filter(c12, gl), 0, atol=1e-13)
+    # inside the ring: weight (ell + delta - kappa) / (2 delta) at kappa = 6
+    c6 = np.cos(2 * np.pi * 6 * ix / n)[None, :] * np.ones((n, 1))
+    assert np.allclose(decentral.apply_filter(c6, gl), 0.5 * c6, atol=1e-13)
+
+
+def test_psf_filter_uses_same_physical_frequency():
+    n, ell, delta = 16, 4.3, 1.0
+    ix = np.arange(2 * n)
+    k0 = 4  # Fourier pixels of the N image -> index 8 on the 2N grid
+    c = np.cos(2 * np.pi * k0 * ix / n)[None, :] * np.ones((2 * n, 1))
+    g2, _ = decentral.psf_filters(n, ell, delta, "L")
+    expect = np.clip((ell + delta - k0) / (2 * delta), 0, 1)
+    assert np.allclose(decentral.apply_filter(c, g2), expect * c, atol=1e-13)
+
+
+def test_composition_degenerates_to_serial():
+    rng = np.random.default_rng(15)
+    n = 16
+    resid = rng.standard_normal((n, n))
+    psf = rng.standard_normal((2 * n, 2 * n))
+    # ell beyond every frequency: Gamma_L = 1, first cycle weights
+    d = decentral.compose_dirty(resid, None, None, 1e6, 1.0, "L", 1.0, 0.0)
+    p = decentral.compose_psf(psf, None, 1e6, 1.0, "L", 1.0, 0.0)
+    assert np.allclose(d, resid, atol=1e-13) and np.allclose(p, psf, atol=1e-13)
+
+
+def test_rho_aggregate_invariant():
+    # rho_H^n = Gamma_H (sum Phi_H - sum ibar_L) = Gamma_H(i_H - i_L) every cycle
+    rng = np.random.default_rng(16)
+    n, ell, delta = 16, 4.0, 1.0
+    rho = None
+    model_l = np.zeros((n, n))
+    model_h = np.zeros((n, n))
+    gl = decentral.gamma_low(n, ell, delta)
+    for _ in range(4):
+        dl, dh = rng.standard_normal((2, n, n))
+        phi_h = decentral.exchange(dh, ell, delta, "H")
+        rho = decentral.update_rho(rho, phi_h, dl, ell, delta, "L")
+        model_l += dl
+        model_h += dh
+        target = decentral.apply_filter(model_h - model_l, 1.0 - gl)
+        assert np.allclose(rho, target, atol=1e-12)
+
+
+def test_combine_equal_weights():
+    a = np.arange(12.0).reshape(3, 4)
+    b = -2.0 * a + 1
+    assert np.array_equal(decentral.combine([a, b]), 0.5 * a + 0.5 * b)
