@@ -1,0 +1,215 @@
+/*
+ * imager.h - C-ABI of the MI355X (gfx950) major-cycle imager.
+ *
+ * Hot path of the spatial-frequency-decentralized reconstruction of
+ * Wang et al., "A Decentralized Framework for Radio-Interferometric Image
+ * Reconstruction" (arXiv 2507.22128): for one node (visibility partition)
+ * the major-cycle residual of Eq. 2, i~ = F^dagger G (v - G^dagger F i^),
+ * its PSF H, and the pseudo-full-resolution composition of Eq. 7
+ * (Section 4.2), with the partition of Fig. 3 (Section 3), uniform
+ * weighting (Section 5.1), the aggregate update of Eq. 5 (Section 4.1) and
+ * the final combination (Section 5.2).
+ *
+ * Conventions used by every call (they are readings of passages the paper
+ * leaves silent):
+ *   - images are N x N float32, row-major [iy][ix]; pixel (ix, iy) has
+ *     direction cosines l = (ix - N/2) cell, m = (iy - N/2) cell;
+ *   - the forward operator is (A x)_k = sum_p x_p exp(-2 pi i (u_k l_p +
+ *     v_k m_p)) (Eq. 1 with the C, D, w and 1/n terms dropped, as the text
+ *     after Eq. 1 allows), approximated by gridding with the
+ *     exponential-of-semicircle kernel of support W on a 2x padded grid;
+ *   - residual / dirty images are Re A^H (w . r) / sum(w); the PSF is
+ *     Re A'^H (w) / sum(w) on a 2N x 2N image with the same pixel size,
+ *     centred at pixel (N, N);
+ *   - "members" of a partition are its visibilities in increasing order of
+ *     their index in the array given to imager_create.
+ *
+ * Memory and streams: every pointer argument documented "device" must be
+ * device memory of the handle's device (e.g. a torch tensor's data
+ * pointer); "host" pointers are ordinary host memory.  The caller owns all
+ * memory it passes; the library never frees it.  imager_create copies,
+ * sorts and bins the visibilities into library-owned device memory, so the
+ * caller may free its arrays when it returns.  All library allocations are
+ * released by imager_destroy.  Calls other than create, destroy, info and
+ * last_error only enqueue work on the handle's stream and return; results
+ * are valid after imager_sync or any later synchronisation of that stream.
+ *
+ * Errors: every call returns an imgr_status.  EINVAL: bad arguments,
+ * nothing enqueued.  ENOMEM: the device footprint would exceed
+ * hbm_budget, or hipMalloc failed; the handle is unchanged.  EDEVICE: a HIP
+ * runtime error; the handle then refuses further work with ESTATE until it
+ * is destroyed.  imager_last_error returns a message for the last failure.
+ * A handle must not be used by two host threads at once; different handles
+ * are independent.
+ */
+#ifndef IMAGER_H
+#define IMAGER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct imgr_s *imgr_t;
+
+typedef enum {
+  IMGR_OK = 0,
+  IMGR_EINVAL = 1,
+  IMGR_ENOMEM = 2,
+  IMGR_EDEVICE = 3,
+  IMGR_ESTATE = 4,
+  IMGR_ENOTIMPL = 5
+} imgr_status;
+
+/* visibility element types (interleaved re, im) */
+enum { IMGR_C64 = 0, IMGR_C128 = 1 };
+
+/* imgr_config.weighting */
+enum { IMGR_WEIGHT_NATURAL = 0, IMGR_WEIGHT_UNIFORM = 1 };
+
+/* partition indices; with n_partitions == 1 only IMGR_PART_LOW (= all) exists */
+enum { IMGR_PART_LOW = 0, IMGR_PART_HIGH = 1 };
+
+/* imgr_config.flags and imager_major_cycle flags */
+enum {
+  /* degrid model + rho_other instead of model (the "local model plus the
+     other partition's previous image" form); default degrids model alone */
+  IMGR_DEGRID_COMPOSITE = 1
+};
+
+/* imager_grid modes */
+enum { IMGR_GRID_DIRTY = 0, IMGR_GRID_UNNORMALIZED = 1 };
+
+/* imager_combine_partitions modes */
+enum { IMGR_COMBINE_EXCHANGE = 0, IMGR_COMBINE_FINAL = 1 };
+
+typedef struct {
+  int32_t n_pix;        /* N: power of two, 64 <= N <= 2048 */
+  double cell_rad;      /* pixel size in radians (> 0) */
+  int32_t support;      /* W: 4, 6, 8, 10 or 12; 0 selects 8 */
+  double es_beta;       /* ES kernel beta; <= 0 selects 2.30 W */
+  int32_t weighting;    /* IMGR_WEIGHT_* */
+  int32_t n_partitions; /* 1 (serial) or 2 (V_L, V_H) */
+  double ell_pix;       /* partition radius ell in Fourier pixels; < 0: lower median */
+  double delta_pix;     /* half-width of the overlap ring; <= 0 selects 1 */
+  int32_t tile;         /* tile side in grid cells, 16 or 32; 0 selects 32 */
+  int32_t chunk;        /* max visibilities per work chunk; 0 selects 4096 */
+  int32_t flags;        /* reserved, 0 */
+  size_t hbm_budget;    /* bytes of device memory the handle may hold; 0 = no cap */
+  void *stream;         /* hipStream_t for all work; NULL = the null stream */
+} imgr_config;
+
+typedef struct {
+  int64_t n_vis;        /* number of visibilities */
+  double freq_hz;       /* observing frequency; u = uvw * freq / c */
+  const double *uvw;    /* [n_vis][3] metres */
+  const void *vis;      /* [n_vis] complex, element type vis_dtype */
+  int32_t vis_dtype;    /* IMGR_C64 or IMGR_C128 */
+  const float *weight;  /* [n_vis] natural weights, or NULL for all ones */
+  const uint8_t *flag;  /* [n_vis], nonzero = flagged (dropped), or NULL */
+  int32_t on_device;    /* 0: the five arrays are host memory; 1: device */
+} imgr_vis;
+
+typedef struct {
+  int32_t n_pix, n_grid, support, tile, n_partitions;
+  double cell_rad, es_beta, ell_pix, delta_pix;
+  int64_t n_valid;      /* unflagged visibilities */
+  int64_t n_vis[2];     /* members per partition (overlap counted in both) */
+  int64_t n_chunks[2];  /* work chunks per partition */
+  double sum_w[2];      /* summed imaging weights per partition (FP64) */
+  size_t device_bytes;  /* device memory held by the handle */
+  double create_ms;     /* wall time of imager_create */
+} imgr_info;
+
+/* Build a handle: scale (u, v) in FP64, drop flagged visibilities, apply the
+ * weighting, split into V_L = {rho <= ell + delta} and V_H = {rho >= ell -
+ * delta} (Fig. 3; rho = |uv| in Fourier pixels), sort each partition by uv
+ * tile, and grid each partition's PSF once.  Synchronous.  *out receives
+ * the handle (NULL on error). */
+imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *out);
+
+imgr_status imager_destroy(imgr_t h);
+
+imgr_status imager_info(imgr_t h, imgr_info *out);
+
+/* Original indices (int64, host) of the members of partition part, in
+ * member order: idx[n_vis[part]].  Synchronous. */
+imgr_status imager_vis_index(imgr_t h, int32_t part, int64_t *idx);
+
+/* Imaging weights (float32, host) of the members in member order. Synchronous. */
+imgr_status imager_vis_weight(imgr_t h, int32_t part, float *w);
+
+/* Degridding G^dagger F of Eq. 2: predicted visibilities of the N x N
+ * model (device float32) at the members of partition part, written as
+ * complex64 (device, [n_vis[part]], member order). */
+imgr_status imager_degrid(imgr_t h, int32_t part, const float *model, void *vis_out);
+
+/* Gridding F^dagger G of Eq. 2 of member visibilities vis_in (device
+ * complex64, member order): image_out (device N x N float32) receives
+ * Re A^H (w . vis) / sum(w) (IMGR_GRID_DIRTY) or without the division
+ * (IMGR_GRID_UNNORMALIZED). */
+imgr_status imager_grid(imgr_t h, int32_t part, const void *vis_in, float *image_out,
+                        int32_t mode);
+
+/* The partition's PSF (Section 2, operator H of Eqs. 4, 5, 7): 2N x 2N
+ * float32 (device), normalised to peak 1 at pixel (N, N). */
+imgr_status imager_psf(imgr_t h, int32_t part, float *psf_out);
+
+/* One major cycle of node `part` (Eq. 2 then Eq. 7):
+ *   residual_local = Re A^H (w . (v - A model)) / sum(w)      (Eq. 2)
+ *   residual_out   = gamma Gamma_own residual_local + mu H_other rho_other
+ * with Gamma_own the node's filter (Gamma_L for IMGR_PART_LOW) and H_other
+ * the other partition's PSF.  With one partition residual_out =
+ * residual_local.  rho_other may be NULL (then the mu term is dropped).
+ * model, rho_other: device N x N float32; residual_out: device N x N
+ * float32; residual_local_out: device N x N float32 or NULL.
+ * flags: IMGR_DEGRID_COMPOSITE degrids model + rho_other. */
+imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model,
+                               const float *rho_other, double gamma, double mu,
+                               float *residual_out, float *residual_local_out,
+                               int32_t flags);
+
+/* Composed PSF of Eq. 7, gamma Gamma_own H_own + mu Gamma_other H_other,
+ * 2N x 2N float32 (device). */
+imgr_status imager_composed_psf(imgr_t h, int32_t part, double gamma, double mu,
+                                float *psf_out);
+
+/* Multi-scale CLEAN minor cycle (Eq. 6 and Eq. 7).  Not available in this
+ * version: returns IMGR_ENOTIMPL. */
+imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t part, const void *params,
+                                       const float *dirty, const float *psf,
+                                       float *model_delta);
+
+/* FISTA minor cycle for Eqs. 4 and 5.  Not available in this version:
+ * returns IMGR_ENOTIMPL. */
+imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const void *params,
+                                     const float *dirty, const float *rho_other,
+                                     float *model_delta);
+
+/* Exchange and combination between the two partitions (Section 4.1,
+ * Fig. 2, Section 5.2).
+ * IMGR_COMBINE_EXCHANGE: a = ibar_L^n, b = ibar_H^n (device N x N float32,
+ *   the nodes' latest deconvolved residuals); out_a, out_b (device N x N
+ *   float32) are the aggregates rho_H held by node L and rho_L held by node
+ *   H, updated in place:
+ *     out_a += Gamma_H (b - a)     (Phi_H - Gamma_H ibar_L)
+ *     out_b += Gamma_L (a - b)     (Phi_L - Gamma_L ibar_H)
+ * IMGR_COMBINE_FINAL: out_a (device N x N float64) = w_a a + w_b b computed
+ *   in FP64 (the paper uses w_a = w_b = 0.5); out_b unused. */
+imgr_status imager_combine_partitions(imgr_t h, int32_t mode, const float *a, const float *b,
+                                      double w_a, double w_b, void *out_a, void *out_b);
+
+/* Wait for all work enqueued on the handle's stream. */
+imgr_status imager_sync(imgr_t h);
+
+/* Message for the last failure on h (or, for h == NULL, of the calling
+ * thread's last imager_create).  Never NULL. */
+const char *imager_last_error(imgr_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMAGER_H */

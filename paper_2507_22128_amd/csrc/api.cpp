@@ -1,0 +1,421 @@
+// C-ABI entry points of the imager library: argument checks, handle
+// lifetime, device-memory accounting, and the order in which each call
+// enqueues its kernels on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace imgr {
+
+void *dev_alloc(imgr_s *h, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 16);
+  if (h->budget && h->bytes + bytes > h->budget)
+    throw Error{IMGR_ENOMEM, "device footprint would exceed hbm_budget (" +
+                                 std::to_string(h->bytes + bytes) + " > " +
+                                 std::to_string(h->budget) + " bytes)"};
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{IMGR_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+  }
+  h->bytes += bytes;
+  h->allocs.push_back(p);
+  // remember the size in a parallel list for accounting on free
+  h->alloc_sizes.push_back(bytes);
+  return p;
+}
+
+void dev_free(imgr_s *h, void *p) {
+  if (!p) return;
+  for (size_t i = 0; i < h->allocs.size(); ++i) {
+    if (h->allocs[i] == p) {
+      h->bytes -= h->alloc_sizes[i];
+      h->allocs.erase(h->allocs.begin() + i);
+      h->alloc_sizes.erase(h->alloc_sizes.begin() + i);
+      (void)hipFree(p);
+      return;
+    }
+  }
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// 1 / psi_hat(p), p = ix - n/2, for an n-pixel image axis on an ng-cell grid:
+// psi_hat(p) = (W/2) int_{-1}^{1} phi(z) cos(pi W z p / ng) dz (FP64).
+static std::vector<float> correction_inv(int n, int ng, int W, double beta) {
+  std::vector<double> z, wq;
+  gauss_legendre(128, z, wq);
+  std::vector<double> phi(z.size());
+  for (size_t k = 0; k < z.size(); ++k) phi[k] = std::exp(beta * (std::sqrt(1.0 - z[k] * z[k]) - 1.0));
+  std::vector<float> out(n);
+  for (int ix = 0; ix < n; ++ix) {
+    const double p = (double)(ix - n / 2);
+    double acc = 0.0;
+    for (size_t k = 0; k < z.size(); ++k) acc += wq[k] * phi[k] * std::cos(M_PI * W * z[k] * p / ng);
+    out[ix] = (float)(1.0 / (0.5 * W * acc));
+  }
+  return out;
+}
+
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static void fail(imgr_s *h, const Error &e) {
+  h->err = e.msg;
+  if (e.code == IMGR_EDEVICE) h->broken = true;
+}
+
+static void build_psf(imgr_s *h, int p) {
+  hipStream_t s = h->stream;
+  Partition &P = h->part[p];
+  const int n2 = 2 * h->N, ng2 = 2 * h->Ng, t2 = 2 * h->T;
+  P.psf = (float *)dev_alloc(h, (size_t)n2 * n2 * sizeof(float));
+  P.psf_hat = (float2 *)dev_alloc(h, (size_t)n2 * n2 * sizeof(float2));
+  const int S2 = t2 + h->W - 1;
+  float2 *grid = (float2 *)dev_alloc(h, (size_t)ng2 * ng2 * sizeof(float2));
+  float2 *tmp = (float2 *)dev_alloc(h, (size_t)ng2 * ng2 * sizeof(float2));
+  float2 *rows = (float2 *)dev_alloc(h, (size_t)n2 * ng2 * sizeof(float2));
+  float2 *scr = (float2 *)dev_alloc(h, (size_t)std::max(P.n_chunks, 1) * S2 * S2 * sizeof(float2));
+  degrid_grid(h, p, MODE_PSF, nullptr, nullptr, nullptr, t2, ng2, scr, s);
+  flush_chunks(h, p, t2, ng2, scr, grid, s);
+  fft_grid_to_image(h, grid, h->cinv2, n2, ng2, (float)(1.0 / P.sum_w), rows, tmp, P.psf, s);
+  IMGR_HIP(hipStreamSynchronize(s));
+  dev_free(h, scr);
+  dev_free(h, rows);
+  dev_free(h, tmp);
+  dev_free(h, grid);
+  psf_spectrum(h, p, s);
+  IMGR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace imgr
+
+using namespace imgr;
+
+static thread_local std::string g_create_error;
+
+#define API_BEGIN(h)                                                  \
+  if (!(h)) return IMGR_EINVAL;                                       \
+  if ((h)->broken) {                                                  \
+    (h)->err = "handle is unusable after an earlier device error";    \
+    return IMGR_ESTATE;                                               \
+  }                                                                   \
+  try {
+#define API_END(h)          \
+  }                         \
+  catch (const Error &e) {  \
+    fail((h), e);           \
+    return e.code;          \
+  }                         \
+  catch (const std::exception &e) { \
+    (h)->err = e.what();    \
+    return IMGR_EINVAL;     \
+  }                         \
+  return IMGR_OK;
+
+extern "C" {
+
+imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *out) {
+  if (out) *out = nullptr;
+  if (!cfg || !vis || !out) {
+    g_create_error = "null argument";
+    return IMGR_EINVAL;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  imgr_s *h = new imgr_s();
+  try {
+    IMGR_CHECK(pow2(cfg->n_pix) && cfg->n_pix >= 64 && cfg->n_pix <= 2048,
+               "n_pix must be a power of two in [64, 2048]");
+    h->N = cfg->n_pix;
+    h->Ng = 2 * h->N;
+    h->W = cfg->support ? cfg->support : 8;
+    IMGR_CHECK(h->W == 4 || h->W == 6 || h->W == 8 || h->W == 10 || h->W == 12,
+               "support must be 4, 6, 8, 10 or 12");
+    h->beta = cfg->es_beta > 0 ? cfg->es_beta : 2.30 * h->W;
+    h->T = cfg->tile ? cfg->tile : 32;
+    IMGR_CHECK(h->T == 16 || h->T == 32, "tile must be 16 or 32");
+    IMGR_CHECK(h->Ng % h->T == 0 && h->Ng / h->T >= 3, "grid too small for the tile");
+    h->C = cfg->chunk ? cfg->chunk : 4096;
+    IMGR_CHECK(h->C >= 64 && h->C <= (1 << 20), "chunk must be in [64, 2^20]");
+    IMGR_CHECK(cfg->n_partitions == 1 || cfg->n_partitions == 2, "n_partitions must be 1 or 2");
+    h->n_parts = cfg->n_partitions;
+    IMGR_CHECK(cfg->weighting == IMGR_WEIGHT_NATURAL || cfg->weighting == IMGR_WEIGHT_UNIFORM,
+               "weighting must be natural or uniform");
+    h->weighting = cfg->weighting;
+    h->ell = cfg->ell_pix;
+    h->delta = cfg->delta_pix > 0 ? cfg->delta_pix : 1.0;
+    h->budget = cfg->hbm_budget;
+    h->stream = (hipStream_t)cfg->stream;
+    IMGR_CHECK(vis->n_vis > 0 && vis->n_vis < (int64_t)INT32_MAX, "n_vis must be in [1, 2^31)");
+    IMGR_CHECK(vis->uvw && vis->vis, "uvw and vis are required");
+    IMGR_CHECK(vis->vis_dtype == IMGR_C64 || vis->vis_dtype == IMGR_C128, "vis_dtype");
+    IMGR_CHECK(vis->freq_hz > 0, "freq_hz must be positive");
+    IMGR_CHECK(cfg->cell_rad > 0, "cell_rad must be given (> 0)");
+    h->cell = cfg->cell_rad;
+    h->ntx = h->Ng / h->T;
+    h->n_tiles = h->ntx * h->ntx;
+
+    // tables
+    {
+      std::vector<float> c1 = correction_inv(h->N, h->Ng, h->W, h->beta);
+      std::vector<float> c2 = correction_inv(2 * h->N, 2 * h->Ng, h->W, h->beta);
+      h->cinv = (float *)dev_alloc(h, c1.size() * sizeof(float));
+      h->cinv2 = (float *)dev_alloc(h, c2.size() * sizeof(float));
+      IMGR_HIP(hipMemcpy(h->cinv, c1.data(), c1.size() * sizeof(float), hipMemcpyHostToDevice));
+      IMGR_HIP(hipMemcpy(h->cinv2, c2.data(), c2.size() * sizeof(float), hipMemcpyHostToDevice));
+      std::vector<float2> tw(kTwMax);
+      for (int m = 0; m < kTwMax; ++m) {
+        const double a = 2.0 * M_PI * (double)m / (double)kTwMax;
+        tw[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
+      }
+      h->tw = (float2 *)dev_alloc(h, kTwMax * sizeof(float2));
+      IMGR_HIP(hipMemcpy(h->tw, tw.data(), kTwMax * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    const size_t ng2 = (size_t)h->Ng * h->Ng;
+    h->grid_a = (float2 *)dev_alloc(h, ng2 * sizeof(float2));
+    h->grid_b = (float2 *)dev_alloc(h, ng2 * sizeof(float2));
+    h->rows = (float2 *)dev_alloc(h, (size_t)h->N * h->Ng * sizeof(float2));
+    h->img_a = (float *)dev_alloc(h, (size_t)h->N * h->N * sizeof(float));
+    h->img_b = (float *)dev_alloc(h, (size_t)h->N * h->N * sizeof(float));
+
+    prep_build(h, vis);
+
+    int max_chunks = 1;
+    for (int p = 0; p < h->n_parts; ++p) max_chunks = std::max(max_chunks, h->part[p].n_chunks);
+    const int S = h->T + h->W - 1;
+    h->scratch_elems = (size_t)max_chunks * S * S;
+    h->scratch = (float2 *)dev_alloc(h, h->scratch_elems * sizeof(float2));
+    for (int p = 0; p < h->n_parts; ++p) {
+      IMGR_CHECK(h->part[p].n > 0, "a partition is empty (check ell / delta)");
+      build_psf(h, p);
+    }
+    IMGR_HIP(hipStreamSynchronize(h->stream));
+  } catch (const Error &e) {
+    g_create_error = e.msg;
+    for (void *p : h->allocs) (void)hipFree(p);
+    (void)hipGetLastError();
+    delete h;
+    return e.code;
+  } catch (const std::exception &e) {
+    g_create_error = e.what();
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+    return IMGR_EINVAL;
+  }
+  h->create_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return IMGR_OK;
+}
+
+imgr_status imager_destroy(imgr_t h) {
+  if (!h) return IMGR_EINVAL;
+  (void)hipStreamSynchronize(h->stream);
+  for (void *p : h->allocs) (void)hipFree(p);
+  delete h;
+  return IMGR_OK;
+}
+
+imgr_status imager_info(imgr_t h, imgr_info *o) {
+  if (!h || !o) return IMGR_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->n_pix = h->N;
+  o->n_grid = h->Ng;
+  o->support = h->W;
+  o->tile = h->T;
+  o->n_partitions = h->n_parts;
+  o->cell_rad = h->cell;
+  o->es_beta = h->beta;
+  o->ell_pix = h->ell;
+  o->delta_pix = h->delta;
+  o->n_valid = h->n_valid;
+  for (int p = 0; p < h->n_parts; ++p) {
+    o->n_vis[p] = h->part[p].n;
+    o->n_chunks[p] = h->part[p].n_chunks;
+    o->sum_w[p] = h->part[p].sum_w;
+  }
+  o->device_bytes = h->bytes;
+  o->create_ms = h->create_ms;
+  return IMGR_OK;
+}
+
+static void check_part(imgr_s *h, int part) {
+  IMGR_CHECK(part >= 0 && part < h->n_parts, "partition index out of range");
+}
+
+imgr_status imager_vis_index(imgr_t h, int32_t part, int64_t *idx) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(idx != nullptr, "idx is NULL");
+  const Partition &P = h->part[part];
+  std::vector<int32_t> orig(P.n), pos(P.n);
+  IMGR_HIP(hipMemcpyAsync(orig.data(), P.orig, P.n * 4, hipMemcpyDeviceToHost, h->stream));
+  IMGR_HIP(hipMemcpyAsync(pos.data(), P.outpos, P.n * 4, hipMemcpyDeviceToHost, h->stream));
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  for (int64_t s = 0; s < P.n; ++s) idx[pos[s]] = orig[s];
+  API_END(h)
+}
+
+imgr_status imager_vis_weight(imgr_t h, int32_t part, float *w) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(w != nullptr, "w is NULL");
+  const Partition &P = h->part[part];
+  std::vector<float> ws(P.n);
+  std::vector<int32_t> pos(P.n);
+  IMGR_HIP(hipMemcpyAsync(ws.data(), P.w, P.n * 4, hipMemcpyDeviceToHost, h->stream));
+  IMGR_HIP(hipMemcpyAsync(pos.data(), P.outpos, P.n * 4, hipMemcpyDeviceToHost, h->stream));
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  for (int64_t s = 0; s < P.n; ++s) w[pos[s]] = ws[s];
+  API_END(h)
+}
+
+imgr_status imager_degrid(imgr_t h, int32_t part, const float *model, void *vis_out) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(model && vis_out, "null pointer");
+  hipStream_t s = h->stream;
+  fft_model_to_grid(h, model, nullptr, h->cinv, h->N, h->Ng, h->rows, h->grid_b, h->grid_a, s);
+  degrid_grid(h, part, MODE_DEGRID, h->grid_a, nullptr, (float2 *)vis_out, h->T, h->Ng, nullptr, s);
+  API_END(h)
+}
+
+imgr_status imager_grid(imgr_t h, int32_t part, const void *vis_in, float *image_out,
+                        int32_t mode) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(vis_in && image_out, "null pointer");
+  IMGR_CHECK(mode == IMGR_GRID_DIRTY || mode == IMGR_GRID_UNNORMALIZED, "mode");
+  hipStream_t s = h->stream;
+  degrid_grid(h, part, MODE_GRID, nullptr, (const float2 *)vis_in, nullptr, h->T, h->Ng, h->scratch, s);
+  flush_chunks(h, part, h->T, h->Ng, h->scratch, h->grid_a, s);
+  const float scale = mode == IMGR_GRID_DIRTY ? (float)(1.0 / h->part[part].sum_w) : 1.f;
+  fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, scale, h->rows, h->grid_b, image_out, s);
+  API_END(h)
+}
+
+imgr_status imager_psf(imgr_t h, int32_t part, float *psf_out) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(psf_out, "null pointer");
+  const size_t n2 = (size_t)2 * h->N;
+  IMGR_HIP(hipMemcpyAsync(psf_out, h->part[part].psf, n2 * n2 * sizeof(float),
+                          hipMemcpyDeviceToDevice, h->stream));
+  API_END(h)
+}
+
+imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model, const float *rho_other,
+                               double gamma, double mu, float *residual_out,
+                               float *residual_local_out, int32_t flags) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(model && residual_out, "null pointer");
+  IMGR_CHECK(!(flags & IMGR_DEGRID_COMPOSITE) || rho_other, "composite degrid needs rho_other");
+  hipStream_t s = h->stream;
+  const Partition &P = h->part[part];
+  float *local = residual_local_out ? residual_local_out : h->img_a;
+  // a1: model -> model grid
+  fft_model_to_grid(h, model, (flags & IMGR_DEGRID_COMPOSITE) ? rho_other : nullptr, h->cinv, h->N,
+                    h->Ng, h->rows, h->grid_b, h->grid_a, s);
+  // a2 + a3: degrid, residual, grid (one pass per chunk), flush
+  degrid_grid(h, part, MODE_DEGRID_GRID, h->grid_a, nullptr, nullptr, h->T, h->Ng, h->scratch, s);
+  flush_chunks(h, part, h->T, h->Ng, h->scratch, h->grid_a, s);
+  // a4: residual grid -> residual image
+  fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), h->rows,
+                    h->grid_b, local, s);
+  // a6: pseudo-full-resolution composition
+  if (h->n_parts == 2) {
+    compose(h, part, local, rho_other, gamma, mu, residual_out, s);
+  } else if (residual_out != local) {
+    IMGR_HIP(hipMemcpyAsync(residual_out, local, (size_t)h->N * h->N * sizeof(float),
+                            hipMemcpyDeviceToDevice, s));
+  }
+  API_END(h)
+}
+
+imgr_status imager_composed_psf(imgr_t h, int32_t part, double gamma, double mu, float *psf_out) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(psf_out, "null pointer");
+  if (h->n_parts == 1) {
+    const size_t n2 = (size_t)2 * h->N;
+    IMGR_HIP(hipMemcpyAsync(psf_out, h->part[part].psf, n2 * n2 * sizeof(float),
+                            hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    composed_psf(h, part, gamma, mu, psf_out, h->stream);
+  }
+  API_END(h)
+}
+
+imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t, const void *, const float *,
+                                       const float *, float *) {
+  if (!h) return IMGR_EINVAL;
+  h->err = "minor_cycle_msclean is not available in this version";
+  return IMGR_ENOTIMPL;
+}
+
+imgr_status imager_minor_cycle_fista(imgr_t h, int32_t, const void *, const float *,
+                                     const float *, float *) {
+  if (!h) return IMGR_EINVAL;
+  h->err = "minor_cycle_fista is not available in this version";
+  return IMGR_ENOTIMPL;
+}
+
+imgr_status imager_combine_partitions(imgr_t h, int32_t mode, const float *a, const float *b,
+                                      double w_a, double w_b, void *out_a, void *out_b) {
+  API_BEGIN(h)
+  IMGR_CHECK(a && b && out_a, "null pointer");
+  if (mode == IMGR_COMBINE_EXCHANGE) {
+    IMGR_CHECK(h->n_parts == 2, "exchange needs two partitions");
+    IMGR_CHECK(out_b, "null pointer");
+    exchange(h, a, b, (float *)out_a, (float *)out_b, h->stream);
+  } else if (mode == IMGR_COMBINE_FINAL) {
+    combine_final(h, a, b, w_a, w_b, (double *)out_a, h->stream);
+  } else {
+    throw Error{IMGR_EINVAL, "mode"};
+  }
+  API_END(h)
+}
+
+imgr_status imager_sync(imgr_t h) {
+  API_BEGIN(h)
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  API_END(h)
+}
+
+const char *imager_last_error(imgr_t h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Shared definitions of the HIP imager library (internal header).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/imager.h"
+
+namespace imgr {
+
+// ----------------------------------------------------------------- complex
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// twiddle table: tw[m] = exp(-2 pi i m / kTwMax), FP64-computed, f32-stored
+constexpr int kTwMax = 16384;
+
+// ----------------------------------------------------------------- handle
+
+struct Partition {
+  int64_t n = 0;              // members
+  int n_chunks = 0;
+  double sum_w = 0.0;
+  float4 *posvis = nullptr;   // [n] {dx, dy, re, im}: offsets in the tile, visibility
+  float *w = nullptr;         // [n] imaging weight
+  int32_t *orig = nullptr;    // [n] original index
+  int32_t *outpos = nullptr;  // [n] member rank (position in member order)
+  int32_t *chunk_tile = nullptr;   // [n_chunks]
+  int32_t *chunk_begin = nullptr;  // [n_chunks + 1]
+  int32_t *tile_chunk = nullptr;   // [n_tiles + 1] first chunk of each tile
+  float *psf = nullptr;            // (2N)^2 normalised PSF, centre (N, N)
+  float2 *psf_hat = nullptr;       // (2N)^2 plain DFT of psf
+};
+
+}  // namespace imgr
+
+struct imgr_s {
+  // geometry
+  int N = 0, Ng = 0, W = 8, T = 32, ntx = 0, n_tiles = 0, n_parts = 1, C = 4096;
+  double cell = 0, beta = 0, ell = 0, delta = 1;
+  int weighting = 0;
+  int64_t n_valid = 0;
+  hipStream_t stream = nullptr;
+  imgr::Partition part[2];
+  // tables
+  float *cinv = nullptr;       // [N]  1 / psi_hat, N image on the Ng grid
+  float *cinv2 = nullptr;      // [2N] 1 / psi_hat, 2N image on the 2 Ng grid
+  float2 *tw = nullptr;        // [kTwMax]
+  // work buffers
+  float2 *grid_a = nullptr;    // Ng^2
+  float2 *grid_b = nullptr;    // Ng^2
+  float2 *rows = nullptr;      // N x Ng (row-pass intermediate)
+  float2 *scratch = nullptr;   // chunk sub-grids
+  size_t scratch_elems = 0;
+  float *img_a = nullptr;      // N^2 f32
+  float *img_b = nullptr;      // N^2 f32
+  // bookkeeping
+  std::vector<void *> allocs;
+  std::vector<size_t> alloc_sizes;
+  size_t bytes = 0, budget = 0;
+  double create_ms = 0;
+  bool broken = false;
+  std::string err;
+};
+
+namespace imgr {
+
+// ----------------------------------------------------------------- errors
+
+struct Error {
+  imgr_status code;
+  std::string msg;
+};
+
+#define IMGR_HIP(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::imgr::Error{IMGR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define IMGR_CHECK(cond, msg)                                   \
+  do {                                                          \
+    if (!(cond)) throw ::imgr::Error{IMGR_EINVAL, (msg)};       \
+  } while (0)
+
+// device allocation accounted against the handle's budget
+void *dev_alloc(imgr_s *h, size_t bytes);
+void dev_free(imgr_s *h, void *p);
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ----------------------------------------------------------------- prep (a0)
+void prep_build(imgr_s *h, const imgr_vis *vis);
+
+// ----------------------------------------------------------------- FFT
+// centred forward transform of an N x N real image (times 1/psi_hat on both
+// axes, plus optional second image) into the Ng x Ng grid `out`
+void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, const float *cinv,
+                       int n, int ng, float2 *rows, float2 *tmp, float2 *out, hipStream_t s);
+// centred inverse transform of the Ng x Ng grid `in` (already multiplied by
+// (-1)^(gx+gy)) cropped to N x N, times (-1)^(px+py)/psi_hat^2 * scale, real part
+void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
+                       float2 *rows, float2 *tmp, float *out, hipStream_t s);
+// plain 2-D DFT of an n x n complex buffer in place (dir -1 forward, +1 inverse, unnormalised)
+void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t s);
+
+// ----------------------------------------------------------------- de/gridding
+enum GridMode { MODE_DEGRID_GRID = 0, MODE_GRID = 1, MODE_DEGRID = 2, MODE_PSF = 3 };
+// run the chunk kernel of partition p; grid_in: model grid (modes 0, 2);
+// vis_in: member-order visibilities (mode 1) or nullptr; vis_out (mode 2)
+void degrid_grid(imgr_s *h, int p, int mode, const float2 *grid_in, const float2 *vis_in,
+                 float2 *vis_out, int tile, int ng, float2 *scratch, hipStream_t s);
+// deterministic flush of the chunk sub-grids into an ng x ng grid, with (-1)^(x+y)
+void flush_chunks(imgr_s *h, int p, int tile, int ng, const float2 *scratch, float2 *grid_out,
+                  hipStream_t s);
+
+// ----------------------------------------------------------------- composition
+void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma, double mu,
+             float *out, hipStream_t s);
+void composed_psf(imgr_s *h, int p, double gamma, double mu, float *out, hipStream_t s);
+void exchange(imgr_s *h, const float *a, const float *b, float *rho_a, float *rho_b, hipStream_t s);
+void combine_final(imgr_s *h, const float *a, const float *b, double wa, double wb, double *out,
+                   hipStream_t s);
+void psf_spectrum(imgr_s *h, int p, hipStream_t s);
+
+// ----------------------------------------------------------------- misc kernels
+void add_images(const float *a, const float *b, float *out, int64_t n, hipStream_t s);
+
+}  // namespace imgr

@@ -1,0 +1,375 @@
+// Hand-written radix-8/4/2 Stockham FFTs for gfx950.
+//
+// The 2-D transforms of Eq. 2 (F and F^dagger, Section 2) are split into
+//   * row passes: one workgroup per row, the whole row in LDS (<= 8192
+//     points, padded one slot per 32 against bank conflicts of the
+//     strided Stockham stores);
+//   * column passes: a four-step split L = P * Q done in two kernels over
+//     blocks of 64 adjacent columns (512-byte coalesced row segments); in
+//     LDS each wave owns 64 columns, so every lane of a wave uses the same
+//     row index and twiddle (no bank conflicts, scalar twiddle loads).
+// Zero rows of a padded input are never read and rows outside a crop are
+// never written.  The centred transform of the gridder (grid cell g holds
+// frequency g - Ng/2) is the plain DFT with (-1)^index modulation on both
+// sides, which the load and store of the passes apply.
+#include "common.h"
+
+namespace imgr {
+namespace {
+
+__device__ __forceinline__ int padi(int i) { return i + (i >> 5); }
+
+template <int DIR>
+__device__ __forceinline__ float2 tw_get(const float2 *__restrict__ tw, int idx) {
+  float2 t = tw[idx];
+  if (DIR > 0) t.y = -t.y;
+  return t;
+}
+
+// multiply by -i (forward, DIR < 0) or +i (inverse)
+template <int DIR>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2 &y0, float2 &y1, float2 &y2, float2 &y3) {
+  float2 t0 = cadd(y0, y2), t1 = csub(y0, y2), t2 = cadd(y1, y3), t3 = mul_mi<DIR>(csub(y1, y3));
+  y0 = cadd(t0, t2);
+  y2 = csub(t0, t2);
+  y1 = cadd(t1, t3);
+  y3 = csub(t1, t3);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2 *x) {
+  if constexpr (R == 2) {
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(x[0], x[1], x[2], x[3]);
+  } else {
+    static_assert(R == 8, "radix");
+    const float h = 0.70710678118654752440f;
+    float2 a0 = cadd(x[0], x[4]), a1 = cadd(x[1], x[5]), a2 = cadd(x[2], x[6]), a3 = cadd(x[3], x[7]);
+    float2 b0 = csub(x[0], x[4]), b1 = csub(x[1], x[5]), b2 = csub(x[2], x[6]), b3 = csub(x[3], x[7]);
+    // b_n *= W8^n, W8 = exp(DIR * 2 pi i / 8)
+    if (DIR < 0) {
+      b1 = make_float2((b1.x + b1.y) * h, (b1.y - b1.x) * h);
+      b3 = make_float2((b3.y - b3.x) * h, -(b3.x + b3.y) * h);
+    } else {
+      b1 = make_float2((b1.x - b1.y) * h, (b1.x + b1.y) * h);
+      b3 = make_float2(-(b3.x + b3.y) * h, (b3.x - b3.y) * h);
+    }
+    b2 = mul_mi<DIR>(b2);
+    dft4<DIR>(a0, a1, a2, a3);
+    dft4<DIR>(b0, b1, b2, b3);
+    x[0] = a0; x[2] = a1; x[4] = a2; x[6] = a3;
+    x[1] = b0; x[3] = b1; x[5] = b2; x[7] = b3;
+  }
+}
+
+// One sequence of length L in padded LDS, NT threads, Stockham passes from
+// sub-length NS upward (radix 8 while possible, then 4 or 2).
+template <int L, int NT, int NS, int DIR>
+__device__ __forceinline__ void stockham_seq(float2 *s, const float2 *__restrict__ tw, int t) {
+  if constexpr (NS < L) {
+    constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
+    constexpr int NB = L / R;
+    constexpr int PER = (NB + NT - 1) / NT;
+    float2 x[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = t + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[q][r] = s[padi(j + r * NB)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = t + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+        const int k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r)
+            x[q][r] = cmul(x[q][r], tw_get<DIR>(tw, r * k * (kTwMax / (NS * R))));
+        }
+        dft<R, DIR>(x[q]);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[padi(base + r * NS)] = x[q][r];
+      }
+    }
+    __syncthreads();
+    stockham_seq<L, NT, NS * R, DIR>(s, tw, t);
+  }
+}
+
+// 64 sequences of length LEN stored as s[pos][64] (column c = lane), 256
+// threads: wave w does butterflies j = w, w + 4, ...
+template <int LEN, int NS, int DIR>
+__device__ __forceinline__ void stockham_cols(float2 *s, const float2 *__restrict__ tw, int t) {
+  if constexpr (NS < LEN) {
+    constexpr int R = (LEN / NS >= 8) ? 8 : (LEN / NS);
+    constexpr int NB = LEN / R;
+    constexpr int PER = (NB + 3) / 4;
+    const int c = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    float2 x[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = wv + 4 * q;
+      if (j < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[q][r] = s[(j + r * NB) * 64 + c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = wv + 4 * q;
+      if (j < NB) {
+        const int k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r)
+            x[q][r] = cmul(x[q][r], tw_get<DIR>(tw, r * k * (kTwMax / (NS * R))));
+        }
+        dft<R, DIR>(x[q]);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[(base + r * NS) * 64 + c] = x[q][r];
+      }
+    }
+    __syncthreads();
+    stockham_cols<LEN, NS * R, DIR>(s, tw, t);
+  }
+}
+
+template <int L>
+struct RowThreads {
+  static constexpr int v = (L / 8 < 64) ? 64 : ((L / 8 > 1024) ? 1024 : L / 8);
+};
+
+// ---------------------------------------------------------------- row kernels
+
+// model (n x n f32) [+ model_add] -> rows (n x L complex): correction 1/psi on
+// both axes, centred zero-padding, (-1)^(x+y) modulation, forward row DFT.
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
+    const float *__restrict__ model, const float *__restrict__ model_add,
+    const float *__restrict__ cinv, int n, float2 *__restrict__ rows,
+    const float2 *__restrict__ tw) {
+  constexpr int NT = RowThreads<L>::v;
+  __shared__ float2 s[L + L / 32];
+  const int r = blockIdx.x;
+  const int o = (L - n) / 2;
+  const int y = o + r;
+  const float cy = cinv[r];
+  for (int x = threadIdx.x; x < L; x += NT) {
+    float v = 0.f;
+    if (x >= o && x < o + n) {
+      const int ix = x - o;
+      v = model[(size_t)r * n + ix];
+      if (model_add) v += model_add[(size_t)r * n + ix];
+      v *= cinv[ix] * cy;
+      if ((x + y) & 1) v = -v;
+    }
+    s[padi(x)] = make_float2(v, 0.f);
+  }
+  __syncthreads();
+  stockham_seq<L, NT, 1, -1>(s, tw, threadIdx.x);
+  for (int x = threadIdx.x; x < L; x += NT) rows[(size_t)r * L + x] = s[padi(x)];
+}
+
+// rows (n x L complex) -> image (n x n f32): inverse row DFT, crop of the
+// centre, (-1)^(x+y), correction 1/psi on both axes, real part, scale.
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
+    const float2 *__restrict__ rows, const float *__restrict__ cinv, int n, float scale,
+    float *__restrict__ out, const float2 *__restrict__ tw) {
+  constexpr int NT = RowThreads<L>::v;
+  __shared__ float2 s[L + L / 32];
+  const int r = blockIdx.x;
+  const int o = (L - n) / 2;
+  const int y = o + r;
+  for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = rows[(size_t)r * L + x];
+  __syncthreads();
+  stockham_seq<L, NT, 1, 1>(s, tw, threadIdx.x);
+  const float cy = cinv[r] * scale;
+  for (int ix = threadIdx.x; ix < n; ix += NT) {
+    const int x = o + ix;
+    float v = s[padi(x)].x;
+    if ((x + y) & 1) v = -v;
+    out[(size_t)r * n + ix] = v * cinv[ix] * cy;
+  }
+}
+
+// plain in-place complex row DFTs of an L x L buffer
+template <int L, int DIR>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(float2 *__restrict__ buf,
+                                                                 const float2 *__restrict__ tw) {
+  constexpr int NT = RowThreads<L>::v;
+  __shared__ float2 s[L + L / 32];
+  float2 *row = buf + (size_t)blockIdx.x * L;
+  for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = row[x];
+  __syncthreads();
+  stockham_seq<L, NT, 1, DIR>(s, tw, threadIdx.x);
+  for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
+}
+
+// ---------------------------------------------------------------- column kernels
+// Column DFT of length L = P * Q over an L x L array (row stride L):
+//   pass 1 (block (cb, y2)): A[k1] = sum_y1 x[Q y1 + y2] w_P^(y1 k1), times
+//          w_L^(y2 k1), stored at row Q k1 + y2 of dst;
+//   pass 2 (block (cb, k1)): X[k1 + P k2] = sum_y2 A[Q k1 + y2] w_Q^(y2 k2).
+// Pass 1 reads source row y from src row (y - src_row0) and treats rows
+// outside [y_lo, y_hi) as zero.  Pass 2 keeps output rows k in [k_lo, k_hi),
+// stored at dst row (k - dst_row0), optionally times (-1)^(k + x).
+
+template <int P, int Q, int DIR>
+__global__ __launch_bounds__(256) void k_cols_p1(const float2 *__restrict__ src, int src_row0,
+                                                 int y_lo, int y_hi, float2 *__restrict__ dst,
+                                                 const float2 *__restrict__ tw) {
+  constexpr int L = P * Q;
+  __shared__ float2 s[P * 64];
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * 64;
+  const int y2 = blockIdx.y;
+  for (int i = t; i < P * 64; i += 256) {
+    const int y1 = i >> 6, c = i & 63;
+    const int y = Q * y1 + y2;
+    float2 v = make_float2(0.f, 0.f);
+    if (y >= y_lo && y < y_hi) v = src[(size_t)(y - src_row0) * L + x0 + c];
+    s[i] = v;
+  }
+  __syncthreads();
+  stockham_cols<P, 1, DIR>(s, tw, t);
+  for (int i = t; i < P * 64; i += 256) {
+    const int k1 = i >> 6, c = i & 63;
+    const int m = (y2 * k1) & (L - 1);
+    dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], tw_get<DIR>(tw, m * (kTwMax / L)));
+  }
+}
+
+template <int P, int Q, int DIR>
+__global__ __launch_bounds__(256) void k_cols_p2(const float2 *__restrict__ src,
+                                                 float2 *__restrict__ dst, int dst_row0, int k_lo,
+                                                 int k_hi, int modulate,
+                                                 const float2 *__restrict__ tw) {
+  constexpr int L = P * Q;
+  __shared__ float2 s[Q * 64];
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * 64;
+  const int k1 = blockIdx.y;
+  for (int i = t; i < Q * 64; i += 256) {
+    const int y2 = i >> 6, c = i & 63;
+    s[i] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+  }
+  __syncthreads();
+  stockham_cols<Q, 1, DIR>(s, tw, t);
+  for (int i = t; i < Q * 64; i += 256) {
+    const int k2 = i >> 6, c = i & 63;
+    const int k = k1 + P * k2;
+    if (k >= k_lo && k < k_hi) {
+      float2 v = s[i];
+      if (modulate && ((k + x0 + c) & 1)) v = make_float2(-v.x, -v.y);
+      dst[(size_t)(k - dst_row0) * L + x0 + c] = v;
+    }
+  }
+}
+
+template <int L>
+struct Split;
+template <> struct Split<64> { static constexpr int P = 8, Q = 8; };
+template <> struct Split<128> { static constexpr int P = 8, Q = 16; };
+template <> struct Split<256> { static constexpr int P = 16, Q = 16; };
+template <> struct Split<512> { static constexpr int P = 16, Q = 32; };
+template <> struct Split<1024> { static constexpr int P = 32, Q = 32; };
+template <> struct Split<2048> { static constexpr int P = 32, Q = 64; };
+template <> struct Split<4096> { static constexpr int P = 64, Q = 64; };
+template <> struct Split<8192> { static constexpr int P = 64, Q = 128; };
+
+template <int L, int DIR>
+void cols(const float2 *src, int src_row0, int y_lo, int y_hi, float2 *tmp, float2 *dst,
+          int dst_row0, int k_lo, int k_hi, int modulate, const float2 *tw, hipStream_t s) {
+  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR>), dim3(L / 64, Q), dim3(256), 0, s, src, src_row0,
+                     y_lo, y_hi, tmp, tw);
+  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR>), dim3(L / 64, P), dim3(256), 0, s, tmp, dst,
+                     dst_row0, k_lo, k_hi, modulate, tw);
+}
+
+template <int L>
+void model_to_grid_t(imgr_s *h, const float *model, const float *model_add, const float *cinv,
+                     int n, float2 *rows, float2 *tmp, float2 *out, hipStream_t s) {
+  const int o = (L - n) / 2;
+  hipLaunchKernelGGL((k_rows_model<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, model, model_add,
+                     cinv, n, rows, h->tw);
+  cols<L, -1>(rows, o, o, o + n, tmp, out, 0, 0, L, 1, h->tw, s);
+}
+
+template <int L>
+void grid_to_image_t(imgr_s *h, const float2 *in, const float *cinv, int n, float scale,
+                     float2 *rows, float2 *tmp, float *out, hipStream_t s) {
+  const int o = (L - n) / 2;
+  cols<L, 1>(in, 0, 0, L, tmp, rows, o, o, o + n, 0, h->tw, s);
+  hipLaunchKernelGGL((k_rows_image<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, rows, cinv, n,
+                     scale, out, h->tw);
+}
+
+template <int L>
+void plain_t(imgr_s *h, float2 *buf, float2 *tmp, int dir, hipStream_t s) {
+  if (dir < 0) {
+    hipLaunchKernelGGL((k_rows_plain<L, -1>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, h->tw);
+    cols<L, -1>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, h->tw, s);
+  } else {
+    hipLaunchKernelGGL((k_rows_plain<L, 1>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, h->tw);
+    cols<L, 1>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, h->tw, s);
+  }
+}
+
+}  // namespace
+
+#define IMGR_FFT_SIZES(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+
+void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, const float *cinv,
+                       int n, int ng, float2 *rows, float2 *tmp, float2 *out, hipStream_t s) {
+  switch (ng) {
+#define X(L) \
+  case L: model_to_grid_t<L>(h, model, model_add, cinv, n, rows, tmp, out, s); break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
+                       float2 *rows, float2 *tmp, float *out, hipStream_t s) {
+  switch (ng) {
+#define X(L) \
+  case L: grid_to_image_t<L>(h, in, cinv, n, scale, rows, tmp, out, s); break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: plain_t<L>(h, buf, tmp, dir, s); break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+}  // namespace imgr

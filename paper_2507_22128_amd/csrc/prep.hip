@@ -1,0 +1,526 @@
+// Preparation of a handle (once per imager_create): FP64 coordinate chain,
+// uniform weighting (Section 5.1), spatial-frequency partition of Fig. 3
+// with ell at the lower median of rho unless given, stable sort of each
+// partition by uv tile, chunk tables, and packing into the 20-byte
+// per-visibility stream the de/gridding kernels read.
+//
+// Every decision that turns a floating-point value into an integer (tap
+// cell, tile, uniform-weight cell, partition membership) is taken in FP64
+// with plain multiply / add / sqrt (no contraction), the same operation
+// sequence the CPU oracle uses, so the integer results agree bit for bit.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace imgr {
+namespace {
+
+constexpr double kC = 299792458.0;
+
+// ---------------------------------------------------------------- coordinates
+
+__global__ void k_coords(int64_t m, const double *__restrict__ uvw,
+                         const uint8_t *__restrict__ flag, double lam_scale, double g_scale,
+                         double g_half, double p_scale, int n_img, int ng,
+                         double *__restrict__ gx, double *__restrict__ gy,
+                         double *__restrict__ rho, int32_t *__restrict__ cellkey,
+                         uint8_t *__restrict__ valid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double u = uvw[3 * i] * lam_scale;
+  double v = uvw[3 * i + 1] * lam_scale;
+  bool ok = flag ? (flag[i] == 0) : true;
+  if (!isfinite(u) || !isfinite(v)) {  // unusable coordinates are dropped like flags
+    ok = false;
+    u = 0.0;
+    v = 0.0;
+  }
+  double x = u * g_scale + g_half;
+  double y = v * g_scale + g_half;
+  // periodic grid: bring coordinates into [0, Ng) (x == Ng after rounding is cell 0)
+  if (x < 0.0 || x >= (double)ng) x = x - (double)ng * floor(x / (double)ng);
+  if (y < 0.0 || y >= (double)ng) y = y - (double)ng * floor(y / (double)ng);
+  if (!(x < (double)ng)) x = 0.0;
+  if (!(y < (double)ng)) y = 0.0;
+  gx[i] = x;
+  gy[i] = y;
+  const double pu = u * p_scale, pv = v * p_scale;
+  rho[i] = sqrt(pu * pu + pv * pv);
+  long long cu = (long long)floor(pu + 0.5) % n_img;
+  long long cv = (long long)floor(pv + 0.5) % n_img;
+  if (cu < 0) cu += n_img;
+  if (cv < 0) cv += n_img;
+  cellkey[i] = (int32_t)(cv * n_img + cu);
+  valid[i] = ok ? 1 : 0;
+}
+
+__global__ void k_cell_hist(int64_t m, const int32_t *__restrict__ cellkey,
+                            const uint8_t *__restrict__ valid, int32_t *__restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && valid[i]) atomicAdd(&counts[cellkey[i]], 1);
+}
+
+__global__ void k_weights(int64_t m, const float *__restrict__ w_in,
+                          const int32_t *__restrict__ cellkey, const uint8_t *__restrict__ valid,
+                          const int32_t *__restrict__ counts, int uniform,
+                          double *__restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double wi = w_in ? (double)w_in[i] : 1.0;
+  double r = 0.0;
+  if (valid[i]) r = uniform ? wi / (double)counts[cellkey[i]] : wi;
+  w[i] = r;
+}
+
+__global__ void k_valid_int(int64_t m, const uint8_t *__restrict__ valid,
+                            int32_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = valid[i] ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- radix select
+
+__global__ void k_select_hist(int64_t m, const double *__restrict__ rho,
+                              const uint8_t *__restrict__ valid, unsigned long long pmask,
+                              unsigned long long pval, int shift, int32_t *__restrict__ hist) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+    if (!valid[i]) continue;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(rho[i]);
+    if ((b & pmask) != pval) continue;
+    atomicAdd(&h[(b >> shift) & 255], 1);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------- partition keys
+
+__global__ void k_part_keys(int64_t m, const double *__restrict__ gx,
+                            const double *__restrict__ gy, const double *__restrict__ rho,
+                            const uint8_t *__restrict__ valid, int which, double lo_max,
+                            double hi_min, int tile, int ntx, uint32_t *__restrict__ keys,
+                            int32_t *__restrict__ vals, int32_t *__restrict__ member) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  bool in = valid[i];
+  if (which == 0) in = in && (rho[i] <= lo_max);
+  if (which == 1) in = in && (rho[i] >= hi_min);
+  uint32_t key = (uint32_t)(ntx * ntx);
+  if (in) {
+    const int cx = (int)floor(gx[i]), cy = (int)floor(gy[i]);
+    key = (uint32_t)((cy / tile) * ntx + (cx / tile));
+  }
+  keys[i] = key;
+  vals[i] = (int32_t)i;
+  member[i] = in ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- scan (int32)
+
+constexpr int kScanBlock = 1024;  // elements per block, 256 threads x 4
+
+__device__ int block_excl_scan(int v, int *sh) {
+  // inclusive scan of 256 values in LDS (Hillis-Steele), returns exclusive
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int a = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_sums(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ sums) {
+  __shared__ int sh[256];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int s = 0;
+  for (int k = 0; k < 4; ++k)
+    if (base + k < n) s += in[base + k];
+  const int ex = block_excl_scan(s, sh);
+  if (threadIdx.x == 255) sums[blockIdx.x] = ex + s;
+}
+
+__global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n,
+                             const int32_t *__restrict__ offs, int32_t *__restrict__ out) {
+  __shared__ int sh[256];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int v[4], s = 0;
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int run = block_excl_scan(s, sh) + offs[blockIdx.x];
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// exclusive scan of n int32 values (in and out may alias); returns the total
+int64_t scan_exclusive(imgr_s *h, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  int32_t *sums = (int32_t *)dev_alloc(h, (nb + 1) * sizeof(int32_t));
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, in, n, sums);
+  IMGR_HIP(hipGetLastError());
+  int64_t total;
+  if (nb == 1) {
+    int32_t t;
+    IMGR_HIP(hipMemcpyAsync(&t, sums, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    IMGR_HIP(hipStreamSynchronize(s));
+    total = t;
+    IMGR_HIP(hipMemsetAsync(sums, 0, sizeof(int32_t), s));
+  } else {
+    total = scan_exclusive(h, sums, sums, nb, s);
+  }
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, n, sums, out);
+  IMGR_HIP(hipGetLastError());
+  IMGR_HIP(hipStreamSynchronize(s));
+  dev_free(h, sums);
+  return total;
+}
+
+// ---------------------------------------------------------------- radix sort
+// Stable LSD radix sort of (uint32 key, int32 value) pairs, 8-bit digits.
+// Block b owns elements [b * 4096, (b + 1) * 4096) in both kernels.
+
+constexpr int kSortItems = 4096;
+
+__global__ void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift, int nb,
+                             int32_t *__restrict__ counts) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortItems;
+  for (int k = threadIdx.x; k < kSortItems; k += 256) {
+    const int64_t i = base + k;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
+                                int64_t n, int shift, int nb, const int32_t *__restrict__ offs,
+                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout) {
+  __shared__ int32_t base[256];
+  __shared__ int32_t wcnt[4][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  base[t] = offs[(int64_t)t * nb + blockIdx.x];
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int round = 0; round < kSortItems / 256; ++round) {
+    const int64_t i = (int64_t)blockIdx.x * kSortItems + round * 256 + t;
+    const bool ok = i < n;
+    const uint32_t key = ok ? kin[i] : 0u;
+    const int d = (key >> shift) & 255;
+    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    unsigned long long same = __ballot(ok);
+    for (int bit = 0; bit < 8; ++bit) {
+      const unsigned long long bb = __ballot(ok && ((d >> bit) & 1));
+      same &= ((d >> bit) & 1) ? bb : ~bb;
+    }
+    const int rank = __popcll(same & below);
+    const int cnt = __popcll(same);
+    if (ok && rank == cnt - 1) wcnt[wv][d] = cnt;
+    __syncthreads();
+    if (ok) {
+      int pos = base[d] + rank;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    __syncthreads();
+  }
+}
+
+void radix_sort(imgr_s *h, uint32_t *&keys, int32_t *&vals, uint32_t *&ktmp, int32_t *&vtmp,
+                int64_t n, int key_bits, hipStream_t s) {
+  const int nb = (int)((n + kSortItems - 1) / kSortItems);
+  int32_t *counts = (int32_t *)dev_alloc(h, (size_t)256 * nb * sizeof(int32_t));
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(256), 0, s, keys, n, shift, nb, counts);
+    IMGR_HIP(hipGetLastError());
+    scan_exclusive(h, counts, counts, (int64_t)256 * nb, s);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(256), 0, s, keys, vals, n, shift, nb,
+                       counts, ktmp, vtmp);
+    IMGR_HIP(hipGetLastError());
+    std::swap(keys, ktmp);
+    std::swap(vals, vtmp);
+  }
+  IMGR_HIP(hipStreamSynchronize(s));
+  dev_free(h, counts);
+}
+
+// ---------------------------------------------------------------- tiles, chunks, pack
+
+__global__ void k_tile_hist(int64_t n, const uint32_t *__restrict__ keys, int n_tiles,
+                            int32_t *__restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && keys[i] < (uint32_t)n_tiles) atomicAdd(&cnt[keys[i]], 1);
+}
+
+__global__ void k_chunk_count(int n_tiles, const int32_t *__restrict__ cnt, int cap,
+                              int32_t *__restrict__ nch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tiles) nch[t] = (cnt[t] + cap - 1) / cap;
+}
+
+// chunks of tile t split its cnt[t] visibilities evenly:
+// chunk q covers [start + cnt*q/k, start + cnt*(q+1)/k)
+__global__ void k_make_chunks(int n_tiles, const int32_t *__restrict__ cnt,
+                              const int32_t *__restrict__ tstart,
+                              const int32_t *__restrict__ tchunk, int32_t *__restrict__ ctile,
+                              int32_t *__restrict__ cbegin) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int k = tchunk[t + 1] - tchunk[t];
+  for (int q = 0; q < k; ++q) {
+    ctile[tchunk[t] + q] = t;
+    cbegin[tchunk[t] + q] = tstart[t] + (int)(((int64_t)cnt[t] * q) / k);
+  }
+}
+
+__global__ void k_pack(int64_t n, const uint32_t *__restrict__ keys,
+                       const int32_t *__restrict__ idx, const double *__restrict__ gx,
+                       const double *__restrict__ gy, const void *__restrict__ vis, int c128,
+                       const double *__restrict__ w64, const int32_t *__restrict__ rank,
+                       int tile, int ntx, float4 *__restrict__ posvis, float *__restrict__ w,
+                       int32_t *__restrict__ orig, int32_t *__restrict__ outpos) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = idx[s];
+  const int t = (int)keys[s];
+  const int tx = t % ntx, ty = t / ntx;
+  float re, im;
+  if (c128) {
+    const double2 z = ((const double2 *)vis)[i];
+    re = (float)z.x;
+    im = (float)z.y;
+  } else {
+    const float2 z = ((const float2 *)vis)[i];
+    re = z.x;
+    im = z.y;
+  }
+  posvis[s] = make_float4((float)(gx[i] - (double)(tx * tile)),
+                          (float)(gy[i] - (double)(ty * tile)), re, im);
+  w[s] = (float)w64[i];
+  orig[s] = i;
+  outpos[s] = rank[i];
+}
+
+__global__ void k_sum_members(int64_t m, const double *__restrict__ w,
+                              const int32_t *__restrict__ member, double *__restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t b = (int64_t)blockIdx.x * per, e = min(m, b + per);
+  for (int64_t i = b + threadIdx.x; i < e; i += 256)
+    if (member[i]) acc += w[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+T *alloc_n(imgr_s *h, int64_t n) {
+  return (T *)dev_alloc(h, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+}
+
+double lower_median_rho(imgr_s *h, int64_t m, const double *rho, const uint8_t *valid,
+                        int64_t n_valid, hipStream_t s) {
+  int32_t *hist = alloc_n<int32_t>(h, 256);
+  unsigned long long pmask = 0, pval = 0;
+  int64_t rank = (n_valid - 1) / 2;
+  std::vector<int32_t> hh(256);
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    IMGR_HIP(hipMemsetAsync(hist, 0, 256 * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_select_hist, dim3(1024), dim3(256), 0, s, m, rho, valid, pmask, pval,
+                       shift, hist);
+    IMGR_HIP(hipGetLastError());
+    IMGR_HIP(hipMemcpyAsync(hh.data(), hist, 256 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    IMGR_HIP(hipStreamSynchronize(s));
+    int d = 0;
+    for (; d < 256; ++d) {
+      if (rank < hh[d]) break;
+      rank -= hh[d];
+    }
+    if (d == 256) throw Error{IMGR_EDEVICE, "median selection lost its rank"};
+    pmask |= 255ull << shift;
+    pval |= (unsigned long long)d << shift;
+  }
+  dev_free(h, hist);
+  double med;
+  memcpy(&med, &pval, sizeof(double));
+  return med;
+}
+
+void build_partition(imgr_s *h, int p, int which, int64_t m, const double *gx, const double *gy,
+                     const double *rho, const uint8_t *valid, const double *w64,
+                     const void *vis_dev, int c128, hipStream_t s) {
+  Partition &P = h->part[p];
+  const int n_tiles = h->n_tiles;
+  const unsigned nbk = cdiv(m, 256);
+  uint32_t *keys = alloc_n<uint32_t>(h, m), *ktmp = alloc_n<uint32_t>(h, m);
+  int32_t *vals = alloc_n<int32_t>(h, m), *vtmp = alloc_n<int32_t>(h, m);
+  int32_t *member = alloc_n<int32_t>(h, m);
+  hipLaunchKernelGGL(k_part_keys, dim3(nbk), dim3(256), 0, s, m, gx, gy, rho, valid, which,
+                     h->ell + h->delta, h->ell - h->delta, h->T, h->ntx, keys, vals, member);
+  IMGR_HIP(hipGetLastError());
+  // member rank in original order, and the member count
+  int32_t *rank = alloc_n<int32_t>(h, m);
+  const int64_t n = scan_exclusive(h, member, rank, m, s);
+  P.n = n;
+  // summed weight (FP64, fixed order: 256 block partials summed on the host)
+  {
+    double *part = alloc_n<double>(h, 256);
+    hipLaunchKernelGGL(k_sum_members, dim3(256), dim3(256), 0, s, m, w64, member, part);
+    IMGR_HIP(hipGetLastError());
+    std::vector<double> hp(256);
+    IMGR_HIP(hipMemcpyAsync(hp.data(), part, 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IMGR_HIP(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (double v : hp) acc += v;
+    P.sum_w = acc;
+    dev_free(h, part);
+  }
+  // stable sort by tile; non-members (key n_tiles) go last
+  int key_bits = 0;
+  while ((1ll << key_bits) <= n_tiles) key_bits += 8;
+  radix_sort(h, keys, vals, ktmp, vtmp, m, key_bits, s);
+  // tile counts, starts, chunks
+  int32_t *cnt = alloc_n<int32_t>(h, n_tiles + 1);
+  int32_t *tstart = alloc_n<int32_t>(h, n_tiles + 1);
+  int32_t *nch = alloc_n<int32_t>(h, n_tiles + 1);
+  IMGR_HIP(hipMemsetAsync(cnt, 0, (n_tiles + 1) * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_tile_hist, dim3(cdiv(std::max<int64_t>(n, 1), 256)), dim3(256), 0, s, n,
+                     keys, n_tiles, cnt);
+  IMGR_HIP(hipGetLastError());
+  scan_exclusive(h, cnt, tstart, n_tiles + 1, s);
+  hipLaunchKernelGGL(k_chunk_count, dim3(cdiv(n_tiles + 1, 256)), dim3(256), 0, s, n_tiles + 1,
+                     cnt, h->C, nch);
+  IMGR_HIP(hipGetLastError());
+  P.tile_chunk = alloc_n<int32_t>(h, n_tiles + 1);
+  // nch[n_tiles] is 0 (cnt[n_tiles] == 0), so the scan's last entry is the total
+  P.n_chunks = (int)scan_exclusive(h, nch, P.tile_chunk, n_tiles + 1, s);
+  P.chunk_tile = alloc_n<int32_t>(h, P.n_chunks);
+  P.chunk_begin = alloc_n<int32_t>(h, P.n_chunks + 1);
+  hipLaunchKernelGGL(k_make_chunks, dim3(cdiv(n_tiles, 256)), dim3(256), 0, s, n_tiles, cnt,
+                     tstart, P.tile_chunk, P.chunk_tile, P.chunk_begin);
+  IMGR_HIP(hipGetLastError());
+  {
+    const int32_t nn = (int32_t)n;
+    IMGR_HIP(hipMemcpyAsync(P.chunk_begin + P.n_chunks, &nn, sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+  }
+  // pack the per-visibility stream
+  P.posvis = alloc_n<float4>(h, n);
+  P.w = alloc_n<float>(h, n);
+  P.orig = alloc_n<int32_t>(h, n);
+  P.outpos = alloc_n<int32_t>(h, n);
+  if (n > 0)
+    hipLaunchKernelGGL(k_pack, dim3(cdiv(n, 256)), dim3(256), 0, s, n, keys, vals, gx, gy,
+                       vis_dev, c128, w64, rank, h->T, h->ntx, P.posvis, P.w, P.orig, P.outpos);
+  IMGR_HIP(hipGetLastError());
+  IMGR_HIP(hipStreamSynchronize(s));
+  for (void *q : {(void *)keys, (void *)ktmp, (void *)vals, (void *)vtmp, (void *)member,
+                  (void *)rank, (void *)cnt, (void *)tstart, (void *)nch})
+    dev_free(h, q);
+}
+
+}  // namespace
+
+void prep_build(imgr_s *h, const imgr_vis *vis) {
+  hipStream_t s = h->stream;
+  const int64_t m = vis->n_vis;
+  const int c128 = vis->vis_dtype == IMGR_C128;
+  const size_t vbytes = (size_t)m * (c128 ? 16 : 8);
+  // inputs on the device
+  const double *uvw = vis->uvw;
+  const void *vdev = vis->vis;
+  const float *wdev = vis->weight;
+  const uint8_t *fdev = vis->flag;
+  std::vector<void *> staged;
+  if (!vis->on_device) {
+    double *a = alloc_n<double>(h, 3 * m);
+    IMGR_HIP(hipMemcpyAsync(a, vis->uvw, (size_t)m * 24, hipMemcpyHostToDevice, s));
+    uvw = a;
+    void *b = dev_alloc(h, std::max<size_t>(vbytes, 1));
+    IMGR_HIP(hipMemcpyAsync(b, vis->vis, vbytes, hipMemcpyHostToDevice, s));
+    vdev = b;
+    staged.push_back(a);
+    staged.push_back(b);
+    if (vis->weight) {
+      float *c = alloc_n<float>(h, m);
+      IMGR_HIP(hipMemcpyAsync(c, vis->weight, (size_t)m * 4, hipMemcpyHostToDevice, s));
+      wdev = c;
+      staged.push_back(c);
+    }
+    if (vis->flag) {
+      uint8_t *d = alloc_n<uint8_t>(h, m);
+      IMGR_HIP(hipMemcpyAsync(d, vis->flag, (size_t)m, hipMemcpyHostToDevice, s));
+      fdev = d;
+      staged.push_back(d);
+    }
+  }
+  double *gx = alloc_n<double>(h, m), *gy = alloc_n<double>(h, m), *rho = alloc_n<double>(h, m);
+  double *w64 = alloc_n<double>(h, m);
+  int32_t *cellkey = alloc_n<int32_t>(h, m);
+  uint8_t *valid = alloc_n<uint8_t>(h, m);
+  const unsigned nbk = cdiv(m, 256);
+  const double lam_scale = vis->freq_hz / kC;
+  const double g_scale = (double)h->Ng * h->cell;
+  const double p_scale = (double)h->N * h->cell;
+  if (m > 0)
+    hipLaunchKernelGGL(k_coords, dim3(nbk), dim3(256), 0, s, m, uvw, fdev, lam_scale, g_scale,
+                       (double)(h->Ng / 2), p_scale, h->N, h->Ng, gx, gy, rho, cellkey, valid);
+  IMGR_HIP(hipGetLastError());
+  // uniform weighting: per-cell counts of unflagged visibilities
+  int32_t *counts = alloc_n<int32_t>(h, (int64_t)h->N * h->N);
+  IMGR_HIP(hipMemsetAsync(counts, 0, (size_t)h->N * h->N * sizeof(int32_t), s));
+  if (m > 0) {
+    hipLaunchKernelGGL(k_cell_hist, dim3(nbk), dim3(256), 0, s, m, cellkey, valid, counts);
+    hipLaunchKernelGGL(k_weights, dim3(nbk), dim3(256), 0, s, m, wdev, cellkey, valid, counts,
+                       h->weighting == IMGR_WEIGHT_UNIFORM ? 1 : 0, w64);
+  }
+  IMGR_HIP(hipGetLastError());
+  // number of unflagged visibilities
+  {
+    int32_t *vi = alloc_n<int32_t>(h, m);
+    if (m > 0)
+      hipLaunchKernelGGL(k_valid_int, dim3(nbk), dim3(256), 0, s, m, valid, vi);
+    IMGR_HIP(hipGetLastError());
+    h->n_valid = scan_exclusive(h, vi, vi, m, s);
+    dev_free(h, vi);
+  }
+  if (h->n_valid == 0) throw Error{IMGR_EINVAL, "no unflagged visibilities"};
+  // partition radius
+  if (h->n_parts == 2 && h->ell < 0) h->ell = lower_median_rho(h, m, rho, valid, h->n_valid, s);
+  for (int p = 0; p < h->n_parts; ++p)
+    build_partition(h, p, h->n_parts == 1 ? 2 : p, m, gx, gy, rho, valid, w64, vdev, c128, s);
+  IMGR_HIP(hipStreamSynchronize(s));
+  for (void *q : {(void *)gx, (void *)gy, (void *)rho, (void *)w64, (void *)cellkey,
+                  (void *)valid, (void *)counts})
+    dev_free(h, q);
+  for (void *q : staged) dev_free(h, q);
+}
+
+}  // namespace imgr

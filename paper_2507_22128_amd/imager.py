@@ -1,0 +1,298 @@
+"""ctypes binding of ``libimager.so`` (C-ABI in ``include/imager.h``).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Device buffers are torch CUDA tensors; the handle runs on the torch stream
+that is current when it is created, so library work and torch work are
+ordered on one stream.  There is no CPU fallback: without the built
+library every call raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libimager.so")
+_LIB = None
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTIMPL = range(6)
+C64, C128 = 0, 1
+WEIGHT_NATURAL, WEIGHT_UNIFORM = 0, 1
+PART_LOW, PART_HIGH = 0, 1
+DEGRID_COMPOSITE = 1
+GRID_DIRTY, GRID_UNNORMALIZED = 0, 1
+COMBINE_EXCHANGE, COMBINE_FINAL = 0, 1
+
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTIMPL"}
+
+
+class ImagerError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_pix", ctypes.c_int32), ("cell_rad", ctypes.c_double),
+                ("support", ctypes.c_int32), ("es_beta", ctypes.c_double),
+                ("weighting", ctypes.c_int32), ("n_partitions", ctypes.c_int32),
+                ("ell_pix", ctypes.c_double), ("delta_pix", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+class Vis(ctypes.Structure):
+    _fields_ = [("n_vis", ctypes.c_int64), ("freq_hz", ctypes.c_double),
+                ("uvw", ctypes.c_void_p), ("vis", ctypes.c_void_p), ("vis_dtype", ctypes.c_int32),
+                ("weight", ctypes.c_void_p), ("flag", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_pix", ctypes.c_int32), ("n_grid", ctypes.c_int32),
+                ("support", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("n_partitions", ctypes.c_int32), ("cell_rad", ctypes.c_double),
+                ("es_beta", ctypes.c_double), ("ell_pix", ctypes.c_double),
+                ("delta_pix", ctypes.c_double), ("n_valid", ctypes.c_int64),
+                ("n_vis", ctypes.c_int64 * 2), ("n_chunks", ctypes.c_int64 * 2),
+                ("sum_w", ctypes.c_double * 2), ("device_bytes", ctypes.c_size_t),
+                ("create_ms", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_D = ctypes.c_double
+_SIGS = {
+    "imager_create": [ctypes.POINTER(Config), ctypes.POINTER(Vis), ctypes.POINTER(_P)],
+    "imager_destroy": [_P],
+    "imager_info": [_P, ctypes.POINTER(Info)],
+    "imager_vis_index": [_P, _I, _P],
+    "imager_vis_weight": [_P, _I, _P],
+    "imager_degrid": [_P, _I, _P, _P],
+    "imager_grid": [_P, _I, _P, _P, _I],
+    "imager_psf": [_P, _I, _P],
+    "imager_major_cycle": [_P, _I, _P, _P, _D, _D, _P, _P, _I],
+    "imager_composed_psf": [_P, _I, _D, _D, _P],
+    "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P],
+    "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P],
+    "imager_combine_partitions": [_P, _I, _P, _P, _D, _D, _P, _P],
+    "imager_sync": [_P],
+}
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImagerError(EINVAL, "libimager.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.imager_last_error.argtypes = [_P]
+        L.imager_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, shape, torch):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape):
+        raise ImagerError(EINVAL, "expected a contiguous cuda float32 tensor of shape %s" % (shape,))
+    return t
+
+
+class Imager:
+    """One handle: the visibilities of one data set, sorted and binned per
+    partition, plus PSFs and work buffers, resident on the current GPU."""
+
+    def __init__(self, handle, info, stream):
+        self._h = handle
+        self.info = info
+        self._stream = stream
+
+    # ------------------------------------------------------------ lifetime
+    @classmethod
+    def create(cls, data=None, *, uvw=None, vis=None, freq_hz=None, cell=None, n_pix=None,
+               weight=None, flag=None, weighting="uniform", n_partitions=1, ell=-1.0, delta=1.0,
+               support=8, beta=0.0, tile=0, chunk=0, hbm_budget=0, stream=None):
+        """Build a handle from host numpy arrays or cuda tensors.  ``data`` may be
+        a dict from ``synth.make`` supplying uvw, vis, freq_hz, cell, n_pix."""
+        import torch
+        if data is not None:
+            uvw = data["uvw"] if uvw is None else uvw
+            vis = data["vis"] if vis is None else vis
+            freq_hz = data["freq_hz"] if freq_hz is None else freq_hz
+            cell = data["cell"] if cell is None else cell
+            n_pix = data["n_img"] if n_pix is None else n_pix
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        keep = []
+        on_dev = isinstance(uvw, torch.Tensor) and uvw.is_cuda
+
+        def hostbuf(a, dtype):
+            a = np.ascontiguousarray(a, dtype=dtype)
+            keep.append(a)
+            return ctypes.c_void_p(a.ctypes.data)
+
+        v = Vis()
+        if on_dev:
+            for t in (uvw, vis, weight, flag):
+                if t is not None:
+                    assert t.is_cuda and t.is_contiguous()
+                    keep.append(t)
+            v.n_vis = uvw.shape[0]
+            v.uvw = uvw.data_ptr()
+            v.vis = vis.data_ptr()
+            v.vis_dtype = C128 if vis.dtype == torch.complex128 else C64
+            v.weight = None if weight is None else weight.data_ptr()
+            v.flag = None if flag is None else flag.data_ptr()
+            v.on_device = 1
+        else:
+            vis = np.asarray(vis)
+            v.n_vis = len(vis)
+            v.uvw = hostbuf(uvw, np.float64)
+            c128 = vis.dtype == np.complex128
+            v.vis = hostbuf(vis, np.complex128 if c128 else np.complex64)
+            v.vis_dtype = C128 if c128 else C64
+            v.weight = None if weight is None else hostbuf(weight, np.float32)
+            v.flag = None if flag is None else hostbuf(flag, np.uint8)
+            v.on_device = 0
+        v.freq_hz = float(freq_hz)
+        c = Config()
+        c.n_pix = int(n_pix)
+        c.cell_rad = float(cell)
+        c.support = int(support)
+        c.es_beta = float(beta)
+        c.weighting = WEIGHT_UNIFORM if weighting == "uniform" else WEIGHT_NATURAL
+        c.n_partitions = int(n_partitions)
+        c.ell_pix = -1.0 if ell is None else float(ell)
+        c.delta_pix = float(delta)
+        c.tile = int(tile)
+        c.chunk = int(chunk)
+        c.flags = 0
+        c.hbm_budget = int(hbm_budget)
+        c.stream = ctypes.c_void_p(stream.cuda_stream)
+        h = ctypes.c_void_p()
+        st = L.imager_create(ctypes.byref(c), ctypes.byref(v), ctypes.byref(h))
+        if st != OK:
+            raise ImagerError(st, L.imager_last_error(None).decode())
+        info = Info()
+        L.imager_info(h, ctypes.byref(info))
+        return cls(h, info, stream)
+
+    def destroy(self):
+        if self._h is not None:
+            lib().imager_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise ImagerError(st, lib().imager_last_error(self._h).decode())
+
+    # ------------------------------------------------------------ properties
+    @property
+    def n_pix(self):
+        return self.info.n_pix
+
+    def n_vis(self, part):
+        return self.info.n_vis[part]
+
+    def sum_w(self, part):
+        return self.info.sum_w[part]
+
+    def _empty(self, shape, dtype):
+        import torch
+        return torch.empty(shape, dtype=getattr(torch, dtype), device="cuda")
+
+    # ------------------------------------------------------------ calls
+    def vis_index(self, part):
+        out = np.empty(self.n_vis(part), np.int64)
+        self._check(lib().imager_vis_index(self._h, part, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def vis_weight(self, part):
+        out = np.empty(self.n_vis(part), np.float32)
+        self._check(lib().imager_vis_weight(self._h, part, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def degrid(self, part, model, out=None):
+        import torch
+        n = self.n_pix
+        _dev_f32(model, (n, n), torch)
+        out = self._empty((self.n_vis(part),), "complex64") if out is None else out
+        self._check(lib().imager_degrid(self._h, part, _ptr(model), _ptr(out)))
+        return out
+
+    def grid(self, part, vis, mode=GRID_DIRTY, out=None):
+        import torch
+        n = self.n_pix
+        if not (vis.is_cuda and vis.dtype == torch.complex64 and vis.is_contiguous()
+                and vis.shape == (self.n_vis(part),)):
+            raise ImagerError(EINVAL, "vis must be a contiguous cuda complex64 member vector")
+        out = self._empty((n, n), "float32") if out is None else out
+        self._check(lib().imager_grid(self._h, part, _ptr(vis), _ptr(out), mode))
+        return out
+
+    def psf(self, part, out=None):
+        n2 = 2 * self.n_pix
+        out = self._empty((n2, n2), "float32") if out is None else out
+        self._check(lib().imager_psf(self._h, part, _ptr(out)))
+        return out
+
+    def major_cycle(self, part, model, rho_other=None, gamma=1.0, mu=0.0, composite=False,
+                    out=None, local_out=None):
+        import torch
+        n = self.n_pix
+        _dev_f32(model, (n, n), torch)
+        if rho_other is not None:
+            _dev_f32(rho_other, (n, n), torch)
+        out = self._empty((n, n), "float32") if out is None else out
+        self._check(lib().imager_major_cycle(
+            self._h, part, _ptr(model), _ptr(rho_other), float(gamma), float(mu), _ptr(out),
+            _ptr(local_out), DEGRID_COMPOSITE if composite else 0))
+        return out
+
+    def composed_psf(self, part, gamma, mu, out=None):
+        n2 = 2 * self.n_pix
+        out = self._empty((n2, n2), "float32") if out is None else out
+        self._check(lib().imager_composed_psf(self._h, part, float(gamma), float(mu), _ptr(out)))
+        return out
+
+    def exchange(self, delta_low, delta_high, rho_for_low, rho_for_high):
+        """rho_for_low += Gamma_H (dH - dL); rho_for_high += Gamma_L (dL - dH)."""
+        self._check(lib().imager_combine_partitions(
+            self._h, COMBINE_EXCHANGE, _ptr(delta_low), _ptr(delta_high), 0.0, 0.0,
+            _ptr(rho_for_low), _ptr(rho_for_high)))
+
+    def combine_final(self, a, b, wa=0.5, wb=0.5, out=None):
+        n = self.n_pix
+        out = self._empty((n, n), "float64") if out is None else out
+        self._check(lib().imager_combine_partitions(
+            self._h, COMBINE_FINAL, _ptr(a), _ptr(b), float(wa), float(wb), _ptr(out), None))
+        return out
+
+    def minor_cycle_msclean(self, *a, **k):
+        self._check(lib().imager_minor_cycle_msclean(self._h, 0, None, None, None, None))
+
+    def minor_cycle_fista(self, *a, **k):
+        self._check(lib().imager_minor_cycle_fista(self._h, 0, None, None, None, None))
+
+    def sync(self):
+        self._check(lib().imager_sync(self._h))

@@ -1,0 +1,64 @@
+"""Shared pieces of the GPU tests: seeded inputs and the oracle's answers."""
+
+import functools
+import sys
+
+import numpy as np
+
+from oracle import decentral, geometry, imaging
+from paper_2507_22128_amd import synth
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=8)
+def workload(name, n_time=None, seed=None):
+    return synth.make(name, n_time=n_time, seed=seed)
+
+
+def uv(d):
+    return geometry.uv_lambda(d["uvw"], d["freq_hz"])
+
+
+def random_model(n, rng, n_points=30, smooth=True):
+    """A model image with point components and a smooth blob (f64)."""
+    m = np.zeros((n, n))
+    ix = rng.integers(n // 8, n - n // 8, n_points)
+    iy = rng.integers(n // 8, n - n // 8, n_points)
+    np.add.at(m, (iy, ix), rng.uniform(0.05, 0.5, n_points))
+    if smooth:
+        yy, xx = np.mgrid[0:n, 0:n]
+        m += 0.2 * np.exp(-((xx - 0.6 * n) ** 2 + (yy - 0.4 * n) ** 2) / (2 * (0.03 * n) ** 2))
+    return m
+
+
+def oracle_weights(d, n, valid=None, uniform=True):
+    u, v = uv(d)
+    if uniform:
+        return imaging.uniform_weights(u, v, n, d["cell"], valid=valid)
+    w = np.ones(len(u))
+    if valid is not None:
+        w[~valid] = 0
+    return w
+
+
+def to_dev(x, dtype="float32"):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=getattr(torch, dtype), device="cuda")
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+__all__ = ["rel", "say", "workload", "uv", "random_model", "oracle_weights", "to_dev", "to_np",
+           "decentral", "imaging", "geometry"]

@@ -1,0 +1,263 @@
+"""Parity of the HIP library with the FP64 oracle (GPU required).
+
+Every comparison uses the same seeded inputs on both sides: the oracle
+consumes the exact arrays handed to the library (complex64 visibilities are
+up-cast exactly).  Floating-point results must agree to a relative L2 error
+of 1e-5; integer decisions (weights' cells, partition membership, ell) must
+agree bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import (decentral, imaging, oracle_weights, random_model, rel, say, to_dev,
+                     to_np, uv, workload)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _imager():
+    from paper_2507_22128_amd import imager
+    return imager
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    say("case: tiny workload, 1 partition, uniform weights")
+    d = workload("tiny")
+    h = _imager().Imager.create(d, n_partitions=1, weighting="uniform")
+    yield d, h
+    h.destroy()
+
+
+def test_tiny_weights_and_members_bitwise(tiny):
+    d, h = tiny
+    n = d["n_img"]
+    w = oracle_weights(d, n)
+    assert np.array_equal(h.vis_index(0), np.arange(len(w)))
+    assert np.array_equal(h.vis_weight(0), w.astype(np.float32))
+    assert h.sum_w(0) == pytest.approx(w.sum(), rel=1e-13)
+
+
+def test_tiny_dirty_image(tiny):
+    import torch
+    d, h = tiny
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    ref = imaging.dirty_image(u, v, d["vis"], w, n, d["cell"])
+    got = to_np(h.major_cycle(0, torch.zeros((n, n), device="cuda")))
+    say("tiny dirty rel err %.3e" % rel(got, ref))
+    assert rel(got, ref) < TOL
+    vis = to_dev(d["vis"], "complex64")
+    got2 = to_np(h.grid(0, vis))
+    assert rel(got2, ref) < TOL
+
+
+def test_tiny_degrid(tiny):
+    d, h = tiny
+    n = d["n_img"]
+    u, v = uv(d)
+    model = random_model(n, np.random.default_rng(1))
+    ref = imaging.Operator(u, v, d["cell"], n).forward(model)
+    got = to_np(h.degrid(0, to_dev(model)))
+    say("tiny degrid rel err %.3e" % rel(got, ref))
+    assert rel(got, ref) < TOL
+
+
+def test_tiny_grid_adjoint(tiny):
+    d, h = tiny
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    rng = np.random.default_rng(2)
+    y = (rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))).astype(np.complex64)
+    ref = imaging.Operator(u, v, d["cell"], n).adjoint(w * y.astype(np.complex128)).real
+    got = to_np(h.grid(0, to_dev(y, "complex64"), mode=_imager().GRID_UNNORMALIZED))
+    say("tiny grid rel err %.3e" % rel(got, ref))
+    assert rel(got, ref) < TOL
+
+
+def test_tiny_psf(tiny):
+    d, h = tiny
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    ref = imaging.psf2(u, v, w, n, d["cell"])
+    got = to_np(h.psf(0))
+    say("tiny psf rel err %.3e" % rel(got, ref))
+    assert rel(got, ref) < TOL
+    assert np.unravel_index(np.argmax(got), got.shape) == (n, n)
+    assert abs(got[n, n] - 1.0) < 1e-5
+
+
+def test_tiny_major_cycle_repeatable(tiny):
+    d, h = tiny
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    model = 0.5 * d["truth"]
+    ref, _ = imaging.residual_image(u, v, d["vis"], w, model, d["cell"])
+    m = to_dev(model)
+    a = h.major_cycle(0, m)
+    b = h.major_cycle(0, m)
+    say("tiny major cycle rel err %.3e" % rel(to_np(a), ref))
+    assert rel(to_np(a), ref) < TOL
+    # LDS accumulation order may differ between runs: same result to rounding
+    assert rel(to_np(b), to_np(a)) < 1e-6
+
+
+VARIANTS = [
+    dict(tile=16, support=6, chunk=64, flag_rate=0.1, weighting="natural"),
+    dict(tile=32, support=12, chunk=100000, flag_rate=0.0, weighting="uniform"),
+    dict(tile=16, support=4, chunk=777, flag_rate=0.3, weighting="uniform"),
+    dict(tile=32, support=10, chunk=4096, flag_rate=0.02, weighting="natural"),
+]
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "T%d-W%d-C%d" % (v["tile"], v["support"], v["chunk"]))
+def test_variants_dirty_and_residual(var):
+    say("case: variant %s" % var)
+    d = workload("tiny", n_time=20)
+    n = d["n_img"]
+    rng = np.random.default_rng(var["chunk"])
+    flag = (rng.random(len(d["vis"])) < var["flag_rate"]).astype(np.uint8)
+    valid = flag == 0
+    h = _imager().Imager.create(d, n_partitions=1, weighting=var["weighting"], tile=var["tile"],
+                                support=var["support"], chunk=var["chunk"], flag=flag)
+    try:
+        u, v = uv(d)
+        w = oracle_weights(d, n, valid=valid, uniform=var["weighting"] == "uniform")
+        assert np.array_equal(h.vis_index(0), np.nonzero(valid)[0])
+        assert np.array_equal(h.vis_weight(0), w[valid].astype(np.float32))
+        model = random_model(n, rng)
+        sel = valid
+        ref, _ = imaging.residual_image(u[sel], v[sel], d["vis"][sel], w[sel], model, d["cell"],
+                                        support=var["support"])
+        got = to_np(h.major_cycle(0, to_dev(model)))
+        say("variant residual rel err %.3e" % rel(got, ref))
+        assert rel(got, ref) < TOL
+    finally:
+        h.destroy()
+
+
+# ------------------------------------------------------------------ two partitions
+
+@pytest.fixture(scope="module")
+def medium():
+    say("case: decentral workload (16 time steps), 2 partitions")
+    d = workload("decentral", n_time=16)
+    h = _imager().Imager.create(d, n_partitions=2, weighting="uniform")
+    yield d, h
+    h.destroy()
+
+
+def _medium_oracle(d):
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    low, high, ell = imaging.partition(u, v, n, d["cell"])
+    return u, v, w, low, high, ell
+
+
+def test_partition_bitwise(medium):
+    d, h = medium
+    u, v, w, low, high, ell = _medium_oracle(d)
+    assert h.info.ell_pix == ell
+    assert np.array_equal(h.vis_index(0), np.nonzero(low)[0])
+    assert np.array_equal(h.vis_index(1), np.nonzero(high)[0])
+    for p, mask in ((0, low), (1, high)):
+        assert np.array_equal(h.vis_weight(p), w[mask].astype(np.float32))
+        assert h.sum_w(p) == pytest.approx(w[mask].sum(), rel=1e-12)
+
+
+def test_partition_residuals_psfs_and_composition(medium):
+    d, h = medium
+    n = d["n_img"]
+    u, v, w, low, high, ell = _medium_oracle(d)
+    rng = np.random.default_rng(5)
+    model = random_model(n, rng)
+    rho = 0.01 * random_model(n, rng)
+    psfs, locals_ = {}, {}
+    for p, mask in ((0, low), (1, high)):
+        psfs[p] = imaging.psf2(u[mask], v[mask], w[mask], n, d["cell"])
+        got_psf = to_np(h.psf(p))
+        say("part %d psf rel err %.3e" % (p, rel(got_psf, psfs[p])))
+        assert rel(got_psf, psfs[p]) < TOL
+        locals_[p], _ = imaging.residual_image(u[mask], v[mask], d["vis"][mask], w[mask], model,
+                                               d["cell"])
+    wl, wh = w[low].sum(), w[high].sum()
+    import torch
+    for p, own in ((0, "L"), (1, "H")):
+        gamma, mu = decentral.weights_schedule(2, (wl, wh)[p], (wh, wl)[p])
+        local = torch.empty((n, n), device="cuda")
+        out = h.major_cycle(p, to_dev(model), to_dev(rho), gamma, mu, local_out=local)
+        say("part %d local residual rel err %.3e" % (p, rel(to_np(local), locals_[p])))
+        assert rel(to_np(local), locals_[p]) < TOL
+        ref = decentral.compose_dirty(locals_[p], rho, psfs[1 - p], ell, 1.0, own, gamma, mu)
+        say("part %d composed residual rel err %.3e" % (p, rel(to_np(out), ref)))
+        assert rel(to_np(out), ref) < TOL
+        ref_psf = decentral.compose_psf(psfs[p], psfs[1 - p], ell, 1.0, own, gamma, mu)
+        got_psf = to_np(h.composed_psf(p, gamma, mu))
+        say("part %d composed psf rel err %.3e" % (p, rel(got_psf, ref_psf)))
+        assert rel(got_psf, ref_psf) < TOL
+    # first cycle: gamma = 1, mu = 0, no rho
+    out1 = to_np(h.major_cycle(0, to_dev(model)))
+    ref1 = decentral.compose_dirty(locals_[0], None, None, ell, 1.0, "L", 1.0, 0.0)
+    assert rel(out1, ref1) < TOL
+
+
+def test_composite_degrid(medium):
+    d, h = medium
+    n = d["n_img"]
+    u, v, w, low, high, ell = _medium_oracle(d)
+    rng = np.random.default_rng(6)
+    model = random_model(n, rng)
+    rho = 0.05 * random_model(n, rng)
+    import torch
+    local = torch.empty((n, n), device="cuda")
+    h.major_cycle(1, to_dev(model), to_dev(rho), 0.5, 0.0, composite=True, local_out=local)
+    ref, _ = imaging.residual_image(u[high], v[high], d["vis"][high], w[high], model + rho,
+                                    d["cell"])
+    assert rel(to_np(local), ref) < TOL
+
+
+def test_exchange_and_final_combination(medium):
+    d, h = medium
+    n = d["n_img"]
+    _, _, _, _, _, ell = _medium_oracle(d)
+    rng = np.random.default_rng(7)
+    a, b = rng.standard_normal((2, n, n)).astype(np.float32)
+    ra, rb = rng.standard_normal((2, n, n)).astype(np.float32)
+    ta, tb = to_dev(ra), to_dev(rb)
+    h.exchange(to_dev(a), to_dev(b), ta, tb)
+    a64, b64 = a.astype(np.float64), b.astype(np.float64)
+    # node L's aggregate: rho_H + Phi_H - Gamma_H ibar_L with Phi_H = Gamma_H ibar_H
+    ref_a = decentral.update_rho(ra.astype(np.float64), decentral.exchange(b64, ell, 1.0, "H"),
+                                 a64, ell, 1.0, "L")
+    ref_b = decentral.update_rho(rb.astype(np.float64), decentral.exchange(a64, ell, 1.0, "L"),
+                                 b64, ell, 1.0, "H")
+    assert rel(to_np(ta) - ra, ref_a - ra) < TOL
+    assert rel(to_np(tb) - rb, ref_b - rb) < TOL
+    fin = to_np(h.combine_final(to_dev(a), to_dev(b)))
+    assert np.array_equal(fin, decentral.combine([a64, b64]))
+
+
+def test_errors_are_reported(medium):
+    d, h = medium
+    imager = _imager()
+    with pytest.raises(imager.ImagerError) as e:
+        h.minor_cycle_fista()
+    assert e.value.code == imager.ENOTIMPL
+    import torch
+    with pytest.raises(imager.ImagerError):
+        h.major_cycle(5, torch.zeros((d["n_img"],) * 2, device="cuda"))
+    # an empty partition is refused at create
+    with pytest.raises(imager.ImagerError) as e:
+        imager.Imager.create(d, n_partitions=2, ell=1e9)
+    assert e.value.code == imager.EINVAL
+    # hbm budget far below the footprint
+    with pytest.raises(imager.ImagerError) as e:
+        imager.Imager.create(d, n_partitions=2, hbm_budget=1 << 20)
+    assert e.value.code == imager.ENOMEM
