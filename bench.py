@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the major-cycle measurement operator on one MI355X.
+
+A step is one decentralized major cycle of the two-partition workload:
+for each node (V_L, then V_H) the model is transformed to the grid, every
+visibility is degridded, its weighted residual gridded, the grid flushed and
+transformed back to the residual image (Eq. 2), and the residual is composed
+with the other node's aggregate through the other node's PSF (Eq. 7).
+Preparation (weighting, partition, sort) and the PSFs are one-time work of
+imager_create and are timed separately (create_ms).
+
+Prints one JSON line.  ``value`` is whole-job throughput: unflagged
+visibilities of the data set per second of major cycle (Mvis/s), inputs
+resident in HBM.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "major-cycle Mvis/s (grid+degrid) at ≤1e-5 rel err, %HBM roofline; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, doubled by
+# packed FP32 instructions (published figure).  The library is built with
+# packed FP32 disabled, so its reachable ceiling is half of it.
+FP32_PEAK_PACKED = 157.3
+FP32_PEAK_UNPACKED = 78.6
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def flops_per_vis(w):
+    """Arithmetic of one visibility in the fused de/grid kernel (W taps/axis):
+    2W kernel weights (6 flop each incl. sqrt and exp), degrid 4W^2 + 4W,
+    residual 4, gridding 2W + 2W^2 products and 2W^2 accumulations."""
+    return 8 * w * w + 18 * w + 4
+
+
+def cpu_baseline(args, gpu_gamma_mu):
+    """The FP64 oracle, as it stands, on a sample of the same workload (the
+    first n_time time steps); the GPU runs the same sample to report the
+    error of the benchmarked path against it."""
+    import numpy as np
+    import torch
+    from oracle import decentral, geometry, imaging
+    from paper_2507_22128_amd import imager, synth
+
+    d = synth.make(args.workload, n_time=args.cpu_sample_times)
+    n = d["n_img"]
+    u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
+    w = imaging.uniform_weights(u, v, n, d["cell"])
+    low, high, ell = imaging.partition(u, v, n, d["cell"])
+    masks = (low, high)
+    model = 0.5 * d["truth"]
+    rho = 0.01 * d["truth"]
+    psfs = [imaging.psf2(u[m], v[m], w[m], n, d["cell"]) for m in masks]
+    wsum = [w[m].sum() for m in masks]
+    gm = [decentral.weights_schedule(2, wsum[p], wsum[1 - p]) for p in (0, 1)]
+    t0 = time.perf_counter()
+    outs = []
+    for p, own in ((0, "L"), (1, "H")):
+        m = masks[p]
+        loc, _ = imaging.residual_image(u[m], v[m], d["vis"][m], w[m], model, d["cell"])
+        outs.append(decentral.compose_dirty(loc, rho, psfs[1 - p], ell, 1.0, own, *gm[p]))
+    t_cpu = time.perf_counter() - t0
+    n_valid = len(u)
+    # the GPU on the same sample
+    h = imager.Imager.create(d, n_partitions=2, weighting="uniform")
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+    errs = []
+    for p in (0, 1):
+        got = h.major_cycle(p, dev(model), dev(rho), *gm[p]).cpu().double().numpy()
+        errs.append(float(np.linalg.norm(got - outs[p]) / np.linalg.norm(outs[p])))
+    h.destroy()
+    return {
+        "value": n_valid / t_cpu / 1e6,
+        "unit": "Mvis/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "one decentralized major cycle (both partitions, Eq. 2 + Eq. 7) of the first %d "
+                  "time steps of the same array, sky and image (%d visibilities), FP64 "
+                  "NumPy/SciPy, single thread, %.1f s" % (args.cpu_sample_times, n_valid, t_cpu),
+        "gpu_rel_err_on_sample": max(errs),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="decentral")
+    ap.add_argument("--cpu-sample-times", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build images on a single GPU; --gpus %d is not supported "
+              "(the two partitions run on one device)" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2507_22128_amd import imager, synth
+
+    t0 = time.perf_counter()
+    d = synth.make(args.workload)
+    wl = d["workload"]
+    n = d["n_img"]
+    log("workload %s: %d visibilities, N=%d (generated in %.1f s)"
+        % (args.workload, len(d["vis"]), n, time.perf_counter() - t0))
+    h = imager.Imager.create(d, n_partitions=2, weighting="uniform")
+    info = h.info
+    log("create: %.1f ms, partitions %d / %d visibilities, %d / %d chunks, ell %.3f px"
+        % (info.create_ms, info.n_vis[0], info.n_vis[1], info.n_chunks[0], info.n_chunks[1],
+           info.ell_pix))
+
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+    model = [dev(0.5 * d["truth"]), dev(0.5 * d["truth"])]
+    rho = [dev(0.01 * d["truth"]), dev(0.01 * d["truth"])]
+    out = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    local = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    wsum = [info.sum_w[0], info.sum_w[1]]
+    gm = [(wsum[p] / (wsum[0] + wsum[1]), wsum[1 - p] / (wsum[0] + wsum[1])) for p in (0, 1)]
+
+    def step():
+        for p in (0, 1):
+            h.major_cycle(p, model[p], rho[p], gm[p][0], gm[p][1], out=out[p], local_out=local[p])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        step()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cycles, stage_ms = h.get_timing()
+    h.set_timing(False)
+    per_step = sorted(a.elapsed_time(b) for a, b in ev)
+    ms_per_step = 1e3 * wall / args.steps
+    n_valid = info.n_valid
+    value = n_valid / (ms_per_step / 1e3) / 1e6
+    log("%d steps: %.3f ms/step, %.0f Mvis/s" % (args.steps, ms_per_step, value))
+    stage_avg = {k: v / cycles for k, v in stage_ms.items()}
+    log("per node-cycle stage ms: %s" % json.dumps({k: round(v, 4) for k, v in stage_avg.items()}))
+
+    # roofline of the dominant kernel: the fused de/grid chunk kernel (one
+    # launch per node-cycle); units averaged over the two partitions' launches
+    ng = info.n_grid
+    wt = info.support
+    m_avg = 0.5 * (info.n_vis[0] + info.n_vis[1])
+    t_launch = stage_avg["degrid_grid"] / 1e3
+    flops = flops_per_vis(wt) * m_avg
+    bytes_alg = 20.0 * m_avg + 16.0 * ng * ng
+    achieved_tf = flops / t_launch / 1e12
+    achieved_gbs = bytes_alg / t_launch / 1e9
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved_tf, 3),
+        "peak": FP32_PEAK_UNPACKED,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tf / FP32_PEAK_UNPACKED, 4),
+        "traffic": None,
+        "kernel": "k_chunk<32,%d,MODE_DEGRID_GRID> (fused degrid / residual / grid)" % wt,
+        "avg_launch_ms": round(stage_avg["degrid_grid"], 4),
+        "flop_per_vis": flops_per_vis(wt),
+        "frac_of_packed_peak": round(achieved_tf / FP32_PEAK_PACKED, 4),
+        "hbm_achieved_gbs": round(achieved_gbs, 1),
+        "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "bytes_alg_per_launch": bytes_alg,
+    }
+    # whole-cycle algorithmic bytes: visibility stream, ~8 grid passes, images
+    cycle_bytes = sum(20.0 * info.n_vis[p] + 64.0 * ng * ng + 8.0 * n * n for p in (0, 1))
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mvis/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %d antennas in an %.0f km disk, %d baselines x %d times = %d "
+                        "visibilities (complex64), 1 channel at %.2f GHz, uniform weighting, "
+                        "2 partitions split at the median |uv| (delta 1 px), %d^2 image, "
+                        "2x padded grid, ES support %d"
+                        % (args.workload, wl.n_ant, 2 * wl.radius_m / 1e3,
+                           wl.n_ant * (wl.n_ant - 1) // 2, wl.n_time, len(d["vis"]),
+                           wl.freq_hz / 1e9, n, wt),
+            "n_vis": int(n_valid),
+            "n_vis_partitions": [int(info.n_vis[0]), int(info.n_vis[1])],
+            "n_pix": n,
+            "n_grid": ng,
+            "parallelism": "single GPU, both partitions on one device",
+        },
+        "p50_ms": round(per_step[len(per_step) // 2], 4),
+        "p99_ms": round(per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))], 4),
+        "create_ms": round(info.create_ms, 1),
+        "stage_ms_per_node_cycle": {k: round(v, 4) for k, v in stage_avg.items()},
+        "cycle_hbm_frac": round(cycle_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+    }
+    h.destroy()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a sample) ...")
+        res["cpu_baseline"] = cpu_baseline(args, gm)
+        log("cpu baseline: %.3f Mvis/s" % res["cpu_baseline"]["value"])
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -201,6 +201,25 @@ imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const void *params,
 imgr_status imager_combine_partitions(imgr_t h, int32_t mode, const float *a, const float *b,
                                       double w_a, double w_b, void *out_a, void *out_b);
 
+/* Device-time accounting of imager_major_cycle, for benchmarks.  While
+ * enabled, every major cycle records HIP events on the handle's stream
+ * around its stages; imager_get_timing synchronises the stream, returns the
+ * summed milliseconds per stage and the number of cycles since the last
+ * get (or enable), and clears the sums.  Stages:
+ *   0 model -> model grid (gridding correction, padding, forward FFT)
+ *   1 fused degrid / residual / grid over the uv-tile chunks
+ *   2 flush of the chunk sub-grids into the residual grid
+ *   3 residual grid -> residual image (inverse FFT, crop, correction)
+ *   4 composition of Eq. 7 (or the copy for one partition) */
+#define IMGR_N_STAGES 5
+typedef struct {
+  int64_t cycles;
+  double ms[IMGR_N_STAGES];
+} imgr_timing;
+
+imgr_status imager_set_timing(imgr_t h, int32_t enable);
+imgr_status imager_get_timing(imgr_t h, imgr_timing *out);
+
 /* Wait for all work enqueued on the handle's stream. */
 imgr_status imager_sync(imgr_t h);
 

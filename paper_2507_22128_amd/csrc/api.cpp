@@ -118,6 +118,23 @@ static void build_psf(imgr_s *h, int p) {
   IMGR_HIP(hipStreamSynchronize(s));
 }
 
+static hipEvent_t take_event(imgr_s *h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  IMGR_HIP(hipEventCreate(&e));
+  return e;
+}
+
+static void recycle_events(imgr_s *h) {
+  for (auto &set : h->ev_sets)
+    for (hipEvent_t e : set) h->ev_pool.push_back(e);
+  h->ev_sets.clear();
+}
+
 }  // namespace imgr
 
 using namespace imgr;
@@ -241,6 +258,8 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
 imgr_status imager_destroy(imgr_t h) {
   if (!h) return IMGR_EINVAL;
   (void)hipStreamSynchronize(h->stream);
+  recycle_events(h);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   for (void *p : h->allocs) (void)hipFree(p);
   delete h;
   return IMGR_OK;
@@ -344,15 +363,29 @@ imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model, const
   hipStream_t s = h->stream;
   const Partition &P = h->part[part];
   float *local = residual_local_out ? residual_local_out : h->img_a;
+  std::vector<hipEvent_t> *ev = nullptr;
+  if (h->timing) {
+    h->ev_sets.emplace_back();
+    ev = &h->ev_sets.back();
+    for (int k = 0; k <= IMGR_N_STAGES; ++k) ev->push_back(take_event(h));
+  }
+  auto mark = [&](int k) {
+    if (ev) IMGR_HIP(hipEventRecord((*ev)[k], s));
+  };
+  mark(0);
   // a1: model -> model grid
   fft_model_to_grid(h, model, (flags & IMGR_DEGRID_COMPOSITE) ? rho_other : nullptr, h->cinv, h->N,
                     h->Ng, h->rows, h->grid_b, h->grid_a, s);
+  mark(1);
   // a2 + a3: degrid, residual, grid (one pass per chunk), flush
   degrid_grid(h, part, MODE_DEGRID_GRID, h->grid_a, nullptr, nullptr, h->T, h->Ng, h->scratch, s);
+  mark(2);
   flush_chunks(h, part, h->T, h->Ng, h->scratch, h->grid_a, s);
+  mark(3);
   // a4: residual grid -> residual image
   fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), h->rows,
                     h->grid_b, local, s);
+  mark(4);
   // a6: pseudo-full-resolution composition
   if (h->n_parts == 2) {
     compose(h, part, local, rho_other, gamma, mu, residual_out, s);
@@ -360,6 +393,7 @@ imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model, const
     IMGR_HIP(hipMemcpyAsync(residual_out, local, (size_t)h->N * h->N * sizeof(float),
                             hipMemcpyDeviceToDevice, s));
   }
+  mark(5);
   API_END(h)
 }
 
@@ -404,6 +438,31 @@ imgr_status imager_combine_partitions(imgr_t h, int32_t mode, const float *a, co
   } else {
     throw Error{IMGR_EINVAL, "mode"};
   }
+  API_END(h)
+}
+
+imgr_status imager_set_timing(imgr_t h, int32_t enable) {
+  API_BEGIN(h)
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  recycle_events(h);
+  h->timing = enable != 0;
+  API_END(h)
+}
+
+imgr_status imager_get_timing(imgr_t h, imgr_timing *out) {
+  API_BEGIN(h)
+  IMGR_CHECK(out, "null pointer");
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (auto &set : h->ev_sets) {
+    for (int k = 0; k < IMGR_N_STAGES; ++k) {
+      float ms = 0.f;
+      IMGR_HIP(hipEventElapsedTime(&ms, set[k], set[k + 1]));
+      out->ms[k] += ms;
+    }
+    out->cycles += 1;
+  }
+  recycle_events(h);
   API_END(h)
 }
 

@@ -63,6 +63,10 @@ struct imgr_s {
   size_t scratch_elems = 0;
   float *img_a = nullptr;      // N^2 f32
   float *img_b = nullptr;      // N^2 f32
+  // stage timing (imager_set_timing): one set of events per recorded cycle
+  bool timing = false;
+  std::vector<std::vector<hipEvent_t>> ev_sets;
+  std::vector<hipEvent_t> ev_pool;
   // bookkeeping
   std::vector<void *> allocs;
   std::vector<size_t> alloc_sizes;

@@ -76,8 +76,17 @@ _SIGS = {
     "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P],
     "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P],
     "imager_combine_partitions": [_P, _I, _P, _P, _D, _D, _P, _P],
+    "imager_set_timing": [_P, _I],
+    "imager_get_timing": [_P, _P],
     "imager_sync": [_P],
 }
+
+N_STAGES = 5
+STAGES = ("model_fft", "degrid_grid", "flush", "residual_fft", "compose")
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int64), ("ms", ctypes.c_double * N_STAGES)]
 
 
 def library_path():
@@ -293,6 +302,15 @@ class Imager:
 
     def minor_cycle_fista(self, *a, **k):
         self._check(lib().imager_minor_cycle_fista(self._h, 0, None, None, None, None))
+
+    def set_timing(self, enable):
+        self._check(lib().imager_set_timing(self._h, 1 if enable else 0))
+
+    def get_timing(self):
+        """(cycles, {stage: summed ms}) since the last call; synchronises."""
+        t = Timing()
+        self._check(lib().imager_get_timing(self._h, ctypes.byref(t)))
+        return t.cycles, dict(zip(STAGES, list(t.ms)))
 
     def sync(self):
         self._check(lib().imager_sync(self._h))
