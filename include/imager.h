@@ -94,8 +94,9 @@ typedef struct {
   int32_t n_partitions; /* 1 (serial) or 2 (V_L, V_H) */
   double ell_pix;       /* partition radius ell in Fourier pixels; < 0: lower median */
   double delta_pix;     /* half-width of the overlap ring; <= 0 selects 1 */
-  int32_t tile;         /* tile side in grid cells, 16 or 32; 0 selects 32 */
-  int32_t chunk;        /* max visibilities per work chunk; 0 selects 4096 */
+  int32_t tile;         /* block side in grid cells, 4 or 8, with tile + support - 1
+                           <= 16; 0 selects 8 for support <= 8, else 4 */
+  int32_t chunk;        /* max visibilities per work chunk, >= 16; 0 selects 1024 */
   int32_t flags;        /* reserved, 0 */
   size_t hbm_budget;    /* bytes of device memory the handle may hold; 0 = no cap */
   void *stream;         /* hipStream_t for all work; NULL = the null stream */
@@ -126,7 +127,7 @@ typedef struct {
 /* Build a handle: scale (u, v) in FP64, drop flagged visibilities, apply the
  * weighting, split into V_L = {rho <= ell + delta} and V_H = {rho >= ell -
  * delta} (Fig. 3; rho = |uv| in Fourier pixels), sort each partition by uv
- * tile, and grid each partition's PSF once.  Synchronous.  *out receives
+ * block, and grid each partition's PSF once.  Synchronous.  *out receives
  * the handle (NULL on error). */
 imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *out);
 
@@ -207,7 +208,7 @@ imgr_status imager_combine_partitions(imgr_t h, int32_t mode, const float *a, co
  * summed milliseconds per stage and the number of cycles since the last
  * get (or enable), and clears the sums.  Stages:
  *   0 model -> model grid (gridding correction, padding, forward FFT)
- *   1 fused degrid / residual / grid over the uv-tile chunks
+ *   1 fused degrid / residual / grid over the uv-block chunks
  *   2 flush of the chunk sub-grids into the residual grid
  *   3 residual grid -> residual image (inverse FFT, crop, correction)
  *   4 composition of Eq. 7 (or the copy for one partition) */

@@ -95,25 +95,37 @@ static void fail(imgr_s *h, const Error &e) {
   if (e.code == IMGR_EDEVICE) h->broken = true;
 }
 
+static void free_bins(imgr_s *h, Bins &B) {
+  for (void *q : {(void *)B.posvis, (void *)B.w, (void *)B.orig, (void *)B.outpos,
+                  (void *)B.chunk_block, (void *)B.chunk_begin, (void *)B.block_chunk,
+                  (void *)B.order})
+    dev_free(h, q);
+  B = Bins();
+}
+
+// PSF of partition p: unit visibilities gridded on the 2 Ng grid (same cell
+// size), transformed to the 2N x 2N image and normalised by sum(w); then
+// its plain DFT for the H x products of Eq. 7
 static void build_psf(imgr_s *h, int p) {
   hipStream_t s = h->stream;
   Partition &P = h->part[p];
-  const int n2 = 2 * h->N, ng2 = 2 * h->Ng, t2 = 2 * h->T;
+  const int n2 = 2 * h->N, ng2 = 2 * h->Ng;
   P.psf = (float *)dev_alloc(h, (size_t)n2 * n2 * sizeof(float));
   P.psf_hat = (float2 *)dev_alloc(h, (size_t)n2 * n2 * sizeof(float2));
-  const int S2 = t2 + h->W - 1;
   float2 *grid = (float2 *)dev_alloc(h, (size_t)ng2 * ng2 * sizeof(float2));
   float2 *tmp = (float2 *)dev_alloc(h, (size_t)ng2 * ng2 * sizeof(float2));
   float2 *rows = (float2 *)dev_alloc(h, (size_t)n2 * ng2 * sizeof(float2));
-  float2 *scr = (float2 *)dev_alloc(h, (size_t)std::max(P.n_chunks, 1) * S2 * S2 * sizeof(float2));
-  degrid_grid(h, p, MODE_PSF, nullptr, nullptr, nullptr, t2, ng2, scr, s);
-  flush_chunks(h, p, t2, ng2, scr, grid, s);
+  float2 *scr = (float2 *)dev_alloc(
+      h, (size_t)std::max(P.psf_bins.n_chunks, 1) * kWin * kWin * sizeof(float2));
+  degrid_grid(h, P.psf_bins, MODE_PSF, nullptr, nullptr, nullptr, scr, s);
+  flush_chunks(h, P.psf_bins, scr, grid, s);
   fft_grid_to_image(h, grid, h->cinv2, n2, ng2, (float)(1.0 / P.sum_w), rows, tmp, P.psf, s);
   IMGR_HIP(hipStreamSynchronize(s));
   dev_free(h, scr);
   dev_free(h, rows);
   dev_free(h, tmp);
   dev_free(h, grid);
+  free_bins(h, P.psf_bins);
   psf_spectrum(h, p, s);
   IMGR_HIP(hipStreamSynchronize(s));
 }
@@ -179,11 +191,12 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
     IMGR_CHECK(h->W == 4 || h->W == 6 || h->W == 8 || h->W == 10 || h->W == 12,
                "support must be 4, 6, 8, 10 or 12");
     h->beta = cfg->es_beta > 0 ? cfg->es_beta : 2.30 * h->W;
-    h->T = cfg->tile ? cfg->tile : 32;
-    IMGR_CHECK(h->T == 16 || h->T == 32, "tile must be 16 or 32");
-    IMGR_CHECK(h->Ng % h->T == 0 && h->Ng / h->T >= 3, "grid too small for the tile");
-    h->C = cfg->chunk ? cfg->chunk : 4096;
-    IMGR_CHECK(h->C >= 64 && h->C <= (1 << 20), "chunk must be in [64, 2^20]");
+    h->blk = cfg->tile ? cfg->tile : (h->W <= 8 ? 8 : 4);
+    IMGR_CHECK(h->blk == 4 || h->blk == 8, "tile (block side) must be 4 or 8");
+    IMGR_CHECK(window_supported(h->W, h->blk),
+               "tile + support - 1 must not exceed 16 (the footprint window)");
+    h->C = cfg->chunk ? cfg->chunk : 1024;
+    IMGR_CHECK(h->C >= 16 && h->C <= (1 << 20), "chunk must be in [16, 2^20]");
     IMGR_CHECK(cfg->n_partitions == 1 || cfg->n_partitions == 2, "n_partitions must be 1 or 2");
     h->n_parts = cfg->n_partitions;
     IMGR_CHECK(cfg->weighting == IMGR_WEIGHT_NATURAL || cfg->weighting == IMGR_WEIGHT_UNIFORM,
@@ -199,8 +212,6 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
     IMGR_CHECK(vis->freq_hz > 0, "freq_hz must be positive");
     IMGR_CHECK(cfg->cell_rad > 0, "cell_rad must be given (> 0)");
     h->cell = cfg->cell_rad;
-    h->ntx = h->Ng / h->T;
-    h->n_tiles = h->ntx * h->ntx;
 
     // tables
     {
@@ -228,12 +239,12 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
     prep_build(h, vis);
 
     int max_chunks = 1;
-    for (int p = 0; p < h->n_parts; ++p) max_chunks = std::max(max_chunks, h->part[p].n_chunks);
-    const int S = h->T + h->W - 1;
-    h->scratch_elems = (size_t)max_chunks * S * S;
+    for (int p = 0; p < h->n_parts; ++p)
+      max_chunks = std::max(max_chunks, h->part[p].bins.n_chunks);
+    h->scratch_elems = (size_t)max_chunks * kWin * kWin;
     h->scratch = (float2 *)dev_alloc(h, h->scratch_elems * sizeof(float2));
     for (int p = 0; p < h->n_parts; ++p) {
-      IMGR_CHECK(h->part[p].n > 0, "a partition is empty (check ell / delta)");
+      IMGR_CHECK(h->part[p].bins.n > 0, "a partition is empty (check ell / delta)");
       build_psf(h, p);
     }
     IMGR_HIP(hipStreamSynchronize(h->stream));
@@ -271,7 +282,7 @@ imgr_status imager_info(imgr_t h, imgr_info *o) {
   o->n_pix = h->N;
   o->n_grid = h->Ng;
   o->support = h->W;
-  o->tile = h->T;
+  o->tile = h->blk;
   o->n_partitions = h->n_parts;
   o->cell_rad = h->cell;
   o->es_beta = h->beta;
@@ -279,8 +290,8 @@ imgr_status imager_info(imgr_t h, imgr_info *o) {
   o->delta_pix = h->delta;
   o->n_valid = h->n_valid;
   for (int p = 0; p < h->n_parts; ++p) {
-    o->n_vis[p] = h->part[p].n;
-    o->n_chunks[p] = h->part[p].n_chunks;
+    o->n_vis[p] = h->part[p].bins.n;
+    o->n_chunks[p] = h->part[p].bins.n_chunks;
     o->sum_w[p] = h->part[p].sum_w;
   }
   o->device_bytes = h->bytes;
@@ -296,7 +307,7 @@ imgr_status imager_vis_index(imgr_t h, int32_t part, int64_t *idx) {
   API_BEGIN(h)
   check_part(h, part);
   IMGR_CHECK(idx != nullptr, "idx is NULL");
-  const Partition &P = h->part[part];
+  const Bins &P = h->part[part].bins;
   std::vector<int32_t> orig(P.n), pos(P.n);
   IMGR_HIP(hipMemcpyAsync(orig.data(), P.orig, P.n * 4, hipMemcpyDeviceToHost, h->stream));
   IMGR_HIP(hipMemcpyAsync(pos.data(), P.outpos, P.n * 4, hipMemcpyDeviceToHost, h->stream));
@@ -309,7 +320,7 @@ imgr_status imager_vis_weight(imgr_t h, int32_t part, float *w) {
   API_BEGIN(h)
   check_part(h, part);
   IMGR_CHECK(w != nullptr, "w is NULL");
-  const Partition &P = h->part[part];
+  const Bins &P = h->part[part].bins;
   std::vector<float> ws(P.n);
   std::vector<int32_t> pos(P.n);
   IMGR_HIP(hipMemcpyAsync(ws.data(), P.w, P.n * 4, hipMemcpyDeviceToHost, h->stream));
@@ -325,7 +336,8 @@ imgr_status imager_degrid(imgr_t h, int32_t part, const float *model, void *vis_
   IMGR_CHECK(model && vis_out, "null pointer");
   hipStream_t s = h->stream;
   fft_model_to_grid(h, model, nullptr, h->cinv, h->N, h->Ng, h->rows, h->grid_b, h->grid_a, s);
-  degrid_grid(h, part, MODE_DEGRID, h->grid_a, nullptr, (float2 *)vis_out, h->T, h->Ng, nullptr, s);
+  degrid_grid(h, h->part[part].bins, MODE_DEGRID, h->grid_a, nullptr, (float2 *)vis_out, nullptr,
+              s);
   API_END(h)
 }
 
@@ -336,8 +348,9 @@ imgr_status imager_grid(imgr_t h, int32_t part, const void *vis_in, float *image
   IMGR_CHECK(vis_in && image_out, "null pointer");
   IMGR_CHECK(mode == IMGR_GRID_DIRTY || mode == IMGR_GRID_UNNORMALIZED, "mode");
   hipStream_t s = h->stream;
-  degrid_grid(h, part, MODE_GRID, nullptr, (const float2 *)vis_in, nullptr, h->T, h->Ng, h->scratch, s);
-  flush_chunks(h, part, h->T, h->Ng, h->scratch, h->grid_a, s);
+  const Bins &B = h->part[part].bins;
+  degrid_grid(h, B, MODE_GRID, nullptr, (const float2 *)vis_in, nullptr, h->scratch, s);
+  flush_chunks(h, B, h->scratch, h->grid_a, s);
   const float scale = mode == IMGR_GRID_DIRTY ? (float)(1.0 / h->part[part].sum_w) : 1.f;
   fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, scale, h->rows, h->grid_b, image_out, s);
   API_END(h)
@@ -378,9 +391,9 @@ imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model, const
                     h->Ng, h->rows, h->grid_b, h->grid_a, s);
   mark(1);
   // a2 + a3: degrid, residual, grid (one pass per chunk), flush
-  degrid_grid(h, part, MODE_DEGRID_GRID, h->grid_a, nullptr, nullptr, h->T, h->Ng, h->scratch, s);
+  degrid_grid(h, P.bins, MODE_DEGRID_GRID, h->grid_a, nullptr, nullptr, h->scratch, s);
   mark(2);
-  flush_chunks(h, part, h->T, h->Ng, h->scratch, h->grid_a, s);
+  flush_chunks(h, P.bins, h->scratch, h->grid_a, s);
   mark(3);
   // a4: residual grid -> residual image
   fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), h->rows,

@@ -26,26 +26,39 @@ constexpr int kTwMax = 16384;
 
 // ----------------------------------------------------------------- handle
 
-struct Partition {
-  int64_t n = 0;              // members
+// Visibilities of one partition binned for one grid: sorted by the
+// blk x blk block of grid cells that holds the first tap of their footprint
+// shifted by W/2 - 1, and cut into chunks of at most C visibilities of one
+// block.  Every footprint of a block lies in a 16 x 16 window of the grid
+// whose origin is the block origin minus W/2 - 1.
+struct Bins {
+  int64_t n = 0;               // members
   int n_chunks = 0;
-  double sum_w = 0.0;
-  float4 *posvis = nullptr;   // [n] {dx, dy, re, im}: offsets in the tile, visibility
-  float *w = nullptr;         // [n] imaging weight
-  int32_t *orig = nullptr;    // [n] original index
-  int32_t *outpos = nullptr;  // [n] member rank (position in member order)
-  int32_t *chunk_tile = nullptr;   // [n_chunks]
+  int ng = 0;                  // grid side the positions refer to
+  int nb = 0;                  // blocks per grid side (ng / blk)
+  float4 *posvis = nullptr;    // [n] {dx, dy, re, im}: offsets from the block origin, visibility
+  float *w = nullptr;          // [n] imaging weight
+  int32_t *orig = nullptr;     // [n] original index
+  int32_t *outpos = nullptr;   // [n] member rank (position in member order)
+  int32_t *chunk_block = nullptr;  // [n_chunks] block of each chunk
   int32_t *chunk_begin = nullptr;  // [n_chunks + 1]
-  int32_t *tile_chunk = nullptr;   // [n_tiles + 1] first chunk of each tile
-  float *psf = nullptr;            // (2N)^2 normalised PSF, centre (N, N)
-  float2 *psf_hat = nullptr;       // (2N)^2 plain DFT of psf
+  int32_t *block_chunk = nullptr;  // [nb * nb + 1] first chunk of each block
+  int32_t *order = nullptr;        // [n_chunks] launch order: largest chunk first
+};
+
+struct Partition {
+  double sum_w = 0.0;
+  Bins bins;                   // on the Ng grid (major cycle, degrid, grid)
+  Bins psf_bins;               // on the 2 Ng grid of the 2N x 2N PSF (freed after create)
+  float *psf = nullptr;        // (2N)^2 normalised PSF, centre (N, N)
+  float2 *psf_hat = nullptr;   // (2N)^2 plain DFT of psf
 };
 
 }  // namespace imgr
 
 struct imgr_s {
   // geometry
-  int N = 0, Ng = 0, W = 8, T = 32, ntx = 0, n_tiles = 0, n_parts = 1, C = 4096;
+  int N = 0, Ng = 0, W = 8, blk = 8, n_parts = 1, C = 1024;
   double cell = 0, beta = 0, ell = 0, delta = 1;
   int weighting = 0;
   int64_t n_valid = 0;
@@ -59,7 +72,7 @@ struct imgr_s {
   float2 *grid_a = nullptr;    // Ng^2
   float2 *grid_b = nullptr;    // Ng^2
   float2 *rows = nullptr;      // N x Ng (row-pass intermediate)
-  float2 *scratch = nullptr;   // chunk sub-grids
+  float2 *scratch = nullptr;   // 16 x 16 chunk windows
   size_t scratch_elems = 0;
   float *img_a = nullptr;      // N^2 f32
   float *img_b = nullptr;      // N^2 f32
@@ -120,13 +133,18 @@ void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t
 
 // ----------------------------------------------------------------- de/gridding
 enum GridMode { MODE_DEGRID_GRID = 0, MODE_GRID = 1, MODE_DEGRID = 2, MODE_PSF = 3 };
-// run the chunk kernel of partition p; grid_in: model grid (modes 0, 2);
-// vis_in: member-order visibilities (mode 1) or nullptr; vis_out (mode 2)
-void degrid_grid(imgr_s *h, int p, int mode, const float2 *grid_in, const float2 *vis_in,
-                 float2 *vis_out, int tile, int ng, float2 *scratch, hipStream_t s);
-// deterministic flush of the chunk sub-grids into an ng x ng grid, with (-1)^(x+y)
-void flush_chunks(imgr_s *h, int p, int tile, int ng, const float2 *scratch, float2 *grid_out,
+constexpr int kWin = 16;  // window side (cells) of a block's footprints
+// one chunk pass over bins b: grid_in is the model grid (modes 0, 2),
+// vis_in member-order visibilities (mode 1), vis_out member-order
+// predictions (mode 2); every gridding mode writes one window per chunk
+// to scratch ([n_chunks][16][16])
+void degrid_grid(imgr_s *h, const Bins &b, int mode, const float2 *grid_in, const float2 *vis_in,
+                 float2 *vis_out, float2 *scratch, hipStream_t s);
+// deterministic flush of the chunk windows into the b.ng x b.ng grid, with (-1)^(x+y)
+void flush_chunks(imgr_s *h, const Bins &b, const float2 *scratch, float2 *grid_out,
                   hipStream_t s);
+// whether kernels exist for support W with blocks of blk cells
+bool window_supported(int W, int blk);
 
 // ----------------------------------------------------------------- composition
 void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma, double mu,

@@ -1,277 +1,284 @@
-// Tile-binned de/gridding with the exponential-of-semicircle kernel.
+// De/gridding of Eq. 2 on the matrix cores (gfx950 MFMA, FP32 in and out).
 //
-// Visibilities of a partition are sorted by uv tile (T x T grid cells) and
-// split into chunks of at most C visibilities.  One workgroup owns one
-// chunk: it stages the (T+W-1)^2 model sub-grid of its tile in LDS
-// (degridding, G^dagger F of Eq. 2), forms the weighted residual
-// w (v - v_hat) in registers, and accumulates it with the same tap weights
-// into an LDS sub-grid (gridding, F^dagger G of Eq. 2).  The sub-grid is
-// written once per chunk; a separate flush sums, for every grid cell, the
-// sub-grids of the chunks of the 3 x 3 neighbouring tiles in a fixed order
-// in FP64, so there are no global atomics and the grid is reproducible bit
-// for bit.  Tap weights are evaluated in FP32 from the offset of the
-// visibility inside its tile, which the prep step derives from FP64
-// coordinates.
+// The visibilities of a partition are binned by the blk x blk block of grid
+// cells that holds the first tap of their W x W footprint shifted by
+// W/2 - 1, so every footprint of a block lies in one 16 x 16 window of the
+// grid (window origin = block origin - (W/2 - 1)).  For the visibilities k
+// of one block both halves of Eq. 2 are dense products over that window:
+//   degridding (G^dagger F)  v_hat_k = ky_k^T  G  kx_k       (G: model window)
+//   gridding   (F^dagger G)  A       = sum_k (r_k ky_k) kx_k^T
+// with kx_k, ky_k the separable exponential-of-semicircle tap weights placed
+// at the visibility's offset in the window (zero elsewhere).  Both products
+// run as v_mfma_f32_16x16x4f32 on batches of 16 visibilities: G kx with the
+// window column as inner index for the prediction, and the sum of outer
+// products with the visibility as inner index for the accumulation.  The
+// residual window therefore stays in accumulator registers for the whole
+// chunk; there are no LDS or global atomics.  One wave owns one chunk (at
+// most C visibilities of one block), evaluates each of its 2W tap weights
+// once per visibility and shares them between the two products through
+// LDS, forms the weighted residual w (v - v_hat) in registers, and writes
+// its window once.  The flush then adds, for every grid cell, the windows of
+// the chunks of the neighbouring blocks in a fixed order in FP64, so the
+// grid is reproducible bit for bit.
 #include "common.h"
 
 namespace imgr {
 namespace {
 
-// ES kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)), here as
-// exp2(beta log2(e) (sqrt(max(1 - z^2, 0)) - 1)).
-template <int W>
-__device__ __forceinline__ void es_taps(float f, float bl2e, float *k) {
-  constexpr int H = W / 2 - 1;
-  constexpr float inv_half = 2.0f / W;
-#pragma unroll
-  for (int i = 0; i < W; ++i) {
-    const float z = ((float)(i - H) - f) * inv_half;
-    const float t = fmaxf(1.0f - z * z, 0.0f);
-    k[i] = __builtin_amdgcn_exp2f(bl2e * (__builtin_amdgcn_sqrtf(t) - 1.0f));
-  }
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// phi(z) = exp(beta (sqrt(1 - z^2) - 1)) as exp2(beta log2(e) (sqrt(.) - 1))
+__device__ __forceinline__ float es_phi(float z, float bl2e) {
+  const float t = fmaxf(1.0f - z * z, 0.0f);
+  return __builtin_amdgcn_exp2f(bl2e * (__builtin_amdgcn_sqrtf(t) - 1.0f));
 }
 
-template <int T, int W, int MODE>
-struct ChunkLds {
-  static constexpr int S = T + W - 1;
-  static constexpr bool kDegrid = (MODE == MODE_DEGRID_GRID || MODE == MODE_DEGRID);
-  static constexpr bool kGrid = (MODE != MODE_DEGRID);
-  static constexpr bool kIm = kGrid && (MODE != MODE_PSF);
-};
+// slot of window column p in a row of the x-weight table: column 4s + q is
+// stored at 4q + s, so that the four columns q, 4 + q, 8 + q, 12 + q one
+// lane feeds to the four K-steps of G kx are one 16-byte read
+__device__ __forceinline__ int xslot(int p) { return ((p & 3) << 2) | (p >> 2); }
 
-// posvis: {dx, dy, re, im} with dx, dy the offsets (cells) of the
-// visibility from its tile origin on the grid the prep step binned for;
-// `pos_scale` = 2 grids on the twice finer PSF grid with tiles of 2T.
-template <int T, int W, int MODE>
-__global__ __launch_bounds__(256) void k_chunk(
+template <int W, int BLK, int MODE>
+__global__ __launch_bounds__(64) void k_window(
     const float4 *__restrict__ posvis, const float *__restrict__ wts,
-    const int32_t *__restrict__ outpos, const int32_t *__restrict__ chunk_tile,
-    const int32_t *__restrict__ chunk_begin, int ntx, int ng, float pos_scale, float bl2e,
-    const float2 *__restrict__ grid_in, const float2 *__restrict__ vis_in,
+    const int32_t *__restrict__ outpos, const int32_t *__restrict__ chunk_block,
+    const int32_t *__restrict__ chunk_begin, const int32_t *__restrict__ order, int nb, int ng,
+    float bl2e, const float2 *__restrict__ grid_in, const float2 *__restrict__ vis_in,
     float2 *__restrict__ vis_out, float2 *__restrict__ scratch) {
-  using L = ChunkLds<T, W, MODE>;
-  constexpr int S = L::S;
+  static_assert(BLK + W - 1 <= kWin, "footprints of a block must fit the window");
   constexpr int H = W / 2 - 1;
-  __shared__ float2 sub[L::kDegrid ? S * S : 1];
-  __shared__ float acc_re[L::kGrid ? S * S : 1];
-  __shared__ float acc_im[L::kIm ? S * S : 1];
+  constexpr int TPL = (W + 3) / 4;  // taps per lane and axis
+  constexpr float kInvHalf = 2.0f / W;
+  constexpr bool kDegrid = (MODE == MODE_DEGRID_GRID || MODE == MODE_DEGRID);
+  constexpr bool kGrid = (MODE != MODE_DEGRID);
+  constexpr bool kCplx = (MODE != MODE_PSF);
+  // per batch: tap weights of the 16 visibilities over the 16 window
+  // positions (x in xslot order, y in natural order) and the residuals
+  __shared__ __attribute__((aligned(16))) float kx_t[16 * 16];
+  __shared__ __attribute__((aligned(16))) float ky_t[16 * 16];
+  __shared__ float2 r_t[16];
 
-  const int chunk = blockIdx.x;
-  const int tile = chunk_tile[chunk];
-  const int tx = tile % ntx, ty = tile / ntx;
-  const int gx0 = tx * T - H, gy0 = ty * T - H;
-  const int t = threadIdx.x;
+  const int l = threadIdx.x, c16 = l & 15, g = l >> 4;
+  const int chunk = order[blockIdx.x];
+  const int blk = chunk_block[chunk];
+  const int wx0 = (blk % nb) * BLK - H, wy0 = (blk / nb) * BLK - H;
 
-  if constexpr (L::kDegrid) {
-    for (int i = t; i < S * S; i += 256) {
-      const int sy = i / S, sx = i - sy * S;
-      const int gx = (gx0 + sx) & (ng - 1), gy = (gy0 + sy) & (ng - 1);
-      sub[i] = grid_in[(size_t)gy * ng + gx];
+  // model window as the A operand of G kx: lane (c16, g) holds
+  // G[y = c16][x = 4 s + g] for the K-steps s = 0..3
+  float gre[4], gim[4];
+  if constexpr (kDegrid) {
+    const int gy = (wy0 + c16) & (ng - 1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int gx = (wx0 + 4 * s + g) & (ng - 1);
+      const float2 v = grid_in[(size_t)gy * ng + gx];
+      gre[s] = v.x;
+      gim[s] = v.y;
     }
   }
-  if constexpr (L::kGrid) {
-    for (int i = t; i < S * S; i += 256) {
-      acc_re[i] = 0.f;
-      if constexpr (L::kIm) acc_im[i] = 0.f;
-    }
-  }
-  __syncthreads();
+  floatx4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
 
   const int b = chunk_begin[chunk], e = chunk_begin[chunk + 1];
-  for (int v = b + t; v < e; v += 256) {
-    const float4 pv = posvis[v];
-    const float dx = pv.x * pos_scale, dy = pv.y * pos_scale;
-    const int cx = min(max((int)floorf(dx), 0), T - 1);
-    const int cy = min(max((int)floorf(dy), 0), T - 1);
-    float kx[W], ky[W];
-    es_taps<W>(dx - (float)cx, bl2e, kx);
-    es_taps<W>(dy - (float)cy, bl2e, ky);
+  // lane (c16, g) works on visibility c16 of each batch; the record of the
+  // next batch is loaded while the current one is processed
+  const float4 pv_pad = make_float4(0.5f, 0.5f, 0.f, 0.f);
+  float4 pv_next = (b + c16 < e) ? posvis[b + c16] : pv_pad;
+  float w_next = 0.f;
+  if constexpr (kGrid) w_next = (b + c16 < e) ? wts[b + c16] : 0.f;
+  for (int base = b; base < e; base += 16) {
+    const int v = base + c16;
+    const bool valid = v < e;
+    const float4 pv = pv_next;
+    const float w = w_next;
+    {
+      const int vn = v + 16;
+      pv_next = (vn < e) ? posvis[vn] : pv_pad;
+      if constexpr (kGrid) w_next = (vn < e) ? wts[vn] : 0.f;
+    }
+    const int ox = min(max((int)floorf(pv.x), 0), BLK - 1);
+    const int oy = min(max((int)floorf(pv.y), 0), BLK - 1);
+    const float fx = pv.x - (float)ox, fy = pv.y - (float)oy;
 
-    float2 pred = make_float2(0.f, 0.f);
-    if constexpr (L::kDegrid) {
+    // tap weights: clear this lane's quarter of the two table rows of its
+    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis
+    *(floatx4 *)&kx_t[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    *(floatx4 *)&ky_t[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const float2 *srow = sub + (cy + j) * S + cx;
-        float rx = 0.f, ry = 0.f;
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-          const float2 g = srow[i];
-          rx = fmaf(kx[i], g.x, rx);
-          ry = fmaf(kx[i], g.y, ry);
-        }
-        pred.x = fmaf(ky[j], rx, pred.x);
-        pred.y = fmaf(ky[j], ry, pred.y);
+    for (int q = 0; q < TPL; ++q) {
+      const int t = g * TPL + q;
+      if (t < W) {
+        kx_t[c16 * 16 + xslot(ox + t)] = es_phi(((float)(t - H) - fx) * kInvHalf, bl2e);
+        ky_t[c16 * 16 + oy + t] = es_phi(((float)(t - H) - fy) * kInvHalf, bl2e);
       }
+    }
+    __syncthreads();
+
+    float pr = 0.f, pi = 0.f;
+    if constexpr (kDegrid) {
+      // T[y][k] = sum_x G[y][x] kx_k[x]: B[x = 4 s + g][k = c16]
+      const floatx4 bx = *(const floatx4 *)&kx_t[c16 * 16 + 4 * g];
+      floatx4 tre = {0.f, 0.f, 0.f, 0.f}, tim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        tre = __builtin_amdgcn_mfma_f32_16x16x4f32(gre[s], bx[s], tre, 0, 0, 0);
+        tim = __builtin_amdgcn_mfma_f32_16x16x4f32(gim[s], bx[s], tim, 0, 0, 0);
+      }
+      // lane (c16, g) holds T[4 g + r][c16]; v_hat_k = sum_y ky_k[y] T[y][k]
+      const floatx4 by = *(const floatx4 *)&ky_t[c16 * 16 + 4 * g];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pr = fmaf(by[r], tre[r], pr);
+        pi = fmaf(by[r], tim[r], pi);
+      }
+      pr += __shfl_xor(pr, 16);
+      pi += __shfl_xor(pi, 16);
+      pr += __shfl_xor(pr, 32);
+      pi += __shfl_xor(pi, 32);
     }
     if constexpr (MODE == MODE_DEGRID) {
-      vis_out[outpos[v]] = pred;
-    } else {
-      const float w = wts[v];
-      float2 r;
-      if constexpr (MODE == MODE_DEGRID_GRID) {
-        r = make_float2(w * (pv.z - pred.x), w * (pv.w - pred.y));
-      } else if constexpr (MODE == MODE_GRID) {
-        const float2 x = vis_in[outpos[v]];
-        r = make_float2(w * x.x, w * x.y);
-      } else {  // MODE_PSF
-        r = make_float2(w, 0.f);
-      }
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const float rx = r.x * ky[j], ry = r.y * ky[j];
-        const int base = (cy + j) * S + cx;
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-          atomicAdd(&acc_re[base + i], rx * kx[i]);
-          if constexpr (MODE != MODE_PSF) atomicAdd(&acc_im[base + i], ry * kx[i]);
+      if (valid && g == 0) vis_out[outpos[v]] = make_float2(pr, pi);
+    }
+    if constexpr (kGrid) {
+      if (g == 0) {
+        float2 r;
+        if constexpr (MODE == MODE_DEGRID_GRID) {
+          r = make_float2(w * (pv.z - pr), w * (pv.w - pi));
+        } else if constexpr (MODE == MODE_GRID) {
+          const float2 x = valid ? vis_in[outpos[v]] : make_float2(0.f, 0.f);
+          r = make_float2(w * x.x, w * x.y);
+        } else {  // MODE_PSF: unit visibilities
+          r = make_float2(w, 0.f);
         }
+        r_t[c16] = r;
+      }
+      __syncthreads();
+      // A[y][x] += sum_k (r_k ky_k[y]) kx_k[x]; K-step s covers k = 4 s + g
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + g;
+        const float kyv = ky_t[k * 16 + c16];
+        const float kxv = kx_t[k * 16 + xslot(c16)];
+        const float2 rk = r_t[k];
+        acc_re = __builtin_amdgcn_mfma_f32_16x16x4f32(rk.x * kyv, kxv, acc_re, 0, 0, 0);
+        if constexpr (kCplx)
+          acc_im = __builtin_amdgcn_mfma_f32_16x16x4f32(rk.y * kyv, kxv, acc_im, 0, 0, 0);
       }
     }
+    __syncthreads();  // the tables are rewritten by the next batch
   }
 
-  if constexpr (L::kGrid) {
-    __syncthreads();
-    float2 *out = scratch + (size_t)chunk * S * S;
-    for (int i = t; i < S * S; i += 256)
-      out[i] = make_float2(acc_re[i], L::kIm ? acc_im[i] : 0.f);
+  if constexpr (kGrid) {
+    // lane (c16, g) holds A[4 g + r][c16]
+    float2 *out = scratch + (size_t)chunk * (kWin * kWin);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      out[(4 * g + r) * kWin + c16] = make_float2(acc_re[r], kCplx ? acc_im[r] : 0.f);
   }
 }
 
-// For every cell of output tile blockIdx.x: FP64 sum over the chunks of the
-// 3 x 3 neighbouring tiles (fixed order: row offset, column offset, chunk),
-// times (-1)^(x + y) for the centred inverse DFT that follows.
-template <int T, int W>
+// One thread per grid cell, 16 x 16 cells per workgroup: FP64 sum over the
+// chunk windows of the blocks whose window covers the cell (fixed order:
+// block row offset, block column offset, chunk), times (-1)^(x + y) for the
+// centred inverse DFT that follows.
+template <int W, int BLK>
 __global__ __launch_bounds__(256) void k_flush(const float2 *__restrict__ scratch,
-                                               const int32_t *__restrict__ tile_chunk, int ntx,
+                                               const int32_t *__restrict__ block_chunk, int nb,
                                                int ng, float2 *__restrict__ grid_out) {
-  constexpr int S = T + W - 1;
   constexpr int H = W / 2 - 1;
-  const int tile = blockIdx.x;
-  const int tx = tile % ntx, ty = tile / ntx;
-  for (int i = threadIdx.x; i < T * T; i += 256) {
-    const int lx = i % T, ly = i / T;
-    double re = 0.0, im = 0.0;
+  constexpr int R = kWin / BLK;
+  const int nq = ng / 16;
+  const int cx = (blockIdx.x % nq) * 16 + (threadIdx.x & 15);
+  const int cy = (blockIdx.x / nq) * 16 + (threadIdx.x >> 4);
+  const int bx = cx / BLK, by = cy / BLK, lx = cx % BLK, ly = cy % BLK;
+  double re = 0.0, im = 0.0;
 #pragma unroll
-    for (int dty = -1; dty <= 1; ++dty) {
-      const int sy = ly + H - dty * T;
-      if (sy < 0 || sy >= S) continue;
-      const int nty = (ty + dty + ntx) % ntx;
+  for (int dby = -R; dby <= R; ++dby) {
+    const int wy = ly + H - dby * BLK;
+    if (wy < 0 || wy >= kWin) continue;
+    const int nby = (by + dby + nb) % nb;
 #pragma unroll
-      for (int dtx = -1; dtx <= 1; ++dtx) {
-        const int sx = lx + H - dtx * T;
-        if (sx < 0 || sx >= S) continue;
-        const int ntxx = (tx + dtx + ntx) % ntx;
-        const int n = nty * ntx + ntxx;
-        const int c0 = tile_chunk[n], c1 = tile_chunk[n + 1];
-        for (int c = c0; c < c1; ++c) {
-          const float2 v = scratch[(size_t)c * S * S + sy * S + sx];
-          re += (double)v.x;
-          im += (double)v.y;
-        }
+    for (int dbx = -R; dbx <= R; ++dbx) {
+      const int wx = lx + H - dbx * BLK;
+      if (wx < 0 || wx >= kWin) continue;
+      const int n = nby * nb + (bx + dbx + nb) % nb;
+      const int c0 = block_chunk[n], c1 = block_chunk[n + 1];
+      for (int c = c0; c < c1; ++c) {
+        const float2 v = scratch[(size_t)c * (kWin * kWin) + wy * kWin + wx];
+        re += (double)v.x;
+        im += (double)v.y;
       }
     }
-    const int gx = tx * T + lx, gy = ty * T + ly;
-    const float sg = ((gx + gy) & 1) ? -1.f : 1.f;
-    grid_out[(size_t)gy * ng + gx] = make_float2(sg * (float)re, sg * (float)im);
   }
+  const float sg = ((cx + cy) & 1) ? -1.f : 1.f;
+  grid_out[(size_t)cy * ng + cx] = make_float2(sg * (float)re, sg * (float)im);
 }
 
-template <int T, int W>
-void chunk_launch(imgr_s *h, const Partition &P, int mode, float pos_scale, int ng,
-                  const float2 *grid_in, const float2 *vis_in, float2 *vis_out, float2 *scratch,
-                  hipStream_t s) {
+template <int W, int BLK>
+void launch_window(imgr_s *h, const Bins &B, int mode, const float2 *grid_in,
+                   const float2 *vis_in, float2 *vis_out, float2 *scratch, hipStream_t s) {
   const float bl2e = (float)(h->beta * 1.4426950408889634);
-  const int ntx = ng / T;
-  dim3 grid(P.n_chunks), block(256);
-  if constexpr (T > 32) {
-    // tiles of 64 cells only serve the PSF grid (2T for T = 32): the fused
-    // modes would need more LDS than a workgroup may hold
-    if (mode != MODE_PSF) throw Error{IMGR_EINVAL, "tile 64 is PSF-only"};
-    hipLaunchKernelGGL((k_chunk<T, W, MODE_PSF>), grid, block, 0, s, P.posvis, P.w, P.outpos,
-                       P.chunk_tile, P.chunk_begin, ntx, ng, pos_scale, bl2e, grid_in, vis_in,
-                       vis_out, scratch);
-    return;
-  } else {
+  dim3 grid(B.n_chunks), block(64);
+#define L_(M)                                                                                   \
+  hipLaunchKernelGGL((k_window<W, BLK, M>), grid, block, 0, s, B.posvis, B.w, B.outpos,           \
+                     B.chunk_block, B.chunk_begin, B.order, B.nb, B.ng, bl2e, grid_in, vis_in,    \
+                     vis_out, scratch)
   switch (mode) {
-    case MODE_DEGRID_GRID:
-      hipLaunchKernelGGL((k_chunk<T, W, MODE_DEGRID_GRID>), grid, block, 0, s, P.posvis, P.w,
-                         P.outpos, P.chunk_tile, P.chunk_begin, ntx, ng, pos_scale, bl2e, grid_in,
-                         vis_in, vis_out, scratch);
-      break;
-    case MODE_GRID:
-      hipLaunchKernelGGL((k_chunk<T, W, MODE_GRID>), grid, block, 0, s, P.posvis, P.w, P.outpos,
-                         P.chunk_tile, P.chunk_begin, ntx, ng, pos_scale, bl2e, grid_in, vis_in,
-                         vis_out, scratch);
-      break;
-    case MODE_DEGRID:
-      hipLaunchKernelGGL((k_chunk<T, W, MODE_DEGRID>), grid, block, 0, s, P.posvis, P.w,
-                         P.outpos, P.chunk_tile, P.chunk_begin, ntx, ng, pos_scale, bl2e, grid_in,
-                         vis_in, vis_out, scratch);
-      break;
-    case MODE_PSF:
-      hipLaunchKernelGGL((k_chunk<T, W, MODE_PSF>), grid, block, 0, s, P.posvis, P.w, P.outpos,
-                         P.chunk_tile, P.chunk_begin, ntx, ng, pos_scale, bl2e, grid_in, vis_in,
-                         vis_out, scratch);
-      break;
+    case MODE_DEGRID_GRID: L_(MODE_DEGRID_GRID); break;
+    case MODE_GRID: L_(MODE_GRID); break;
+    case MODE_DEGRID: L_(MODE_DEGRID); break;
+    case MODE_PSF: L_(MODE_PSF); break;
+    default: throw Error{IMGR_EINVAL, "unknown de/gridding mode"};
   }
-  }
+#undef L_
 }
 
-template <int W>
-void chunk_dispatch_t(imgr_s *h, const Partition &P, int mode, int tile, float pos_scale, int ng,
-                      const float2 *grid_in, const float2 *vis_in, float2 *vis_out,
-                      float2 *scratch, hipStream_t s) {
-  switch (tile) {
-    case 16: chunk_launch<16, W>(h, P, mode, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    case 32: chunk_launch<32, W>(h, P, mode, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    case 64: chunk_launch<64, W>(h, P, mode, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    default: throw Error{IMGR_EINVAL, "unsupported tile"};
-  }
+template <int W, int BLK>
+void launch_flush(const Bins &B, const float2 *scratch, float2 *out, hipStream_t s) {
+  const int nq = B.ng / 16;
+  hipLaunchKernelGGL((k_flush<W, BLK>), dim3(nq * nq), dim3(256), 0, s, scratch, B.block_chunk,
+                     B.nb, B.ng, out);
 }
+
+// (W, blk) pairs the library is built for: blk + W - 1 <= 16
+#define IMGR_WB_CASES(X) \
+  X(4, 8) X(6, 8) X(8, 8) X(4, 4) X(6, 4) X(8, 4) X(10, 4) X(12, 4)
 
 }  // namespace
 
-void degrid_grid(imgr_s *h, int p, int mode, const float2 *grid_in, const float2 *vis_in,
-                 float2 *vis_out, int tile, int ng, float2 *scratch, hipStream_t s) {
-  const Partition &P = h->part[p];
-  if (P.n_chunks == 0) return;
-  const float pos_scale = (float)tile / (float)h->T;
-  switch (h->W) {
-    case 4: chunk_dispatch_t<4>(h, P, mode, tile, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    case 6: chunk_dispatch_t<6>(h, P, mode, tile, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    case 8: chunk_dispatch_t<8>(h, P, mode, tile, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    case 10: chunk_dispatch_t<10>(h, P, mode, tile, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    case 12: chunk_dispatch_t<12>(h, P, mode, tile, pos_scale, ng, grid_in, vis_in, vis_out, scratch, s); break;
-    default: throw Error{IMGR_EINVAL, "unsupported support W"};
-  }
-  IMGR_HIP(hipGetLastError());
+bool window_supported(int W, int blk) {
+#define C_(w, b) if (W == w && blk == b) return true;
+  IMGR_WB_CASES(C_)
+#undef C_
+  return false;
 }
 
-template <int W>
-static void flush_t(int tile, const int32_t *tile_chunk, int ntx, int ng, const float2 *scratch,
-                    float2 *out, hipStream_t s) {
-  dim3 grid(ntx * ntx), block(256);
-  switch (tile) {
-    case 16: hipLaunchKernelGGL((k_flush<16, W>), grid, block, 0, s, scratch, tile_chunk, ntx, ng, out); break;
-    case 32: hipLaunchKernelGGL((k_flush<32, W>), grid, block, 0, s, scratch, tile_chunk, ntx, ng, out); break;
-    case 64: hipLaunchKernelGGL((k_flush<64, W>), grid, block, 0, s, scratch, tile_chunk, ntx, ng, out); break;
-    default: throw Error{IMGR_EINVAL, "unsupported tile"};
+void degrid_grid(imgr_s *h, const Bins &B, int mode, const float2 *grid_in, const float2 *vis_in,
+                 float2 *vis_out, float2 *scratch, hipStream_t s) {
+  if (B.n_chunks == 0) return;
+  IMGR_CHECK(B.ng >= 16 && (B.ng & (B.ng - 1)) == 0 && B.nb * h->blk == B.ng, "bin geometry");
+#define C_(w, b)                                                                         \
+  if (h->W == w && h->blk == b) {                                                        \
+    launch_window<w, b>(h, B, mode, grid_in, vis_in, vis_out, scratch, s);               \
+    IMGR_HIP(hipGetLastError());                                                         \
+    return;                                                                              \
   }
+  IMGR_WB_CASES(C_)
+#undef C_
+  throw Error{IMGR_EINVAL, "unsupported support / block combination"};
 }
 
-void flush_chunks(imgr_s *h, int p, int tile, int ng, const float2 *scratch, float2 *grid_out,
+void flush_chunks(imgr_s *h, const Bins &B, const float2 *scratch, float2 *grid_out,
                   hipStream_t s) {
-  const Partition &P = h->part[p];
-  const int ntx = ng / tile;
-  switch (h->W) {
-    case 4: flush_t<4>(tile, P.tile_chunk, ntx, ng, scratch, grid_out, s); break;
-    case 6: flush_t<6>(tile, P.tile_chunk, ntx, ng, scratch, grid_out, s); break;
-    case 8: flush_t<8>(tile, P.tile_chunk, ntx, ng, scratch, grid_out, s); break;
-    case 10: flush_t<10>(tile, P.tile_chunk, ntx, ng, scratch, grid_out, s); break;
-    case 12: flush_t<12>(tile, P.tile_chunk, ntx, ng, scratch, grid_out, s); break;
-    default: throw Error{IMGR_EINVAL, "unsupported support W"};
+  IMGR_CHECK(B.ng >= 16 && (B.ng & (B.ng - 1)) == 0 && B.nb * h->blk == B.ng, "bin geometry");
+#define C_(w, b)                                    \
+  if (h->W == w && h->blk == b) {                   \
+    launch_flush<w, b>(B, scratch, grid_out, s);    \
+    IMGR_HIP(hipGetLastError());                    \
+    return;                                         \
   }
-  IMGR_HIP(hipGetLastError());
+  IMGR_WB_CASES(C_)
+#undef C_
+  throw Error{IMGR_EINVAL, "unsupported support / block combination"};
 }
 
 }  // namespace imgr

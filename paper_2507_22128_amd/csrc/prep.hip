@@ -1,11 +1,12 @@
 // Preparation of a handle (once per imager_create): FP64 coordinate chain,
 // uniform weighting (Section 5.1), spatial-frequency partition of Fig. 3
 // with ell at the lower median of rho unless given, stable sort of each
-// partition by uv tile, chunk tables, and packing into the 20-byte
+// partition by uv block (on the Ng grid of the major cycle and on the 2 Ng
+// grid of the PSF), chunk tables, and packing into the 20-byte
 // per-visibility stream the de/gridding kernels read.
 //
 // Every decision that turns a floating-point value into an integer (tap
-// cell, tile, uniform-weight cell, partition membership) is taken in FP64
+// cell, block, uniform-weight cell, partition membership) is taken in FP64
 // with plain multiply / add / sqrt (no contraction), the same operation
 // sequence the CPU oracle uses, so the integer results agree bit for bit.
 #pragma clang fp contract(off)
@@ -100,26 +101,35 @@ __global__ void k_select_hist(int64_t m, const double *__restrict__ rho,
   if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-// ---------------------------------------------------------------- partition keys
+// ---------------------------------------------------------------- membership, block keys
 
-__global__ void k_part_keys(int64_t m, const double *__restrict__ gx,
-                            const double *__restrict__ gy, const double *__restrict__ rho,
-                            const uint8_t *__restrict__ valid, int which, double lo_max,
-                            double hi_min, int tile, int ntx, uint32_t *__restrict__ keys,
-                            int32_t *__restrict__ vals, int32_t *__restrict__ member) {
+// which: 0 = V_L (rho <= lo_max), 1 = V_H (rho >= hi_min), 2 = all valid
+__global__ void k_member(int64_t m, const double *__restrict__ rho,
+                         const uint8_t *__restrict__ valid, int which, double lo_max,
+                         double hi_min, int32_t *__restrict__ member) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   bool in = valid[i];
   if (which == 0) in = in && (rho[i] <= lo_max);
   if (which == 1) in = in && (rho[i] >= hi_min);
-  uint32_t key = (uint32_t)(ntx * ntx);
-  if (in) {
-    const int cx = (int)floor(gx[i]), cy = (int)floor(gy[i]);
-    key = (uint32_t)((cy / tile) * ntx + (cx / tile));
+  member[i] = in ? 1 : 0;
+}
+
+// block of the first tap: floor(scale * g) / blk (scale 1 or 2 is exact);
+// non-members get key nb * nb and sort last
+__global__ void k_block_keys(int64_t m, const double *__restrict__ gx,
+                             const double *__restrict__ gy, const int32_t *__restrict__ member,
+                             double scale, int blk, int nb, uint32_t *__restrict__ keys,
+                             int32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t key = (uint32_t)nb * (uint32_t)nb;
+  if (member[i]) {
+    const int cx = (int)floor(gx[i] * scale), cy = (int)floor(gy[i] * scale);
+    key = (uint32_t)((cy / blk) * nb + (cx / blk));
   }
   keys[i] = key;
   vals[i] = (int32_t)i;
-  member[i] = in ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- scan (int32)
@@ -266,46 +276,46 @@ void radix_sort(imgr_s *h, uint32_t *&keys, int32_t *&vals, uint32_t *&ktmp, int
   dev_free(h, counts);
 }
 
-// ---------------------------------------------------------------- tiles, chunks, pack
+// ---------------------------------------------------------------- blocks, chunks, pack
 
-__global__ void k_tile_hist(int64_t n, const uint32_t *__restrict__ keys, int n_tiles,
-                            int32_t *__restrict__ cnt) {
+__global__ void k_block_hist(int64_t n, const uint32_t *__restrict__ keys, int n_blocks,
+                             int32_t *__restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && keys[i] < (uint32_t)n_tiles) atomicAdd(&cnt[keys[i]], 1);
+  if (i < n && keys[i] < (uint32_t)n_blocks) atomicAdd(&cnt[keys[i]], 1);
 }
 
-__global__ void k_chunk_count(int n_tiles, const int32_t *__restrict__ cnt, int cap,
+__global__ void k_chunk_count(int n_blocks, const int32_t *__restrict__ cnt, int cap,
                               int32_t *__restrict__ nch) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_tiles) nch[t] = (cnt[t] + cap - 1) / cap;
+  if (t < n_blocks) nch[t] = (cnt[t] + cap - 1) / cap;
 }
 
-// chunks of tile t split its cnt[t] visibilities evenly:
+// chunks of block t split its cnt[t] visibilities evenly:
 // chunk q covers [start + cnt*q/k, start + cnt*(q+1)/k)
-__global__ void k_make_chunks(int n_tiles, const int32_t *__restrict__ cnt,
-                              const int32_t *__restrict__ tstart,
-                              const int32_t *__restrict__ tchunk, int32_t *__restrict__ ctile,
+__global__ void k_make_chunks(int n_blocks, const int32_t *__restrict__ cnt,
+                              const int32_t *__restrict__ bstart,
+                              const int32_t *__restrict__ bchunk, int32_t *__restrict__ cblock,
                               int32_t *__restrict__ cbegin) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int k = tchunk[t + 1] - tchunk[t];
+  if (t >= n_blocks) return;
+  const int k = bchunk[t + 1] - bchunk[t];
   for (int q = 0; q < k; ++q) {
-    ctile[tchunk[t] + q] = t;
-    cbegin[tchunk[t] + q] = tstart[t] + (int)(((int64_t)cnt[t] * q) / k);
+    cblock[bchunk[t] + q] = t;
+    cbegin[bchunk[t] + q] = bstart[t] + (int)(((int64_t)cnt[t] * q) / k);
   }
 }
 
 __global__ void k_pack(int64_t n, const uint32_t *__restrict__ keys,
                        const int32_t *__restrict__ idx, const double *__restrict__ gx,
-                       const double *__restrict__ gy, const void *__restrict__ vis, int c128,
-                       const double *__restrict__ w64, const int32_t *__restrict__ rank,
-                       int tile, int ntx, float4 *__restrict__ posvis, float *__restrict__ w,
+                       const double *__restrict__ gy, double scale, const void *__restrict__ vis,
+                       int c128, const double *__restrict__ w64, const int32_t *__restrict__ rank,
+                       int blk, int nb, float4 *__restrict__ posvis, float *__restrict__ w,
                        int32_t *__restrict__ orig, int32_t *__restrict__ outpos) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = idx[s];
   const int t = (int)keys[s];
-  const int tx = t % ntx, ty = t / ntx;
+  const int bx = t % nb, by = t / nb;
   float re, im;
   if (c128) {
     const double2 z = ((const double2 *)vis)[i];
@@ -316,8 +326,8 @@ __global__ void k_pack(int64_t n, const uint32_t *__restrict__ keys,
     re = z.x;
     im = z.y;
   }
-  posvis[s] = make_float4((float)(gx[i] - (double)(tx * tile)),
-                          (float)(gy[i] - (double)(ty * tile)), re, im);
+  posvis[s] = make_float4((float)(gx[i] * scale - (double)(bx * blk)),
+                          (float)(gy[i] * scale - (double)(by * blk)), re, im);
   w[s] = (float)w64[i];
   orig[s] = i;
   outpos[s] = rank[i];
@@ -373,22 +383,96 @@ double lower_median_rho(imgr_s *h, int64_t m, const double *rho, const uint8_t *
   return med;
 }
 
+// Sort the members of a partition by block of the (scale * g) grid of side
+// ng, cut chunks, and pack the 20-byte per-visibility stream.
+void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member,
+                 const int32_t *rank, const double *gx, const double *gy, double scale, int ng,
+                 const double *w64, const void *vis_dev, int c128, hipStream_t s) {
+  const int blk = h->blk;
+  B.n = n;
+  B.ng = ng;
+  B.nb = ng / blk;
+  const int n_blocks = B.nb * B.nb;
+  const unsigned nbk = cdiv(m, 256);
+  uint32_t *keys = alloc_n<uint32_t>(h, m), *ktmp = alloc_n<uint32_t>(h, m);
+  int32_t *vals = alloc_n<int32_t>(h, m), *vtmp = alloc_n<int32_t>(h, m);
+  hipLaunchKernelGGL(k_block_keys, dim3(nbk), dim3(256), 0, s, m, gx, gy, member, scale, blk,
+                     B.nb, keys, vals);
+  IMGR_HIP(hipGetLastError());
+  // stable sort by block; non-members (key n_blocks) go last
+  int key_bits = 0;
+  while ((1ll << key_bits) <= n_blocks) key_bits += 8;
+  radix_sort(h, keys, vals, ktmp, vtmp, m, key_bits, s);
+  // block counts, starts, chunks
+  int32_t *cnt = alloc_n<int32_t>(h, n_blocks + 1);
+  int32_t *bstart = alloc_n<int32_t>(h, n_blocks + 1);
+  int32_t *nch = alloc_n<int32_t>(h, n_blocks + 1);
+  IMGR_HIP(hipMemsetAsync(cnt, 0, (n_blocks + 1) * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_block_hist, dim3(cdiv(std::max<int64_t>(n, 1), 256)), dim3(256), 0, s, n,
+                     keys, n_blocks, cnt);
+  IMGR_HIP(hipGetLastError());
+  scan_exclusive(h, cnt, bstart, n_blocks + 1, s);
+  hipLaunchKernelGGL(k_chunk_count, dim3(cdiv(n_blocks + 1, 256)), dim3(256), 0, s, n_blocks + 1,
+                     cnt, h->C, nch);
+  IMGR_HIP(hipGetLastError());
+  B.block_chunk = alloc_n<int32_t>(h, n_blocks + 1);
+  // nch[n_blocks] is 0 (cnt[n_blocks] == 0), so the scan's last entry is the total
+  B.n_chunks = (int)scan_exclusive(h, nch, B.block_chunk, n_blocks + 1, s);
+  B.chunk_block = alloc_n<int32_t>(h, B.n_chunks);
+  B.chunk_begin = alloc_n<int32_t>(h, B.n_chunks + 1);
+  hipLaunchKernelGGL(k_make_chunks, dim3(cdiv(n_blocks, 256)), dim3(256), 0, s, n_blocks, cnt,
+                     bstart, B.block_chunk, B.chunk_block, B.chunk_begin);
+  IMGR_HIP(hipGetLastError());
+  // launch order: largest chunk first (stable), so the heavy blocks of the
+  // dense uv core start early and the tail of the launch is short
+  {
+    std::vector<int32_t> cb(B.n_chunks + 1);
+    if (B.n_chunks > 0)
+      IMGR_HIP(hipMemcpyAsync(cb.data(), B.chunk_begin, B.n_chunks * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+    IMGR_HIP(hipStreamSynchronize(s));
+    cb[B.n_chunks] = (int32_t)n;
+    std::vector<int32_t> ord(B.n_chunks);
+    for (int c = 0; c < B.n_chunks; ++c) ord[c] = c;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+      return cb[a + 1] - cb[a] > cb[b + 1] - cb[b];
+    });
+    B.order = alloc_n<int32_t>(h, B.n_chunks);
+    if (B.n_chunks > 0)
+      IMGR_HIP(hipMemcpyAsync(B.order, ord.data(), B.n_chunks * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+    const int32_t nn = (int32_t)n;
+    IMGR_HIP(hipMemcpyAsync(B.chunk_begin + B.n_chunks, &nn, sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+    IMGR_HIP(hipStreamSynchronize(s));
+  }
+  // pack the per-visibility stream
+  B.posvis = alloc_n<float4>(h, n);
+  B.w = alloc_n<float>(h, n);
+  B.orig = alloc_n<int32_t>(h, n);
+  B.outpos = alloc_n<int32_t>(h, n);
+  if (n > 0)
+    hipLaunchKernelGGL(k_pack, dim3(cdiv(n, 256)), dim3(256), 0, s, n, keys, vals, gx, gy, scale,
+                       vis_dev, c128, w64, rank, blk, B.nb, B.posvis, B.w, B.orig, B.outpos);
+  IMGR_HIP(hipGetLastError());
+  IMGR_HIP(hipStreamSynchronize(s));
+  for (void *q : {(void *)keys, (void *)ktmp, (void *)vals, (void *)vtmp, (void *)cnt,
+                  (void *)bstart, (void *)nch})
+    dev_free(h, q);
+}
+
 void build_partition(imgr_s *h, int p, int which, int64_t m, const double *gx, const double *gy,
                      const double *rho, const uint8_t *valid, const double *w64,
                      const void *vis_dev, int c128, hipStream_t s) {
   Partition &P = h->part[p];
-  const int n_tiles = h->n_tiles;
   const unsigned nbk = cdiv(m, 256);
-  uint32_t *keys = alloc_n<uint32_t>(h, m), *ktmp = alloc_n<uint32_t>(h, m);
-  int32_t *vals = alloc_n<int32_t>(h, m), *vtmp = alloc_n<int32_t>(h, m);
   int32_t *member = alloc_n<int32_t>(h, m);
-  hipLaunchKernelGGL(k_part_keys, dim3(nbk), dim3(256), 0, s, m, gx, gy, rho, valid, which,
-                     h->ell + h->delta, h->ell - h->delta, h->T, h->ntx, keys, vals, member);
+  hipLaunchKernelGGL(k_member, dim3(nbk), dim3(256), 0, s, m, rho, valid, which,
+                     h->ell + h->delta, h->ell - h->delta, member);
   IMGR_HIP(hipGetLastError());
   // member rank in original order, and the member count
   int32_t *rank = alloc_n<int32_t>(h, m);
   const int64_t n = scan_exclusive(h, member, rank, m, s);
-  P.n = n;
   // summed weight (FP64, fixed order: 256 block partials summed on the host)
   {
     double *part = alloc_n<double>(h, 256);
@@ -402,48 +486,12 @@ void build_partition(imgr_s *h, int p, int which, int64_t m, const double *gx, c
     P.sum_w = acc;
     dev_free(h, part);
   }
-  // stable sort by tile; non-members (key n_tiles) go last
-  int key_bits = 0;
-  while ((1ll << key_bits) <= n_tiles) key_bits += 8;
-  radix_sort(h, keys, vals, ktmp, vtmp, m, key_bits, s);
-  // tile counts, starts, chunks
-  int32_t *cnt = alloc_n<int32_t>(h, n_tiles + 1);
-  int32_t *tstart = alloc_n<int32_t>(h, n_tiles + 1);
-  int32_t *nch = alloc_n<int32_t>(h, n_tiles + 1);
-  IMGR_HIP(hipMemsetAsync(cnt, 0, (n_tiles + 1) * sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_tile_hist, dim3(cdiv(std::max<int64_t>(n, 1), 256)), dim3(256), 0, s, n,
-                     keys, n_tiles, cnt);
-  IMGR_HIP(hipGetLastError());
-  scan_exclusive(h, cnt, tstart, n_tiles + 1, s);
-  hipLaunchKernelGGL(k_chunk_count, dim3(cdiv(n_tiles + 1, 256)), dim3(256), 0, s, n_tiles + 1,
-                     cnt, h->C, nch);
-  IMGR_HIP(hipGetLastError());
-  P.tile_chunk = alloc_n<int32_t>(h, n_tiles + 1);
-  // nch[n_tiles] is 0 (cnt[n_tiles] == 0), so the scan's last entry is the total
-  P.n_chunks = (int)scan_exclusive(h, nch, P.tile_chunk, n_tiles + 1, s);
-  P.chunk_tile = alloc_n<int32_t>(h, P.n_chunks);
-  P.chunk_begin = alloc_n<int32_t>(h, P.n_chunks + 1);
-  hipLaunchKernelGGL(k_make_chunks, dim3(cdiv(n_tiles, 256)), dim3(256), 0, s, n_tiles, cnt,
-                     tstart, P.tile_chunk, P.chunk_tile, P.chunk_begin);
-  IMGR_HIP(hipGetLastError());
-  {
-    const int32_t nn = (int32_t)n;
-    IMGR_HIP(hipMemcpyAsync(P.chunk_begin + P.n_chunks, &nn, sizeof(int32_t),
-                            hipMemcpyHostToDevice, s));
-  }
-  // pack the per-visibility stream
-  P.posvis = alloc_n<float4>(h, n);
-  P.w = alloc_n<float>(h, n);
-  P.orig = alloc_n<int32_t>(h, n);
-  P.outpos = alloc_n<int32_t>(h, n);
-  if (n > 0)
-    hipLaunchKernelGGL(k_pack, dim3(cdiv(n, 256)), dim3(256), 0, s, n, keys, vals, gx, gy,
-                       vis_dev, c128, w64, rank, h->T, h->ntx, P.posvis, P.w, P.orig, P.outpos);
-  IMGR_HIP(hipGetLastError());
-  IMGR_HIP(hipStreamSynchronize(s));
-  for (void *q : {(void *)keys, (void *)ktmp, (void *)vals, (void *)vtmp, (void *)member,
-                  (void *)rank, (void *)cnt, (void *)tstart, (void *)nch})
-    dev_free(h, q);
+  // the Ng grid of the major cycle, and the 2 Ng grid of the 2N x 2N PSF
+  // (same cell size, so grid coordinates double exactly)
+  bin_members(h, P.bins, m, n, member, rank, gx, gy, 1.0, h->Ng, w64, vis_dev, c128, s);
+  bin_members(h, P.psf_bins, m, n, member, rank, gx, gy, 2.0, 2 * h->Ng, w64, vis_dev, c128, s);
+  dev_free(h, member);
+  dev_free(h, rank);
 }
 
 }  // namespace
