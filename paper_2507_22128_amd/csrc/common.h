@@ -128,6 +128,15 @@ void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, co
 // (-1)^(gx+gy)) cropped to N x N, times (-1)^(px+py)/psi_hat^2 * scale, real part
 void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
                        float2 *rows, float2 *tmp, float *out, hipStream_t s);
+// out (+)= Re F_N^-1 (Gamma_own . F_N (a - b)) * coef for N x N images
+// (b may be NULL; plain DFTs; Gamma_L for own_low, else Gamma_H);
+// work holds N x L and tmp L x L complex values (L = N here, 2N below)
+void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float coef, float *out,
+                 int accumulate, float2 *work, float2 *tmp, hipStream_t s);
+// out (+)= coef * (psf * a), the linear convolution of the N x N image a by
+// the 2N x 2N PSF with spectrum psf_hat (centre (N, N)), cropped to N x N
+void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef, float *out,
+                    int accumulate, float2 *work, float2 *tmp, hipStream_t s);
 // plain 2-D DFT of an n x n complex buffer in place (dir -1 forward, +1 inverse, unnormalised)
 void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t s);
 

@@ -35,24 +35,6 @@ __device__ __forceinline__ float gamma_low(int kx, int ky, int nd, double ell, d
   return (float)fmin(fmax(g, 0.0), 1.0);
 }
 
-__global__ void k_gamma_mul(float2 *__restrict__ buf, const float2 *__restrict__ src, int nd,
-                            double ell, double delta, double scale, int low, float coef) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nd * nd) return;
-  const int ky = (int)(i / nd), kx = (int)(i % nd);
-  float g = gamma_low(kx, ky, nd, ell, delta, scale);
-  if (!low) g = 1.f - g;
-  const float2 v = src[i];
-  buf[i] = make_float2(v.x * g * coef, v.y * g * coef);
-}
-
-__global__ void k_spec_mul(float2 *__restrict__ buf, const float2 *__restrict__ spec, int64_t n,
-                           float coef) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  buf[i] = cscale(cmul(buf[i], spec[i]), coef);
-}
-
 // out = gamma Gamma_own a + mu Gamma_other b, per frequency
 __global__ void k_spec_combine(float2 *__restrict__ out, const float2 *__restrict__ a,
                                const float2 *__restrict__ b, int nd, double ell, double delta,
@@ -113,28 +95,13 @@ void psf_spectrum(imgr_s *h, int p, hipStream_t s) {
 void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma,
              double mu, float *out, hipStream_t s) {
   const int n = h->N, nd = 2 * n;
-  float2 *buf = h->grid_a, *tmp = h->grid_b;
-  hipLaunchKernelGGL(k_pad_real, g1((int64_t)n * n), dim3(256), 0, s, resid, nullptr, n, buf, n);
-  fft2_plain(h, buf, tmp, n, -1, s);
-  hipLaunchKernelGGL(k_gamma_mul, g1((int64_t)n * n), dim3(256), 0, s, buf, buf, n, h->ell,
-                     h->delta, 1.0, p == IMGR_PART_LOW ? 1 : 0,
-                     (float)(gamma / ((double)n * n)));
-  fft2_plain(h, buf, tmp, n, 1, s);
-  hipLaunchKernelGGL(k_crop_real, g1((int64_t)n * n), dim3(256), 0, s, buf, n, 0, 0, n, 1.f, out,
-                     0);
-  IMGR_HIP(hipGetLastError());
-  if (mu != 0.0 && rho_other) {
-    const Partition &O = h->part[1 - p];
-    hipLaunchKernelGGL(k_pad_real, g1((int64_t)nd * nd), dim3(256), 0, s, rho_other, nullptr, n,
-                       buf, nd);
-    fft2_plain(h, buf, tmp, nd, -1, s);
-    hipLaunchKernelGGL(k_spec_mul, g1((int64_t)nd * nd), dim3(256), 0, s, buf, O.psf_hat,
-                       (int64_t)nd * nd, (float)(mu / ((double)nd * nd)));
-    fft2_plain(h, buf, tmp, nd, 1, s);
-    hipLaunchKernelGGL(k_crop_real, g1((int64_t)n * n), dim3(256), 0, s, buf, nd, n, n, n, 1.f,
-                       out, 1);
-    IMGR_HIP(hipGetLastError());
-  }
+  // both grids are free once the residual image is out
+  float2 *work = h->grid_a, *tmp = h->grid_b;
+  image_gamma(h, resid, nullptr, p == IMGR_PART_LOW ? 1 : 0, (float)(gamma / ((double)n * n)),
+              out, 0, work, tmp, s);
+  if (mu != 0.0 && rho_other)
+    image_psf_conv(h, rho_other, h->part[1 - p].psf_hat, (float)(mu / ((double)nd * nd)), out, 1,
+                   work, tmp, s);
 }
 
 void composed_psf(imgr_s *h, int p, double gamma, double mu, float *out, hipStream_t s) {
@@ -155,20 +122,9 @@ void composed_psf(imgr_s *h, int p, double gamma, double mu, float *out, hipStre
 void exchange(imgr_s *h, const float *a, const float *b, float *rho_a, float *rho_b,
               hipStream_t s) {
   const int n = h->N;
-  const int64_t nn = (int64_t)n * n;
-  float2 *spec = h->grid_a, *work = h->grid_a + nn, *tmp = h->grid_b;
-  hipLaunchKernelGGL(k_pad_real, g1(nn), dim3(256), 0, s, b, a, n, spec, n);
-  fft2_plain(h, spec, tmp, n, -1, s);
-  const float inv = (float)(1.0 / (double)nn);
-  hipLaunchKernelGGL(k_gamma_mul, g1(nn), dim3(256), 0, s, work, spec, n, h->ell, h->delta, 1.0,
-                     0, inv);
-  fft2_plain(h, work, tmp, n, 1, s);
-  hipLaunchKernelGGL(k_crop_real, g1(nn), dim3(256), 0, s, work, n, 0, 0, n, 1.f, rho_a, 1);
-  hipLaunchKernelGGL(k_gamma_mul, g1(nn), dim3(256), 0, s, work, spec, n, h->ell, h->delta, 1.0,
-                     1, -inv);
-  fft2_plain(h, work, tmp, n, 1, s);
-  hipLaunchKernelGGL(k_crop_real, g1(nn), dim3(256), 0, s, work, n, 0, 0, n, 1.f, rho_b, 1);
-  IMGR_HIP(hipGetLastError());
+  const float inv = (float)(1.0 / ((double)n * n));
+  image_gamma(h, b, a, 0, inv, rho_a, 1, h->grid_a, h->grid_b, s);
+  image_gamma(h, a, b, 1, inv, rho_b, 1, h->grid_a, h->grid_b, s);
 }
 
 void combine_final(imgr_s *h, const float *a, const float *b, double wa, double wb, double *out,

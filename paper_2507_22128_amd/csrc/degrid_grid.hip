@@ -27,10 +27,27 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// phi(z) = exp(beta (sqrt(1 - z^2) - 1)) as exp2(beta log2(e) (sqrt(.) - 1))
-__device__ __forceinline__ float es_phi(float z, float bl2e) {
-  const float t = fmaxf(1.0f - z * z, 0.0f);
-  return __builtin_amdgcn_exp2f(bl2e * (__builtin_amdgcn_sqrtf(t) - 1.0f));
+#ifndef IMGR_WIN_WAVES
+#define IMGR_WIN_WAVES 4
+#endif
+// independent waves per workgroup (each owns one chunk and an LDS slice)
+constexpr int kWaves = IMGR_WIN_WAVES;
+
+// orders the LDS traffic of one wave around a point where its lanes
+// exchange data (no other wave shares the data)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// sum of v over the four lanes c16 + 16 g (g = 0..3) of a wave, the same
+// value in all four (row swaps: rows 0<->1, 2<->3, then halves)
+__device__ __forceinline__ float sum_rows(float v) {
+  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
 // slot of window column p in a row of the x-weight table: column 4s + q is
@@ -39,29 +56,47 @@ __device__ __forceinline__ float es_phi(float z, float bl2e) {
 __device__ __forceinline__ int xslot(int p) { return ((p & 3) << 2) | (p >> 2); }
 
 template <int W, int BLK, int MODE>
-__global__ __launch_bounds__(64) void k_window(
+__global__ __launch_bounds__(64 * kWaves) void k_window(
     const float4 *__restrict__ posvis, const float *__restrict__ wts,
     const int32_t *__restrict__ outpos, const int32_t *__restrict__ chunk_block,
-    const int32_t *__restrict__ chunk_begin, const int32_t *__restrict__ order, int nb, int ng,
-    float bl2e, const float2 *__restrict__ grid_in, const float2 *__restrict__ vis_in,
-    float2 *__restrict__ vis_out, float2 *__restrict__ scratch) {
+    const int32_t *__restrict__ chunk_begin, const int32_t *__restrict__ order, int n_chunks,
+    int nb, int ng, float bl2e, const float2 *__restrict__ grid_in,
+    const float2 *__restrict__ vis_in, float2 *__restrict__ vis_out,
+    float2 *__restrict__ scratch) {
   static_assert(BLK + W - 1 <= kWin, "footprints of a block must fit the window");
   constexpr int H = W / 2 - 1;
   constexpr int TPL = (W + 3) / 4;  // taps per lane and axis
-  constexpr float kInvHalf = 2.0f / W;
+  constexpr float kC = 2.0f / W;    // z = (t - H - f) * kC for tap t at fraction f
   constexpr bool kDegrid = (MODE == MODE_DEGRID_GRID || MODE == MODE_DEGRID);
   constexpr bool kGrid = (MODE != MODE_DEGRID);
   constexpr bool kCplx = (MODE != MODE_PSF);
-  // per batch: tap weights of the 16 visibilities over the 16 window
-  // positions (x in xslot order, y in natural order) and the residuals
-  __shared__ __attribute__((aligned(16))) float kx_t[16 * 16];
-  __shared__ __attribute__((aligned(16))) float ky_t[16 * 16];
-  __shared__ float2 r_t[16];
+  // per wave and batch: tap weights of the 16 visibilities over the 16
+  // window positions (x in xslot order, y in natural order), residuals
+  __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
+  __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
+  __shared__ float2 r_s[kWaves][16];
 
-  const int l = threadIdx.x, c16 = l & 15, g = l >> 4;
-  const int chunk = order[blockIdx.x];
+  const int wave = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, c16 = l & 15, g = l >> 4;
+  const int slot = blockIdx.x * kWaves + wave;
+  if (slot >= n_chunks) return;  // the wave has no chunk; no other wave waits for it
+  float *kx_t = kx_s[wave];
+  float *ky_t = ky_s[wave];
+  float2 *r_t = r_s[wave];
+  const int chunk = order[slot];
   const int blk = chunk_block[chunk];
   const int wx0 = (blk % nb) * BLK - H, wy0 = (blk / nb) * BLK - H;
+
+  // 1 - z^2 of this lane's taps as quadratics in the fraction f:
+  // alpha + beta f - kC^2 f^2 with a = t - H
+  float qa[TPL], qb[TPL];
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    const float a = (float)(g * TPL + q - H);
+    qa[q] = 1.0f - kC * kC * a * a;
+    qb[q] = 2.0f * kC * kC * a;
+  }
+  constexpr float qc = -kC * kC;
 
   // model window as the A operand of G kx: lane (c16, g) holds
   // G[y = c16][x = 4 s + g] for the K-steps s = 0..3
@@ -80,38 +115,40 @@ __global__ __launch_bounds__(64) void k_window(
 
   const int b = chunk_begin[chunk], e = chunk_begin[chunk + 1];
   // lane (c16, g) works on visibility c16 of each batch; the record of the
-  // next batch is loaded while the current one is processed
-  const float4 pv_pad = make_float4(0.5f, 0.5f, 0.f, 0.f);
-  float4 pv_next = (b + c16 < e) ? posvis[b + c16] : pv_pad;
+  // next batch is loaded while the current one is processed (indices past
+  // the chunk are clamped to its last visibility and masked by `valid`)
+  float4 pv_next = posvis[min(b + c16, e - 1)];
   float w_next = 0.f;
-  if constexpr (kGrid) w_next = (b + c16 < e) ? wts[b + c16] : 0.f;
+  if constexpr (kGrid) w_next = wts[min(b + c16, e - 1)];
   for (int base = b; base < e; base += 16) {
     const int v = base + c16;
     const bool valid = v < e;
     const float4 pv = pv_next;
-    const float w = w_next;
-    {
-      const int vn = v + 16;
-      pv_next = (vn < e) ? posvis[vn] : pv_pad;
-      if constexpr (kGrid) w_next = (vn < e) ? wts[vn] : 0.f;
-    }
+    const float w = valid ? w_next : 0.f;
+    pv_next = posvis[min(v + 16, e - 1)];
+    if constexpr (kGrid) w_next = wts[min(v + 16, e - 1)];
     const int ox = min(max((int)floorf(pv.x), 0), BLK - 1);
     const int oy = min(max((int)floorf(pv.y), 0), BLK - 1);
     const float fx = pv.x - (float)ox, fy = pv.y - (float)oy;
 
     // tap weights: clear this lane's quarter of the two table rows of its
-    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis
+    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis:
+    // phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1))
     *(floatx4 *)&kx_t[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
     *(floatx4 *)&ky_t[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < TPL; ++q) {
       const int t = g * TPL + q;
       if (t < W) {
-        kx_t[c16 * 16 + xslot(ox + t)] = es_phi(((float)(t - H) - fx) * kInvHalf, bl2e);
-        ky_t[c16 * 16 + oy + t] = es_phi(((float)(t - H) - fy) * kInvHalf, bl2e);
+        const float sx = fmaxf(fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]), 0.0f);
+        const float sy = fmaxf(fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]), 0.0f);
+        kx_t[c16 * 16 + xslot(ox + t)] =
+            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sx), -bl2e));
+        ky_t[c16 * 16 + oy + t] =
+            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sy), -bl2e));
       }
     }
-    __syncthreads();
+    wave_sync();
 
     float pr = 0.f, pi = 0.f;
     if constexpr (kDegrid) {
@@ -130,10 +167,8 @@ __global__ __launch_bounds__(64) void k_window(
         pr = fmaf(by[r], tre[r], pr);
         pi = fmaf(by[r], tim[r], pi);
       }
-      pr += __shfl_xor(pr, 16);
-      pi += __shfl_xor(pi, 16);
-      pr += __shfl_xor(pr, 32);
-      pi += __shfl_xor(pi, 32);
+      pr = sum_rows(pr);
+      pi = sum_rows(pi);
     }
     if constexpr (MODE == MODE_DEGRID) {
       if (valid && g == 0) vis_out[outpos[v]] = make_float2(pr, pi);
@@ -151,7 +186,7 @@ __global__ __launch_bounds__(64) void k_window(
         }
         r_t[c16] = r;
       }
-      __syncthreads();
+      wave_sync();
       // A[y][x] += sum_k (r_k ky_k[y]) kx_k[x]; K-step s covers k = 4 s + g
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -164,7 +199,7 @@ __global__ __launch_bounds__(64) void k_window(
           acc_im = __builtin_amdgcn_mfma_f32_16x16x4f32(rk.y * kyv, kxv, acc_im, 0, 0, 0);
       }
     }
-    __syncthreads();  // the tables are rewritten by the next batch
+    wave_sync();  // the tables are rewritten by the next batch
   }
 
   if constexpr (kGrid) {
@@ -217,11 +252,11 @@ template <int W, int BLK>
 void launch_window(imgr_s *h, const Bins &B, int mode, const float2 *grid_in,
                    const float2 *vis_in, float2 *vis_out, float2 *scratch, hipStream_t s) {
   const float bl2e = (float)(h->beta * 1.4426950408889634);
-  dim3 grid(B.n_chunks), block(64);
+  dim3 grid(cdiv(B.n_chunks, kWaves)), block(64 * kWaves);
 #define L_(M)                                                                                   \
   hipLaunchKernelGGL((k_window<W, BLK, M>), grid, block, 0, s, B.posvis, B.w, B.outpos,           \
-                     B.chunk_block, B.chunk_begin, B.order, B.nb, B.ng, bl2e, grid_in, vis_in,    \
-                     vis_out, scratch)
+                     B.chunk_block, B.chunk_begin, B.order, B.n_chunks, B.nb, B.ng, bl2e,         \
+                     grid_in, vis_in, vis_out, scratch)
   switch (mode) {
     case MODE_DEGRID_GRID: L_(MODE_DEGRID_GRID); break;
     case MODE_GRID: L_(MODE_GRID); break;

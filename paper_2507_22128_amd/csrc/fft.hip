@@ -71,9 +71,10 @@ __device__ __forceinline__ void dft(float2 *x) {
 }
 
 // One sequence of length L in padded LDS, NT threads, Stockham passes from
-// sub-length NS upward (radix 8 while possible, then 4 or 2).
+// sub-length NS upward (radix 8 while possible, then 4 or 2).  tw holds
+// w_L^m = exp(-2 pi i m / L), m < L (the row kernels stage it in LDS).
 template <int L, int NT, int NS, int DIR>
-__device__ __forceinline__ void stockham_seq(float2 *s, const float2 *__restrict__ tw, int t) {
+__device__ __forceinline__ void stockham_seq(float2 *s, const float2 *tw, int t) {
   if constexpr (NS < L) {
     constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
     constexpr int NB = L / R;
@@ -96,7 +97,7 @@ __device__ __forceinline__ void stockham_seq(float2 *s, const float2 *__restrict
         if constexpr (NS > 1) {
 #pragma unroll
           for (int r = 1; r < R; ++r)
-            x[q][r] = cmul(x[q][r], tw_get<DIR>(tw, r * k * (kTwMax / (NS * R))));
+            x[q][r] = cmul(x[q][r], tw_get<DIR>(tw, r * k * (L / (NS * R))));
         }
         dft<R, DIR>(x[q]);
         const int base = (j - k) * R + k;
@@ -150,6 +151,12 @@ __device__ __forceinline__ void stockham_cols(float2 *s, const float2 *__restric
   }
 }
 
+// stage w_L^m, m < L, from the kTwMax-entry table into LDS
+template <int L, int NT>
+__device__ __forceinline__ void stage_twiddles(float2 *twl, const float2 *__restrict__ tw) {
+  for (int m = threadIdx.x; m < L; m += NT) twl[m] = tw[m * (kTwMax / L)];
+}
+
 template <int L>
 struct RowThreads {
   static constexpr int v = (L / 8 < 64) ? 64 : ((L / 8 > 1024) ? 1024 : L / 8);
@@ -166,6 +173,8 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
     const float2 *__restrict__ tw) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
+  __shared__ float2 twl[L];
+  stage_twiddles<L, NT>(twl, tw);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
     s[padi(x)] = make_float2(v, 0.f);
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, -1>(s, tw, threadIdx.x);
+  stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
   for (int x = threadIdx.x; x < L; x += NT) rows[(size_t)r * L + x] = s[padi(x)];
 }
 
@@ -194,12 +203,14 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
     float *__restrict__ out, const float2 *__restrict__ tw) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
+  __shared__ float2 twl[L];
+  stage_twiddles<L, NT>(twl, tw);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
   for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = rows[(size_t)r * L + x];
   __syncthreads();
-  stockham_seq<L, NT, 1, 1>(s, tw, threadIdx.x);
+  stockham_seq<L, NT, 1, 1>(s, twl, threadIdx.x);
   const float cy = cinv[r] * scale;
   for (int ix = threadIdx.x; ix < n; ix += NT) {
     const int x = o + ix;
@@ -215,10 +226,12 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(float2 *__restr
                                                                  const float2 *__restrict__ tw) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
+  __shared__ float2 twl[L];
+  stage_twiddles<L, NT>(twl, tw);
   float2 *row = buf + (size_t)blockIdx.x * L;
   for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = row[x];
   __syncthreads();
-  stockham_seq<L, NT, 1, DIR>(s, tw, threadIdx.x);
+  stockham_seq<L, NT, 1, DIR>(s, twl, threadIdx.x);
   for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
 }
 
@@ -283,6 +296,140 @@ __global__ __launch_bounds__(256) void k_cols_p2(const float2 *__restrict__ src,
   }
 }
 
+// ---------------------------------------------------------------- image-domain filters
+// Products in the plain 2-D DFT domain of an image (Gamma filters of
+// Section 4.1 on the N x N grid; linear convolution by a 2N x 2N PSF on the
+// zero-padded 2N x 2N grid, Eq. 7): a real-input row pass, one column pass
+// that transforms, multiplies and transforms back with whole columns in LDS,
+// and a real-output row pass.
+
+// rows r < gridDim.x: (a - b) (n_in real values, zero padded to L) -> plain
+// forward row DFT -> out[r][0..L)
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
+    const float *__restrict__ a, const float *__restrict__ b, int n_in,
+    float2 *__restrict__ out, const float2 *__restrict__ tw) {
+  constexpr int NT = RowThreads<L>::v;
+  __shared__ float2 s[L + L / 32];
+  __shared__ float2 twl[L];
+  stage_twiddles<L, NT>(twl, tw);
+  const int r = blockIdx.x;
+  for (int x = threadIdx.x; x < L; x += NT) {
+    float v = 0.f;
+    if (x < n_in) {
+      v = a[(size_t)r * n_in + x];
+      if (b) v -= b[(size_t)r * n_in + x];
+    }
+    s[padi(x)] = make_float2(v, 0.f);
+  }
+  __syncthreads();
+  stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
+  for (int x = threadIdx.x; x < L; x += NT) out[(size_t)r * L + x] = s[padi(x)];
+}
+
+// rows r < gridDim.x: inverse plain row DFT of in[r][0..L), then
+// out[r][c] (+)= Re s[col0 + c] for c < n_out
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
+    const float2 *__restrict__ in, int col0, int n_out, float *__restrict__ out, int accumulate,
+    const float2 *__restrict__ tw) {
+  constexpr int NT = RowThreads<L>::v;
+  __shared__ float2 s[L + L / 32];
+  __shared__ float2 twl[L];
+  stage_twiddles<L, NT>(twl, tw);
+  const int r = blockIdx.x;
+  for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = in[(size_t)r * L + x];
+  __syncthreads();
+  stockham_seq<L, NT, 1, 1>(s, twl, threadIdx.x);
+  for (int c = threadIdx.x; c < n_out; c += NT) {
+    const float v = s[padi(col0 + c)].x;
+    float *o = out + (size_t)r * n_out + c;
+    *o = accumulate ? *o + v : v;
+  }
+}
+
+// Spectral product between a forward and an inverse column DFT, four-step
+// form (L = P * Q, blocks of 64 columns):
+//   forward pass 1 (k_cols_p1) leaves A[Q k1 + y2];
+//   mid (block (cb, k1)): X[k1 + P k2] = sum_y2 A[Q k1 + y2] w_Q^(y2 k2)
+//          (forward), times the spectral factor, then
+//          B[y2] = sum_k2 X[k1 + P k2] w_Q^(-y2 k2) w_L^(-y2 k1), stored back
+//          at row Q k1 + y2 (in place);
+//   fin (block (cb, y2)): x[y2 + Q y1] = sum_k1 B[Q k1 + y2] w_P^(-y1 k1),
+//          rows y in [k_lo, k_hi) stored at dst row y - k_lo.
+enum { FILT_GAMMA = 0, FILT_SPEC = 1 };
+
+// Gamma_L(kappa) = clip((ell + delta - kappa) / (2 delta), 0, 1) at the
+// plain-DFT frequency (kx, ky) of an nd-point grid, kappa = |k| / scale
+__device__ __forceinline__ float gamma_low_at(int kx, int ky, int nd, double ell, double delta,
+                                              double scale) {
+  const int fx = (kx < nd / 2) ? kx : kx - nd;
+  const int fy = (ky < nd / 2) ? ky : ky - nd;
+  const double kappa = sqrt((double)fx * fx + (double)fy * fy) / scale;
+  const double g = (ell + delta - kappa) / (2.0 * delta);
+  return (float)fmin(fmax(g, 0.0), 1.0);
+}
+
+template <int P, int Q, int MODE>
+__global__ __launch_bounds__(256) void k_cols_mid(float2 *__restrict__ buf,
+                                                  const float2 *__restrict__ spec, double ell,
+                                                  double delta, double gscale, int own_low,
+                                                  float coef, const float2 *__restrict__ tw) {
+  constexpr int L = P * Q;
+  __shared__ float2 s[Q * 64];
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * 64;
+  const int k1 = blockIdx.y;
+  for (int i = t; i < Q * 64; i += 256) {
+    const int y2 = i >> 6, c = i & 63;
+    s[i] = buf[(size_t)(Q * k1 + y2) * L + x0 + c];
+  }
+  __syncthreads();
+  stockham_cols<Q, 1, -1>(s, tw, t);
+  for (int i = t; i < Q * 64; i += 256) {
+    const int k2 = i >> 6, c = i & 63;
+    const int k = k1 + P * k2;
+    float2 v = s[i];
+    if constexpr (MODE == FILT_GAMMA) {
+      float g = gamma_low_at(x0 + c, k, L, ell, delta, gscale);
+      if (!own_low) g = 1.f - g;
+      v = cscale(v, g * coef);
+    } else {
+      v = cscale(cmul(v, spec[(size_t)k * L + x0 + c]), coef);
+    }
+    s[i] = v;
+  }
+  __syncthreads();
+  stockham_cols<Q, 1, 1>(s, tw, t);
+  for (int i = t; i < Q * 64; i += 256) {
+    const int y2 = i >> 6, c = i & 63;
+    const int m = (y2 * k1) & (L - 1);
+    buf[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], tw_get<1>(tw, m * (kTwMax / L)));
+  }
+}
+
+template <int P, int Q>
+__global__ __launch_bounds__(256) void k_cols_fin(const float2 *__restrict__ src,
+                                                  float2 *__restrict__ dst, int k_lo, int k_hi,
+                                                  const float2 *__restrict__ tw) {
+  constexpr int L = P * Q;
+  __shared__ float2 s[P * 64];
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * 64;
+  const int y2 = blockIdx.y;
+  for (int i = t; i < P * 64; i += 256) {
+    const int k1 = i >> 6, c = i & 63;
+    s[i] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+  }
+  __syncthreads();
+  stockham_cols<P, 1, 1>(s, tw, t);
+  for (int i = t; i < P * 64; i += 256) {
+    const int y1 = i >> 6, c = i & 63;
+    const int y = y2 + Q * y1;
+    if (y >= k_lo && y < k_hi) dst[(size_t)(y - k_lo) * L + x0 + c] = s[i];
+  }
+}
+
 template <int L>
 struct Split;
 template <> struct Split<64> { static constexpr int P = 8, Q = 8; };
@@ -333,6 +480,29 @@ void plain_t(imgr_s *h, float2 *buf, float2 *tmp, int dir, hipStream_t s) {
   }
 }
 
+template <int L>
+void filter_t(imgr_s *h, const float *a, const float *b, int n_in, int mode, const float2 *spec,
+              int own_low, double gscale, float coef, int k_lo, int k_hi, int col0, int n_out,
+              float *out, int accumulate, float2 *work, float2 *tmp, hipStream_t s) {
+  // n_in rows of n_in pixels in (zero padded to L x L), rows [k_lo, k_hi) x
+  // cols [col0, col0 + n_out) out; work: n_in x L, tmp: L x L
+  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  hipLaunchKernelGGL((k_rows_real_fwd<L>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b, n_in,
+                     work, h->tw);
+  hipLaunchKernelGGL((k_cols_p1<P, Q, -1>), dim3(L / 64, Q), dim3(256), 0, s, work, 0, 0, n_in,
+                     tmp, h->tw);
+  if (mode == FILT_GAMMA)
+    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_GAMMA>), dim3(L / 64, P), dim3(256), 0, s, tmp, spec,
+                       h->ell, h->delta, gscale, own_low, coef, h->tw);
+  else
+    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_SPEC>), dim3(L / 64, P), dim3(256), 0, s, tmp, spec,
+                       h->ell, h->delta, gscale, own_low, coef, h->tw);
+  hipLaunchKernelGGL((k_cols_fin<P, Q>), dim3(L / 64, Q), dim3(256), 0, s, tmp, work, k_lo, k_hi,
+                     h->tw);
+  hipLaunchKernelGGL((k_rows_inv_real<L>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s, work,
+                     col0, n_out, out, accumulate, h->tw);
+}
+
 }  // namespace
 
 #define IMGR_FFT_SIZES(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
@@ -354,6 +524,38 @@ void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, in
   switch (ng) {
 #define X(L) \
   case L: grid_to_image_t<L>(h, in, cinv, n, scale, rows, tmp, out, s); break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float coef, float *out,
+                 int accumulate, float2 *work, float2 *tmp, hipStream_t s) {
+  const int n = h->N;
+  switch (n) {
+#define X(L)                                                                                   \
+  case L:                                                                                      \
+    filter_t<L>(h, a, b, n, FILT_GAMMA, nullptr, own_low, 1.0, coef, 0, n, 0, n, out,          \
+                accumulate, work, tmp, s);                                                     \
+    break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef, float *out,
+                    int accumulate, float2 *work, float2 *tmp, hipStream_t s) {
+  const int n = h->N, nd = 2 * n;
+  switch (nd) {
+#define X(L)                                                                                   \
+  case L:                                                                                      \
+    filter_t<L>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, n, n, out,          \
+                accumulate, work, tmp, s);                                                     \
+    break;
     IMGR_FFT_SIZES(X)
 #undef X
     default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
