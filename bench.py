@@ -22,11 +22,27 @@ import time
 
 METRIC = "major-cycle Mvis/s (grid+degrid) at ≤1e-5 rel err, %HBM roofline; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, doubled by
-# packed FP32 instructions (published figure).  The library is built with
-# packed FP32 disabled, so its reachable ceiling is half of it.
-FP32_PEAK_PACKED = 157.3
-FP32_PEAK_UNPACKED = 78.6
+# MI355X published dense FP32 matrix peak (TFLOP/s).  The de/gridding
+# products run as FP32 MFMA; on gfx950 these issue through the same pipe as
+# vector FP32, so 157.3 is the ceiling of the whole kernel's arithmetic.
+FP32_PEAK_MATRIX = 157.3
+
+
+# HBM bytes per launch of the fused de/grid kernel on this workload, from the
+# FETCH_SIZE / WRITE_SIZE counter runs with the copy-kernel calibration
+# (profiles/k_window_decentral_hbm_traffic.md), valid only for the kernel
+# source the counters were taken on.
+KWINDOW_TRAFFIC = {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
+                   "sha256_16": "2db654782d2702a4",
+                   "bytes_per_launch": (98324.7 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)}
+
+
+def measured_traffic():
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), KWINDOW_TRAFFIC["src"])
+    with open(path, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return KWINDOW_TRAFFIC["bytes_per_launch"] if sha == KWINDOW_TRAFFIC["sha256_16"] else None
 
 
 def log(msg):
@@ -95,8 +111,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="decentral")
-    ap.add_argument("--cpu-sample-times", type=int, default=64)
+    ap.add_argument("--cpu-sample-times", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before the steps, run a plain device copy of this many MiB three "
+                         "times (a known-size kernel to scale hardware byte counters by)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -128,9 +147,21 @@ def main():
     wsum = [info.sum_w[0], info.sum_w[1]]
     gm = [(wsum[p] / (wsum[0] + wsum[1]), wsum[1 - p] / (wsum[0] + wsum[1])) for p in (0, 1)]
 
+    gammas, mus = [gm[0][0], gm[1][0]], [gm[0][1], gm[1][1]]
+
     def step():
-        for p in (0, 1):
-            h.major_cycle(p, model[p], rho[p], gm[p][0], gm[p][1], out=out[p], local_out=local[p])
+        # both nodes' major cycles, concurrent on the device
+        h.major_cycle_nodes(model, rho, gammas, mus, outs=out, local_outs=local)
+
+    if args.calibrate_copy_mb:
+        nb = args.calibrate_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x %d MiB device to device" % args.calibrate_copy_mb)
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -147,36 +178,48 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cycles, stage_ms = h.get_timing()
-    h.set_timing(False)
     per_step = sorted(a.elapsed_time(b) for a, b in ev)
     ms_per_step = 1e3 * wall / args.steps
     n_valid = info.n_valid
     value = n_valid / (ms_per_step / 1e3) / 1e6
     log("%d steps: %.3f ms/step, %.0f Mvis/s" % (args.steps, ms_per_step, value))
-    stage_avg = {k: v / cycles for k, v in stage_ms.items()}
-    log("per node-cycle stage ms: %s" % json.dumps({k: round(v, 4) for k, v in stage_avg.items()}))
+    stage_conc = {k: v / cycles for k, v in stage_ms.items()}
+    log("per node-cycle stage ms (nodes concurrent): %s"
+        % json.dumps({k: round(v, 4) for k, v in stage_conc.items()}))
+    # the same cycles one node at a time on one stream: each kernel's own
+    # launch duration (what a kernel trace reports), for the roofline
+    for _ in range(args.steps):
+        for p in (0, 1):
+            h.major_cycle(p, model[p], rho[p], gammas[p], mus[p], out=out[p], local_out=local[p])
+    cycles_s, stage_ms_s = h.get_timing()
+    h.set_timing(False)
+    stage_avg = {k: v / cycles_s for k, v in stage_ms_s.items()}
+    log("per node-cycle stage ms (one node at a time): %s"
+        % json.dumps({k: round(v, 4) for k, v in stage_avg.items()}))
 
-    # roofline of the dominant kernel: the fused de/grid chunk kernel (one
-    # launch per node-cycle); units averaged over the two partitions' launches
+    # roofline of the dominant kernel: the fused de/grid window kernel (one
+    # launch per node-cycle, timed by the handle's stage events on its
+    # stream in the one-node-at-a-time pass); units averaged over the two
+    # partitions' launches
     ng = info.n_grid
     wt = info.support
     m_avg = 0.5 * (info.n_vis[0] + info.n_vis[1])
     t_launch = stage_avg["degrid_grid"] / 1e3
     flops = flops_per_vis(wt) * m_avg
-    bytes_alg = 20.0 * m_avg + 16.0 * ng * ng
+    bytes_alg = 20.0 * m_avg
     achieved_tf = flops / t_launch / 1e12
     achieved_gbs = bytes_alg / t_launch / 1e9
     roofline = {
-        "bound": "alu",
+        "bound": "mfma",
         "achieved": round(achieved_tf, 3),
-        "peak": FP32_PEAK_UNPACKED,
+        "peak": FP32_PEAK_MATRIX,
         "unit": "TFLOP/s",
-        "frac": round(achieved_tf / FP32_PEAK_UNPACKED, 4),
-        "traffic": None,
-        "kernel": "k_chunk<32,%d,MODE_DEGRID_GRID> (fused degrid / residual / grid)" % wt,
+        "frac": round(achieved_tf / FP32_PEAK_MATRIX, 4),
+        "traffic": measured_traffic(),
+        "kernel": "k_window<%d,%d,MODE_DEGRID_GRID> (fused degrid / residual / grid)"
+                  % (wt, info.tile),
         "avg_launch_ms": round(stage_avg["degrid_grid"], 4),
         "flop_per_vis": flops_per_vis(wt),
-        "frac_of_packed_peak": round(achieved_tf / FP32_PEAK_PACKED, 4),
         "hbm_achieved_gbs": round(achieved_gbs, 1),
         "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
         "bytes_alg_per_launch": bytes_alg,
@@ -214,6 +257,7 @@ def main():
         "p99_ms": round(per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))], 4),
         "create_ms": round(info.create_ms, 1),
         "stage_ms_per_node_cycle": {k: round(v, 4) for k, v in stage_avg.items()},
+        "stage_ms_per_node_cycle_concurrent": {k: round(v, 4) for k, v in stage_conc.items()},
         "cycle_hbm_frac": round(cycle_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
     }

@@ -172,6 +172,21 @@ imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model,
                                float *residual_out, float *residual_local_out,
                                int32_t flags);
 
+/* The major cycles of all nodes at once (Section 4: the nodes of the
+ * decentralized framework work concurrently between exchanges).  Each
+ * array has one entry per partition (n_partitions entries); entry p has
+ * the meaning of the same argument of imager_major_cycle for part = p, and
+ * rho_other / residual_local_out may be NULL (all entries absent).  The
+ * nodes run concurrently on library-owned streams with their own work
+ * buffers, forked from and joined back into the handle's stream, so the
+ * call is ordered on that stream like any other.  Results equal those of
+ * imager_major_cycle for each node, bit for bit.  Output buffers of
+ * different nodes must not overlap. */
+imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
+                                     const float *const *rho_other, const double *gamma,
+                                     const double *mu, float *const *residual_out,
+                                     float *const *residual_local_out, int32_t flags);
+
 /* Composed PSF of Eq. 7, gamma Gamma_own H_own + mu Gamma_other H_other,
  * 2N x 2N float32 (device). */
 imgr_status imager_composed_psf(imgr_t h, int32_t part, double gamma, double mu,

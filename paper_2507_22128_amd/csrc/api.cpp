@@ -147,6 +147,69 @@ static void recycle_events(imgr_s *h) {
   h->ev_sets.clear();
 }
 
+// frees everything the handle holds (streams, events, device memory) and the handle
+static void release(imgr_s *h) {
+  for (int p = 0; p < 2; ++p)
+    if (h->node_stream[p]) (void)hipStreamSynchronize(h->node_stream[p]);
+  recycle_events(h);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  for (int p = 0; p < 2; ++p) {
+    if (h->ev_join[p]) (void)hipEventDestroy(h->ev_join[p]);
+    if (h->node_stream[p]) (void)hipStreamDestroy(h->node_stream[p]);
+  }
+  for (void *q : h->allocs) (void)hipFree(q);
+  delete h;
+}
+
+static void check_cycle_args(imgr_s *h, int part, const float *model, const float *rho_other,
+                             const float *residual_out, int flags) {
+  IMGR_CHECK(part >= 0 && part < h->n_parts, "partition index out of range");
+  IMGR_CHECK(model && residual_out, "null pointer");
+  IMGR_CHECK(!(flags & IMGR_DEGRID_COMPOSITE) || rho_other, "composite degrid needs rho_other");
+}
+
+// One node's major cycle (Eq. 2 then Eq. 7) enqueued on stream s with the
+// node's own work buffers; stage events are recorded on s when timing is on.
+static void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other,
+                       double gamma, double mu, float *residual_out, float *residual_local_out,
+                       int flags, hipStream_t s) {
+  const Partition &P = h->part[part];
+  Work &wk = h->work[part];
+  float *local = residual_local_out ? residual_local_out : wk.img;
+  std::vector<hipEvent_t> *ev = nullptr;
+  if (h->timing) {
+    h->ev_sets.emplace_back();
+    ev = &h->ev_sets.back();
+    for (int k = 0; k <= IMGR_N_STAGES; ++k) ev->push_back(take_event(h));
+  }
+  auto mark = [&](int k) {
+    if (ev) IMGR_HIP(hipEventRecord((*ev)[k], s));
+  };
+  mark(0);
+  // a1: model -> model grid
+  fft_model_to_grid(h, model, (flags & IMGR_DEGRID_COMPOSITE) ? rho_other : nullptr, h->cinv, h->N,
+                    h->Ng, wk.rows, wk.grid_b, wk.grid_a, s);
+  mark(1);
+  // a2 + a3: degrid, residual, grid (one pass per chunk), flush
+  degrid_grid(h, P.bins, MODE_DEGRID_GRID, wk.grid_a, nullptr, nullptr, wk.scratch, s);
+  mark(2);
+  flush_chunks(h, P.bins, wk.scratch, wk.grid_a, s);
+  mark(3);
+  // a4: residual grid -> residual image
+  fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), wk.rows,
+                    wk.grid_b, local, s);
+  mark(4);
+  // a6: pseudo-full-resolution composition
+  if (h->n_parts == 2) {
+    compose(h, part, local, rho_other, gamma, mu, residual_out, s);
+  } else if (residual_out != local) {
+    IMGR_HIP(hipMemcpyAsync(residual_out, local, (size_t)h->N * h->N * sizeof(float),
+                            hipMemcpyDeviceToDevice, s));
+  }
+  mark(5);
+}
+
 }  // namespace imgr
 
 using namespace imgr;
@@ -230,19 +293,27 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
       IMGR_HIP(hipMemcpy(h->tw, tw.data(), kTwMax * sizeof(float2), hipMemcpyHostToDevice));
     }
     const size_t ng2 = (size_t)h->Ng * h->Ng;
-    h->grid_a = (float2 *)dev_alloc(h, ng2 * sizeof(float2));
-    h->grid_b = (float2 *)dev_alloc(h, ng2 * sizeof(float2));
-    h->rows = (float2 *)dev_alloc(h, (size_t)h->N * h->Ng * sizeof(float2));
-    h->img_a = (float *)dev_alloc(h, (size_t)h->N * h->N * sizeof(float));
-    h->img_b = (float *)dev_alloc(h, (size_t)h->N * h->N * sizeof(float));
+    for (int p = 0; p < h->n_parts; ++p) {
+      Work &wk = h->work[p];
+      wk.grid_a = (float2 *)dev_alloc(h, ng2 * sizeof(float2));
+      wk.grid_b = (float2 *)dev_alloc(h, ng2 * sizeof(float2));
+      wk.rows = (float2 *)dev_alloc(h, (size_t)h->N * h->Ng * sizeof(float2));
+      wk.img = (float *)dev_alloc(h, (size_t)h->N * h->N * sizeof(float));
+    }
 
     prep_build(h, vis);
 
-    int max_chunks = 1;
-    for (int p = 0; p < h->n_parts; ++p)
-      max_chunks = std::max(max_chunks, h->part[p].bins.n_chunks);
-    h->scratch_elems = (size_t)max_chunks * kWin * kWin;
-    h->scratch = (float2 *)dev_alloc(h, h->scratch_elems * sizeof(float2));
+    for (int p = 0; p < h->n_parts; ++p) {
+      const size_t nc = (size_t)std::max(h->part[p].bins.n_chunks, 1);
+      h->work[p].scratch = (float2 *)dev_alloc(h, nc * kWin * kWin * sizeof(float2));
+    }
+    if (h->n_parts == 2) {
+      IMGR_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      for (int p = 0; p < 2; ++p) {
+        IMGR_HIP(hipStreamCreateWithFlags(&h->node_stream[p], hipStreamNonBlocking));
+        IMGR_HIP(hipEventCreateWithFlags(&h->ev_join[p], hipEventDisableTiming));
+      }
+    }
     for (int p = 0; p < h->n_parts; ++p) {
       IMGR_CHECK(h->part[p].bins.n > 0, "a partition is empty (check ell / delta)");
       build_psf(h, p);
@@ -250,14 +321,12 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
     IMGR_HIP(hipStreamSynchronize(h->stream));
   } catch (const Error &e) {
     g_create_error = e.msg;
-    for (void *p : h->allocs) (void)hipFree(p);
+    release(h);
     (void)hipGetLastError();
-    delete h;
     return e.code;
   } catch (const std::exception &e) {
     g_create_error = e.what();
-    for (void *p : h->allocs) (void)hipFree(p);
-    delete h;
+    release(h);
     return IMGR_EINVAL;
   }
   h->create_ms =
@@ -269,10 +338,7 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
 imgr_status imager_destroy(imgr_t h) {
   if (!h) return IMGR_EINVAL;
   (void)hipStreamSynchronize(h->stream);
-  recycle_events(h);
-  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  for (void *p : h->allocs) (void)hipFree(p);
-  delete h;
+  release(h);
   return IMGR_OK;
 }
 
@@ -335,8 +401,9 @@ imgr_status imager_degrid(imgr_t h, int32_t part, const float *model, void *vis_
   check_part(h, part);
   IMGR_CHECK(model && vis_out, "null pointer");
   hipStream_t s = h->stream;
-  fft_model_to_grid(h, model, nullptr, h->cinv, h->N, h->Ng, h->rows, h->grid_b, h->grid_a, s);
-  degrid_grid(h, h->part[part].bins, MODE_DEGRID, h->grid_a, nullptr, (float2 *)vis_out, nullptr,
+  Work &wk = h->work[part];
+  fft_model_to_grid(h, model, nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b, wk.grid_a, s);
+  degrid_grid(h, h->part[part].bins, MODE_DEGRID, wk.grid_a, nullptr, (float2 *)vis_out, nullptr,
               s);
   API_END(h)
 }
@@ -349,10 +416,11 @@ imgr_status imager_grid(imgr_t h, int32_t part, const void *vis_in, float *image
   IMGR_CHECK(mode == IMGR_GRID_DIRTY || mode == IMGR_GRID_UNNORMALIZED, "mode");
   hipStream_t s = h->stream;
   const Bins &B = h->part[part].bins;
-  degrid_grid(h, B, MODE_GRID, nullptr, (const float2 *)vis_in, nullptr, h->scratch, s);
-  flush_chunks(h, B, h->scratch, h->grid_a, s);
+  Work &wk = h->work[part];
+  degrid_grid(h, B, MODE_GRID, nullptr, (const float2 *)vis_in, nullptr, wk.scratch, s);
+  flush_chunks(h, B, wk.scratch, wk.grid_a, s);
   const float scale = mode == IMGR_GRID_DIRTY ? (float)(1.0 / h->part[part].sum_w) : 1.f;
-  fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, scale, h->rows, h->grid_b, image_out, s);
+  fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, scale, wk.rows, wk.grid_b, image_out, s);
   API_END(h)
 }
 
@@ -370,43 +438,35 @@ imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model, const
                                double gamma, double mu, float *residual_out,
                                float *residual_local_out, int32_t flags) {
   API_BEGIN(h)
-  check_part(h, part);
-  IMGR_CHECK(model && residual_out, "null pointer");
-  IMGR_CHECK(!(flags & IMGR_DEGRID_COMPOSITE) || rho_other, "composite degrid needs rho_other");
-  hipStream_t s = h->stream;
-  const Partition &P = h->part[part];
-  float *local = residual_local_out ? residual_local_out : h->img_a;
-  std::vector<hipEvent_t> *ev = nullptr;
-  if (h->timing) {
-    h->ev_sets.emplace_back();
-    ev = &h->ev_sets.back();
-    for (int k = 0; k <= IMGR_N_STAGES; ++k) ev->push_back(take_event(h));
+  check_cycle_args(h, part, model, rho_other, residual_out, flags);
+  node_cycle(h, part, model, rho_other, gamma, mu, residual_out, residual_local_out, flags,
+             h->stream);
+  API_END(h)
+}
+
+imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
+                                     const float *const *rho_other, const double *gamma,
+                                     const double *mu, float *const *residual_out,
+                                     float *const *residual_local_out, int32_t flags) {
+  API_BEGIN(h)
+  IMGR_CHECK(model && gamma && mu && residual_out, "null pointer");
+  for (int p = 0; p < h->n_parts; ++p)
+    check_cycle_args(h, p, model[p], rho_other ? rho_other[p] : nullptr, residual_out[p], flags);
+  auto ro = [&](int p) { return rho_other ? rho_other[p] : nullptr; };
+  auto lo = [&](int p) { return residual_local_out ? residual_local_out[p] : nullptr; };
+  if (h->n_parts == 1) {
+    node_cycle(h, 0, model[0], ro(0), gamma[0], mu[0], residual_out[0], lo(0), flags, h->stream);
+  } else {
+    // fork both nodes off the caller's stream, join them back into it
+    IMGR_HIP(hipEventRecord(h->ev_fork, h->stream));
+    for (int p = 0; p < 2; ++p) {
+      IMGR_HIP(hipStreamWaitEvent(h->node_stream[p], h->ev_fork, 0));
+      node_cycle(h, p, model[p], ro(p), gamma[p], mu[p], residual_out[p], lo(p), flags,
+                 h->node_stream[p]);
+      IMGR_HIP(hipEventRecord(h->ev_join[p], h->node_stream[p]));
+    }
+    for (int p = 0; p < 2; ++p) IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[p], 0));
   }
-  auto mark = [&](int k) {
-    if (ev) IMGR_HIP(hipEventRecord((*ev)[k], s));
-  };
-  mark(0);
-  // a1: model -> model grid
-  fft_model_to_grid(h, model, (flags & IMGR_DEGRID_COMPOSITE) ? rho_other : nullptr, h->cinv, h->N,
-                    h->Ng, h->rows, h->grid_b, h->grid_a, s);
-  mark(1);
-  // a2 + a3: degrid, residual, grid (one pass per chunk), flush
-  degrid_grid(h, P.bins, MODE_DEGRID_GRID, h->grid_a, nullptr, nullptr, h->scratch, s);
-  mark(2);
-  flush_chunks(h, P.bins, h->scratch, h->grid_a, s);
-  mark(3);
-  // a4: residual grid -> residual image
-  fft_grid_to_image(h, h->grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), h->rows,
-                    h->grid_b, local, s);
-  mark(4);
-  // a6: pseudo-full-resolution composition
-  if (h->n_parts == 2) {
-    compose(h, part, local, rho_other, gamma, mu, residual_out, s);
-  } else if (residual_out != local) {
-    IMGR_HIP(hipMemcpyAsync(residual_out, local, (size_t)h->N * h->N * sizeof(float),
-                            hipMemcpyDeviceToDevice, s));
-  }
-  mark(5);
   API_END(h)
 }
 

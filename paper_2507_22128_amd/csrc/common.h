@@ -46,6 +46,15 @@ struct Bins {
   int32_t *order = nullptr;        // [n_chunks] launch order: largest chunk first
 };
 
+// work buffers of one node's major cycle
+struct Work {
+  float2 *grid_a = nullptr;   // Ng^2 (model grid, residual grid)
+  float2 *grid_b = nullptr;   // Ng^2 (transform scratch)
+  float2 *rows = nullptr;     // N x Ng (row-pass intermediate)
+  float2 *scratch = nullptr;  // [n_chunks][16][16] chunk windows
+  float *img = nullptr;       // N^2 (node-local residual)
+};
+
 struct Partition {
   double sum_w = 0.0;
   Bins bins;                   // on the Ng grid (major cycle, degrid, grid)
@@ -68,14 +77,12 @@ struct imgr_s {
   float *cinv = nullptr;       // [N]  1 / psi_hat, N image on the Ng grid
   float *cinv2 = nullptr;      // [2N] 1 / psi_hat, 2N image on the 2 Ng grid
   float2 *tw = nullptr;        // [kTwMax]
-  // work buffers
-  float2 *grid_a = nullptr;    // Ng^2
-  float2 *grid_b = nullptr;    // Ng^2
-  float2 *rows = nullptr;      // N x Ng (row-pass intermediate)
-  float2 *scratch = nullptr;   // 16 x 16 chunk windows
-  size_t scratch_elems = 0;
-  float *img_a = nullptr;      // N^2 f32
-  float *img_b = nullptr;      // N^2 f32
+  // per-node work buffers and streams: the two nodes' major cycles may run
+  // concurrently (imager_major_cycle_nodes)
+  imgr::Work work[2];
+  hipStream_t node_stream[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[2] = {nullptr, nullptr};
   // stage timing (imager_set_timing): one set of events per recorded cycle
   bool timing = false;
   std::vector<std::vector<hipEvent_t>> ev_sets;

@@ -88,7 +88,7 @@ void psf_spectrum(imgr_s *h, int p, hipStream_t s) {
   hipLaunchKernelGGL(k_pad_real, g1((int64_t)nd * nd), dim3(256), 0, s, P.psf, nullptr, nd,
                      P.psf_hat, nd);
   IMGR_HIP(hipGetLastError());
-  fft2_plain(h, P.psf_hat, h->grid_b, nd, -1, s);
+  fft2_plain(h, P.psf_hat, h->work[p].grid_b, nd, -1, s);
 }
 
 // Eq. 7: out = gamma Gamma_own resid + mu H_other rho_other
@@ -96,7 +96,7 @@ void compose(imgr_s *h, int p, const float *resid, const float *rho_other, doubl
              double mu, float *out, hipStream_t s) {
   const int n = h->N, nd = 2 * n;
   // both grids are free once the residual image is out
-  float2 *work = h->grid_a, *tmp = h->grid_b;
+  float2 *work = h->work[p].grid_a, *tmp = h->work[p].grid_b;
   image_gamma(h, resid, nullptr, p == IMGR_PART_LOW ? 1 : 0, (float)(gamma / ((double)n * n)),
               out, 0, work, tmp, s);
   if (mu != 0.0 && rho_other)
@@ -108,7 +108,7 @@ void composed_psf(imgr_s *h, int p, double gamma, double mu, float *out, hipStre
   const int nd = 2 * h->N;
   const Partition &P = h->part[p];
   const float2 *other = (h->n_parts == 2 && mu != 0.0) ? h->part[1 - p].psf_hat : nullptr;
-  float2 *buf = h->grid_a, *tmp = h->grid_b;
+  float2 *buf = h->work[p].grid_a, *tmp = h->work[p].grid_b;
   hipLaunchKernelGGL(k_spec_combine, g1((int64_t)nd * nd), dim3(256), 0, s, buf, P.psf_hat, other,
                      nd, h->ell, h->delta, 2.0, p == IMGR_PART_LOW ? 1 : 0, (float)gamma,
                      (float)mu, (float)(1.0 / ((double)nd * nd)));
@@ -123,8 +123,8 @@ void exchange(imgr_s *h, const float *a, const float *b, float *rho_a, float *rh
               hipStream_t s) {
   const int n = h->N;
   const float inv = (float)(1.0 / ((double)n * n));
-  image_gamma(h, b, a, 0, inv, rho_a, 1, h->grid_a, h->grid_b, s);
-  image_gamma(h, a, b, 1, inv, rho_b, 1, h->grid_a, h->grid_b, s);
+  image_gamma(h, b, a, 0, inv, rho_a, 1, h->work[0].grid_a, h->work[0].grid_b, s);
+  image_gamma(h, a, b, 1, inv, rho_b, 1, h->work[0].grid_a, h->work[0].grid_b, s);
 }
 
 void combine_final(imgr_s *h, const float *a, const float *b, double wa, double wb, double *out,

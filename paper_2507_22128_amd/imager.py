@@ -72,6 +72,7 @@ _SIGS = {
     "imager_grid": [_P, _I, _P, _P, _I],
     "imager_psf": [_P, _I, _P],
     "imager_major_cycle": [_P, _I, _P, _P, _D, _D, _P, _P, _I],
+    "imager_major_cycle_nodes": [_P, _P, _P, _P, _P, _P, _P, _I],
     "imager_composed_psf": [_P, _I, _D, _D, _P],
     "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P],
     "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P],
@@ -277,6 +278,28 @@ class Imager:
             self._h, part, _ptr(model), _ptr(rho_other), float(gamma), float(mu), _ptr(out),
             _ptr(local_out), DEGRID_COMPOSITE if composite else 0))
         return out
+
+    def major_cycle_nodes(self, models, rho_others=None, gammas=None, mus=None, composite=False,
+                          outs=None, local_outs=None):
+        """All nodes' major cycles at once (concurrent on the device); lists
+        with one entry per partition.  Returns the list of outputs."""
+        import torch
+        n, k = self.n_pix, self.info.n_partitions
+        for m in models:
+            _dev_f32(m, (n, n), torch)
+        outs = [self._empty((n, n), "float32") for _ in range(k)] if outs is None else outs
+        gammas = [1.0] * k if gammas is None else gammas
+        mus = [0.0] * k if mus is None else mus
+        arr = lambda ts: (ctypes.c_void_p * k)(*[None if t is None else t.data_ptr() for t in ts])
+        dbl = lambda xs: (ctypes.c_double * k)(*[float(x) for x in xs])
+        if rho_others is not None:
+            for r in rho_others:
+                _dev_f32(r, (n, n), torch)
+        self._check(lib().imager_major_cycle_nodes(
+            self._h, arr(models), None if rho_others is None else arr(rho_others), dbl(gammas),
+            dbl(mus), arr(outs), None if local_outs is None else arr(local_outs),
+            DEGRID_COMPOSITE if composite else 0))
+        return outs
 
     def composed_psf(self, part, gamma, mu, out=None):
         n2 = 2 * self.n_pix

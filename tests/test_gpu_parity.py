@@ -214,6 +214,23 @@ def test_partition_residuals_psfs_and_composition(medium):
     assert rel(out1, ref1) < TOL
 
 
+def test_concurrent_nodes_equal_single_calls(medium):
+    """Both nodes' cycles on their own streams give each node's result bit
+    for bit, and twice in a row (work buffers are per node)."""
+    import torch
+    d, h = medium
+    n = d["n_img"]
+    rng = np.random.default_rng(9)
+    models = [to_dev(random_model(n, rng)) for _ in range(2)]
+    rhos = [to_dev(0.01 * random_model(n, rng)) for _ in range(2)]
+    gam, mus = [0.6, 0.4], [0.4, 0.6]
+    single = [h.major_cycle(p, models[p], rhos[p], gam[p], mus[p]) for p in (0, 1)]
+    for _ in range(2):
+        both = h.major_cycle_nodes(models, rhos, gam, mus)
+        for p in (0, 1):
+            assert torch.equal(both[p], single[p]), "node %d differs" % p
+
+
 def test_composite_degrid(medium):
     d, h = medium
     n = d["n_img"]
