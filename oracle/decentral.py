@@ -109,3 +109,66 @@ def combine(images, weights=None):
     for w, im in zip(weights, images):
         out = out + w * np.asarray(im, np.float64)
     return out
+
+
+def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, niter=2000,
+                        threshold=0.0, partitions=2, ell=None, delta=1.0, support=8):
+    """The major/minor loop with multi-scale CLEAN, serial (partitions = 1)
+    or decentralized over V_L / V_H (partitions = 2), in FP64.
+
+    Per major cycle n and node (Section 4.2):
+      i~     = residual of the node's own model on its own visibilities (Eq. 2)
+      D, P   = gamma Gamma_own i~ + mu H_other rho_other,
+               gamma Gamma_own H_own + mu Gamma_other H_other           (Eq. 7)
+      ibar   = ms-CLEAN(D, P, psi^n, K), psi^1 the node's own scales    (Eq. 7)
+      model += ibar                                                     (Eq. 3)
+    then the nodes exchange Phi = Gamma_own ibar and update rho (Section
+    4.1); the final image is the equal-weight average (Section 5.2).
+    Serially the loop is Eq. 2 -> ms-CLEAN(i~, H, S, K) -> Eq. 3.
+
+    Returns (final image, per-node models, history) with history a list of
+    per-cycle dicts {node: (dirty D, psf P, components)}.
+    """
+    from . import imaging, msclean as msc
+    m = len(u)
+    if partitions == 1:
+        masks = {"L": np.ones(m, bool)}
+        nodes = ("L",)
+    else:
+        low, high, ell = imaging.partition(u, v, n_img, cell, ell=ell, delta=delta)
+        masks = {"L": low, "H": high}
+        nodes = ("L", "H")
+    other = {"L": "H", "H": "L"}
+    psf = {k: imaging.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support)
+           for k, mk in masks.items()}
+    wsum = {k: w[mk].sum() for k, mk in masks.items()}
+    models = {k: np.zeros((n_img, n_img)) for k in nodes}
+    rho = {k: np.zeros((n_img, n_img)) for k in nodes}   # rho_other held by node k
+    history = []
+    for cyc in range(1, n_cycles + 1):
+        step, deltas = {}, {}
+        for k in nodes:
+            mk = masks[k]
+            resid, _ = imaging.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
+                                              support=support)
+            if partitions == 1:
+                d_img, p_img, active = resid, psf[k], None
+            else:
+                gamma, mu = weights_schedule(cyc, wsum[k], wsum[other[k]])
+                d_img = compose_dirty(resid, rho[k], psf[other[k]], ell, delta, k, gamma, mu)
+                p_img = compose_psf(psf[k], psf[other[k]], ell, delta, k, gamma, mu)
+                active = msc.scale_subset(scales, n_img, ell, delta, k) if cyc == 1 else None
+            ibar, _, comps = msc.msclean(d_img, p_img, scales, gain, niter, threshold, active)
+            deltas[k] = ibar
+            step[k] = (d_img, p_img, comps)
+        for k in nodes:
+            models[k] = models[k] + deltas[k]
+        if partitions == 2:
+            new_rho = {}
+            for k in nodes:
+                phi_recv = exchange(deltas[other[k]], ell, delta, other[k])
+                new_rho[k] = update_rho(rho[k], phi_recv, deltas[k], ell, delta, k)
+            rho = new_rho
+        history.append(step)
+    final = combine([models[k] for k in nodes])
+    return final, models, history
