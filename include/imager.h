@@ -192,11 +192,79 @@ imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
 imgr_status imager_composed_psf(imgr_t h, int32_t part, double gamma, double mu,
                                 float *psf_out);
 
-/* Multi-scale CLEAN minor cycle (Eq. 6 and Eq. 7).  Not available in this
- * version: returns IMGR_ENOTIMPL. */
-imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t part, const void *params,
-                                       const float *dirty, const float *psf,
-                                       float *model_delta);
+/* Multi-scale CLEAN minor cycle (Eq. 6; Eq. 7 for a node of the
+ * decentralized loop), after Cornwell's multi-scale CLEAN as the paper uses
+ * it.  Scale functions phi_s: a unit impulse for s = 0, else the truncated
+ * paraboloid 1 - (r/s)^2 on r < s normalised to unit sum.  With R_s =
+ * phi_s * dirty and B_ab = phi_a * phi_b * psf (linear convolutions, zero
+ * outside the image), each of at most max_iter iterations
+ *   - stops if max |R_0| < threshold (R_0 the unsmoothed residual),
+ *   - picks (s*, p*) = argmax of bias_s |R_s(p)| over the selectable scales,
+ *     bias_s = 1 - bias_slope s / max(S); ties go to the smaller scale
+ *     index, then the smaller flat pixel index iy N + ix,
+ *   - takes alpha = gain R_{s*}(p*) / B_{s*s*}(0), adds alpha phi_{s*}
+ *     centred at p* to the model, and subtracts alpha B_{s*t} shifted to p*
+ *     from every R_t.
+ * Everything that decides a peak is evaluated in FP64 on the device.
+ * dirty: device N x N float32 (e.g. the composed residual of
+ * imager_major_cycle); psf: device 2N x 2N float32 centred at (N, N)
+ * (e.g. imager_composed_psf).  Outputs (device float32 N x N, each may be
+ * NULL): model_delta = the deconvolved residual ibar of Eqs. 6 / 7;
+ * model_accum += model_delta (the update of Eq. 3); residual_out = R_0
+ * after the last component.  comps (device, max_iter entries, or NULL)
+ * receives the components in order; *n_comps (host) their number.
+ * The call keeps an FP64 work area per node in the handle (grown on
+ * demand) and synchronises the handle's stream before it returns. */
+#define IMGR_MAX_SCALES 8
+typedef struct {
+  int32_t n_scales;                /* |S|, 1 .. IMGR_MAX_SCALES */
+  double scales[IMGR_MAX_SCALES];  /* scale radii in pixels, >= 0 (0: point) */
+  uint32_t active_mask;            /* bit i: scale i selectable (psi^n); 0 = all */
+  double gain;                     /* loop gain in (0, 1] */
+  int32_t max_iter;                /* K >= 0 */
+  double threshold;                /* absolute threshold on max |R_0| */
+  double bias_slope;               /* small-scale bias slope, e.g. 0.6 */
+  int32_t own_scales_only;         /* 1: further restrict to the scales present in
+                                      the node's own domain (psi^1 of Eq. 7, reading:
+                                      V_L: s >= N / (2 (ell + delta)), V_H:
+                                      s <= N / (ell - delta), else the nearest) */
+} imgr_msclean_params;
+
+typedef struct {
+  int32_t scale;                   /* index into imgr_msclean_params.scales */
+  int32_t iy, ix;                  /* pixel of the component's centre */
+  int32_t reserved;
+  double amp;                      /* flux: the model gets amp * phi_scale there */
+} imgr_component;
+
+imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t part, const imgr_msclean_params *params,
+                                       const float *dirty, const float *psf, float *model_delta,
+                                       float *model_accum, float *residual_out,
+                                       imgr_component *comps, int32_t *n_comps);
+
+/* The whole major/minor loop with multi-scale CLEAN (Section 4.2): for
+ * cycle n = 1 .. n_cycles and every node k, concurrently,
+ *   i~ = residual of model[k] on the node's visibilities            (Eq. 2)
+ *   D, P = the composed dirty image and PSF with the other node's
+ *          rho[k] and PSF, gamma = 1, mu = 0 at n = 1, else the
+ *          partitions' shares of the summed imaging weights (reading) (Eq. 7)
+ *   ibar = ms-CLEAN(D, P, psi^n, K), psi^1 = the node's own scales
+ *   model[k] += ibar                                                 (Eq. 3)
+ * then the exchange rho[0] += Gamma_H (ibar_H - ibar_L), rho[1] +=
+ * Gamma_L (ibar_L - ibar_H) (Section 4.1), and finally final_image =
+ * 0.5 model[0] + 0.5 model[1] in FP64 (Section 5.2).  With one partition
+ * the loop is Eq. 2 -> ms-CLEAN(i~, H, S, K) -> Eq. 3 and final_image =
+ * model[0].  model[k], rho[k]: device N x N float32, read and updated in
+ * place (start from zeros for a fresh reconstruction; rho may be NULL with
+ * one partition); final_image: device N x N float64.  n_comps (host,
+ * n_cycles x n_partitions, row-major, or NULL) receives the components
+ * taken per cycle and node.  params->active_mask limits every cycle's
+ * scales; own_scales_only is ignored (psi is applied as above).
+ * Synchronises the handle's stream before returning. */
+imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
+                                       const imgr_msclean_params *params, float *const *model,
+                                       float *const *rho, double *final_image,
+                                       int32_t *n_comps);
 
 /* FISTA minor cycle for Eqs. 4 and 5.  Not available in this version:
  * returns IMGR_ENOTIMPL. */

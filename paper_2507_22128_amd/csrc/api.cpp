@@ -149,6 +149,7 @@ static void recycle_events(imgr_s *h) {
 
 // frees everything the handle holds (streams, events, device memory) and the handle
 static void release(imgr_s *h) {
+  (void)hipStreamSynchronize(h->stream);
   for (int p = 0; p < 2; ++p)
     if (h->node_stream[p]) (void)hipStreamSynchronize(h->node_stream[p]);
   recycle_events(h);
@@ -161,6 +162,7 @@ static void release(imgr_s *h) {
   for (void *q : h->allocs) (void)hipFree(q);
   delete h;
 }
+
 
 static void check_cycle_args(imgr_s *h, int part, const float *model, const float *rho_other,
                              const float *residual_out, int flags) {
@@ -484,11 +486,98 @@ imgr_status imager_composed_psf(imgr_t h, int32_t part, double gamma, double mu,
   API_END(h)
 }
 
-imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t, const void *, const float *,
-                                       const float *, float *) {
-  if (!h) return IMGR_EINVAL;
-  h->err = "minor_cycle_msclean is not available in this version";
-  return IMGR_ENOTIMPL;
+imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t part, const imgr_msclean_params *params,
+                                       const float *dirty, const float *psf, float *model_delta,
+                                       float *model_accum, float *residual_out,
+                                       imgr_component *comps, int32_t *n_comps) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(params && dirty && psf && n_comps, "null pointer");
+  const imgr_msclean_params &p = *params;
+  IMGR_CHECK(p.n_scales >= 1 && p.n_scales <= IMGR_MAX_SCALES, "n_scales must be in [1, 8]");
+  for (int i = 0; i < p.n_scales; ++i)
+    IMGR_CHECK(p.scales[i] >= 0.0 && p.scales[i] <= 64.0 && std::isfinite(p.scales[i]),
+               "scales must be in [0, 64] pixels");
+  IMGR_CHECK(p.gain > 0.0 && p.gain <= 1.0, "gain must be in (0, 1]");
+  IMGR_CHECK(p.max_iter >= 0, "max_iter must be >= 0");
+  IMGR_CHECK(std::isfinite(p.threshold) && std::isfinite(p.bias_slope), "threshold / bias");
+  IMGR_CHECK(p.active_mask == 0u || (p.active_mask & ((1u << p.n_scales) - 1u)) != 0u,
+             "active_mask selects no scale");
+  imgr_msclean_params q = p;
+  if (p.own_scales_only) q.active_mask = (p.active_mask ? p.active_mask : ~0u) &
+                                         msclean_own_scales(h, part, p);
+  msclean_enqueue(h, part, q, dirty, psf, model_delta, model_accum, residual_out, comps,
+                  h->stream);
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  *n_comps = msclean_count(h, part);
+  API_END(h)
+}
+
+imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
+                                       const imgr_msclean_params *params, float *const *model,
+                                       float *const *rho, double *final_image,
+                                       int32_t *n_comps) {
+  API_BEGIN(h)
+  IMGR_CHECK(params && model && final_image, "null pointer");
+  IMGR_CHECK(n_cycles >= 1, "n_cycles must be >= 1");
+  IMGR_CHECK(h->n_parts == 1 || rho, "rho is required with two partitions");
+  const imgr_msclean_params &p = *params;
+  IMGR_CHECK(p.n_scales >= 1 && p.n_scales <= IMGR_MAX_SCALES, "n_scales must be in [1, 8]");
+  IMGR_CHECK(p.gain > 0.0 && p.gain <= 1.0 && p.max_iter >= 0, "gain / max_iter");
+  for (int k = 0; k < h->n_parts; ++k) IMGR_CHECK(model[k] && (!rho || rho[k]), "null pointer");
+  const int n = h->N;
+  const size_t nn = (size_t)n * n;
+  for (int k = 0; k < h->n_parts; ++k) {
+    if (!h->loop_dirty[k]) {
+      h->loop_dirty[k] = (float *)dev_alloc(h, nn * sizeof(float));
+      h->loop_psf[k] = (float *)dev_alloc(h, 4 * nn * sizeof(float));
+      h->loop_delta[k] = (float *)dev_alloc(h, nn * sizeof(float));
+    }
+  }
+  const double wsum = h->part[0].sum_w + (h->n_parts == 2 ? h->part[1].sum_w : 0.0);
+  for (int cyc = 1; cyc <= n_cycles; ++cyc) {
+    if (h->n_parts == 1) {
+      hipStream_t s = h->stream;
+      node_cycle(h, 0, model[0], nullptr, 1.0, 0.0, h->loop_dirty[0], nullptr, 0, s);
+      IMGR_HIP(hipMemcpyAsync(h->loop_psf[0], h->part[0].psf, 4 * nn * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+      msclean_enqueue(h, 0, p, h->loop_dirty[0], h->loop_psf[0], h->loop_delta[0], model[0],
+                      nullptr, nullptr, s);
+    } else {
+      IMGR_HIP(hipEventRecord(h->ev_fork, h->stream));
+      for (int k = 0; k < 2; ++k) {
+        hipStream_t s = h->node_stream[k];
+        IMGR_HIP(hipStreamWaitEvent(s, h->ev_fork, 0));
+        // Eq. 7 weights (reading): gamma = 1, mu = 0 at the first cycle,
+        // then the partitions' shares of the summed imaging weights
+        const double gamma = (cyc == 1) ? 1.0 : h->part[k].sum_w / wsum;
+        const double mu = (cyc == 1) ? 0.0 : h->part[1 - k].sum_w / wsum;
+        node_cycle(h, k, model[k], rho[k], gamma, mu, h->loop_dirty[k], nullptr, 0, s);
+        composed_psf(h, k, gamma, mu, h->loop_psf[k], s);
+        imgr_msclean_params q = p;
+        if (cyc == 1) q.active_mask = (p.active_mask ? p.active_mask : ~0u) &
+                                      msclean_own_scales(h, k, p);
+        msclean_enqueue(h, k, q, h->loop_dirty[k], h->loop_psf[k], h->loop_delta[k], model[k],
+                        nullptr, nullptr, s);
+        IMGR_HIP(hipEventRecord(h->ev_join[k], s));
+      }
+      for (int k = 0; k < 2; ++k) IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[k], 0));
+      // Phi / rho exchange (Section 4.1): rho_H at node L, rho_L at node H
+      exchange(h, h->loop_delta[0], h->loop_delta[1], rho[0], rho[1], h->stream);
+    }
+    if (n_comps) {
+      IMGR_HIP(hipStreamSynchronize(h->stream));
+      for (int k = 0; k < h->n_parts; ++k)
+        n_comps[(size_t)(cyc - 1) * h->n_parts + k] = msclean_count(h, k);
+    }
+  }
+  // final image: equal-weight average of the nodes' models in FP64 (Section 5.2)
+  if (h->n_parts == 2)
+    combine_final(h, model[0], model[1], 0.5, 0.5, final_image, h->stream);
+  else
+    combine_final(h, model[0], model[0], 1.0, 0.0, final_image, h->stream);
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  API_END(h)
 }
 
 imgr_status imager_minor_cycle_fista(imgr_t h, int32_t, const void *, const float *,

@@ -55,6 +55,17 @@ struct Work {
   float *img = nullptr;       // N^2 (node-local residual)
 };
 
+// device work area of one node's multi-scale CLEAN (kept between calls)
+struct CleanWork {
+  double *R = nullptr;       // [n_int][N^2] smoothed residuals
+  double *B = nullptr;       // [n_pairs][(2N)^2] cross PSFs
+  double *kern = nullptr;    // scale kernels and their pairwise convolutions
+  double *model = nullptr;   // N^2
+  void *state = nullptr;     // loop state
+  void *slots = nullptr;     // per-block peak candidates
+  size_t R_elems = 0, B_elems = 0, k_elems = 0;
+};
+
 struct Partition {
   double sum_w = 0.0;
   Bins bins;                   // on the Ng grid (major cycle, degrid, grid)
@@ -80,6 +91,12 @@ struct imgr_s {
   // per-node work buffers and streams: the two nodes' major cycles may run
   // concurrently (imager_major_cycle_nodes)
   imgr::Work work[2];
+  imgr::CleanWork clean[2];
+  // per-node images of the reconstruction loop: composed dirty (N^2),
+  // composed PSF ((2N)^2), deconvolved residual (N^2)
+  float *loop_dirty[2] = {nullptr, nullptr};
+  float *loop_psf[2] = {nullptr, nullptr};
+  float *loop_delta[2] = {nullptr, nullptr};
   hipStream_t node_stream[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[2] = {nullptr, nullptr};
@@ -170,6 +187,16 @@ void exchange(imgr_s *h, const float *a, const float *b, float *rho_a, float *rh
 void combine_final(imgr_s *h, const float *a, const float *b, double wa, double wb, double *out,
                    hipStream_t s);
 void psf_spectrum(imgr_s *h, int p, hipStream_t s);
+
+// ----------------------------------------------------------------- minor cycles
+// multi-scale CLEAN of node `part`, enqueued on stream s; msclean_count
+// (after s has completed) returns the number of components it took
+void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const float *dirty,
+                     const float *psf, float *model_delta, float *model_accum, float *resid_out,
+                     imgr_component *comps, hipStream_t s);
+int msclean_count(imgr_s *h, int part);
+uint32_t msclean_own_scales(const imgr_s *h, int part, const imgr_msclean_params &prm);
+void msclean_release(imgr_s *h, int part);
 
 // ----------------------------------------------------------------- misc kernels
 void add_images(const float *a, const float *b, float *out, int64_t n, hipStream_t s);

@@ -1,0 +1,440 @@
+// Multi-scale CLEAN minor cycle (Eq. 6 and Eq. 7, Section 4.2) in FP64.
+//
+// For the scale set S (scale 0 added internally, not selectable, when S
+// lacks it, so the unsmoothed residual R_0 is always tracked):
+//   R_s  = phi_s * D               (N x N, linear convolution, zero outside)
+//   B_ab = phi_a * phi_b * P       (2N x 2N, a <= b, centre (N, N))
+// then per iteration k < K:
+//   step:   apply the previous component's update R_t -= alpha B_{s*t}
+//           (shifted to p*), and find the block-local peak of
+//           bias_s |R_s(p)| over the selectable scales (ties: smaller scale,
+//           then smaller flat index) and the block-local max |R_0|;
+//   select: one workgroup reduces the block results; stops (for good) if
+//           max |R_0| < threshold, else alpha = gain R_{s*}(p*) / B_{s*s*}(0),
+//           records the component and adds alpha phi_{s*} at p* to the model.
+// Every operation that can decide an argmax is done in FP64 with separate
+// multiply / subtract roundings, in the order of the plain definition, so
+// the decisions are those of an FP64 evaluation.  The host launches the K
+// step/select pairs without waiting; once stopped, every later kernel
+// returns at once.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace imgr {
+namespace {
+
+constexpr int kMaxInt = IMGR_MAX_SCALES + 1;  // internal scales (scale 0 may be added)
+constexpr int kStepThreads = 256;
+constexpr int kStepBlocks = 1024;
+
+struct CleanState {
+  int stop;     // no more components
+  int pend;     // the last component's update is not yet applied
+  int s, p;     // last component: internal scale, flat pixel
+  double alpha;
+  int n_comps;
+  int pad;
+};
+
+struct Cand {
+  double v;     // bias_s |R_s(p)|
+  int s, p;     // internal scale, flat pixel
+  double peak0; // max |R_0|
+};
+
+__device__ __forceinline__ bool better(double v1, int s1, int p1, double v2, int s2, int p2) {
+  return v1 > v2 || (v1 == v2 && (s1 < s2 || (s1 == s2 && p1 < p2)));
+}
+
+struct StepArgs {
+  double *R;            // [n_int][N*N]
+  const double *B;      // [n_pairs][(2N)^2]
+  int pair[kMaxInt][kMaxInt];
+  double bias[kMaxInt];
+  int selectable[kMaxInt];
+  int n_int, n, r0;     // internal scales, image side, internal index of scale 0
+};
+
+__device__ __forceinline__ void reduce_cand(Cand &c, Cand *sh) {
+  // wave then workgroup reduction under the total order of `better`
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(c.v, off);
+    const int os = __shfl_xor(c.s, off), op = __shfl_xor(c.p, off);
+    const double o0 = __shfl_xor(c.peak0, off);
+    if (better(ov, os, op, c.v, c.s, c.p)) {
+      c.v = ov;
+      c.s = os;
+      c.p = op;
+    }
+    c.peak0 = fmax(c.peak0, o0);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      if (better(sh[w].v, sh[w].s, sh[w].p, c.v, c.s, c.p)) {
+        c.v = sh[w].v;
+        c.s = sh[w].s;
+        c.p = sh[w].p;
+      }
+      c.peak0 = fmax(c.peak0, sh[w].peak0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kStepThreads) void k_clean_step(StepArgs a, CleanState *st,
+                                                              Cand *slots) {
+  __shared__ Cand sh[kStepThreads / 64];
+  if (st->stop) return;
+  const int n = a.n, nn = n * n, n2 = 2 * n;
+  const bool pend = st->pend != 0;
+  const int ps = st->s, pp = st->p;
+  const double alpha = st->alpha;
+  const int py = pp / n, px = pp % n;
+  Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0};
+  for (int i = blockIdx.x * kStepThreads + threadIdx.x; i < nn; i += gridDim.x * kStepThreads) {
+    const int y = i / n, x = i % n;
+    const size_t bi = (size_t)(n + y - py) * n2 + (n + x - px);
+    for (int t = 0; t < a.n_int; ++t) {
+      double *r = a.R + (size_t)t * nn + i;
+      double v = *r;
+      if (pend) {
+        const double b = a.B[(size_t)a.pair[ps][t] * n2 * n2 + bi];
+        v = __dsub_rn(v, __dmul_rn(alpha, b));
+        *r = v;
+      }
+      if (a.selectable[t]) {
+        const double bv = __dmul_rn(a.bias[t], fabs(v));
+        if (better(bv, t, i, c.v, c.s, c.p)) {
+          c.v = bv;
+          c.s = t;
+          c.p = i;
+        }
+      }
+      if (t == a.r0) c.peak0 = fmax(c.peak0, fabs(v));
+    }
+  }
+  reduce_cand(c, sh);
+  if (threadIdx.x == 0) slots[blockIdx.x] = c;
+}
+
+struct SelectArgs {
+  const double *R;
+  const double *B;
+  int pair[kMaxInt][kMaxInt];
+  const double *kern;   // scale kernels, concatenated
+  int koff[kMaxInt], krad[kMaxInt];
+  int user[kMaxInt];    // internal -> user scale index
+  int n, n_int;
+  double gain, threshold;
+};
+
+__global__ __launch_bounds__(256) void k_clean_select(SelectArgs a, CleanState *st,
+                                                      const Cand *slots, int n_slots,
+                                                      imgr_component *comps, double *model) {
+  __shared__ Cand sh[4];
+  __shared__ int go;
+  __shared__ double s_alpha;
+  __shared__ int s_s, s_p;
+  if (st->stop) return;
+  Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0};
+  for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+    const Cand o = slots[i];
+    if (better(o.v, o.s, o.p, c.v, c.s, c.p)) {
+      c.v = o.v;
+      c.s = o.s;
+      c.p = o.p;
+    }
+    c.peak0 = fmax(c.peak0, o.peak0);
+  }
+  reduce_cand(c, sh);
+  const int n = a.n, nn = n * n, n2 = 2 * n;
+  if (threadIdx.x == 0) {
+    st->pend = 0;
+    go = 0;
+    if (!(c.peak0 >= a.threshold) || c.s >= a.n_int) {
+      st->stop = 1;
+    } else {
+      const double rv = a.R[(size_t)c.s * nn + c.p];
+      const double bc = a.B[(size_t)a.pair[c.s][c.s] * n2 * n2 + (size_t)n * n2 + n];
+      const double alpha = __ddiv_rn(__dmul_rn(a.gain, rv), bc);
+      const int k = st->n_comps;
+      imgr_component cp;
+      cp.scale = a.user[c.s];
+      cp.iy = c.p / n;
+      cp.ix = c.p % n;
+      cp.reserved = 0;
+      cp.amp = alpha;
+      if (comps) comps[k] = cp;
+      st->n_comps = k + 1;
+      st->s = c.s;
+      st->p = c.p;
+      st->alpha = alpha;
+      st->pend = 1;
+      s_alpha = alpha;
+      s_s = c.s;
+      s_p = c.p;
+      go = 1;
+    }
+  }
+  __syncthreads();
+  if (!go) return;
+  // model += alpha phi_s centred at p (clipped to the image)
+  const int r = a.krad[s_s], w = 2 * r + 1;
+  const double *k = a.kern + a.koff[s_s];
+  const int cy = s_p / n, cx = s_p % n;
+  for (int j = threadIdx.x; j < w * w; j += blockDim.x) {
+    const int y = cy + j / w - r, x = cx + j % w - r;
+    if (y >= 0 && y < n && x >= 0 && x < n) {
+      double *m = model + (size_t)y * n + x;
+      *m = __dadd_rn(*m, __dmul_rn(s_alpha, k[j]));
+    }
+  }
+}
+
+// out (n x n) = in * k (linear, zero outside), k of side 2r+1, centred
+template <typename T>
+__global__ __launch_bounds__(256) void k_conv_same(const T *__restrict__ in, int n,
+                                                   const double *__restrict__ k, int r,
+                                                   double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * n) return;
+  const int y = (int)(i / n), x = (int)(i % n);
+  const int w = 2 * r + 1;
+  double acc = 0.0;
+  for (int a = -r; a <= r; ++a) {
+    const int yy = y - a;
+    if (yy < 0 || yy >= n) continue;
+    const T *row = in + (size_t)yy * n;
+    const double *kr = k + (size_t)(a + r) * w + r;
+    for (int b = -r; b <= r; ++b) {
+      const int xx = x - b;
+      if (xx < 0 || xx >= n) continue;
+      acc = fma(kr[b], (double)row[xx], acc);
+    }
+  }
+  out[i] = acc;
+}
+
+// pending update on R_0 only, then the f32 outputs
+struct FinishArgs {
+  int pair_r0[kMaxInt];  // pair index of (t, r0) for each internal scale t
+};
+
+__global__ void k_clean_finish(double *R0, const double *B, FinishArgs fa, const CleanState *st,
+                               int n, const double *model, float *model_delta,
+                               float *model_accum, float *resid_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn = n * n, n2 = 2 * n;
+  if (i >= nn) return;
+  double v = R0[i];
+  if (st->pend) {
+    const int y = (int)(i / n), x = (int)(i % n);
+    const int py = st->p / n, px = st->p % n;
+    const double *b = B + (size_t)fa.pair_r0[st->s] * n2 * n2;
+    v = __dsub_rn(v, __dmul_rn(st->alpha, b[(size_t)(n + y - py) * n2 + (n + x - px)]));
+    R0[i] = v;
+  }
+  const float m = (float)model[i];
+  if (model_delta) model_delta[i] = m;
+  if (model_accum) model_accum[i] += m;
+  if (resid_out) resid_out[i] = (float)v;
+}
+
+// phi_s: 1 at s = 0; else 1 - (x^2 + y^2) / s^2 on r = ceil(s) - 1, unit sum
+std::vector<double> scale_kernel(double s, int &r) {
+  if (s == 0.0) {
+    r = 0;
+    return {1.0};
+  }
+  r = (int)std::ceil(s) - 1;
+  const int w = 2 * r + 1;
+  std::vector<double> k(w * w);
+  double sum = 0.0;
+  for (int y = -r; y <= r; ++y)
+    for (int x = -r; x <= r; ++x) {
+      double v = 1.0 - (double)(x * x + y * y) / (s * s);
+      if (v < 0.0) v = 0.0;
+      k[(y + r) * w + (x + r)] = v;
+      sum += v;
+    }
+  for (double &v : k) v /= sum;
+  return k;
+}
+
+// full 2-D convolution of two centred odd kernels
+std::vector<double> conv_full(const std::vector<double> &a, int ra, const std::vector<double> &b,
+                              int rb, int &r) {
+  r = ra + rb;
+  const int wa = 2 * ra + 1, wb = 2 * rb + 1, w = 2 * r + 1;
+  std::vector<double> out(w * w, 0.0);
+  for (int y1 = 0; y1 < wa; ++y1)
+    for (int x1 = 0; x1 < wa; ++x1)
+      for (int y2 = 0; y2 < wb; ++y2)
+        for (int x2 = 0; x2 < wb; ++x2)
+          out[(y1 + y2) * w + (x1 + x2)] += a[y1 * wa + x1] * b[y2 * wb + x2];
+  return out;
+}
+
+}  // namespace
+
+void msclean_release(imgr_s *h, int part) {
+  CleanWork &cw = h->clean[part];
+  for (void *q : {(void *)cw.R, (void *)cw.B, (void *)cw.kern, (void *)cw.model, cw.state,
+                  cw.slots})
+    dev_free(h, q);
+  cw = CleanWork();
+}
+
+// mask of the scales of S present in the node's own spatial-frequency
+// domain (psi^1 of Eq. 7; reading): V_L keeps s >= N / (2 (ell + delta)),
+// V_H keeps s <= N / (ell - delta); if none qualifies, the scale nearest to
+// the bound.  With one partition: every scale.
+uint32_t msclean_own_scales(const imgr_s *h, int part, const imgr_msclean_params &prm) {
+  const int ns = prm.n_scales;
+  if (h->n_parts == 1) return (1u << ns) - 1u;
+  const double bound = (part == IMGR_PART_LOW) ? h->N / (2.0 * (h->ell + h->delta))
+                                               : h->N / (h->ell - h->delta);
+  uint32_t m = 0;
+  for (int i = 0; i < ns; ++i) {
+    const double sv = prm.scales[i];
+    if ((part == IMGR_PART_LOW) ? (sv >= bound) : (sv <= bound)) m |= 1u << i;
+  }
+  if (m == 0) {
+    int best = 0;
+    for (int i = 1; i < ns; ++i)
+      if (std::fabs(prm.scales[i] - bound) < std::fabs(prm.scales[best] - bound)) best = i;
+    m = 1u << best;
+  }
+  return m;
+}
+
+int msclean_count(imgr_s *h, int part) {
+  CleanState hs;
+  IMGR_HIP(hipMemcpy(&hs, h->clean[part].state, sizeof(CleanState), hipMemcpyDeviceToHost));
+  return hs.n_comps;
+}
+
+void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const float *dirty,
+                     const float *psf, float *model_delta, float *model_accum, float *resid_out,
+                     imgr_component *comps, hipStream_t s) {
+  const int n = h->N, nn = n * n, n2 = 2 * n;
+  const int ns = prm.n_scales;
+  // internal scales: scale 0 first when S lacks it (tracked, not selectable)
+  int r0_user = -1;
+  for (int i = 0; i < ns; ++i)
+    if (prm.scales[i] == 0.0) {
+      r0_user = i;
+      break;
+    }
+  const int shift = (r0_user < 0) ? 1 : 0;
+  const int n_int = ns + shift;
+  std::vector<double> sc(n_int);
+  std::vector<int> user(n_int, -1), selectable(n_int, 0);
+  if (shift) sc[0] = 0.0;
+  double smax = 0.0;
+  for (int i = 0; i < ns; ++i) smax = std::max(smax, prm.scales[i]);
+  for (int i = 0; i < ns; ++i) {
+    sc[i + shift] = prm.scales[i];
+    user[i + shift] = i;
+    selectable[i + shift] = (prm.active_mask == 0u || ((prm.active_mask >> i) & 1u)) ? 1 : 0;
+  }
+  const int r0 = shift ? 0 : r0_user;
+  // kernels phi_s and phi_a * phi_b
+  std::vector<std::vector<double>> ph(n_int);
+  std::vector<int> rad(n_int);
+  for (int i = 0; i < n_int; ++i) ph[i] = scale_kernel(sc[i], rad[i]);
+  std::vector<double> kall;
+  std::vector<int> koff(n_int);
+  for (int i = 0; i < n_int; ++i) {
+    koff[i] = (int)kall.size();
+    kall.insert(kall.end(), ph[i].begin(), ph[i].end());
+  }
+  int pair[kMaxInt][kMaxInt];
+  std::vector<int> poff, prad;
+  int n_pairs = 0;
+  for (int a = 0; a < n_int; ++a)
+    for (int b = a; b < n_int; ++b) {
+      int r;
+      std::vector<double> c = conv_full(ph[a], rad[a], ph[b], rad[b], r);
+      poff.push_back((int)kall.size());
+      prad.push_back(r);
+      kall.insert(kall.end(), c.begin(), c.end());
+      pair[a][b] = pair[b][a] = n_pairs++;
+    }
+  // device work area of this node (grown on demand, kept for later calls)
+  CleanWork &cw = h->clean[part];
+  const size_t need_R = (size_t)n_int * nn, need_B = (size_t)n_pairs * n2 * n2;
+  if (cw.R_elems < need_R || cw.B_elems < need_B || cw.k_elems < kall.size()) {
+    msclean_release(h, part);
+    cw.R = (double *)dev_alloc(h, need_R * sizeof(double));
+    cw.B = (double *)dev_alloc(h, need_B * sizeof(double));
+    cw.kern = (double *)dev_alloc(h, kall.size() * sizeof(double));
+    cw.model = (double *)dev_alloc(h, (size_t)nn * sizeof(double));
+    cw.state = dev_alloc(h, sizeof(CleanState));
+    cw.slots = dev_alloc(h, (size_t)kStepBlocks * sizeof(Cand));
+    cw.R_elems = need_R;
+    cw.B_elems = need_B;
+    cw.k_elems = kall.size();
+  }
+  IMGR_HIP(hipMemcpyAsync(cw.kern, kall.data(), kall.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+  IMGR_HIP(hipMemsetAsync(cw.model, 0, (size_t)nn * sizeof(double), s));
+  IMGR_HIP(hipMemsetAsync(cw.state, 0, sizeof(CleanState), s));
+  // R_s = phi_s * D, B_ab = phi_a phi_b * P
+  for (int i = 0; i < n_int; ++i)
+    hipLaunchKernelGGL(k_conv_same<float>, dim3(cdiv(nn, 256)), dim3(256), 0, s, dirty, n,
+                       cw.kern + koff[i], rad[i], cw.R + (size_t)i * nn);
+  for (int q = 0; q < n_pairs; ++q)
+    hipLaunchKernelGGL(k_conv_same<float>, dim3(cdiv((int64_t)n2 * n2, 256)), dim3(256), 0, s,
+                       psf, n2, cw.kern + poff[q], prad[q], cw.B + (size_t)q * n2 * n2);
+  IMGR_HIP(hipGetLastError());
+
+  StepArgs sa;
+  sa.R = cw.R;
+  sa.B = cw.B;
+  SelectArgs se;
+  se.R = cw.R;
+  se.B = cw.B;
+  se.kern = cw.kern;
+  for (int a = 0; a < kMaxInt; ++a) {
+    for (int b = 0; b < kMaxInt; ++b)
+      sa.pair[a][b] = se.pair[a][b] = (a < n_int && b < n_int) ? pair[a][b] : 0;
+    sa.bias[a] = 0.0;
+    sa.selectable[a] = 0;
+    se.koff[a] = se.krad[a] = 0;
+    se.user[a] = -1;
+  }
+  for (int i = 0; i < n_int; ++i) {
+    sa.bias[i] = (smax == 0.0) ? 1.0 : 1.0 - prm.bias_slope * sc[i] / smax;
+    sa.selectable[i] = selectable[i];
+    se.koff[i] = koff[i];
+    se.krad[i] = rad[i];
+    se.user[i] = user[i];
+  }
+  sa.n_int = se.n_int = n_int;
+  sa.n = se.n = n;
+  sa.r0 = r0;
+  se.gain = prm.gain;
+  se.threshold = prm.threshold;
+  const int nblk = std::min(kStepBlocks, (int)cdiv(nn, kStepThreads));
+  CleanState *st = (CleanState *)cw.state;
+  Cand *slots = (Cand *)cw.slots;
+  for (int k = 0; k < prm.max_iter; ++k) {
+    hipLaunchKernelGGL(k_clean_step, dim3(nblk), dim3(kStepThreads), 0, s, sa, st, slots);
+    hipLaunchKernelGGL(k_clean_select, dim3(1), dim3(256), 0, s, se, st, slots, nblk, comps,
+                       cw.model);
+  }
+  IMGR_HIP(hipGetLastError());
+  FinishArgs fa;
+  for (int t = 0; t < kMaxInt; ++t) fa.pair_r0[t] = (t < n_int) ? pair[t][r0] : 0;
+  hipLaunchKernelGGL(k_clean_finish, dim3(cdiv(nn, 256)), dim3(256), 0, s, cw.R + (size_t)r0 * nn,
+                     cw.B, fa, st, n, cw.model, model_delta, model_accum, resid_out);
+  IMGR_HIP(hipGetLastError());
+}
+
+}  // namespace imgr

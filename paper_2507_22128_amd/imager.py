@@ -74,13 +74,45 @@ _SIGS = {
     "imager_major_cycle": [_P, _I, _P, _P, _D, _D, _P, _P, _I],
     "imager_major_cycle_nodes": [_P, _P, _P, _P, _P, _P, _P, _I],
     "imager_composed_psf": [_P, _I, _D, _D, _P],
-    "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P],
+    "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
+    "imager_reconstruct_msclean": [_P, _I, _P, _P, _P, _P, _P],
     "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P],
     "imager_combine_partitions": [_P, _I, _P, _P, _D, _D, _P, _P],
     "imager_set_timing": [_P, _I],
     "imager_get_timing": [_P, _P],
     "imager_sync": [_P],
 }
+
+MAX_SCALES = 8
+
+
+class MsCleanParams(ctypes.Structure):
+    _fields_ = [("n_scales", ctypes.c_int32), ("scales", ctypes.c_double * MAX_SCALES),
+                ("active_mask", ctypes.c_uint32), ("gain", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("threshold", ctypes.c_double),
+                ("bias_slope", ctypes.c_double), ("own_scales_only", ctypes.c_int32)]
+
+
+COMPONENT_DTYPE = np.dtype([("scale", "<i4"), ("iy", "<i4"), ("ix", "<i4"), ("reserved", "<i4"),
+                            ("amp", "<f8")])
+
+
+def msclean_params(scales, gain=0.1, niter=2000, threshold=0.0, bias_slope=0.6, active=None,
+                   own_scales_only=False):
+    if not 1 <= len(scales) <= MAX_SCALES:
+        raise ImagerError(EINVAL, "between 1 and %d scales" % MAX_SCALES)
+    p = MsCleanParams()
+    p.n_scales = len(scales)
+    for i, sc in enumerate(scales):
+        p.scales[i] = float(sc)
+    p.active_mask = 0 if active is None else sum(1 << int(i) for i in active)
+    p.gain = float(gain)
+    p.max_iter = int(niter)
+    p.threshold = float(threshold)
+    p.bias_slope = float(bias_slope)
+    p.own_scales_only = 1 if own_scales_only else 0
+    return p
+
 
 N_STAGES = 5
 STAGES = ("model_fft", "degrid_grid", "flush", "residual_fft", "compose")
@@ -320,8 +352,43 @@ class Imager:
             self._h, COMBINE_FINAL, _ptr(a), _ptr(b), float(wa), float(wb), _ptr(out), None))
         return out
 
-    def minor_cycle_msclean(self, *a, **k):
-        self._check(lib().imager_minor_cycle_msclean(self._h, 0, None, None, None, None))
+    def minor_cycle_msclean(self, part, dirty, psf, scales, gain=0.1, niter=2000, threshold=0.0,
+                            bias_slope=0.6, active=None, own_scales_only=False, model_accum=None,
+                            want_residual=True):
+        """Multi-scale CLEAN of one node (synchronous).  Returns (model_delta,
+        components (numpy structured array), residual or None)."""
+        import torch
+        n = self.n_pix
+        _dev_f32(dirty, (n, n), torch)
+        _dev_f32(psf, (2 * n, 2 * n), torch)
+        prm = msclean_params(scales, gain, niter, threshold, bias_slope, active, own_scales_only)
+        delta = self._empty((n, n), "float32")
+        resid = self._empty((n, n), "float32") if want_residual else None
+        comps = torch.empty(max(int(niter), 1) * COMPONENT_DTYPE.itemsize, dtype=torch.uint8,
+                            device="cuda")
+        cnt = ctypes.c_int32(0)
+        self._check(lib().imager_minor_cycle_msclean(
+            self._h, part, ctypes.byref(prm), _ptr(dirty), _ptr(psf), _ptr(delta),
+            _ptr(model_accum), _ptr(resid), _ptr(comps), ctypes.byref(cnt)))
+        raw = comps[:cnt.value * COMPONENT_DTYPE.itemsize].cpu().numpy()
+        return delta, np.frombuffer(raw.tobytes(), dtype=COMPONENT_DTYPE), resid
+
+    def reconstruct_msclean(self, n_cycles, scales, gain=0.1, niter=2000, threshold=0.0,
+                            bias_slope=0.6, active=None, models=None, rhos=None):
+        """The whole major/minor loop in the library.  Returns (final image
+        (float64), per-node models, per-node rho, components per cycle and node)."""
+        n, k = self.n_pix, self.info.n_partitions
+        prm = msclean_params(scales, gain, niter, threshold, bias_slope, active)
+        import torch
+        models = [torch.zeros((n, n), device="cuda") for _ in range(k)] if models is None else models
+        rhos = [torch.zeros((n, n), device="cuda") for _ in range(k)] if rhos is None else rhos
+        final = self._empty((n, n), "float64")
+        counts = np.zeros((n_cycles, k), np.int32)
+        arr = lambda ts: (ctypes.c_void_p * k)(*[t.data_ptr() for t in ts])
+        self._check(lib().imager_reconstruct_msclean(
+            self._h, int(n_cycles), ctypes.byref(prm), arr(models), arr(rhos), _ptr(final),
+            counts.ctypes.data_as(ctypes.c_void_p)))
+        return final, models, rhos, counts
 
     def minor_cycle_fista(self, *a, **k):
         self._check(lib().imager_minor_cycle_fista(self._h, 0, None, None, None, None))

@@ -1,0 +1,170 @@
+"""Multi-scale CLEAN on the GPU against the FP64 oracle (GPU required).
+
+Teacher forcing: the GPU minor cycle and the oracle get the same dirty image
+and PSF (the GPU's float32 arrays, up-cast exactly for the oracle), so every
+decision must coincide: identical (scale, iy, ix) sequences, amplitudes to
+FP64 rounding, model and residual to the float32 rounding of the outputs.
+The end-to-end loop compares the library's whole reconstruction with the
+oracle's, where the major cycles differ at the FP32 level.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import imaging, oracle_weights, rel, say, to_dev, to_np, uv, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _imager():
+    from paper_2507_22128_amd import imager
+    return imager
+
+
+def _oracle_msclean():
+    from oracle import msclean
+    return msclean
+
+
+def _compare(comps, ref_comps, model, ref_model, resid, ref_resid):
+    got = [(int(c["scale"]), int(c["iy"]), int(c["ix"])) for c in comps]
+    exp = [tuple(int(v) for v in c[:3]) for c in ref_comps]
+    assert got == exp, "component sequences differ (first at %s)" % next(
+        (i for i, (a, b) in enumerate(zip(got, exp)) if a != b), min(len(got), len(exp)))
+    amps = np.array([c["amp"] for c in comps])
+    ref_amps = np.array([c[3] for c in ref_comps])
+    assert np.abs(amps - ref_amps).max() <= 1e-12 * np.abs(ref_amps).max()
+    assert rel(model, ref_model) < 1e-6
+    if resid is not None:
+        assert rel(resid, ref_resid) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def tiny1():
+    say("case: tiny workload, 1 partition (msCLEAN)")
+    d = workload("tiny")
+    h = _imager().Imager.create(d, n_partitions=1, weighting="uniform")
+    yield d, h
+    h.destroy()
+
+
+def test_msclean_teacher_forced_serial(tiny1):
+    import torch
+    d, h = tiny1
+    n = d["n_img"]
+    dirty = h.major_cycle(0, torch.zeros((n, n), device="cuda"))
+    psf = h.psf(0)
+    scales = [0, 4, 12]
+    delta, comps, resid = h.minor_cycle_msclean(0, dirty, psf, scales, gain=0.1, niter=300)
+    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
+        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), scales, gain=0.1,
+        niter=300)
+    say("serial msclean: %d components, scales used %s" % (len(comps), sorted(set(comps["scale"]))))
+    _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
+    # extended scales only (scale 0 tracked for the threshold, not selectable)
+    delta, comps, resid = h.minor_cycle_msclean(0, dirty, psf, scales, niter=150, active=[1, 2],
+                                                bias_slope=0.3)
+    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
+        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), scales, niter=150,
+        active=[1, 2], bias_slope=0.3)
+    assert set(comps["scale"]) == {1, 2}
+    _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
+
+
+def test_msclean_threshold_count_and_empty(tiny1):
+    import torch
+    d, h = tiny1
+    n = d["n_img"]
+    dirty = h.major_cycle(0, torch.zeros((n, n), device="cuda"))
+    psf = h.psf(0)
+    thr = 0.5 * float(to_np(dirty).__abs__().max())
+    acc = torch.zeros((n, n), device="cuda")
+    delta, comps, resid = h.minor_cycle_msclean(0, dirty, psf, [0, 4], niter=500, threshold=thr,
+                                                model_accum=acc)
+    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
+        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), [0, 4], niter=500,
+        threshold=thr)
+    assert 0 < len(comps) < 500
+    _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
+    assert torch.equal(acc, delta)  # model_accum started at zero
+    d0, c0, r0 = h.minor_cycle_msclean(0, dirty, psf, [0, 4], niter=0)
+    assert len(c0) == 0 and not torch.any(d0) and torch.equal(r0, dirty)
+
+
+@pytest.fixture(scope="module")
+def tiny2():
+    say("case: tiny workload (20 time steps), 2 partitions (msCLEAN)")
+    d = workload("tiny", n_time=20)
+    h = _imager().Imager.create(d, n_partitions=2, weighting="uniform")
+    yield d, h
+    h.destroy()
+
+
+def test_msclean_teacher_forced_two_nodes(tiny2):
+    """Cycle-2 composed images (Eq. 7) of both nodes, and the first-cycle
+    own-scale subsets."""
+    d, h = tiny2
+    n = d["n_img"]
+    rng = np.random.default_rng(12)
+    model = to_dev(0.3 * d["truth"])
+    rho = to_dev(0.002 * rng.standard_normal((n, n)))
+    wl, wh = h.sum_w(0), h.sum_w(1)
+    scales = [0, 4, 12]
+    msc = _oracle_msclean()
+    for p, own in ((0, "L"), (1, "H")):
+        g = (wl, wh)[p] / (wl + wh)
+        dirty = h.major_cycle(p, model, rho, g, 1.0 - g)
+        psf = h.composed_psf(p, g, 1.0 - g)
+        delta, comps, resid = h.minor_cycle_msclean(p, dirty, psf, scales, niter=200)
+        rm, rr, rc = msc.msclean(to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64),
+                                 scales, niter=200)
+        say("node %s: %d components" % (own, len(comps)))
+        _compare(comps, rc, to_np(delta), rm, to_np(resid), rr)
+        # first cycle: gamma = 1, mu = 0, the node's own scales only
+        dirty1 = h.major_cycle(p, model)
+        psf1 = h.composed_psf(p, 1.0, 0.0)
+        active = msc.scale_subset(scales, n, h.info.ell_pix, h.info.delta_pix, own)
+        delta1, comps1, resid1 = h.minor_cycle_msclean(p, dirty1, psf1, scales, niter=100,
+                                                       own_scales_only=True)
+        rm1, rr1, rc1 = msc.msclean(to_np(dirty1).astype(np.float64),
+                                    to_np(psf1).astype(np.float64), scales, niter=100,
+                                    active=active)
+        assert set(comps1["scale"]) <= set(active)
+        _compare(comps1, rc1, to_np(delta1), rm1, to_np(resid1), rr1)
+
+
+def test_reconstruct_msclean_end_to_end(tiny2):
+    """The library's whole decentralized loop against the oracle's loop:
+    same components per cycle and node, final images to FP32 accuracy."""
+    d, h = tiny2
+    from oracle import decentral
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    scales, niter, cycles = [0, 2, 4], 80, 3
+    final, models, rhos, counts = h.reconstruct_msclean(cycles, scales, gain=0.1, niter=niter)
+    ref_final, ref_models, hist = decentral.reconstruct_msclean(
+        u, v, d["vis"], w, n, d["cell"], cycles, scales, gain=0.1, niter=niter, partitions=2)
+    ref_counts = np.array([[len(hc[k][2]) for k in ("L", "H")] for hc in hist])
+    err = rel(to_np(final), ref_final)
+    say("end-to-end: counts %s (oracle %s), final rel err %.3e"
+        % (counts.tolist(), ref_counts.tolist(), err))
+    assert np.array_equal(counts, ref_counts)
+    assert err < 1e-5
+    for k, node in enumerate(("L", "H")):
+        assert rel(to_np(models[k]), ref_models[node]) < 1e-5
+
+
+def test_reconstruct_msclean_serial_end_to_end(tiny1):
+    d, h = tiny1
+    from oracle import decentral
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    final, models, _, counts = h.reconstruct_msclean(2, [0, 2, 4], gain=0.1, niter=60)
+    ref_final, _, hist = decentral.reconstruct_msclean(
+        u, v, d["vis"], w, n, d["cell"], 2, [0, 2, 4], gain=0.1, niter=60, partitions=1)
+    err = rel(to_np(final), ref_final)
+    say("serial end-to-end final rel err %.3e" % err)
+    assert counts.tolist() == [[len(hc["L"][2])] for hc in hist]
+    assert err < 1e-5
