@@ -28,4 +28,4 @@ Parity status of each function is stated in its docstring; items whose
 definition is a reading of a silent or ambiguous passage say so.
 """
 
-from . import geometry, es_kernel, dft, gridding, imaging, decentral, msclean  # noqa: F401
+from . import geometry, es_kernel, dft, gridding, imaging, decentral, msclean, wavelets, fista  # noqa: F401,E501

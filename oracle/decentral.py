@@ -172,3 +172,57 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
         history.append(step)
     final = combine([models[k] for k in nodes])
     return final, models, history
+
+
+def reconstruct_fista(u, v, vis, w, n_img, cell, n_cycles, start_images, lam_frac=1e-3,
+                      n_iter=200, power_iters=30, vanishing=8, levels=3, partitions=2, ell=None,
+                      delta=1.0, support=8):
+    """The major/minor loop with the sparsity-regularised minor cycle (Eqs.
+    4 and 5), serial (partitions = 1) or decentralized, in FP64.
+
+    Per major cycle n and node: i~ = the node's residual (Eq. 2); lambda^n =
+    lam_frac max |i~| (reading of "1e-3 x max |dirty|"); gamma_n = 0 at
+    n = 1, else 1 (Eq. 5); L_hat by ``power_iters`` power iterations from
+    start_images[node]; alpha by ``n_iter`` FISTA iterations; ibar = W alpha;
+    model += ibar (Eq. 3).  Then the Phi / rho exchange of Section 4.1 and,
+    at the end, the equal-weight combination of Section 5.2.
+    Returns (final image, per-node models, history of per-cycle dicts
+    {node: (lambda, L_hat, objective list)}).
+    """
+    from . import fista as fs, imaging, wavelets
+    h = wavelets.daubechies(vanishing)
+    m = len(u)
+    if partitions == 1:
+        masks = {"L": np.ones(m, bool)}
+        nodes = ("L",)
+    else:
+        low, high, ell = imaging.partition(u, v, n_img, cell, ell=ell, delta=delta)
+        masks = {"L": low, "H": high}
+        nodes = ("L", "H")
+    other = {"L": "H", "H": "L"}
+    psf = {k: imaging.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support)
+           for k, mk in masks.items()}
+    models = {k: np.zeros((n_img, n_img)) for k in nodes}
+    rho = {k: np.zeros((n_img, n_img)) for k in nodes}
+    history = []
+    for cyc in range(1, n_cycles + 1):
+        step, deltas = {}, {}
+        for k in nodes:
+            mk = masks[k]
+            resid, _ = imaging.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
+                                              support=support)
+            gamma_n = 0.0 if (cyc == 1 or partitions == 1) else 1.0
+            lam = lam_frac * float(np.abs(resid).max())
+            prob = fs.NodeProblem(resid, psf[k], rho[k], gamma_n, ell, delta, k, h, levels,
+                                  serial=(partitions == 1))
+            L_hat = fs.power_iteration(prob, start_images[k], power_iters)
+            alpha, obj = fs.fista(prob, lam, n_iter, L_hat)
+            deltas[k] = prob.W(alpha)
+            step[k] = (lam, L_hat, obj)
+        for k in nodes:
+            models[k] = models[k] + deltas[k]
+        if partitions == 2:
+            rho = {k: update_rho(rho[k], exchange(deltas[other[k]], ell, delta, other[k]),
+                                 deltas[k], ell, delta, k) for k in nodes}
+        history.append(step)
+    return combine([models[k] for k in nodes]), models, history

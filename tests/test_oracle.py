@@ -514,3 +514,111 @@ def test_decentralized_msclean_loop_runs_and_reduces_residual():
         assert len(hist) == 2 and len(models) == parts
         res, _ = imaging.residual_image(u, v, d["vis"], w, final, d["cell"])
         assert np.linalg.norm(res) < 0.8 * np.linalg.norm(dirty)
+
+
+# ------------------------------------------------------------------ wavelets and FISTA
+
+def test_daubechies_closed_forms():
+    from oracle import wavelets
+    s3 = np.sqrt(3.0)
+    db2 = np.array([1 + s3, 3 + s3, 3 - s3, 1 - s3]) / (4 * np.sqrt(2.0))
+    assert np.abs(wavelets.daubechies(2) - db2).max() < 1e-15
+    assert np.abs(wavelets.daubechies(1) - np.array([1, 1]) / np.sqrt(2.0)).max() < 1e-16
+
+
+@pytest.mark.parametrize("p", [2, 4, 8])
+def test_daubechies_orthonormality_and_moments(p):
+    from oracle import wavelets
+    h = wavelets.daubechies(p)
+    assert len(h) == 2 * p
+    assert abs(h.sum() - np.sqrt(2.0)) < 1e-14
+    for m in range(p):
+        s = float(np.dot(h[: len(h) - 2 * m], h[2 * m:]))
+        assert abs(s - (1.0 if m == 0 else 0.0)) < 1e-14
+    g = wavelets.highpass(h)
+    k = np.arange(len(g), dtype=np.float64)
+    for j in range(p):  # p vanishing moments of the wavelet
+        assert abs(np.dot(g, k ** j)) < 1e-11 * np.dot(np.abs(g), k ** j)
+    assert abs(np.dot(g, k ** p)) > 1e-6 * np.dot(np.abs(g), k ** p)
+
+
+def test_dwt_orthonormal_and_invertible():
+    from oracle import wavelets
+    rng = np.random.default_rng(8)
+    h = wavelets.daubechies(8)
+    x = rng.standard_normal((64, 64))
+    c = wavelets.dwt2(x, h, 3)
+    assert abs(np.linalg.norm(c) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+    assert np.abs(wavelets.idwt2(c, h, 3) - x).max() < 1e-12
+    a = rng.standard_normal((64, 64))
+    assert abs(np.sum(wavelets.idwt2(a, h, 3) * x) - np.sum(a * c)) < 1e-11
+
+
+def test_haar_one_level_closed_form():
+    from oracle import wavelets
+    x = np.array([[1.0, 2.0], [3.0, 4.0]])
+    c = wavelets.dwt2(x, wavelets.daubechies(1), 1)
+    # rows then columns: LL = sum / 2, the three details as signed sums / 2
+    assert np.allclose(c, [[5.0, -1.0], [-2.0, 0.0]], atol=1e-15)
+
+
+def test_fista_closed_form_identity_operator():
+    """H = I, Gamma_own = I, gamma = 0: the minimiser of ||i - W a||^2 +
+    lam ||a||_1 is soft(W^T i, lam / 2), reached by the first FISTA step
+    (L = 2 exactly) and kept."""
+    from oracle import fista, wavelets
+    n = 32
+    rng = np.random.default_rng(9)
+    dirty = rng.standard_normal((n, n))
+    psf = np.zeros((2 * n, 2 * n))
+    psf[n, n] = 1.0
+    h = wavelets.daubechies(8)
+    prob = fista.NodeProblem(dirty, psf, None, 0.0, 0.0, 1.0, "L", h, 3, serial=True)
+    L_hat = fista.power_iteration(prob, rng.standard_normal((n, n)), 30)
+    assert abs(L_hat - 2.0) < 1e-12
+    lam = 0.3
+    alpha, obj = fista.fista(prob, lam, 5, L_hat)
+    expect = fista.soft(wavelets.dwt2(dirty, h, 3), lam / 2.0)
+    assert np.abs(alpha - expect).max() < 1e-12
+    assert max(obj) - min(obj) < 1e-9 * abs(obj[0])
+
+
+def test_fista_decreases_objective_and_respects_lipschitz_bound():
+    """On a two-node problem: the power-iteration L_hat does not exceed the
+    bound 2 max (Gamma_own^2 |psf_hat|^2 + gamma Gamma_other^2) of the
+    circulant embeddings, and FISTA lowers the objective."""
+    from oracle import decentral, fista, wavelets
+    from oracle.imaging import apply_psf
+    psf, n = _small_psf()
+    rng = np.random.default_rng(10)
+    truth = np.zeros((n, n))
+    truth[rng.integers(4, n - 4, 8), rng.integers(4, n - 4, 8)] = rng.uniform(0.2, 1.0, 8)
+    dirty = apply_psf(psf, truth)
+    rho = 0.1 * rng.standard_normal((n, n))
+    ell = 6.0
+    prob = fista.NodeProblem(dirty, psf, rho, 1.0, ell, 1.0, "L", wavelets.daubechies(8), 2)
+    L_hat = fista.power_iteration(prob, rng.standard_normal((n, n)), 30)
+    spec = np.abs(np.fft.fft2(psf)).max()
+    bound = 2.0 * (spec ** 2 + 1.0)
+    assert 0.0 < L_hat <= bound * (1 + 1e-12)
+    lam = 1e-3 * np.abs(dirty).max()
+    alpha, obj = fista.fista(prob, lam, 60, L_hat)
+    assert obj[-1] < 0.5 * prob.objective(np.zeros((n, n)), lam)  # (FISTA is not monotone)
+
+
+def test_decentralized_fista_loop_runs_and_reduces_residual():
+    from oracle import decentral, geometry, imaging
+    from paper_2507_22128_amd import synth
+    d = synth.make("tiny", n_time=6)
+    n = d["n_img"]
+    u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
+    w = imaging.uniform_weights(u, v, n, d["cell"])
+    dirty = imaging.dirty_image(u, v, d["vis"], w, n, d["cell"])
+    rng = np.random.default_rng(21)
+    starts = {"L": rng.standard_normal((n, n)), "H": rng.standard_normal((n, n))}
+    for parts in (1, 2):
+        final, models, hist = decentral.reconstruct_fista(
+            u, v, d["vis"], w, n, d["cell"], 2, starts, n_iter=20, power_iters=10,
+            partitions=parts)
+        res, _ = imaging.residual_image(u, v, d["vis"], w, final, d["cell"])
+        assert np.linalg.norm(res) < 0.9 * np.linalg.norm(dirty)
