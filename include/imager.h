@@ -266,11 +266,59 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
                                        float *const *rho, double *final_image,
                                        int32_t *n_comps);
 
-/* FISTA minor cycle for Eqs. 4 and 5.  Not available in this version:
- * returns IMGR_ENOTIMPL. */
-imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const void *params,
+/* Sparsity-regularised minor cycle of node `part` (Eq. 5; Eq. 4 with
+ * serial = 1): with W the orthonormal periodized Daubechies synthesis
+ * (vanishing moments p, 2p taps, `levels` levels, every coefficient in the
+ * l1 term), H the node's PSF convolution and Gamma_own / Gamma_other the
+ * filters of Section 4.1,
+ *   min_alpha ||Gamma_own (dirty - H W alpha)||^2
+ *             + gamma_n ||rho_other - Gamma_other W alpha||^2 + lambda ||alpha||_1
+ * by n_iter FISTA iterations from alpha = 0 with the constant step 1 / L_hat,
+ * L_hat = 2 x the largest eigenvalue of H Gamma_own^2 H + gamma_n
+ * Gamma_other^2 estimated by power_iters power iterations from the image
+ * power_start (any nonzero N x N image; Beck and Teboulle's method as the
+ * paper uses it).  lambda = params->lambda if > 0, else lambda_frac *
+ * max |dirty|.  dirty: the node's residual i~ of Eq. 2 (device N x N
+ * float32), rho_other: the node's aggregate rho of Eq. 5 (device N x N
+ * float32, ignored when gamma_n = 0 or serial).  Outputs (device, each may
+ * be NULL): model_delta (N x N float32) = W alpha, model_accum += it,
+ * objective (float64 [n_iter]) = the objective after every iteration.
+ * *lipschitz and *lambda_used (host, may be NULL) receive L_hat and lambda.
+ * Synchronises the handle's stream before returning. */
+typedef struct {
+  int32_t vanishing;     /* Daubechies p, 1 .. 10 (8: the 16-tap db8) */
+  int32_t levels;        /* wavelet levels, N >> levels >= 2 p */
+  int32_t n_iter;        /* FISTA iterations >= 0 */
+  int32_t power_iters;   /* power iterations >= 1 */
+  double lambda;         /* > 0: absolute weight of the l1 term */
+  double lambda_frac;    /* lambda <= 0: lambda = lambda_frac * max |dirty| */
+  double gamma_n;        /* weight of the rho term (Eq. 5: 0 at the first cycle, else 1) */
+  int32_t serial;        /* 1: Eq. 4 (Gamma_own = identity, no rho term) */
+} imgr_fista_params;
+
+imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,
                                      const float *dirty, const float *rho_other,
-                                     float *model_delta);
+                                     const float *power_start, float *model_delta,
+                                     float *model_accum, double *objective, double *lipschitz,
+                                     double *lambda_used);
+
+/* The whole major/minor loop with the sparsity-regularised minor cycle
+ * (Section 4.1): for cycle n = 1 .. n_cycles and every node k,
+ * concurrently, i~ = the residual of model[k] (Eq. 2), lambda =
+ * lambda_frac * max |i~| (or params->lambda if > 0), gamma_n = 0 at n = 1
+ * and 1 afterwards (Eq. 5; params->gamma_n is ignored), ibar = W alpha
+ * from imager_minor_cycle_fista with power_start[k], model[k] += ibar
+ * (Eq. 3); then the exchange rho[0] += Gamma_H (ibar_H - ibar_L), rho[1]
+ * += Gamma_L (ibar_L - ibar_H), and final_image = 0.5 model[0] + 0.5
+ * model[1] in FP64 (Section 5.2).  With one partition: Eq. 4 every cycle
+ * and final_image = model[0].  model, rho (device N x N float32, updated in
+ * place; rho may be NULL with one partition), final_image (device N x N
+ * float64); lipschitz, lambdas (host, n_cycles x n_partitions, or NULL).
+ * Synchronises the handle's stream before returning. */
+imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fista_params *params,
+                                     const float *const *power_start, float *const *model,
+                                     float *const *rho, double *final_image, double *lipschitz,
+                                     double *lambdas);
 
 /* Exchange and combination between the two partitions (Section 4.1,
  * Fig. 2, Section 5.2).

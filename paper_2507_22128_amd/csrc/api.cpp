@@ -293,6 +293,13 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
       }
       h->tw = (float2 *)dev_alloc(h, kTwMax * sizeof(float2));
       IMGR_HIP(hipMemcpy(h->tw, tw.data(), kTwMax * sizeof(float2), hipMemcpyHostToDevice));
+      std::vector<double2> tw64(kTwMax);
+      for (int m = 0; m < kTwMax; ++m) {
+        const double a = 2.0 * M_PI * (double)m / (double)kTwMax;
+        tw64[m] = make_double2(std::cos(a), -std::sin(a));
+      }
+      h->tw64 = (double2 *)dev_alloc(h, kTwMax * sizeof(double2));
+      IMGR_HIP(hipMemcpy(h->tw64, tw64.data(), kTwMax * sizeof(double2), hipMemcpyHostToDevice));
     }
     const size_t ng2 = (size_t)h->Ng * h->Ng;
     for (int p = 0; p < h->n_parts; ++p) {
@@ -580,11 +587,91 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
   API_END(h)
 }
 
-imgr_status imager_minor_cycle_fista(imgr_t h, int32_t, const void *, const float *,
-                                     const float *, float *) {
-  if (!h) return IMGR_EINVAL;
-  h->err = "minor_cycle_fista is not available in this version";
-  return IMGR_ENOTIMPL;
+static void check_fista(imgr_s *h, const imgr_fista_params &p) {
+  IMGR_CHECK(p.vanishing >= 1 && p.vanishing <= 10, "vanishing must be in [1, 10]");
+  IMGR_CHECK(p.levels >= 1 && (h->N >> p.levels) >= 1, "levels must be in [1, log2 N]");
+  IMGR_CHECK(p.n_iter >= 0 && p.power_iters >= 1, "n_iter >= 0 and power_iters >= 1");
+  IMGR_CHECK(std::isfinite(p.lambda) && std::isfinite(p.lambda_frac) && std::isfinite(p.gamma_n),
+             "lambda / gamma_n");
+  IMGR_CHECK(p.lambda > 0.0 || p.lambda_frac >= 0.0, "lambda_frac must be >= 0");
+}
+
+imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,
+                                     const float *dirty, const float *rho_other,
+                                     const float *power_start, float *model_delta,
+                                     float *model_accum, double *objective, double *lipschitz,
+                                     double *lambda_used) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(params && dirty && power_start, "null pointer");
+  check_fista(h, *params);
+  IMGR_CHECK(params->serial || params->gamma_n == 0.0 || rho_other || h->n_parts == 1,
+             "gamma_n != 0 needs rho_other");
+  fista_enqueue(h, part, *params, dirty, rho_other, power_start, model_delta, model_accum,
+                objective, h->stream);
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  fista_scalars(h, part, lipschitz, lambda_used);
+  API_END(h)
+}
+
+imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fista_params *params,
+                                     const float *const *power_start, float *const *model,
+                                     float *const *rho, double *final_image, double *lipschitz,
+                                     double *lambdas) {
+  API_BEGIN(h)
+  IMGR_CHECK(params && power_start && model && final_image, "null pointer");
+  IMGR_CHECK(n_cycles >= 1, "n_cycles must be >= 1");
+  IMGR_CHECK(h->n_parts == 1 || rho, "rho is required with two partitions");
+  check_fista(h, *params);
+  for (int k = 0; k < h->n_parts; ++k)
+    IMGR_CHECK(power_start[k] && model[k] && (!rho || rho[k]), "null pointer");
+  const size_t nn = (size_t)h->N * h->N;
+  for (int k = 0; k < h->n_parts; ++k) {
+    if (!h->loop_dirty[k]) {
+      h->loop_dirty[k] = (float *)dev_alloc(h, nn * sizeof(float));
+      h->loop_psf[k] = (float *)dev_alloc(h, 4 * nn * sizeof(float));
+      h->loop_delta[k] = (float *)dev_alloc(h, nn * sizeof(float));
+    }
+  }
+  for (int cyc = 1; cyc <= n_cycles; ++cyc) {
+    imgr_fista_params q = *params;
+    if (h->n_parts == 1) {
+      hipStream_t s = h->stream;
+      q.serial = 1;
+      q.gamma_n = 0.0;
+      node_cycle(h, 0, model[0], nullptr, 1.0, 0.0, h->loop_dirty[0], nullptr, 0, s);
+      fista_enqueue(h, 0, q, h->loop_dirty[0], nullptr, power_start[0], h->loop_delta[0],
+                    model[0], nullptr, s);
+    } else {
+      q.serial = 0;
+      q.gamma_n = (cyc == 1) ? 0.0 : 1.0;  // Eq. 5
+      IMGR_HIP(hipEventRecord(h->ev_fork, h->stream));
+      for (int k = 0; k < 2; ++k) {
+        hipStream_t s = h->node_stream[k];
+        IMGR_HIP(hipStreamWaitEvent(s, h->ev_fork, 0));
+        // the node's own residual i~ (Eq. 2); the composition is not used here
+        node_cycle(h, k, model[k], nullptr, 1.0, 0.0, h->loop_psf[k], h->loop_dirty[k], 0, s);
+        fista_enqueue(h, k, q, h->loop_dirty[k], rho[k], power_start[k], h->loop_delta[k],
+                      model[k], nullptr, s);
+        IMGR_HIP(hipEventRecord(h->ev_join[k], s));
+      }
+      for (int k = 0; k < 2; ++k) IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[k], 0));
+      exchange(h, h->loop_delta[0], h->loop_delta[1], rho[0], rho[1], h->stream);
+    }
+    if (lipschitz || lambdas) {
+      IMGR_HIP(hipStreamSynchronize(h->stream));
+      for (int k = 0; k < h->n_parts; ++k) {
+        const size_t at = (size_t)(cyc - 1) * h->n_parts + k;
+        fista_scalars(h, k, lipschitz ? lipschitz + at : nullptr, lambdas ? lambdas + at : nullptr);
+      }
+    }
+  }
+  if (h->n_parts == 2)
+    combine_final(h, model[0], model[1], 0.5, 0.5, final_image, h->stream);
+  else
+    combine_final(h, model[0], model[0], 1.0, 0.0, final_image, h->stream);
+  IMGR_HIP(hipStreamSynchronize(h->stream));
+  API_END(h)
 }
 
 imgr_status imager_combine_partitions(imgr_t h, int32_t mode, const float *a, const float *b,

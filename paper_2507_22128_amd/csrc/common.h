@@ -20,6 +20,24 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// real type of a complex vector type, and a constructor
+template <class C> struct Real;
+template <> struct Real<float2> { typedef float T; };
+template <> struct Real<double2> { typedef double T; };
+template <class C>
+__device__ __forceinline__ C mkc(typename Real<C>::T re, typename Real<C>::T im) {
+  C c;
+  c.x = re;
+  c.y = im;
+  return c;
+}
 
 // twiddle table: tw[m] = exp(-2 pi i m / kTwMax), FP64-computed, f32-stored
 constexpr int kTwMax = 16384;
@@ -66,12 +84,27 @@ struct CleanWork {
   size_t R_elems = 0, B_elems = 0, k_elems = 0;
 };
 
+// device work area of one node's FISTA (kept between calls; FP64)
+struct FistaWork {
+  double *alpha_prev = nullptr, *y = nullptr;                    // N^2 coefficients
+  double *x = nullptr, *u1 = nullptr, *u2 = nullptr, *u3 = nullptr;  // N^2 images
+  double *cst = nullptr, *tmp = nullptr, *coef = nullptr;        // N^2
+  double *d64 = nullptr, *r64 = nullptr;                         // inputs in FP64
+  double2 *work64 = nullptr, *tmp64 = nullptr;                   // transform buffers
+  double *scal = nullptr;    // device scalars (L_hat, lambda, norms)
+  double *part = nullptr;    // reduction partials
+  double *hlo = nullptr;     // wavelet filters (low, high)
+  int taps = 0, vanishing = 0;
+  size_t n = 0;
+};
+
 struct Partition {
   double sum_w = 0.0;
   Bins bins;                   // on the Ng grid (major cycle, degrid, grid)
   Bins psf_bins;               // on the 2 Ng grid of the 2N x 2N PSF (freed after create)
   float *psf = nullptr;        // (2N)^2 normalised PSF, centre (N, N)
   float2 *psf_hat = nullptr;   // (2N)^2 plain DFT of psf
+  double2 *psf_hat64 = nullptr;  // the same in FP64 (built on first use)
 };
 
 }  // namespace imgr
@@ -88,10 +121,12 @@ struct imgr_s {
   float *cinv = nullptr;       // [N]  1 / psi_hat, N image on the Ng grid
   float *cinv2 = nullptr;      // [2N] 1 / psi_hat, 2N image on the 2 Ng grid
   float2 *tw = nullptr;        // [kTwMax]
+  double2 *tw64 = nullptr;     // [kTwMax], FP64
   // per-node work buffers and streams: the two nodes' major cycles may run
   // concurrently (imager_major_cycle_nodes)
   imgr::Work work[2];
   imgr::CleanWork clean[2];
+  imgr::FistaWork fista[2];
   // per-node images of the reconstruction loop: composed dirty (N^2),
   // composed PSF ((2N)^2), deconvolved residual (N^2)
   float *loop_dirty[2] = {nullptr, nullptr};
@@ -153,7 +188,8 @@ void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, co
 void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
                        float2 *rows, float2 *tmp, float *out, hipStream_t s);
 // out (+)= Re F_N^-1 (Gamma_own . F_N (a - b)) * coef for N x N images
-// (b may be NULL; plain DFTs; Gamma_L for own_low, else Gamma_H);
+// (b may be NULL; plain DFTs; own_low: bit 0 set = Gamma_L, else Gamma_H;
+// bit 1 set = the filter squared);
 // work holds N x L and tmp L x L complex values (L = N here, 2N below)
 void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float coef, float *out,
                  int accumulate, float2 *work, float2 *tmp, hipStream_t s);
@@ -161,6 +197,15 @@ void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float c
 // the 2N x 2N PSF with spectrum psf_hat (centre (N, N)), cropped to N x N
 void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef, float *out,
                     int accumulate, float2 *work, float2 *tmp, hipStream_t s);
+// FP64 versions of the two filters (work: N x 2N, tmp: (2N)^2 double2)
+void image_gamma64(imgr_s *h, const double *a, const double *b, int own_low, double coef,
+                   double *out, int accumulate, double2 *work, double2 *tmp, hipStream_t s);
+void image_psf_conv64(imgr_s *h, const double *a, const double2 *psf_hat, double coef, double *out,
+                      int accumulate, double2 *work, double2 *tmp, hipStream_t s);
+// plain FP64 2-D DFT of an n x n complex buffer in place
+void fft2_plain64(imgr_s *h, double2 *buf, double2 *tmp, int n, int dir, hipStream_t s);
+// the partition's FP64 PSF spectrum (built on first use, kept)
+const double2 *psf_spectrum64(imgr_s *h, int p, hipStream_t s);
 // plain 2-D DFT of an n x n complex buffer in place (dir -1 forward, +1 inverse, unnormalised)
 void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t s);
 
@@ -197,6 +242,13 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
 int msclean_count(imgr_s *h, int part);
 uint32_t msclean_own_scales(const imgr_s *h, int part, const imgr_msclean_params &prm);
 void msclean_release(imgr_s *h, int part);
+
+// sparsity-regularised minor cycle of node `part` (Eqs. 4, 5), enqueued on s
+void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const float *dirty,
+                   const float *rho_other, const float *power_start, float *model_delta,
+                   float *model_accum, double *objective, hipStream_t s);
+// (after s has completed) the step constant L_hat and lambda of the last run
+void fista_scalars(imgr_s *h, int part, double *lipschitz, double *lambda);
 
 // ----------------------------------------------------------------- misc kernels
 void add_images(const float *a, const float *b, float *out, int64_t n, hipStream_t s);

@@ -91,6 +91,27 @@ void psf_spectrum(imgr_s *h, int p, hipStream_t s) {
   fft2_plain(h, P.psf_hat, h->work[p].grid_b, nd, -1, s);
 }
 
+__global__ void k_pad_real64(const float *__restrict__ a, int n, double2 *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)n * n) dst[i] = make_double2((double)a[i], 0.0);
+}
+
+// FP64 spectrum of the partition's 2N x 2N PSF (plain DFT), built once
+const double2 *psf_spectrum64(imgr_s *h, int p, hipStream_t s) {
+  Partition &P = h->part[p];
+  if (P.psf_hat64) return P.psf_hat64;
+  const int nd = 2 * h->N;
+  const size_t m = (size_t)nd * nd;
+  P.psf_hat64 = (double2 *)dev_alloc(h, m * sizeof(double2));
+  double2 *tmp = (double2 *)dev_alloc(h, m * sizeof(double2));
+  hipLaunchKernelGGL(k_pad_real64, g1((int64_t)m), dim3(256), 0, s, P.psf, nd, P.psf_hat64);
+  IMGR_HIP(hipGetLastError());
+  fft2_plain64(h, P.psf_hat64, tmp, nd, -1, s);
+  IMGR_HIP(hipStreamSynchronize(s));
+  dev_free(h, tmp);
+  return P.psf_hat64;
+}
+
 // Eq. 7: out = gamma Gamma_own resid + mu H_other rho_other
 void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma,
              double mu, float *out, hipStream_t s) {

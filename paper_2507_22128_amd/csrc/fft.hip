@@ -19,48 +19,49 @@ namespace {
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }
 
-template <int DIR>
-__device__ __forceinline__ float2 tw_get(const float2 *__restrict__ tw, int idx) {
-  float2 t = tw[idx];
+template <int DIR, class C>
+__device__ __forceinline__ C tw_get(const C *__restrict__ tw, int idx) {
+  C t = tw[idx];
   if (DIR > 0) t.y = -t.y;
   return t;
 }
 
 // multiply by -i (forward, DIR < 0) or +i (inverse)
-template <int DIR>
-__device__ __forceinline__ float2 mul_mi(float2 a) {
-  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+template <int DIR, class C>
+__device__ __forceinline__ C mul_mi(C a) {
+  return DIR < 0 ? mkc<C>(a.y, -a.x) : mkc<C>(-a.y, a.x);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft4(float2 &y0, float2 &y1, float2 &y2, float2 &y3) {
-  float2 t0 = cadd(y0, y2), t1 = csub(y0, y2), t2 = cadd(y1, y3), t3 = mul_mi<DIR>(csub(y1, y3));
+template <int DIR, class C>
+__device__ __forceinline__ void dft4(C &y0, C &y1, C &y2, C &y3) {
+  C t0 = cadd(y0, y2), t1 = csub(y0, y2), t2 = cadd(y1, y3), t3 = mul_mi<DIR>(csub(y1, y3));
   y0 = cadd(t0, t2);
   y2 = csub(t0, t2);
   y1 = cadd(t1, t3);
   y3 = csub(t1, t3);
 }
 
-template <int R, int DIR>
-__device__ __forceinline__ void dft(float2 *x) {
+template <int R, int DIR, class C>
+__device__ __forceinline__ void dft(C *x) {
+  typedef typename Real<C>::T RT;
   if constexpr (R == 2) {
-    float2 a = x[0], b = x[1];
+    C a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
   } else if constexpr (R == 4) {
     dft4<DIR>(x[0], x[1], x[2], x[3]);
   } else {
     static_assert(R == 8, "radix");
-    const float h = 0.70710678118654752440f;
-    float2 a0 = cadd(x[0], x[4]), a1 = cadd(x[1], x[5]), a2 = cadd(x[2], x[6]), a3 = cadd(x[3], x[7]);
-    float2 b0 = csub(x[0], x[4]), b1 = csub(x[1], x[5]), b2 = csub(x[2], x[6]), b3 = csub(x[3], x[7]);
+    const RT h = (RT)0.70710678118654752440L;
+    C a0 = cadd(x[0], x[4]), a1 = cadd(x[1], x[5]), a2 = cadd(x[2], x[6]), a3 = cadd(x[3], x[7]);
+    C b0 = csub(x[0], x[4]), b1 = csub(x[1], x[5]), b2 = csub(x[2], x[6]), b3 = csub(x[3], x[7]);
     // b_n *= W8^n, W8 = exp(DIR * 2 pi i / 8)
     if (DIR < 0) {
-      b1 = make_float2((b1.x + b1.y) * h, (b1.y - b1.x) * h);
-      b3 = make_float2((b3.y - b3.x) * h, -(b3.x + b3.y) * h);
+      b1 = mkc<C>((b1.x + b1.y) * h, (b1.y - b1.x) * h);
+      b3 = mkc<C>((b3.y - b3.x) * h, -(b3.x + b3.y) * h);
     } else {
-      b1 = make_float2((b1.x - b1.y) * h, (b1.x + b1.y) * h);
-      b3 = make_float2(-(b3.x + b3.y) * h, (b3.x - b3.y) * h);
+      b1 = mkc<C>((b1.x - b1.y) * h, (b1.x + b1.y) * h);
+      b3 = mkc<C>(-(b3.x + b3.y) * h, (b3.x - b3.y) * h);
     }
     b2 = mul_mi<DIR>(b2);
     dft4<DIR>(a0, a1, a2, a3);
@@ -73,13 +74,13 @@ __device__ __forceinline__ void dft(float2 *x) {
 // One sequence of length L in padded LDS, NT threads, Stockham passes from
 // sub-length NS upward (radix 8 while possible, then 4 or 2).  tw holds
 // w_L^m = exp(-2 pi i m / L), m < L (the row kernels stage it in LDS).
-template <int L, int NT, int NS, int DIR>
-__device__ __forceinline__ void stockham_seq(float2 *s, const float2 *tw, int t) {
+template <int L, int NT, int NS, int DIR, class C>
+__device__ __forceinline__ void stockham_seq(C *s, const C *tw, int t) {
   if constexpr (NS < L) {
     constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
     constexpr int NB = L / R;
     constexpr int PER = (NB + NT - 1) / NT;
-    float2 x[PER][R];
+    C x[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = t + q * NT;
@@ -106,21 +107,21 @@ __device__ __forceinline__ void stockham_seq(float2 *s, const float2 *tw, int t)
       }
     }
     __syncthreads();
-    stockham_seq<L, NT, NS * R, DIR>(s, tw, t);
+    stockham_seq<L, NT, NS * R, DIR, C>(s, tw, t);
   }
 }
 
 // 64 sequences of length LEN stored as s[pos][64] (column c = lane), 256
 // threads: wave w does butterflies j = w, w + 4, ...
-template <int LEN, int NS, int DIR>
-__device__ __forceinline__ void stockham_cols(float2 *s, const float2 *__restrict__ tw, int t) {
+template <int LEN, int NS, int DIR, class C>
+__device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, int t) {
   if constexpr (NS < LEN) {
     constexpr int R = (LEN / NS >= 8) ? 8 : (LEN / NS);
     constexpr int NB = LEN / R;
     constexpr int PER = (NB + 3) / 4;
     const int c = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    float2 x[PER][R];
+    C x[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = wv + 4 * q;
@@ -147,13 +148,13 @@ __device__ __forceinline__ void stockham_cols(float2 *s, const float2 *__restric
       }
     }
     __syncthreads();
-    stockham_cols<LEN, NS * R, DIR>(s, tw, t);
+    stockham_cols<LEN, NS * R, DIR, C>(s, tw, t);
   }
 }
 
 // stage w_L^m, m < L, from the kTwMax-entry table into LDS
-template <int L, int NT>
-__device__ __forceinline__ void stage_twiddles(float2 *twl, const float2 *__restrict__ tw) {
+template <int L, int NT, class C>
+__device__ __forceinline__ void stage_twiddles(C *twl, const C *__restrict__ tw) {
   for (int m = threadIdx.x; m < L; m += NT) twl[m] = tw[m * (kTwMax / L)];
 }
 
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  stage_twiddles<L, NT>(twl, tw);
+  stage_twiddles<L, NT, float2>(twl, tw);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  stage_twiddles<L, NT>(twl, tw);
+  stage_twiddles<L, NT, float2>(twl, tw);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
@@ -221,17 +222,17 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
 }
 
 // plain in-place complex row DFTs of an L x L buffer
-template <int L, int DIR>
-__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(float2 *__restrict__ buf,
-                                                                 const float2 *__restrict__ tw) {
+template <int L, int DIR, class C>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__ buf,
+                                                                 const C *__restrict__ tw) {
   constexpr int NT = RowThreads<L>::v;
-  __shared__ float2 s[L + L / 32];
-  __shared__ float2 twl[L];
-  stage_twiddles<L, NT>(twl, tw);
-  float2 *row = buf + (size_t)blockIdx.x * L;
+  __shared__ C s[L + L / 32];
+  __shared__ C twl[L];
+  stage_twiddles<L, NT, C>(twl, tw);
+  C *row = buf + (size_t)blockIdx.x * L;
   for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = row[x];
   __syncthreads();
-  stockham_seq<L, NT, 1, DIR>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, DIR, C>(s, twl, threadIdx.x);
   for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
 }
 
@@ -244,19 +245,19 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(float2 *__restr
 // outside [y_lo, y_hi) as zero.  Pass 2 keeps output rows k in [k_lo, k_hi),
 // stored at dst row (k - dst_row0), optionally times (-1)^(k + x).
 
-template <int P, int Q, int DIR>
-__global__ __launch_bounds__(256) void k_cols_p1(const float2 *__restrict__ src, int src_row0,
-                                                 int y_lo, int y_hi, float2 *__restrict__ dst,
-                                                 const float2 *__restrict__ tw) {
+template <int P, int Q, int DIR, class C>
+__global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int src_row0,
+                                                 int y_lo, int y_hi, C *__restrict__ dst,
+                                                 const C *__restrict__ tw) {
   constexpr int L = P * Q;
-  __shared__ float2 s[P * 64];
+  __shared__ C s[P * 64];
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int y2 = blockIdx.y;
   for (int i = t; i < P * 64; i += 256) {
     const int y1 = i >> 6, c = i & 63;
     const int y = Q * y1 + y2;
-    float2 v = make_float2(0.f, 0.f);
+    C v = mkc<C>(0, 0);
     if (y >= y_lo && y < y_hi) v = src[(size_t)(y - src_row0) * L + x0 + c];
     s[i] = v;
   }
@@ -269,13 +270,13 @@ __global__ __launch_bounds__(256) void k_cols_p1(const float2 *__restrict__ src,
   }
 }
 
-template <int P, int Q, int DIR>
-__global__ __launch_bounds__(256) void k_cols_p2(const float2 *__restrict__ src,
-                                                 float2 *__restrict__ dst, int dst_row0, int k_lo,
+template <int P, int Q, int DIR, class C>
+__global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
+                                                 C *__restrict__ dst, int dst_row0, int k_lo,
                                                  int k_hi, int modulate,
-                                                 const float2 *__restrict__ tw) {
+                                                 const C *__restrict__ tw) {
   constexpr int L = P * Q;
-  __shared__ float2 s[Q * 64];
+  __shared__ C s[Q * 64];
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int k1 = blockIdx.y;
@@ -289,8 +290,8 @@ __global__ __launch_bounds__(256) void k_cols_p2(const float2 *__restrict__ src,
     const int k2 = i >> 6, c = i & 63;
     const int k = k1 + P * k2;
     if (k >= k_lo && k < k_hi) {
-      float2 v = s[i];
-      if (modulate && ((k + x0 + c) & 1)) v = make_float2(-v.x, -v.y);
+      C v = s[i];
+      if (modulate && ((k + x0 + c) & 1)) v = mkc<C>(-v.x, -v.y);
       dst[(size_t)(k - dst_row0) * L + x0 + c] = v;
     }
   }
@@ -305,45 +306,47 @@ __global__ __launch_bounds__(256) void k_cols_p2(const float2 *__restrict__ src,
 
 // rows r < gridDim.x: (a - b) (n_in real values, zero padded to L) -> plain
 // forward row DFT -> out[r][0..L)
-template <int L>
+template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
-    const float *__restrict__ a, const float *__restrict__ b, int n_in,
-    float2 *__restrict__ out, const float2 *__restrict__ tw) {
+    const typename Real<C>::T *__restrict__ a, const typename Real<C>::T *__restrict__ b,
+    int n_in, C *__restrict__ out, const C *__restrict__ tw) {
+  typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
-  __shared__ float2 s[L + L / 32];
-  __shared__ float2 twl[L];
-  stage_twiddles<L, NT>(twl, tw);
+  __shared__ C s[L + L / 32];
+  __shared__ C twl[L];
+  stage_twiddles<L, NT, C>(twl, tw);
   const int r = blockIdx.x;
   for (int x = threadIdx.x; x < L; x += NT) {
-    float v = 0.f;
+    RT v = 0;
     if (x < n_in) {
       v = a[(size_t)r * n_in + x];
       if (b) v -= b[(size_t)r * n_in + x];
     }
-    s[padi(x)] = make_float2(v, 0.f);
+    s[padi(x)] = mkc<C>(v, 0);
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, -1, C>(s, twl, threadIdx.x);
   for (int x = threadIdx.x; x < L; x += NT) out[(size_t)r * L + x] = s[padi(x)];
 }
 
 // rows r < gridDim.x: inverse plain row DFT of in[r][0..L), then
 // out[r][c] (+)= Re s[col0 + c] for c < n_out
-template <int L>
+template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
-    const float2 *__restrict__ in, int col0, int n_out, float *__restrict__ out, int accumulate,
-    const float2 *__restrict__ tw) {
+    const C *__restrict__ in, int col0, int n_out, typename Real<C>::T *__restrict__ out,
+    int accumulate, const C *__restrict__ tw) {
+  typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
-  __shared__ float2 s[L + L / 32];
-  __shared__ float2 twl[L];
-  stage_twiddles<L, NT>(twl, tw);
+  __shared__ C s[L + L / 32];
+  __shared__ C twl[L];
+  stage_twiddles<L, NT, C>(twl, tw);
   const int r = blockIdx.x;
   for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = in[(size_t)r * L + x];
   __syncthreads();
-  stockham_seq<L, NT, 1, 1>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, 1, C>(s, twl, threadIdx.x);
   for (int c = threadIdx.x; c < n_out; c += NT) {
-    const float v = s[padi(col0 + c)].x;
-    float *o = out + (size_t)r * n_out + c;
+    const RT v = s[padi(col0 + c)].x;
+    RT *o = out + (size_t)r * n_out + c;
     *o = accumulate ? *o + v : v;
   }
 }
@@ -361,22 +364,23 @@ enum { FILT_GAMMA = 0, FILT_SPEC = 1 };
 
 // Gamma_L(kappa) = clip((ell + delta - kappa) / (2 delta), 0, 1) at the
 // plain-DFT frequency (kx, ky) of an nd-point grid, kappa = |k| / scale
-__device__ __forceinline__ float gamma_low_at(int kx, int ky, int nd, double ell, double delta,
-                                              double scale) {
+__device__ __forceinline__ double gamma_low_at(int kx, int ky, int nd, double ell, double delta,
+                                               double scale) {
   const int fx = (kx < nd / 2) ? kx : kx - nd;
   const int fy = (ky < nd / 2) ? ky : ky - nd;
   const double kappa = sqrt((double)fx * fx + (double)fy * fy) / scale;
   const double g = (ell + delta - kappa) / (2.0 * delta);
-  return (float)fmin(fmax(g, 0.0), 1.0);
+  return fmin(fmax(g, 0.0), 1.0);
 }
 
-template <int P, int Q, int MODE>
-__global__ __launch_bounds__(256) void k_cols_mid(float2 *__restrict__ buf,
-                                                  const float2 *__restrict__ spec, double ell,
-                                                  double delta, double gscale, int own_low,
-                                                  float coef, const float2 *__restrict__ tw) {
+template <int P, int Q, int MODE, class C>
+__global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *__restrict__ spec,
+                                                  double ell, double delta, double gscale,
+                                                  int own_low, typename Real<C>::T coef,
+                                                  const C *__restrict__ tw) {
+  typedef typename Real<C>::T RT;
   constexpr int L = P * Q;
-  __shared__ float2 s[Q * 64];
+  __shared__ C s[Q * 64];
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int k1 = blockIdx.y;
@@ -389,10 +393,11 @@ __global__ __launch_bounds__(256) void k_cols_mid(float2 *__restrict__ buf,
   for (int i = t; i < Q * 64; i += 256) {
     const int k2 = i >> 6, c = i & 63;
     const int k = k1 + P * k2;
-    float2 v = s[i];
+    C v = s[i];
     if constexpr (MODE == FILT_GAMMA) {
-      float g = gamma_low_at(x0 + c, k, L, ell, delta, gscale);
-      if (!own_low) g = 1.f - g;
+      RT g = (RT)gamma_low_at(x0 + c, k, L, ell, delta, gscale);
+      if (!(own_low & 1)) g = (RT)1 - g;
+      if (own_low & 2) g = g * g;
       v = cscale(v, g * coef);
     } else {
       v = cscale(cmul(v, spec[(size_t)k * L + x0 + c]), coef);
@@ -408,12 +413,11 @@ __global__ __launch_bounds__(256) void k_cols_mid(float2 *__restrict__ buf,
   }
 }
 
-template <int P, int Q>
-__global__ __launch_bounds__(256) void k_cols_fin(const float2 *__restrict__ src,
-                                                  float2 *__restrict__ dst, int k_lo, int k_hi,
-                                                  const float2 *__restrict__ tw) {
+template <int P, int Q, class C>
+__global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *__restrict__ dst,
+                                                  int k_lo, int k_hi, const C *__restrict__ tw) {
   constexpr int L = P * Q;
-  __shared__ float2 s[P * 64];
+  __shared__ C s[P * 64];
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int y2 = blockIdx.y;
@@ -441,13 +445,17 @@ template <> struct Split<2048> { static constexpr int P = 32, Q = 64; };
 template <> struct Split<4096> { static constexpr int P = 64, Q = 64; };
 template <> struct Split<8192> { static constexpr int P = 64, Q = 128; };
 
-template <int L, int DIR>
-void cols(const float2 *src, int src_row0, int y_lo, int y_hi, float2 *tmp, float2 *dst,
-          int dst_row0, int k_lo, int k_hi, int modulate, const float2 *tw, hipStream_t s) {
+template <class C> const C *twiddles(const imgr_s *h);
+template <> const float2 *twiddles<float2>(const imgr_s *h) { return h->tw; }
+template <> const double2 *twiddles<double2>(const imgr_s *h) { return h->tw64; }
+
+template <int L, int DIR, class C>
+void cols(const C *src, int src_row0, int y_lo, int y_hi, C *tmp, C *dst, int dst_row0, int k_lo,
+          int k_hi, int modulate, const C *tw, hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
-  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR>), dim3(L / 64, Q), dim3(256), 0, s, src, src_row0,
+  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR, C>), dim3(L / 64, Q), dim3(256), 0, s, src, src_row0,
                      y_lo, y_hi, tmp, tw);
-  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR>), dim3(L / 64, P), dim3(256), 0, s, tmp, dst,
+  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR, C>), dim3(L / 64, P), dim3(256), 0, s, tmp, dst,
                      dst_row0, k_lo, k_hi, modulate, tw);
 }
 
@@ -457,50 +465,53 @@ void model_to_grid_t(imgr_s *h, const float *model, const float *model_add, cons
   const int o = (L - n) / 2;
   hipLaunchKernelGGL((k_rows_model<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, model, model_add,
                      cinv, n, rows, h->tw);
-  cols<L, -1>(rows, o, o, o + n, tmp, out, 0, 0, L, 1, h->tw, s);
+  cols<L, -1, float2>(rows, o, o, o + n, tmp, out, 0, 0, L, 1, h->tw, s);
 }
 
 template <int L>
 void grid_to_image_t(imgr_s *h, const float2 *in, const float *cinv, int n, float scale,
                      float2 *rows, float2 *tmp, float *out, hipStream_t s) {
   const int o = (L - n) / 2;
-  cols<L, 1>(in, 0, 0, L, tmp, rows, o, o, o + n, 0, h->tw, s);
+  cols<L, 1, float2>(in, 0, 0, L, tmp, rows, o, o, o + n, 0, h->tw, s);
   hipLaunchKernelGGL((k_rows_image<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, rows, cinv, n,
                      scale, out, h->tw);
 }
 
-template <int L>
-void plain_t(imgr_s *h, float2 *buf, float2 *tmp, int dir, hipStream_t s) {
+template <int L, class C>
+void plain_t(imgr_s *h, C *buf, C *tmp, int dir, hipStream_t s) {
+  const C *tw = twiddles<C>(h);
   if (dir < 0) {
-    hipLaunchKernelGGL((k_rows_plain<L, -1>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, h->tw);
-    cols<L, -1>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, h->tw, s);
+    hipLaunchKernelGGL((k_rows_plain<L, -1, C>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, tw);
+    cols<L, -1, C>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, tw, s);
   } else {
-    hipLaunchKernelGGL((k_rows_plain<L, 1>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, h->tw);
-    cols<L, 1>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, h->tw, s);
+    hipLaunchKernelGGL((k_rows_plain<L, 1, C>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, tw);
+    cols<L, 1, C>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, tw, s);
   }
 }
 
-template <int L>
-void filter_t(imgr_s *h, const float *a, const float *b, int n_in, int mode, const float2 *spec,
-              int own_low, double gscale, float coef, int k_lo, int k_hi, int col0, int n_out,
-              float *out, int accumulate, float2 *work, float2 *tmp, hipStream_t s) {
-  // n_in rows of n_in pixels in (zero padded to L x L), rows [k_lo, k_hi) x
-  // cols [col0, col0 + n_out) out; work: n_in x L, tmp: L x L
+// n_in rows of n_in pixels in (zero padded to L x L), rows [k_lo, k_hi) x
+// cols [col0, col0 + n_out) out; work: n_in x L, tmp: L x L
+template <int L, class C>
+void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T *b, int n_in,
+              int mode, const C *spec, int own_low, double gscale, typename Real<C>::T coef,
+              int k_lo, int k_hi, int col0, int n_out, typename Real<C>::T *out, int accumulate,
+              C *work, C *tmp, hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
-  hipLaunchKernelGGL((k_rows_real_fwd<L>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b, n_in,
-                     work, h->tw);
-  hipLaunchKernelGGL((k_cols_p1<P, Q, -1>), dim3(L / 64, Q), dim3(256), 0, s, work, 0, 0, n_in,
-                     tmp, h->tw);
+  const C *tw = twiddles<C>(h);
+  hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
+                     n_in, work, tw);
+  hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(L / 64, Q), dim3(256), 0, s, work, 0, 0, n_in,
+                     tmp, tw);
   if (mode == FILT_GAMMA)
-    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_GAMMA>), dim3(L / 64, P), dim3(256), 0, s, tmp, spec,
-                       h->ell, h->delta, gscale, own_low, coef, h->tw);
+    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_GAMMA, C>), dim3(L / 64, P), dim3(256), 0, s, tmp,
+                       spec, h->ell, h->delta, gscale, own_low, coef, tw);
   else
-    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_SPEC>), dim3(L / 64, P), dim3(256), 0, s, tmp, spec,
-                       h->ell, h->delta, gscale, own_low, coef, h->tw);
-  hipLaunchKernelGGL((k_cols_fin<P, Q>), dim3(L / 64, Q), dim3(256), 0, s, tmp, work, k_lo, k_hi,
-                     h->tw);
-  hipLaunchKernelGGL((k_rows_inv_real<L>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s, work,
-                     col0, n_out, out, accumulate, h->tw);
+    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_SPEC, C>), dim3(L / 64, P), dim3(256), 0, s, tmp,
+                       spec, h->ell, h->delta, gscale, own_low, coef, tw);
+  hipLaunchKernelGGL((k_cols_fin<P, Q, C>), dim3(L / 64, Q), dim3(256), 0, s, tmp, work, k_lo,
+                     k_hi, tw);
+  hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
+                     work, col0, n_out, out, accumulate, tw);
 }
 
 }  // namespace
@@ -537,8 +548,8 @@ void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float c
   switch (n) {
 #define X(L)                                                                                   \
   case L:                                                                                      \
-    filter_t<L>(h, a, b, n, FILT_GAMMA, nullptr, own_low, 1.0, coef, 0, n, 0, n, out,          \
-                accumulate, work, tmp, s);                                                     \
+    filter_t<L, float2>(h, a, b, n, FILT_GAMMA, nullptr, own_low, 1.0, coef, 0, n, 0, n, out,  \
+                        accumulate, work, tmp, s);                                             \
     break;
     IMGR_FFT_SIZES(X)
 #undef X
@@ -553,8 +564,8 @@ void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef
   switch (nd) {
 #define X(L)                                                                                   \
   case L:                                                                                      \
-    filter_t<L>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, n, n, out,          \
-                accumulate, work, tmp, s);                                                     \
+    filter_t<L, float2>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, n, n, out,  \
+                        accumulate, work, tmp, s);                                             \
     break;
     IMGR_FFT_SIZES(X)
 #undef X
@@ -566,8 +577,54 @@ void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef
 void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t s) {
   switch (n) {
 #define X(L) \
-  case L: plain_t<L>(h, buf, tmp, dir, s); break;
+  case L: plain_t<L, float2>(h, buf, tmp, dir, s); break;
     IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+// sizes of the FP64 transforms (images up to 2048, their 2N grids)
+#define IMGR_FFT64_SIZES(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+void image_gamma64(imgr_s *h, const double *a, const double *b, int own_low, double coef,
+                   double *out, int accumulate, double2 *work, double2 *tmp, hipStream_t s) {
+  const int n = h->N;
+  switch (n) {
+#define X(L)                                                                                   \
+  case L:                                                                                      \
+    filter_t<L, double2>(h, a, b, n, FILT_GAMMA, nullptr, own_low, 1.0, coef, 0, n, 0, n, out, \
+                         accumulate, work, tmp, s);                                            \
+    break;
+    IMGR_FFT64_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void image_psf_conv64(imgr_s *h, const double *a, const double2 *psf_hat, double coef, double *out,
+                      int accumulate, double2 *work, double2 *tmp, hipStream_t s) {
+  const int n = h->N, nd = 2 * n;
+  switch (nd) {
+#define X(L)                                                                                   \
+  case L:                                                                                      \
+    filter_t<L, double2>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, n, n, out, \
+                         accumulate, work, tmp, s);                                            \
+    break;
+    IMGR_FFT64_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void fft2_plain64(imgr_s *h, double2 *buf, double2 *tmp, int n, int dir, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: plain_t<L, double2>(h, buf, tmp, dir, s); break;
+    IMGR_FFT64_SIZES(X)
 #undef X
     default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
   }

@@ -76,7 +76,8 @@ _SIGS = {
     "imager_composed_psf": [_P, _I, _D, _D, _P],
     "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "imager_reconstruct_msclean": [_P, _I, _P, _P, _P, _P, _P],
-    "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P],
+    "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "imager_reconstruct_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P],
     "imager_combine_partitions": [_P, _I, _P, _P, _D, _D, _P, _P],
     "imager_set_timing": [_P, _I],
     "imager_get_timing": [_P, _P],
@@ -111,6 +112,23 @@ def msclean_params(scales, gain=0.1, niter=2000, threshold=0.0, bias_slope=0.6, 
     p.threshold = float(threshold)
     p.bias_slope = float(bias_slope)
     p.own_scales_only = 1 if own_scales_only else 0
+    return p
+
+
+class FistaParams(ctypes.Structure):
+    _fields_ = [("vanishing", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("n_iter", ctypes.c_int32), ("power_iters", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("lambda_frac", ctypes.c_double),
+                ("gamma_n", ctypes.c_double), ("serial", ctypes.c_int32)]
+
+
+def fista_params(vanishing=8, levels=3, n_iter=200, power_iters=30, lam=0.0, lam_frac=1e-3,
+                 gamma_n=0.0, serial=False):
+    p = FistaParams()
+    p.vanishing, p.levels, p.n_iter, p.power_iters = int(vanishing), int(levels), int(n_iter), \
+        int(power_iters)
+    p.lam, p.lambda_frac, p.gamma_n = float(lam), float(lam_frac), float(gamma_n)
+    p.serial = 1 if serial else 0
     return p
 
 
@@ -390,8 +408,40 @@ class Imager:
             counts.ctypes.data_as(ctypes.c_void_p)))
         return final, models, rhos, counts
 
-    def minor_cycle_fista(self, *a, **k):
-        self._check(lib().imager_minor_cycle_fista(self._h, 0, None, None, None, None))
+    def minor_cycle_fista(self, part, dirty, power_start, rho_other=None, model_accum=None,
+                          want_objective=False, **params):
+        """Sparsity-regularised minor cycle of one node (synchronous).  Returns
+        (model_delta, objective per iteration or None, L_hat, lambda)."""
+        import torch
+        n = self.n_pix
+        _dev_f32(dirty, (n, n), torch)
+        _dev_f32(power_start, (n, n), torch)
+        prm = fista_params(**params)
+        delta = self._empty((n, n), "float32")
+        obj = self._empty((max(prm.n_iter, 1),), "float64") if want_objective else None
+        L, lam = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(lib().imager_minor_cycle_fista(
+            self._h, part, ctypes.byref(prm), _ptr(dirty), _ptr(rho_other), _ptr(power_start),
+            _ptr(delta), _ptr(model_accum), _ptr(obj), ctypes.byref(L), ctypes.byref(lam)))
+        objective = None if obj is None else obj[:prm.n_iter].cpu().numpy()
+        return delta, objective, L.value, lam.value
+
+    def reconstruct_fista(self, n_cycles, power_starts, models=None, rhos=None, **params):
+        """The whole loop with the sparsity-regularised minor cycle.  Returns
+        (final image (float64), models, rhos, L_hat and lambda per cycle and node)."""
+        import torch
+        n, k = self.n_pix, self.info.n_partitions
+        prm = fista_params(**params)
+        models = [torch.zeros((n, n), device="cuda") for _ in range(k)] if models is None else models
+        rhos = [torch.zeros((n, n), device="cuda") for _ in range(k)] if rhos is None else rhos
+        final = self._empty((n, n), "float64")
+        Ls = np.zeros((n_cycles, k))
+        lams = np.zeros((n_cycles, k))
+        arr = lambda ts: (ctypes.c_void_p * k)(*[t.data_ptr() for t in ts])
+        self._check(lib().imager_reconstruct_fista(
+            self._h, int(n_cycles), ctypes.byref(prm), arr(power_starts), arr(models), arr(rhos),
+            _ptr(final), Ls.ctypes.data_as(ctypes.c_void_p), lams.ctypes.data_as(ctypes.c_void_p)))
+        return final, models, rhos, Ls, lams
 
     def set_timing(self, enable):
         self._check(lib().imager_set_timing(self._h, 1 if enable else 0))

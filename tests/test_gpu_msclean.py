@@ -67,7 +67,7 @@ def test_msclean_teacher_forced_serial(tiny1):
     ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
         to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), scales, niter=150,
         active=[1, 2], bias_slope=0.3)
-    assert set(comps["scale"]) == {1, 2}
+    assert len(comps) == 150 and set(comps["scale"]) <= {1, 2}
     _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
 
 

@@ -268,12 +268,13 @@ def test_exchange_and_final_combination(medium):
 
 
 def test_errors_are_reported(medium):
+    import torch
     d, h = medium
     imager = _imager()
     with pytest.raises(imager.ImagerError) as e:
-        h.minor_cycle_fista()
-    assert e.value.code == imager.ENOTIMPL
-    import torch
+        h.minor_cycle_msclean(0, torch.zeros((d["n_img"],) * 2, device="cuda"),
+                              torch.zeros((2 * d["n_img"],) * 2, device="cuda"), [0, 4], gain=2.0)
+    assert e.value.code == imager.EINVAL
     with pytest.raises(imager.ImagerError):
         h.major_cycle(5, torch.zeros((d["n_img"],) * 2, device="cuda"))
     # an empty partition is refused at create
