@@ -105,6 +105,51 @@ def cpu_baseline(args, gpu_gamma_mu):
     }
 
 
+def minor_cycles(h, info, model, rho, gammas, mus, n):
+    """Device time of the two minor cycles on node V_L's cycle-2 problem of
+    the benchmark workload: multi-scale CLEAN (S = {0, 4, 12} px, gain 0.1,
+    K = 2000, FP64) on the composed dirty image and PSF of Eq. 7, and FISTA
+    (db8, 3 levels, 200 iterations, 30 power iterations, lambda = 1e-3 max |i~|,
+    FP64 transforms) on the node's residual and aggregate (Eq. 5)."""
+    import numpy as np
+    import torch
+    out = {}
+    dirty = h.major_cycle(0, model[0], rho[0], gammas[0], mus[0])
+    psf = h.composed_psf(0, gammas[0], mus[0])
+    h.minor_cycle_msclean(0, dirty, psf, [0, 4, 12], niter=10)  # work area, warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, comps, _ = h.minor_cycle_msclean(0, dirty, psf, [0, 4, 12], gain=0.1, niter=2000)
+    t_msc = time.perf_counter() - t0
+    n_int = 3  # smoothed residuals kept (scale 0 is in S)
+    bytes_iter = 24.0 * n_int * n * n  # read R_t, read B_{s*t}, write R_t (FP64) per iteration
+    out["msclean"] = {
+        "ms": round(1e3 * t_msc, 2), "iterations": int(len(comps)),
+        "us_per_iteration": round(1e6 * t_msc / max(len(comps), 1), 2),
+        "update_gbs": round(bytes_iter * len(comps) / t_msc / 1e9, 1),
+        "update_hbm_frac": round(bytes_iter * len(comps) / t_msc / 1e9 / HBM_PEAK_GBS, 4),
+        "config": "node V_L, cycle-2 composed dirty / PSF (Eq. 7), %d^2, S = {0, 4, 12} px, "
+                  "gain 0.1, K = 2000, FP64" % n}
+    local = torch.empty((n, n), device="cuda")
+    h.major_cycle(0, model[0], rho[0], gammas[0], mus[0], local_out=local)
+    start = torch.tensor(np.random.default_rng(7).standard_normal((n, n)), dtype=torch.float32,
+                         device="cuda")
+    h.minor_cycle_fista(0, local, start, rho_other=rho[0], n_iter=2, power_iters=2, gamma_n=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.minor_cycle_fista(0, local, start, rho_other=rho[0], n_iter=200, power_iters=30,
+                        gamma_n=1.0)
+    t_fista = time.perf_counter() - t0
+    out["fista"] = {
+        "ms": round(1e3 * t_fista, 2), "iterations": 200, "power_iterations": 30,
+        "ms_per_iteration": round(1e3 * t_fista / 230, 3),
+        "config": "node V_L, Eq. 5 with gamma_n = 1, %d^2, db8 3 levels, lambda = 1e-3 "
+                  "max |i~|, FP64 transforms" % n}
+    log("minor cycles: msCLEAN %.1f ms (%d iterations), FISTA %.1f ms (200 + 30 power)"
+        % (1e3 * t_msc, len(comps), 1e3 * t_fista))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +158,7 @@ def main():
     ap.add_argument("--workload", default="decentral")
     ap.add_argument("--cpu-sample-times", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-minor-cycles", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the steps, run a plain device copy of this many MiB three "
                          "times (a known-size kernel to scale hardware byte counters by)")
@@ -261,6 +307,8 @@ def main():
         "cycle_hbm_frac": round(cycle_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
     }
+    if not args.no_minor_cycles:
+        res["minor_cycles"] = minor_cycles(h, info, model, rho, gammas, mus, n)
     h.destroy()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample) ...")
