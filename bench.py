@@ -150,6 +150,111 @@ def minor_cycles(h, info, model, rho, gammas, mus, n):
     return out
 
 
+def batched_channels(args):
+    """Batched-channel workload: the major cycle (Eq. 2) of every channel of
+    a 64-channel observation (0.95 - 1.75 GHz, 256 antennas, 480 times,
+    flags 0-60 % per channel, images 512 / 1024 / 2048), one partition per
+    channel.  Support from the 1e-5 accuracy rule, tile and chunk cap from
+    the create-time autotuner on the largest channel, then the chunk cap
+    re-tuned over the fused launch.  Times the fused batch as a replayed HIP
+    graph, the same eagerly, and the per-channel launch loop."""
+    import numpy as np
+    import torch
+    from paper_2507_22128_amd import imager, synth
+    t0 = time.perf_counter()
+    cfg = dict(synth.CHANNELS)
+    cfg["n_chan"] = args.batch_channels
+    d = synth.make_channels(device="cuda", **cfg)
+    torch.cuda.synchronize()
+    chans = d["channels"]
+    n_ok = [int((c["flag"] == 0).sum().item()) for c in chans]
+    log("batch: %d channels generated in %.1f s, %d - %d unflagged visibilities per channel"
+        % (len(chans), time.perf_counter() - t0, min(n_ok), max(n_ok)))
+
+    def mk(c, **kw):
+        return imager.Imager.create(uvw=d["uvw"], vis=c["vis"], freq_hz=c["freq_hz"],
+                                    cell=c["cell"], n_pix=c["n_img"], flag=c["flag"],
+                                    n_partitions=1, weighting="uniform", **kw)
+
+    t0 = time.perf_counter()
+    first = int(np.argmax(n_ok))
+    members = [None] * len(chans)
+    members[first] = mk(chans[first], support=0, tolerance=1e-5, autotune=True)
+    i0 = members[first].info
+    tune_log = members[first].tune_log()
+    for k, c in enumerate(chans):
+        if members[k] is None:
+            members[k] = mk(c, support=i0.support, tile=i0.tile, chunk=i0.chunk)
+    create_s = time.perf_counter() - t0
+    for c in chans:  # the handles hold their own copies
+        c["vis"] = c["flag"] = None
+    torch.cuda.empty_cache()
+    b = imager.Batch(members)
+    chosen, cap_ms = b.autotune()
+    info = b.info()
+    log("batch: %d members created in %.1f s (support %d, tile %d from the create tuner), "
+        "chunk cap %d from the batch tuner %s" % (len(members), create_s, i0.support, i0.tile,
+                                                 chosen, cap_ms))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    models = []
+    for m in members:
+        n = m.n_pix
+        x = torch.zeros(n * n, device="cuda")
+        idx = torch.randint(0, n * n, (200,), generator=g, device="cuda")
+        x[idx] = torch.rand(200, generator=g, device="cuda")
+        models.append(x.view(n, n))
+    res = [torch.empty((m.n_pix, m.n_pix), device="cuda") for m in members]
+    out = {}
+    last = {}
+    for name, mode in (("fused_graph", dict(graph=True)), ("fused_eager", {}),
+                       ("per_channel_loop", dict(loop=True))):
+        for _ in range(args.warmup):
+            b.major_cycle(models, res, **mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            b.major_cycle(models, res, **mode)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.batch_steps
+        out[name] = {"ms_per_cycle": round(ms, 3),
+                     "mvis_per_s": round(info.n_vis / (ms / 1e3) / 1e6, 1)}
+        last[name] = [r.clone() for r in res]
+        log("batch %s: %.3f ms per cycle of all channels, %.0f Mvis/s"
+            % (name, ms, info.n_vis / (ms / 1e3) / 1e6))
+    same = all(torch.equal(a, c) for a, c in zip(last["fused_graph"], last["per_channel_loop"]))
+    sizes = [m.n_pix for m in members]
+    t_win = cap_ms[chosen] / 1e3
+    flops = flops_per_vis(i0.support) * info.n_vis
+    out.update({
+        "workload": "%d channels %.2f - %.2f GHz, %d antennas x %d times (%d visibilities per "
+                    "channel before flags), flags uniform 0 - %.0f %% per channel, images %s, "
+                    "complex64, uniform weighting, 1 partition per channel"
+                    % (len(chans), cfg["f_lo"] / 1e9, cfg["f_hi"] / 1e9, cfg["n_ant"],
+                       cfg["n_time"], d["n_vis"], 100 * cfg["flag_max"],
+                       "/".join(str(x) for x in cfg["sizes"])),
+        "n_channels": len(members),
+        "n_vis": int(info.n_vis),
+        "image_sizes": {str(x): sizes.count(x) for x in sorted(set(sizes))},
+        "support": i0.support, "tile": i0.tile, "chunk": chosen,
+        "n_chunks_fused": int(info.n_chunks),
+        "create_tuner": [{"tile": t, "chunk": c, "ms": round(x, 4)} for t, c, x in tune_log],
+        "batch_tuner_ms": {str(k): round(v, 4) for k, v in cap_ms.items()},
+        "fused_window_flush_ms": round(cap_ms[chosen], 4),
+        "fused_window_flush_tflops": round(flops / t_win / 1e12, 2),
+        "speedup_graph_vs_loop": round(out["per_channel_loop"]["ms_per_cycle"]
+                                       / out["fused_graph"]["ms_per_cycle"], 3),
+        "graph_equals_loop_bitwise": bool(same),
+        "create_s": round(create_s, 1),
+    })
+    b.destroy()
+    for m in members:
+        m.destroy()
+    del d
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +264,9 @@ def main():
     ap.add_argument("--cpu-sample-times", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-minor-cycles", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-channels", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the steps, run a plain device copy of this many MiB three "
                          "times (a known-size kernel to scale hardware byte counters by)")
@@ -310,6 +418,8 @@ def main():
     if not args.no_minor_cycles:
         res["minor_cycles"] = minor_cycles(h, info, model, rho, gammas, mus, n)
     h.destroy()
+    if not args.no_batch:
+        res["batched_channels"] = batched_channels(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample) ...")
         res["cpu_baseline"] = cpu_baseline(args, gm)

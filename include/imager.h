@@ -100,6 +100,16 @@ typedef struct {
   int32_t flags;        /* reserved, 0 */
   size_t hbm_budget;    /* bytes of device memory the handle may hold; 0 = no cap */
   void *stream;         /* hipStream_t for all work; NULL = the null stream */
+  int32_t autotune;     /* 1: choose tile and chunk (those left 0) at create by
+                           timing one degrid / grid launch plus flush of the
+                           first partition for every candidate (imager_tune_log) */
+  double tolerance;     /* > 0 with support == 0: support = the smallest built W
+                           with 3 x 10^(1 - W) <= tolerance.  The relative error
+                           of the exponential-of-semicircle kernel with beta =
+                           2.30 W on a 2x padded grid falls by about a decade per
+                           tap (Barnett, Magland and af Klinteberg 2019), and is
+                           1.0 - 2.3 x 10^(1 - W) for W = 4 .. 12 against the
+                           direct sum; EINVAL if no built support reaches it */
 } imgr_config;
 
 typedef struct {
@@ -122,6 +132,7 @@ typedef struct {
   double sum_w[2];      /* summed imaging weights per partition (FP64) */
   size_t device_bytes;  /* device memory held by the handle */
   double create_ms;     /* wall time of imager_create */
+  int32_t chunk;        /* max visibilities per work chunk (after tuning) */
 } imgr_info;
 
 /* Build a handle: scale (u, v) in FP64, drop flagged visibilities, apply the
@@ -351,6 +362,72 @@ typedef struct {
 
 imgr_status imager_set_timing(imgr_t h, int32_t enable);
 imgr_status imager_get_timing(imgr_t h, imgr_timing *out);
+
+/* Candidates timed by the create-time autotuner (imgr_config.autotune):
+ * entry i < *n has tile[i], chunk[i] and ms[i], the least device time in
+ * milliseconds of one fused degrid / grid launch plus its flush on the
+ * first partition with a zero model.  At most cap entries are written; *n
+ * receives the number of candidates (0 without autotune).  Host arrays. */
+imgr_status imager_tune_log(imgr_t h, int32_t cap, int32_t *tile, int32_t *chunk, float *ms,
+                            int32_t *n);
+
+/* Cut the work chunks of every partition again for cap `chunk` (>= 16)
+ * from the existing sort: the same tables as imager_create with that
+ * chunk, so results equal such a handle's bit for bit.  Synchronous. */
+imgr_status imager_set_chunk(imgr_t h, int32_t chunk);
+
+/* ------------------------------------------------------------------ batches
+ * Frequency channels are the axis along which imaging work is usually
+ * spread (Section 1); a batch runs the major cycles (Eq. 2) of many
+ * single-partition handles, e.g. one per channel with its own image size,
+ * cell and flags, with the de/gridding of ALL of them as one fused launch
+ * over every channel's chunks (largest chunks first across channels) and
+ * one fused flush, while the FFT stages run per channel on the same
+ * stream.  Members must have one partition, equal support and tile, and
+ * one stream, on which the batch enqueues its work.  The caller owns the
+ * members; they must outlive the batch.  The batch uses the members' work
+ * buffers, so a member's own calls and batch calls must be ordered (they
+ * are when issued from one thread: all go to the shared stream). */
+typedef struct imgr_batch_s *imgr_batch_t;
+
+/* imager_batch_major_cycle flags */
+enum {
+  IMGR_BATCH_GRAPH = 1, /* capture the cycle into a HIP graph once per distinct set of
+                           model / residual pointers (or after a re-chunk) and replay it */
+  IMGR_BATCH_LOOP = 2   /* per-member launches, one member after another (the
+                           per-channel loop the fused form is compared with) */
+};
+
+typedef struct {
+  int32_t n_members, support, tile, chunk;
+  int64_t n_vis;        /* member visibilities over all members */
+  int64_t n_chunks;     /* chunks of the fused launch */
+  int32_t graph_ready;  /* 1 if a captured graph is held */
+} imgr_batch_info;
+
+/* members: host array of n >= 1 handles.  Synchronous. */
+imgr_status imager_batch_create(const imgr_t *members, int32_t n, imgr_batch_t *out);
+imgr_status imager_batch_destroy(imgr_batch_t b);
+imgr_status imager_batch_info(imgr_batch_t b, imgr_batch_info *out);
+
+/* residual[i] (device N_i x N_i float32) = the residual image of Eq. 2 for
+ * member i and model[i] (device N_i x N_i float32), equal bit for bit to
+ * imager_major_cycle of that member alone, in every mode.  model, residual:
+ * host arrays of n_members device pointers; residual buffers must not
+ * overlap each other or any model. */
+imgr_status imager_batch_major_cycle(imgr_batch_t b, const float *const *model,
+                                     float *const *residual, int32_t flags);
+
+/* Chunk-cap autotuner of the fused launch: for each caps[i] (>= 16) every
+ * member is re-chunked (imager_set_chunk) and the fused degrid / grid
+ * launch plus flush is timed (least of reps >= 1 runs, zero models);
+ * ms[i] (host, may be NULL) receives the times, and the fastest cap is
+ * applied to all members and returned in *chosen.  Synchronous. */
+imgr_status imager_batch_autotune(imgr_batch_t b, const int32_t *caps, int32_t n_caps,
+                                  int32_t reps, float *ms, int32_t *chosen);
+
+/* Message for the last failure on b.  Never NULL. */
+const char *imager_batch_last_error(imgr_batch_t b);
 
 /* Wait for all work enqueued on the handle's stream. */
 imgr_status imager_sync(imgr_t h);

@@ -95,14 +95,6 @@ static void fail(imgr_s *h, const Error &e) {
   if (e.code == IMGR_EDEVICE) h->broken = true;
 }
 
-static void free_bins(imgr_s *h, Bins &B) {
-  for (void *q : {(void *)B.posvis, (void *)B.w, (void *)B.orig, (void *)B.outpos,
-                  (void *)B.chunk_block, (void *)B.chunk_begin, (void *)B.block_chunk,
-                  (void *)B.order})
-    dev_free(h, q);
-  B = Bins();
-}
-
 // PSF of partition p: unit visibilities gridded on the 2 Ng grid (same cell
 // size), transformed to the 2N x 2N image and normalised by sum(w); then
 // its plain DFT for the H x products of Eq. 7
@@ -173,7 +165,7 @@ static void check_cycle_args(imgr_s *h, int part, const float *model, const floa
 
 // One node's major cycle (Eq. 2 then Eq. 7) enqueued on stream s with the
 // node's own work buffers; stage events are recorded on s when timing is on.
-static void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other,
+void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other,
                        double gamma, double mu, float *residual_out, float *residual_local_out,
                        int flags, hipStream_t s) {
   const Partition &P = h->part[part];
@@ -210,6 +202,27 @@ static void node_cycle(imgr_s *h, int part, const float *model, const float *rho
                             hipMemcpyDeviceToDevice, s));
   }
   mark(5);
+}
+
+// re-cut every partition's chunks for cap C and grow the chunk-window
+// scratch when needed
+void set_chunk(imgr_s *h, int C) {
+  hipStream_t s = h->stream;
+  IMGR_HIP(hipStreamSynchronize(s));
+  for (int p = 0; p < h->n_parts; ++p) {
+    Bins &B = h->part[p].bins;
+    rechunk(h, B, C, s);
+    const size_t nc = (size_t)std::max(B.n_chunks, 1);
+    if (nc > h->scratch_chunks[p]) {
+      dev_free(h, h->work[p].scratch);
+      h->work[p].scratch = nullptr;
+      h->scratch_chunks[p] = 0;
+      h->work[p].scratch = (float2 *)dev_alloc(h, nc * kWin * kWin * sizeof(float2));
+      h->scratch_chunks[p] = nc;
+    }
+  }
+  h->C = C;
+  ++h->layout_version;
 }
 
 }  // namespace imgr
@@ -252,7 +265,12 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
                "n_pix must be a power of two in [64, 2048]");
     h->N = cfg->n_pix;
     h->Ng = 2 * h->N;
-    h->W = cfg->support ? cfg->support : 8;
+    if (cfg->support == 0 && cfg->tolerance > 0) {
+      h->W = support_for_tolerance(cfg->tolerance);
+      IMGR_CHECK(h->W > 0, "no built support reaches the requested tolerance");
+    } else {
+      h->W = cfg->support ? cfg->support : 8;
+    }
     IMGR_CHECK(h->W == 4 || h->W == 6 || h->W == 8 || h->W == 10 || h->W == 12,
                "support must be 4, 6, 8, 10 or 12");
     h->beta = cfg->es_beta > 0 ? cfg->es_beta : 2.30 * h->W;
@@ -262,6 +280,9 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
                "tile + support - 1 must not exceed 16 (the footprint window)");
     h->C = cfg->chunk ? cfg->chunk : 1024;
     IMGR_CHECK(h->C >= 16 && h->C <= (1 << 20), "chunk must be in [16, 2^20]");
+    h->tune = cfg->autotune != 0 && (cfg->tile == 0 || cfg->chunk == 0);
+    h->tile_fixed = cfg->tile;
+    h->chunk_fixed = cfg->chunk;
     IMGR_CHECK(cfg->n_partitions == 1 || cfg->n_partitions == 2, "n_partitions must be 1 or 2");
     h->n_parts = cfg->n_partitions;
     IMGR_CHECK(cfg->weighting == IMGR_WEIGHT_NATURAL || cfg->weighting == IMGR_WEIGHT_UNIFORM,
@@ -315,6 +336,7 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
     for (int p = 0; p < h->n_parts; ++p) {
       const size_t nc = (size_t)std::max(h->part[p].bins.n_chunks, 1);
       h->work[p].scratch = (float2 *)dev_alloc(h, nc * kWin * kWin * sizeof(float2));
+      h->scratch_chunks[p] = nc;
     }
     if (h->n_parts == 2) {
       IMGR_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
@@ -371,7 +393,30 @@ imgr_status imager_info(imgr_t h, imgr_info *o) {
   }
   o->device_bytes = h->bytes;
   o->create_ms = h->create_ms;
+  o->chunk = h->C;
   return IMGR_OK;
+}
+
+imgr_status imager_tune_log(imgr_t h, int32_t cap, int32_t *tile, int32_t *chunk, float *ms,
+                            int32_t *n) {
+  API_BEGIN(h)
+  IMGR_CHECK(n != nullptr && cap >= 0, "bad arguments");
+  IMGR_CHECK(cap == 0 || (tile && chunk && ms), "null output array");
+  const int k = (int)h->tune_log.size();
+  for (int i = 0; i < k && i < cap; ++i) {
+    tile[i] = h->tune_log[i].blk;
+    chunk[i] = h->tune_log[i].C;
+    ms[i] = h->tune_log[i].ms;
+  }
+  *n = k;
+  API_END(h)
+}
+
+imgr_status imager_set_chunk(imgr_t h, int32_t chunk) {
+  API_BEGIN(h)
+  IMGR_CHECK(chunk >= 16 && chunk <= (1 << 20), "chunk must be in [16, 2^20]");
+  set_chunk(h, chunk);
+  API_END(h)
 }
 
 static void check_part(imgr_s *h, int part) {

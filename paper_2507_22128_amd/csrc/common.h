@@ -139,6 +139,16 @@ struct imgr_s {
   bool timing = false;
   std::vector<std::vector<hipEvent_t>> ev_sets;
   std::vector<hipEvent_t> ev_pool;
+  // work layout autotuner (create time): candidates tried and their times
+  bool tune = false;
+  int tile_fixed = 0, chunk_fixed = 0;  // nonzero: not tuned
+  struct TuneEntry {
+    int blk, C;
+    float ms;
+  };
+  std::vector<TuneEntry> tune_log;
+  size_t scratch_chunks[2] = {0, 0};  // capacity of work[p].scratch in chunk windows
+  uint64_t layout_version = 0;        // bumped whenever chunk tables or scratch change
   // bookkeeping
   std::vector<void *> allocs;
   std::vector<size_t> alloc_sizes;
@@ -177,6 +187,21 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 // ----------------------------------------------------------------- prep (a0)
 void prep_build(imgr_s *h, const imgr_vis *vis);
+void free_bins(imgr_s *h, Bins &B);
+// rechunk every partition of h for cap C (imager_set_chunk)
+void set_chunk(imgr_s *h, int C);
+// one node's major cycle enqueued on s (imager_major_cycle)
+void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other, double gamma,
+                double mu, float *residual_out, float *residual_local_out, int flags,
+                hipStream_t s);
+// device time (ms) of one degrid / grid launch plus flush over bins B
+float time_layout(imgr_s *h, const Bins &B, float2 *grid, float2 *scr, int reps, hipStream_t s);
+// chunk indices in decreasing chunk size, ties in index order (cb: chunk
+// starts with the closing entry)
+std::vector<int32_t> largest_first(const std::vector<int32_t> &cb);
+// support W for a target relative accuracy on a 2x padded grid: the
+// smallest built support with 3 x 10^(1 - W) <= tol, or 0 if none
+int support_for_tolerance(double tol);
 
 // ----------------------------------------------------------------- FFT
 // centred forward transform of an N x N real image (times 1/psi_hat on both
@@ -223,6 +248,39 @@ void flush_chunks(imgr_s *h, const Bins &b, const float2 *scratch, float2 *grid_
                   hipStream_t s);
 // whether kernels exist for support W with blocks of blk cells
 bool window_supported(int W, int blk);
+
+// arguments of the window kernel for one grid (one partition's bins)
+struct WinArgs {
+  const float4 *posvis;
+  const float *wts;
+  const int32_t *outpos;
+  const int32_t *chunk_block;
+  const int32_t *chunk_begin;
+  int nb, ng;
+  float bl2e;
+  const float2 *grid_in;
+  const float2 *vis_in;
+  float2 *vis_out;
+  float2 *scratch;
+};
+// arguments of the flush of one grid
+struct FlushArgs {
+  const float2 *scratch;
+  const int32_t *block_chunk;
+  int nb, ng;
+  float2 *grid_out;
+};
+WinArgs win_args(const imgr_s *h, const Bins &B, const float2 *grid_in, const float2 *vis_in,
+                 float2 *vis_out, float2 *scratch);
+// fused degrid / residual / grid over the chunks of many grids: order[i] =
+// (grid, chunk) with grids[] device descriptors; all grids share W and blk
+void degrid_grid_batch(int W, int blk, const WinArgs *grids, const int2 *order, int n_slots,
+                       hipStream_t s);
+// flush of many grids: grid g owns workgroups [group_start[g], group_start[g+1])
+void flush_batch(int W, int blk, const FlushArgs *grids, const int32_t *group_start, int n_grids,
+                 int n_groups, hipStream_t s);
+// rebuild the chunk tables of bins B for a new chunk cap C (the sort stays)
+void rechunk(imgr_s *h, Bins &B, int C, hipStream_t s);
 
 // ----------------------------------------------------------------- composition
 void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma, double mu,

@@ -56,13 +56,8 @@ __device__ __forceinline__ float sum_rows(float v) {
 __device__ __forceinline__ int xslot(int p) { return ((p & 3) << 2) | (p >> 2); }
 
 template <int W, int BLK, int MODE>
-__global__ __launch_bounds__(64 * kWaves) void k_window(
-    const float4 *__restrict__ posvis, const float *__restrict__ wts,
-    const int32_t *__restrict__ outpos, const int32_t *__restrict__ chunk_block,
-    const int32_t *__restrict__ chunk_begin, const int32_t *__restrict__ order, int n_chunks,
-    int nb, int ng, float bl2e, const float2 *__restrict__ grid_in,
-    const float2 *__restrict__ vis_in, float2 *__restrict__ vis_out,
-    float2 *__restrict__ scratch) {
+__device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float *kx_t, float *ky_t,
+                                             float2 *r_t) {
   static_assert(BLK + W - 1 <= kWin, "footprints of a block must fit the window");
   constexpr int H = W / 2 - 1;
   constexpr int TPL = (W + 3) / 4;  // taps per lane and axis
@@ -70,31 +65,28 @@ __global__ __launch_bounds__(64 * kWaves) void k_window(
   constexpr bool kDegrid = (MODE == MODE_DEGRID_GRID || MODE == MODE_DEGRID);
   constexpr bool kGrid = (MODE != MODE_DEGRID);
   constexpr bool kCplx = (MODE != MODE_PSF);
-  // per wave and batch: tap weights of the 16 visibilities over the 16
-  // window positions (x in xslot order, y in natural order), residuals
-  __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
-  __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
-  __shared__ float2 r_s[kWaves][16];
+  const float4 *__restrict__ posvis = a.posvis;
+  const float *__restrict__ wts = a.wts;
+  const int32_t *__restrict__ outpos = a.outpos;
+  const float2 *__restrict__ grid_in = a.grid_in;
+  const float2 *__restrict__ vis_in = a.vis_in;
+  float2 *__restrict__ vis_out = a.vis_out;
+  float2 *__restrict__ scratch = a.scratch;
+  const int nb = a.nb, ng = a.ng;
+  const float bl2e = a.bl2e;
 
-  const int wave = threadIdx.x >> 6;
   const int l = threadIdx.x & 63, c16 = l & 15, g = l >> 4;
-  const int slot = blockIdx.x * kWaves + wave;
-  if (slot >= n_chunks) return;  // the wave has no chunk; no other wave waits for it
-  float *kx_t = kx_s[wave];
-  float *ky_t = ky_s[wave];
-  float2 *r_t = r_s[wave];
-  const int chunk = order[slot];
-  const int blk = chunk_block[chunk];
+  const int blk = a.chunk_block[chunk];
   const int wx0 = (blk % nb) * BLK - H, wy0 = (blk / nb) * BLK - H;
 
   // 1 - z^2 of this lane's taps as quadratics in the fraction f:
-  // alpha + beta f - kC^2 f^2 with a = t - H
+  // alpha + beta f - kC^2 f^2 with t0 = t - H
   float qa[TPL], qb[TPL];
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
-    const float a = (float)(g * TPL + q - H);
-    qa[q] = 1.0f - kC * kC * a * a;
-    qb[q] = 2.0f * kC * kC * a;
+    const float t0 = (float)(g * TPL + q - H);
+    qa[q] = 1.0f - kC * kC * t0 * t0;
+    qb[q] = 2.0f * kC * kC * t0;
   }
   constexpr float qc = -kC * kC;
 
@@ -113,7 +105,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_window(
   }
   floatx4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
 
-  const int b = chunk_begin[chunk], e = chunk_begin[chunk + 1];
+  const int b = a.chunk_begin[chunk], e = a.chunk_begin[chunk + 1];
   // lane (c16, g) works on visibility c16 of each batch; the record of the
   // next batch is loaded while the current one is processed (indices past
   // the chunk are clamped to its last visibility and masked by `valid`)
@@ -211,19 +203,51 @@ __global__ __launch_bounds__(64 * kWaves) void k_window(
   }
 }
 
+// one partition's chunks, launch order `order` (largest first)
+template <int W, int BLK, int MODE>
+__global__ __launch_bounds__(64 * kWaves) void k_window(WinArgs a, const int32_t *__restrict__ order,
+                                                       int n_chunks) {
+  // per wave and batch: tap weights of the 16 visibilities over the 16
+  // window positions (x in xslot order, y in natural order), residuals
+  __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
+  __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
+  __shared__ float2 r_s[kWaves][16];
+  const int wave = threadIdx.x >> 6;
+  const int slot = blockIdx.x * kWaves + wave;
+  if (slot >= n_chunks) return;  // the wave has no chunk; no other wave waits for it
+  window_chunk<W, BLK, MODE>(a, order[slot], kx_s[wave], ky_s[wave], r_s[wave]);
+}
+
+// the chunks of many grids (channels) in one launch: order[slot] = (grid,
+// chunk), largest chunks of all grids first
+template <int W, int BLK, int MODE>
+__global__ __launch_bounds__(64 * kWaves) void k_window_batch(const WinArgs *__restrict__ grids,
+                                                             const int2 *__restrict__ order,
+                                                             int n_slots) {
+  __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
+  __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
+  __shared__ float2 r_s[kWaves][16];
+  const int wave = threadIdx.x >> 6;
+  // wave-uniform, so the descriptor is read through scalar loads
+  const int slot = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
+  if (slot >= n_slots) return;
+  const int2 gc = order[slot];
+  const WinArgs a = grids[gc.x];
+  window_chunk<W, BLK, MODE>(a, gc.y, kx_s[wave], ky_s[wave], r_s[wave]);
+}
+
 // One thread per grid cell, 16 x 16 cells per workgroup: FP64 sum over the
 // chunk windows of the blocks whose window covers the cell (fixed order:
 // block row offset, block column offset, chunk), times (-1)^(x + y) for the
 // centred inverse DFT that follows.
 template <int W, int BLK>
-__global__ __launch_bounds__(256) void k_flush(const float2 *__restrict__ scratch,
-                                               const int32_t *__restrict__ block_chunk, int nb,
-                                               int ng, float2 *__restrict__ grid_out) {
+__device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
   constexpr int H = W / 2 - 1;
   constexpr int R = kWin / BLK;
+  const int nb = a.nb, ng = a.ng;
   const int nq = ng / 16;
-  const int cx = (blockIdx.x % nq) * 16 + (threadIdx.x & 15);
-  const int cy = (blockIdx.x / nq) * 16 + (threadIdx.x >> 4);
+  const int cx = (group % nq) * 16 + (threadIdx.x & 15);
+  const int cy = (group / nq) * 16 + (threadIdx.x >> 4);
   const int bx = cx / BLK, by = cy / BLK, lx = cx % BLK, ly = cy % BLK;
   double re = 0.0, im = 0.0;
 #pragma unroll
@@ -236,27 +260,45 @@ __global__ __launch_bounds__(256) void k_flush(const float2 *__restrict__ scratc
       const int wx = lx + H - dbx * BLK;
       if (wx < 0 || wx >= kWin) continue;
       const int n = nby * nb + (bx + dbx + nb) % nb;
-      const int c0 = block_chunk[n], c1 = block_chunk[n + 1];
+      const int c0 = a.block_chunk[n], c1 = a.block_chunk[n + 1];
       for (int c = c0; c < c1; ++c) {
-        const float2 v = scratch[(size_t)c * (kWin * kWin) + wy * kWin + wx];
+        const float2 v = a.scratch[(size_t)c * (kWin * kWin) + wy * kWin + wx];
         re += (double)v.x;
         im += (double)v.y;
       }
     }
   }
   const float sg = ((cx + cy) & 1) ? -1.f : 1.f;
-  grid_out[(size_t)cy * ng + cx] = make_float2(sg * (float)re, sg * (float)im);
+  a.grid_out[(size_t)cy * ng + cx] = make_float2(sg * (float)re, sg * (float)im);
+}
+
+template <int W, int BLK>
+__global__ __launch_bounds__(256) void k_flush(FlushArgs a) {
+  flush_group<W, BLK>(a, blockIdx.x);
+}
+
+// the flushes of many grids in one launch: grid g owns the workgroups
+// [group_start[g], group_start[g + 1])
+template <int W, int BLK>
+__global__ __launch_bounds__(256) void k_flush_batch(const FlushArgs *__restrict__ grids,
+                                                     const int32_t *__restrict__ group_start,
+                                                     int n_grids) {
+  // the last g with group_start[g] <= blockIdx.x (binary search)
+  int lo = 0, hi = n_grids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (group_start[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  flush_group<W, BLK>(grids[lo], blockIdx.x - group_start[lo]);
 }
 
 template <int W, int BLK>
 void launch_window(imgr_s *h, const Bins &B, int mode, const float2 *grid_in,
                    const float2 *vis_in, float2 *vis_out, float2 *scratch, hipStream_t s) {
-  const float bl2e = (float)(h->beta * 1.4426950408889634);
+  const WinArgs a = win_args(h, B, grid_in, vis_in, vis_out, scratch);
   dim3 grid(cdiv(B.n_chunks, kWaves)), block(64 * kWaves);
-#define L_(M)                                                                                   \
-  hipLaunchKernelGGL((k_window<W, BLK, M>), grid, block, 0, s, B.posvis, B.w, B.outpos,           \
-                     B.chunk_block, B.chunk_begin, B.order, B.n_chunks, B.nb, B.ng, bl2e,         \
-                     grid_in, vis_in, vis_out, scratch)
+#define L_(M) hipLaunchKernelGGL((k_window<W, BLK, M>), grid, block, 0, s, a, B.order, B.n_chunks)
   switch (mode) {
     case MODE_DEGRID_GRID: L_(MODE_DEGRID_GRID); break;
     case MODE_GRID: L_(MODE_GRID); break;
@@ -270,8 +312,22 @@ void launch_window(imgr_s *h, const Bins &B, int mode, const float2 *grid_in,
 template <int W, int BLK>
 void launch_flush(const Bins &B, const float2 *scratch, float2 *out, hipStream_t s) {
   const int nq = B.ng / 16;
-  hipLaunchKernelGGL((k_flush<W, BLK>), dim3(nq * nq), dim3(256), 0, s, scratch, B.block_chunk,
-                     B.nb, B.ng, out);
+  FlushArgs a{scratch, B.block_chunk, B.nb, B.ng, out};
+  hipLaunchKernelGGL((k_flush<W, BLK>), dim3(nq * nq), dim3(256), 0, s, a);
+}
+
+template <int W, int BLK>
+void launch_window_batch(const WinArgs *grids, const int2 *order, int n_slots, hipStream_t s) {
+  dim3 grid(cdiv(n_slots, kWaves)), block(64 * kWaves);
+  hipLaunchKernelGGL((k_window_batch<W, BLK, MODE_DEGRID_GRID>), grid, block, 0, s, grids, order,
+                     n_slots);
+}
+
+template <int W, int BLK>
+void launch_flush_batch(const FlushArgs *grids, const int32_t *group_start, int n_grids,
+                        int n_groups, hipStream_t s) {
+  hipLaunchKernelGGL((k_flush_batch<W, BLK>), dim3(n_groups), dim3(256), 0, s, grids, group_start,
+                     n_grids);
 }
 
 // (W, blk) pairs the library is built for: blk + W - 1 <= 16
@@ -296,6 +352,51 @@ void degrid_grid(imgr_s *h, const Bins &B, int mode, const float2 *grid_in, cons
     launch_window<w, b>(h, B, mode, grid_in, vis_in, vis_out, scratch, s);               \
     IMGR_HIP(hipGetLastError());                                                         \
     return;                                                                              \
+  }
+  IMGR_WB_CASES(C_)
+#undef C_
+  throw Error{IMGR_EINVAL, "unsupported support / block combination"};
+}
+
+WinArgs win_args(const imgr_s *h, const Bins &B, const float2 *grid_in, const float2 *vis_in,
+                 float2 *vis_out, float2 *scratch) {
+  WinArgs a;
+  a.posvis = B.posvis;
+  a.wts = B.w;
+  a.outpos = B.outpos;
+  a.chunk_block = B.chunk_block;
+  a.chunk_begin = B.chunk_begin;
+  a.nb = B.nb;
+  a.ng = B.ng;
+  a.bl2e = (float)(h->beta * 1.4426950408889634);
+  a.grid_in = grid_in;
+  a.vis_in = vis_in;
+  a.vis_out = vis_out;
+  a.scratch = scratch;
+  return a;
+}
+
+void degrid_grid_batch(int W, int blk, const WinArgs *grids, const int2 *order, int n_slots,
+                       hipStream_t s) {
+  if (n_slots == 0) return;
+#define C_(w, b)                                                 \
+  if (W == w && blk == b) {                                      \
+    launch_window_batch<w, b>(grids, order, n_slots, s);         \
+    IMGR_HIP(hipGetLastError());                                 \
+    return;                                                      \
+  }
+  IMGR_WB_CASES(C_)
+#undef C_
+  throw Error{IMGR_EINVAL, "unsupported support / block combination"};
+}
+
+void flush_batch(int W, int blk, const FlushArgs *grids, const int32_t *group_start, int n_grids,
+                 int n_groups, hipStream_t s) {
+#define C_(w, b)                                                              \
+  if (W == w && blk == b) {                                                   \
+    launch_flush_batch<w, b>(grids, group_start, n_grids, n_groups, s);       \
+    IMGR_HIP(hipGetLastError());                                              \
+    return;                                                                   \
   }
   IMGR_WB_CASES(C_)
 #undef C_

@@ -432,11 +432,7 @@ void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member
                               hipMemcpyDeviceToHost, s));
     IMGR_HIP(hipStreamSynchronize(s));
     cb[B.n_chunks] = (int32_t)n;
-    std::vector<int32_t> ord(B.n_chunks);
-    for (int c = 0; c < B.n_chunks; ++c) ord[c] = c;
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-      return cb[a + 1] - cb[a] > cb[b + 1] - cb[b];
-    });
+    const std::vector<int32_t> ord = largest_first(cb);
     B.order = alloc_n<int32_t>(h, B.n_chunks);
     if (B.n_chunks > 0)
       IMGR_HIP(hipMemcpyAsync(B.order, ord.data(), B.n_chunks * sizeof(int32_t),
@@ -459,6 +455,52 @@ void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member
   for (void *q : {(void *)keys, (void *)ktmp, (void *)vals, (void *)vtmp, (void *)cnt,
                   (void *)bstart, (void *)nch})
     dev_free(h, q);
+}
+
+// Create-time autotuner of the work layout: for each candidate block side
+// (tile) the members of the first partition are binned, and for each
+// candidate chunk cap the chunk tables are cut again from the same sort;
+// the pair with the least device time of one degrid / grid launch plus its
+// flush wins and is kept in h->blk, h->C.  Results of every candidate are
+// the same operator up to the FP32 summation order inside a chunk.
+void tune_layout(imgr_s *h, int64_t m, int64_t n, const int32_t *member, const int32_t *rank,
+                 const double *gx, const double *gy, const double *w64, const void *vis_dev,
+                 int c128, hipStream_t s) {
+  std::vector<int> blks, caps;
+  for (int b : {8, 4})
+    if ((h->tile_fixed == 0 || h->tile_fixed == b) && window_supported(h->W, b)) blks.push_back(b);
+  if (h->chunk_fixed) caps.push_back(h->chunk_fixed);
+  else caps = {4096, 2048, 1024, 512, 256};
+  IMGR_CHECK(!blks.empty(), "no tile fits the support");
+  const size_t ng2 = (size_t)h->Ng * h->Ng;
+  float2 *grid = alloc_n<float2>(h, 2 * ng2);  // zero model grid, then the flush target
+  IMGR_HIP(hipMemsetAsync(grid, 0, ng2 * sizeof(float2), s));
+  h->tune_log.clear();
+  float best = 1e30f;
+  int best_blk = blks[0], best_c = caps[0];
+  for (int b : blks) {
+    h->blk = b;
+    h->C = caps[0];
+    Bins T;
+    bin_members(h, T, m, n, member, rank, gx, gy, 1.0, h->Ng, w64, vis_dev, c128, s);
+    for (int c : caps) {
+      if (c != h->C) rechunk(h, T, c, s);
+      h->C = c;
+      float2 *scr = alloc_n<float2>(h, (int64_t)std::max(T.n_chunks, 1) * kWin * kWin);
+      const float ms = time_layout(h, T, grid, scr, 3, s);
+      dev_free(h, scr);
+      h->tune_log.push_back({b, c, ms});
+      if (ms < best) {
+        best = ms;
+        best_blk = b;
+        best_c = c;
+      }
+    }
+    free_bins(h, T);
+  }
+  dev_free(h, grid);
+  h->blk = best_blk;
+  h->C = best_c;
 }
 
 void build_partition(imgr_s *h, int p, int which, int64_t m, const double *gx, const double *gy,
@@ -486,6 +528,7 @@ void build_partition(imgr_s *h, int p, int which, int64_t m, const double *gx, c
     P.sum_w = acc;
     dev_free(h, part);
   }
+  if (h->tune && p == 0) tune_layout(h, m, n, member, rank, gx, gy, w64, vis_dev, c128, s);
   // the Ng grid of the major cycle, and the 2 Ng grid of the 2N x 2N PSF
   // (same cell size, so grid coordinates double exactly)
   bin_members(h, P.bins, m, n, member, rank, gx, gy, 1.0, h->Ng, w64, vis_dev, c128, s);
@@ -495,6 +538,104 @@ void build_partition(imgr_s *h, int p, int which, int64_t m, const double *gx, c
 }
 
 }  // namespace
+
+// chunks in decreasing size, ties in index order; cb = chunk_begin with
+// its closing entry
+std::vector<int32_t> largest_first(const std::vector<int32_t> &cb) {
+  const int nc = (int)cb.size() - 1;
+  std::vector<int32_t> ord(nc);
+  for (int c = 0; c < nc; ++c) ord[c] = c;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+    return cb[a + 1] - cb[a] > cb[b + 1] - cb[b];
+  });
+  return ord;
+}
+
+// Device time of the fused degrid / residual / grid launch plus its flush
+// over bins B (zero model grid), the least of `reps` timed repetitions
+// after one untimed one.
+float time_layout(imgr_s *h, const Bins &B, float2 *grid, float2 *scr, int reps, hipStream_t s) {
+  hipEvent_t e0, e1;
+  IMGR_HIP(hipEventCreate(&e0));
+  IMGR_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (int r = 0; r <= reps; ++r) {
+    IMGR_HIP(hipEventRecord(e0, s));
+    degrid_grid(h, B, MODE_DEGRID_GRID, grid, nullptr, nullptr, scr, s);
+    flush_chunks(h, B, scr, grid + (size_t)B.ng * B.ng, s);
+    IMGR_HIP(hipEventRecord(e1, s));
+    IMGR_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    IMGR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (r > 0) best = std::min(best, ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+int support_for_tolerance(double tol) {
+  if (!(tol > 0.0) || tol >= 1.0) return 0;
+  // the kernel's relative error on a 2x padded grid is about
+  // 1.0 - 2.3 x 10^(1 - W) at beta = 2.30 W (W = 4 .. 12); a margin of 3
+  const int w = (int)std::ceil(1.0 + std::log10(3.0 / tol) - 1e-12);
+  for (int c : {4, 6, 8, 10, 12})
+    if (c >= w) return c;
+  return 0;
+}
+
+void free_bins(imgr_s *h, Bins &B) {
+  for (void *q : {(void *)B.posvis, (void *)B.w, (void *)B.orig, (void *)B.outpos,
+                  (void *)B.chunk_block, (void *)B.chunk_begin, (void *)B.block_chunk,
+                  (void *)B.order})
+    dev_free(h, q);
+  B = Bins();
+}
+
+// Cut the chunk tables of B again for cap C: block b keeps its visibilities
+// [start_b, start_b + cnt_b) and is split into ceil(cnt_b / C) near-equal
+// chunks, exactly as at create with chunk = C.
+void rechunk(imgr_s *h, Bins &B, int C, hipStream_t s) {
+  IMGR_CHECK(C >= 16, "chunk cap must be >= 16");
+  const int n_blocks = B.nb * B.nb;
+  std::vector<int32_t> bc(n_blocks + 1), cb(B.n_chunks + 1);
+  IMGR_HIP(hipMemcpyAsync(bc.data(), B.block_chunk, (n_blocks + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+  IMGR_HIP(hipMemcpyAsync(cb.data(), B.chunk_begin, (B.n_chunks + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+  IMGR_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> nbc(n_blocks + 1), ncb, ncblk;
+  for (int b = 0; b < n_blocks; ++b) {
+    nbc[b] = (int32_t)ncblk.size();
+    const int32_t c0 = bc[b], c1 = bc[b + 1];
+    if (c0 == c1) continue;
+    const int32_t start = cb[c0], cnt = cb[c1] - start;
+    const int k = (cnt + C - 1) / C;
+    for (int q = 0; q < k; ++q) {
+      ncblk.push_back(b);
+      ncb.push_back(start + (int32_t)(((int64_t)cnt * q) / k));
+    }
+  }
+  const int nc = (int)ncblk.size();
+  nbc[n_blocks] = nc;
+  ncb.push_back((int32_t)B.n);
+  const std::vector<int32_t> ord = largest_first(ncb);
+  for (void *q : {(void *)B.chunk_block, (void *)B.chunk_begin, (void *)B.order}) dev_free(h, q);
+  B.n_chunks = nc;
+  B.chunk_block = alloc_n<int32_t>(h, nc);
+  B.chunk_begin = alloc_n<int32_t>(h, nc + 1);
+  B.order = alloc_n<int32_t>(h, nc);
+  IMGR_HIP(hipMemcpyAsync(B.block_chunk, nbc.data(), (n_blocks + 1) * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+  if (nc > 0) {
+    IMGR_HIP(hipMemcpyAsync(B.chunk_block, ncblk.data(), nc * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+    IMGR_HIP(hipMemcpyAsync(B.order, ord.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  IMGR_HIP(hipMemcpyAsync(B.chunk_begin, ncb.data(), (nc + 1) * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+  IMGR_HIP(hipStreamSynchronize(s));
+}
 
 void prep_build(imgr_s *h, const imgr_vis *vis) {
   hipStream_t s = h->stream;

@@ -38,7 +38,8 @@ class Config(ctypes.Structure):
                 ("weighting", ctypes.c_int32), ("n_partitions", ctypes.c_int32),
                 ("ell_pix", ctypes.c_double), ("delta_pix", ctypes.c_double),
                 ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+                ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+                ("autotune", ctypes.c_int32), ("tolerance", ctypes.c_double)]
 
 
 class Vis(ctypes.Structure):
@@ -56,7 +57,16 @@ class Info(ctypes.Structure):
                 ("delta_pix", ctypes.c_double), ("n_valid", ctypes.c_int64),
                 ("n_vis", ctypes.c_int64 * 2), ("n_chunks", ctypes.c_int64 * 2),
                 ("sum_w", ctypes.c_double * 2), ("device_bytes", ctypes.c_size_t),
-                ("create_ms", ctypes.c_double)]
+                ("create_ms", ctypes.c_double), ("chunk", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_members", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("n_vis", ctypes.c_int64),
+                ("n_chunks", ctypes.c_int64), ("graph_ready", ctypes.c_int32)]
+
+
+BATCH_GRAPH, BATCH_LOOP = 1, 2
 
 
 _P = ctypes.c_void_p
@@ -82,6 +92,13 @@ _SIGS = {
     "imager_set_timing": [_P, _I],
     "imager_get_timing": [_P, _P],
     "imager_sync": [_P],
+    "imager_tune_log": [_P, _I, _P, _P, _P, _P],
+    "imager_set_chunk": [_P, _I],
+    "imager_batch_create": [_P, _I, ctypes.POINTER(_P)],
+    "imager_batch_destroy": [_P],
+    "imager_batch_info": [_P, ctypes.POINTER(BatchInfo)],
+    "imager_batch_major_cycle": [_P, _P, _P, _I],
+    "imager_batch_autotune": [_P, _P, _I, _I, _P, _P],
 }
 
 MAX_SCALES = 8
@@ -155,8 +172,10 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
-        L.imager_last_error.argtypes = [_P]
-        L.imager_last_error.restype = ctypes.c_char_p
+        for name in ("imager_last_error", "imager_batch_last_error"):
+            fn = getattr(L, name)
+            fn.argtypes = [_P]
+            fn.restype = ctypes.c_char_p
         _LIB = L
     return _LIB
 
@@ -184,9 +203,12 @@ class Imager:
     @classmethod
     def create(cls, data=None, *, uvw=None, vis=None, freq_hz=None, cell=None, n_pix=None,
                weight=None, flag=None, weighting="uniform", n_partitions=1, ell=-1.0, delta=1.0,
-               support=8, beta=0.0, tile=0, chunk=0, hbm_budget=0, stream=None):
+               support=8, beta=0.0, tile=0, chunk=0, hbm_budget=0, stream=None,
+               autotune=False, tolerance=0.0):
         """Build a handle from host numpy arrays or cuda tensors.  ``data`` may be
-        a dict from ``synth.make`` supplying uvw, vis, freq_hz, cell, n_pix."""
+        a dict from ``synth.make`` supplying uvw, vis, freq_hz, cell, n_pix.
+        ``support=0`` with ``tolerance > 0`` picks the support for that accuracy;
+        ``autotune`` times the candidate tiles / chunk caps left at 0."""
         import torch
         if data is not None:
             uvw = data["uvw"] if uvw is None else uvw
@@ -243,6 +265,8 @@ class Imager:
         c.flags = 0
         c.hbm_budget = int(hbm_budget)
         c.stream = ctypes.c_void_p(stream.cuda_stream)
+        c.autotune = 1 if autotune else 0
+        c.tolerance = float(tolerance)
         h = ctypes.c_void_p()
         st = L.imager_create(ctypes.byref(c), ctypes.byref(v), ctypes.byref(h))
         if st != OK:
@@ -282,6 +306,26 @@ class Imager:
         return torch.empty(shape, dtype=getattr(torch, dtype), device="cuda")
 
     # ------------------------------------------------------------ calls
+    def tune_log(self):
+        """[(tile, chunk, ms)] of the create-time autotuner."""
+        n = ctypes.c_int32()
+        self._check(lib().imager_tune_log(self._h, 0, None, None, None, ctypes.byref(n)))
+        k = n.value
+        t, c, m = np.zeros(k, np.int32), np.zeros(k, np.int32), np.zeros(k, np.float32)
+        if k:
+            self._check(lib().imager_tune_log(self._h, k, t.ctypes.data_as(_P), c.ctypes.data_as(_P),
+                                              m.ctypes.data_as(_P), ctypes.byref(n)))
+        return [(int(a), int(b), float(x)) for a, b, x in zip(t, c, m)]
+
+    def set_chunk(self, chunk):
+        self._check(lib().imager_set_chunk(self._h, int(chunk)))
+        self.refresh_info()
+
+    def refresh_info(self):
+        info = Info()
+        lib().imager_info(self._h, ctypes.byref(info))
+        self.info = info
+
     def vis_index(self, part):
         out = np.empty(self.n_vis(part), np.int64)
         self._check(lib().imager_vis_index(self._h, part, out.ctypes.data_as(ctypes.c_void_p)))
@@ -454,3 +498,74 @@ class Imager:
 
     def sync(self):
         self._check(lib().imager_sync(self._h))
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Major cycles of many single-partition handles (e.g. frequency
+    channels) with one fused de/gridding launch over all of them."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        hs = (ctypes.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        b = ctypes.c_void_p()
+        st = lib().imager_batch_create(hs, len(self.members), ctypes.byref(b))
+        if st != OK:
+            raise ImagerError(st, lib().imager_batch_last_error(None).decode())
+        self._b = b
+
+    def _check(self, st):
+        if st != OK:
+            raise ImagerError(st, lib().imager_batch_last_error(self._b).decode())
+
+    def destroy(self):
+        if self._b is not None:
+            lib().imager_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def info(self):
+        o = BatchInfo()
+        self._check(lib().imager_batch_info(self._b, ctypes.byref(o)))
+        return o
+
+    def major_cycle(self, models, residuals=None, graph=False, loop=False):
+        """residuals[i] = Eq. 2 residual of member i for models[i]."""
+        import torch
+        assert len(models) == len(self.members)
+        for m, t in zip(self.members, models):
+            _dev_f32(t, (m.n_pix, m.n_pix), torch)
+        if residuals is None:
+            residuals = [torch.empty((m.n_pix, m.n_pix), dtype=torch.float32, device="cuda")
+                         for m in self.members]
+        for m, t in zip(self.members, residuals):
+            _dev_f32(t, (m.n_pix, m.n_pix), torch)
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_LOOP if loop else 0)
+        self._keep = (models, residuals)
+        self._check(lib().imager_batch_major_cycle(self._b, _ptr_array(models),
+                                                   _ptr_array(residuals), flags))
+        return residuals
+
+    def autotune(self, caps=(256, 512, 1024, 2048, 4096), reps=3):
+        """Times the fused launch for every chunk cap, applies the fastest;
+        returns (chosen, {cap: ms})."""
+        caps_a = np.asarray(caps, np.int32)
+        ms = np.zeros(len(caps_a), np.float32)
+        chosen = ctypes.c_int32()
+        self._check(lib().imager_batch_autotune(self._b, caps_a.ctypes.data_as(_P), len(caps_a),
+                                                int(reps), ms.ctypes.data_as(_P),
+                                                ctypes.byref(chosen)))
+        for m in self.members:
+            m.refresh_info()
+        return int(chosen.value), {int(c): float(x) for c, x in zip(caps_a, ms)}

@@ -161,3 +161,87 @@ def random_uv_cells(m, n_grid, rng, frac=1.0 / 3.0):
     """Uniform random grid-relative coordinates |u|,|v| <= frac * Ng cells
     (for unit tests of the operator); returned in cells from the centre."""
     return rng.uniform(-frac * n_grid, frac * n_grid, (2, m))
+
+
+# Frequency channels of the 256-antenna array: 0.95 - 1.75 GHz, each flagged
+# uniformly at random with its own fraction in [0, 0.6], image sizes drawn
+# from 512 / 1024 / 2048 (the batched-channel workload).
+CHANNELS = dict(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9, f_hi=1.75e9,
+                flag_max=0.6, sizes=(512, 1024, 2048), n_points=200, seed=5)
+
+
+def make_channels(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9, f_hi=1.75e9,
+                  flag_max=0.6, sizes=(512, 1024, 2048), n_points=200, seed=5, device=None):
+    """Multi-channel workload over one array and one time range.
+
+    Returns dict(uvw [M, 3] float64 metres shared by all channels, channels =
+    list of dict(freq_hz, cell, n_img, flag uint8 [M], vis complex64 [M],
+    flag_frac)).  Channel c is at f_lo + (f_hi - f_lo) c / (n_chan - 1); its
+    cell is 1 / (3 max |u|) at that frequency.  The sky is n_points point
+    sources with log-uniform fluxes in [1 mJy, 1 Jy] and spectral index -0.7
+    (reference 1.4 GHz), placed in the central 80 % of the smallest field of
+    view of the band; noise sigma 1 mJy.  With ``device`` (a torch cuda
+    device) uvw, flag and vis are torch tensors evaluated on that device,
+    else numpy arrays (small cases: the per-time antenna phasors are formed
+    on the CPU)."""
+    rng = np.random.default_rng(seed)
+    xyz = antenna_xyz(n_ant, radius_m, rng)
+    ha = hour_angles(n_time)
+    auvw = antenna_uvw(xyz, ha)                       # [T, A, 3]
+    bi, bj = baselines(n_ant)
+    uvw = (auvw[:, bj, :] - auvw[:, bi, :]).reshape(-1, 3)
+    m_vis = uvw.shape[0]
+    freqs = f_lo + (f_hi - f_lo) * np.arange(n_chan) / max(n_chan - 1, 1)
+    umax_m = max(np.abs(uvw[:, 0]).max(), np.abs(uvw[:, 1]).max())
+    cells = 1.0 / (3.0 * umax_m * freqs / C_LIGHT)
+    n_img = [int(sizes[k]) for k in rng.integers(0, len(sizes), n_chan)]
+    flag_frac = rng.uniform(0.0, flag_max, n_chan)
+    # sky in direction cosines inside the smallest field of view
+    fov = min(sizes) * cells.min()
+    l0 = rng.uniform(-0.4, 0.4, n_points) * fov
+    m0 = rng.uniform(-0.4, 0.4, n_points) * fov
+    flux0 = 10.0 ** rng.uniform(-3.0, 0.0, n_points)
+    seeds = rng.integers(0, 2 ** 31 - 1, n_chan)
+    chans = []
+    if device is not None:
+        import torch
+        t_auvw = torch.tensor(auvw, dtype=torch.float64, device=device)
+        t_l0 = torch.tensor(l0, device=device)
+        t_m0 = torch.tensor(m0, device=device)
+        t_bi = torch.tensor(bi, device=device)
+        t_bj = torch.tensor(bj, device=device)
+        uvw_out = torch.tensor(uvw, dtype=torch.float64, device=device)
+    for c in range(n_chan):
+        f = freqs[c]
+        lam = C_LIGHT / f
+        flux = flux0 * (f / 1.4e9) ** -0.7
+        crng = np.random.default_rng(int(seeds[c]))
+        if device is None:
+            vis = np.empty(m_vis, np.complex128)
+            n_bl = len(bi)
+            for t in range(n_time):
+                ph = np.exp(-2j * np.pi * (np.outer(auvw[t, :, 0] / lam, l0)
+                                           + np.outer(auvw[t, :, 1] / lam, m0)))
+                vmat = (ph * flux) @ ph.conj().T
+                vis[t * n_bl:(t + 1) * n_bl] = vmat[bj, bi]
+            vis += 1e-3 * (crng.standard_normal(m_vis) + 1j * crng.standard_normal(m_vis))
+            flag = (crng.random(m_vis) < flag_frac[c]).astype(np.uint8)
+            vis = vis.astype(np.complex64)
+        else:
+            import torch
+            phase = -2.0 * np.pi * (t_auvw[:, :, 0:1] / lam * t_l0 + t_auvw[:, :, 1:2] / lam * t_m0)
+            ph = torch.polar(torch.ones_like(phase), phase).to(torch.complex64)   # [T, A, S]
+            t_flux = torch.tensor(flux, dtype=torch.float32, device=device)
+            right = ph.conj().transpose(1, 2).contiguous()                         # [T, S, A]
+            vmat = torch.bmm(ph * t_flux, right)                                  # [T, A, A]
+            vis = vmat[:, t_bj, t_bi].reshape(-1)
+            g = torch.Generator(device=device)
+            g.manual_seed(int(seeds[c]))
+            noise = torch.randn(2, m_vis, generator=g, device=device, dtype=torch.float32)
+            vis = vis + 1e-3 * torch.complex(noise[0], noise[1])
+            flag = (torch.rand(m_vis, generator=g, device=device) < flag_frac[c]).to(torch.uint8)
+            del phase, ph, right, vmat, noise
+        chans.append(dict(freq_hz=float(f), cell=float(cells[c]), n_img=n_img[c], flag=flag,
+                          vis=vis, flag_frac=float(flag_frac[c])))
+    return dict(uvw=uvw if device is None else uvw_out, channels=chans, n_vis=m_vis,
+                n_ant=n_ant, n_time=n_time)

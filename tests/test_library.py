@@ -16,7 +16,7 @@ def declared_symbols():
     return sorted(set(re.findall(r"\b(imager_[a-z_]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_hot_path_calls():
     syms = declared_symbols()
     for name in ("imager_create", "imager_degrid", "imager_grid", "imager_major_cycle",
                  "imager_minor_cycle_msclean", "imager_minor_cycle_fista",
@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_signatures_cover_header():
     from paper_2507_22128_amd import imager
-    covered = set(imager._SIGS) | {"imager_last_error"}
+    covered = set(imager._SIGS) | {"imager_last_error", "imager_batch_last_error"}
     assert set(declared_symbols()) <= covered
 
 
@@ -46,3 +46,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert b"null" in lib.imager_last_error(None)
     assert lib.imager_destroy(None) == imager.EINVAL
     assert lib.imager_sync(None) == imager.EINVAL
+    assert lib.imager_batch_create(None, 0, None) == imager.EINVAL
+    assert lib.imager_batch_destroy(None) == imager.EINVAL
+    assert lib.imager_batch_major_cycle(None, None, None, 0) == imager.EINVAL
+    assert lib.imager_batch_autotune(None, None, 0, 1, None, None) == imager.EINVAL
+    assert lib.imager_set_chunk(None, 64) == imager.EINVAL

@@ -174,6 +174,25 @@ def test_gridded_matches_direct_sum_to_design_accuracy():
     assert rel(op6.forward(x), dft.forward(x, u, v, cell)) > 10 * e_fwd
 
 
+@pytest.mark.parametrize("support", [4, 6, 8, 10, 12])
+def test_support_rule_error_bound(support):
+    """The library picks the support for a requested accuracy as the smallest
+    W with 3 x 10^(1 - W) <= tolerance.  Pin that bound on the FP64 gridded
+    operator against the direct sum, and that it is tight to a factor of 30
+    (each extra pair of taps buys about two decades)."""
+    rng = np.random.default_rng(16)
+    n, cell = 64, 1e-3
+    u, v = _uv(rng, 1500, 2 * n, cell)
+    x = rng.standard_normal((n, n))
+    y = rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))
+    op = imaging.Operator(u, v, cell, n, 2, support)
+    bound = 3.0 * 10.0 ** (1 - support)
+    e_fwd = rel(op.forward(x), dft.forward(x, u, v, cell))
+    e_adj = rel(op.adjoint(y), dft.adjoint(y, u, v, cell, n))
+    assert e_fwd <= bound and e_adj <= bound
+    assert e_fwd > bound / 30 and e_adj > bound / 30
+
+
 def test_hermitian_symmetry_for_real_images():
     rng = np.random.default_rng(7)
     n, cell = 32, 1e-3
