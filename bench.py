@@ -255,6 +255,88 @@ def batched_channels(args):
     return out
 
 
+def serving(args):
+    """Serving workload: a Poisson stream of imaging requests shaped like the
+    single-channel workloads (images 512 / 1024, 2.2 - 7.8M unflagged
+    visibilities from the 256-antenna array at 240 times with 0-60 % flags,
+    msCLEAN (S = {0, 4, 12}, K = 500 per cycle) or FISTA (db8, 50 iterations,
+    30 power iterations), 1 or 2 partitions, 5-10 major cycles), served with
+    admission by device-memory footprint and continuous batching at cycle
+    boundaries; compared with plain serial execution of the same requests."""
+    import numpy as np
+    import torch
+    from paper_2507_22128_amd import serve, synth
+    n_req = args.serve_requests
+    d = synth.make_channels(n_chan=n_req, n_time=240, sizes=(512, 1024), seed=6, device="cuda")
+    rng = np.random.default_rng(8)
+    reqs = []
+    for k, c in enumerate(d["channels"]):
+        reqs.append(serve.Request(
+            uvw=d["uvw"], vis=c["vis"], freq_hz=c["freq_hz"], cell=c["cell"], n_pix=c["n_img"],
+            flag=c["flag"], method="msclean" if rng.random() < 0.5 else "fista",
+            n_cycles=int(rng.integers(5, 11)), n_partitions=int(rng.integers(1, 3)), niter=500,
+            fista_iter=50, power_iters=30, name="req%d" % k, power_seed=k))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    serial = serve.run_serial(reqs)
+    t_serial = time.perf_counter() - t0
+    ref = [f for f, _ in serial]
+    log("serving: %d requests, plain serial execution %.2f s" % (n_req, t_serial))
+    out = {"requests": n_req,
+           "mix": {"msclean": sum(r.method == "msclean" for r in reqs),
+                   "fista": sum(r.method == "fista" for r in reqs),
+                   "two_partitions": sum(r.n_partitions == 2 for r in reqs),
+                   "image_sizes": sorted(set(r.n_pix for r in reqs)),
+                   "cycles": [int(min(r.n_cycles for r in reqs)),
+                              int(max(r.n_cycles for r in reqs))]},
+           "hbm_budget_gib": args.serve_budget_gib, "workers": args.serve_workers,
+           "rates": {}}
+    vis_cycles = None
+    for rate in args.serve_rates:
+        arr = np.cumsum(np.random.default_rng(int(rate * 1000)).exponential(1.0 / rate, n_req))
+        with serve.Server(hbm_budget=int(args.serve_budget_gib * 2 ** 30),
+                          workers=args.serve_workers) as srv:
+            t0 = time.perf_counter()
+            futs = []
+            for req, at in zip(reqs, arr):
+                dt = t0 + at - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                futs.append(srv.submit(req))
+            res = [f.result(timeout=600) for f in futs]
+        makespan = max(r.finished for r in res) - t0
+        vis_cycles = sum(r.n_valid * r.n_cycles for r in res)
+        lat = np.array(sorted(r.latency for r in res)) * 1e3
+        errs = []
+        same = True
+        for r, f in zip(res, ref):
+            same = same and bool(torch.equal(r.final, f))
+            errs.append(float(torch.linalg.norm(r.final - f) / torch.linalg.norm(f)))
+        out["rates"][str(rate)] = {
+            "p50_ms": round(float(np.percentile(lat, 50)), 1),
+            "p99_ms": round(float(np.percentile(lat, 99)), 1),
+            "makespan_s": round(makespan, 3),
+            "aggregate_mvis_per_s": round(vis_cycles / makespan / 1e6, 1),
+            "max_resident_requests": srv.max_resident_jobs,
+            "max_concurrent_cycles": srv.max_concurrent_cycles,
+            "admission_waits": srv.admission_waits,
+            "max_reserved_gib": round(srv.max_reserved / 2 ** 30, 2),
+            "max_rel_err_vs_serial": max(errs),
+            "identical_to_serial": same,
+        }
+        log("serving at %.0f req/s: p50 %.0f ms, p99 %.0f ms, makespan %.2f s, %.0f Mvis/s "
+            "(serial %.0f Mvis/s), identical %s" % (rate, np.percentile(lat, 50),
+                                                    np.percentile(lat, 99), makespan,
+                                                    vis_cycles / makespan / 1e6,
+                                                    vis_cycles / t_serial / 1e6, same))
+    out["serial"] = {"seconds": round(t_serial, 3),
+                     "aggregate_mvis_per_s": round(vis_cycles / t_serial / 1e6, 1)}
+    out["vis_cycles"] = int(vis_cycles)
+    del d, reqs, serial, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +349,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[2.0, 10.0, 50.0])
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=float, default=48.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the steps, run a plain device copy of this many MiB three "
                          "times (a known-size kernel to scale hardware byte counters by)")
@@ -420,6 +507,8 @@ def main():
     h.destroy()
     if not args.no_batch:
         res["batched_channels"] = batched_channels(args)
+    if not args.no_serve:
+        res["serving"] = serving(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample) ...")
         res["cpu_baseline"] = cpu_baseline(args, gm)

@@ -133,7 +133,20 @@ typedef struct {
   size_t device_bytes;  /* device memory held by the handle */
   double create_ms;     /* wall time of imager_create */
   int32_t chunk;        /* max visibilities per work chunk (after tuning) */
+  size_t device_peak_bytes; /* most device memory the handle has held at once */
 } imgr_info;
+
+/* Device-memory footprint of a handle before it is built, for admission
+ * control: *resident (host) receives an upper estimate of device_bytes after
+ * imager_create plus the reconstruction loop's buffers and the minor-cycle
+ * work areas (multi-scale CLEAN with n_scales scales if n_scales > 0, FISTA
+ * if fista != 0), *peak (host, may be NULL) one of device_peak_bytes, which
+ * adds the temporaries of imager_create (host-staged inputs if vis_on_host,
+ * sort and binning buffers, the PSF grid, the autotuner's trials).  With
+ * two partitions and ell_pix < 0 (median split) each partition is taken to
+ * hold at most 60 % of the visibilities, with ell_pix >= 0 all of them. */
+imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_on_host,
+                             int32_t n_scales, int32_t fista, size_t *resident, size_t *peak);
 
 /* Build a handle: scale (u, v) in FP64, drop flagged visibilities, apply the
  * weighting, split into V_L = {rho <= ell + delta} and V_H = {rho >= ell -
@@ -239,6 +252,11 @@ typedef struct {
                                       the node's own domain (psi^1 of Eq. 7, reading:
                                       V_L: s >= N / (2 (ell + delta)), V_H:
                                       s <= N / (ell - delta), else the nearest) */
+  int32_t first_cycle;             /* imager_reconstruct_msclean only: number of the
+                                      first cycle it runs (0 or 1: a fresh loop);
+                                      k > 1 continues a loop from the models and
+                                      rho of its cycle k - 1, so cycles may be run
+                                      one call at a time with the same results */
 } imgr_msclean_params;
 
 typedef struct {
@@ -305,6 +323,7 @@ typedef struct {
   double lambda_frac;    /* lambda <= 0: lambda = lambda_frac * max |dirty| */
   double gamma_n;        /* weight of the rho term (Eq. 5: 0 at the first cycle, else 1) */
   int32_t serial;        /* 1: Eq. 4 (Gamma_own = identity, no rho term) */
+  int32_t first_cycle;   /* imager_reconstruct_fista only: as in imgr_msclean_params */
 } imgr_fista_params;
 
 imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,

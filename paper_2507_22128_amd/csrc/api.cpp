@@ -27,6 +27,7 @@ void *dev_alloc(imgr_s *h, size_t bytes) {
     throw Error{IMGR_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
   }
   h->bytes += bytes;
+  h->peak_bytes = std::max(h->peak_bytes, h->bytes);
   h->allocs.push_back(p);
   // remember the size in a parallel list for accounting on free
   h->alloc_sizes.push_back(bytes);
@@ -394,6 +395,57 @@ imgr_status imager_info(imgr_t h, imgr_info *o) {
   o->device_bytes = h->bytes;
   o->create_ms = h->create_ms;
   o->chunk = h->C;
+  o->device_peak_bytes = h->peak_bytes;
+  return IMGR_OK;
+}
+
+imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_on_host,
+                             int32_t n_scales, int32_t fista, size_t *resident, size_t *peak) {
+  if (!cfg || !resident || n_vis < 0 || n_scales < 0 || n_scales > IMGR_MAX_SCALES)
+    return IMGR_EINVAL;
+  if (!pow2(cfg->n_pix) || cfg->n_pix < 64 || cfg->n_pix > 2048) return IMGR_EINVAL;
+  if (cfg->n_partitions != 1 && cfg->n_partitions != 2) return IMGR_EINVAL;
+  const double N = cfg->n_pix, Ng = 2.0 * N, nn = N * N;
+  int W = cfg->support;
+  if (W == 0) W = cfg->tolerance > 0 ? support_for_tolerance(cfg->tolerance) : 8;
+  if (W <= 0) return IMGR_EINVAL;
+  // the smaller tile (more blocks) bounds both candidates
+  const int blk = cfg->tile ? cfg->tile : 4;
+  const int C = cfg->chunk ? cfg->chunk : (cfg->autotune ? 256 : 1024);
+  const int parts = cfg->n_partitions;
+  const double m = (double)n_vis;
+  const double np_ = parts == 2 ? (cfg->ell_pix < 0 ? 0.6 * m : m) : m;
+  auto chunks = [&](double ng) { return np_ / C + (ng / blk) * (ng / blk); };
+  auto tables = [&](double ng) {  // posvis, w, orig, outpos + chunk tables
+    const double nb2 = (ng / blk) * (ng / blk);
+    return 28.0 * np_ + 4.0 * (3.0 * chunks(ng) + nb2 + 2.0);
+  };
+  const double fixed = 4.0 * (N + 2 * N) + 24.0 * kTwMax + 4096.0;
+  double per = 2 * 8.0 * Ng * Ng + 8.0 * N * Ng + 4.0 * nn   // work grids, rows, image
+               + tables(Ng) + 2048.0 * chunks(Ng)             // bins, chunk windows
+               + 12.0 * 4 * nn;                               // PSF and its spectrum
+  double loop = 0.0;
+  if (n_scales > 0 || fista) loop += 6.0 * 4 * nn;            // loop dirty, psf, delta
+  double minor = 0.0;
+  if (n_scales > 0) {
+    const double ni = n_scales + 1, npair = ni * (ni + 1) / 2;
+    minor = std::max(minor, 8.0 * (ni * nn + npair * 4 * nn + nn) + 65536.0);
+  }
+  // FISTA: 11 FP64 images, 6 complex FP64 images of work, the FP64 PSF
+  // spectrum and the temporary it is built in
+  if (fista) minor = std::max(minor, 8.0 * 11 * nn + 16.0 * 6 * nn + 2 * 16.0 * 4 * nn + 65536.0);
+  const double res = fixed + parts * (per + loop + minor);
+  // create-time temporaries on top of the handle's work buffers and tables
+  const double staged = vis_on_host ? (24.0 + 16.0 + 4.0 + 1.0) * m : 0.0;
+  const double prep = 45.0 * m + 4.0 * nn;                   // coordinates, weights, keys
+  const double sortb = 8.0 * m + 16.0 * m + 12.0 * (Ng / blk) * (Ng / blk) * 4;
+  const double psf_build = tables(2 * Ng) + 2 * 8.0 * 4 * Ng * Ng + 8.0 * 2 * N * 2 * Ng +
+                           2048.0 * chunks(2 * Ng) + 16.0 * 4 * nn;
+  const double tune = cfg->autotune ? 2 * 8.0 * Ng * Ng + tables(Ng) + 2048.0 * chunks(Ng) : 0.0;
+  const double create_peak = fixed + parts * (per - 12.0 * 4 * nn) + staged + prep + sortb +
+                             std::max(psf_build + 12.0 * 4 * nn, tune);
+  *resident = (size_t)res;
+  if (peak) *peak = (size_t)std::max(res, create_peak + parts * 12.0 * 4 * nn);
   return IMGR_OK;
 }
 
@@ -587,7 +639,9 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
     }
   }
   const double wsum = h->part[0].sum_w + (h->n_parts == 2 ? h->part[1].sum_w : 0.0);
-  for (int cyc = 1; cyc <= n_cycles; ++cyc) {
+  IMGR_CHECK(p.first_cycle >= 0, "first_cycle must be >= 0");
+  const int c0 = std::max(p.first_cycle, 1);
+  for (int cyc = c0; cyc < c0 + n_cycles; ++cyc) {
     if (h->n_parts == 1) {
       hipStream_t s = h->stream;
       node_cycle(h, 0, model[0], nullptr, 1.0, 0.0, h->loop_dirty[0], nullptr, 0, s);
@@ -620,7 +674,7 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
     if (n_comps) {
       IMGR_HIP(hipStreamSynchronize(h->stream));
       for (int k = 0; k < h->n_parts; ++k)
-        n_comps[(size_t)(cyc - 1) * h->n_parts + k] = msclean_count(h, k);
+        n_comps[(size_t)(cyc - c0) * h->n_parts + k] = msclean_count(h, k);
     }
   }
   // final image: equal-weight average of the nodes' models in FP64 (Section 5.2)
@@ -678,7 +732,9 @@ imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fist
       h->loop_delta[k] = (float *)dev_alloc(h, nn * sizeof(float));
     }
   }
-  for (int cyc = 1; cyc <= n_cycles; ++cyc) {
+  IMGR_CHECK(params->first_cycle >= 0, "first_cycle must be >= 0");
+  const int c0 = std::max(params->first_cycle, 1);
+  for (int cyc = c0; cyc < c0 + n_cycles; ++cyc) {
     imgr_fista_params q = *params;
     if (h->n_parts == 1) {
       hipStream_t s = h->stream;
@@ -706,7 +762,7 @@ imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fist
     if (lipschitz || lambdas) {
       IMGR_HIP(hipStreamSynchronize(h->stream));
       for (int k = 0; k < h->n_parts; ++k) {
-        const size_t at = (size_t)(cyc - 1) * h->n_parts + k;
+        const size_t at = (size_t)(cyc - c0) * h->n_parts + k;
         fista_scalars(h, k, lipschitz ? lipschitz + at : nullptr, lambdas ? lambdas + at : nullptr);
       }
     }

@@ -152,7 +152,7 @@ struct imgr_s {
   // bookkeeping
   std::vector<void *> allocs;
   std::vector<size_t> alloc_sizes;
-  size_t bytes = 0, budget = 0;
+  size_t bytes = 0, budget = 0, peak_bytes = 0;
   double create_ms = 0;
   bool broken = false;
   std::string err;

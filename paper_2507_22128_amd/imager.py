@@ -57,7 +57,8 @@ class Info(ctypes.Structure):
                 ("delta_pix", ctypes.c_double), ("n_valid", ctypes.c_int64),
                 ("n_vis", ctypes.c_int64 * 2), ("n_chunks", ctypes.c_int64 * 2),
                 ("sum_w", ctypes.c_double * 2), ("device_bytes", ctypes.c_size_t),
-                ("create_ms", ctypes.c_double), ("chunk", ctypes.c_int32)]
+                ("create_ms", ctypes.c_double), ("chunk", ctypes.c_int32),
+                ("device_peak_bytes", ctypes.c_size_t)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -93,6 +94,7 @@ _SIGS = {
     "imager_get_timing": [_P, _P],
     "imager_sync": [_P],
     "imager_tune_log": [_P, _I, _P, _P, _P, _P],
+    "imager_footprint": [ctypes.POINTER(Config), ctypes.c_int64, _I, _I, _I, _P, _P],
     "imager_set_chunk": [_P, _I],
     "imager_batch_create": [_P, _I, ctypes.POINTER(_P)],
     "imager_batch_destroy": [_P],
@@ -108,7 +110,8 @@ class MsCleanParams(ctypes.Structure):
     _fields_ = [("n_scales", ctypes.c_int32), ("scales", ctypes.c_double * MAX_SCALES),
                 ("active_mask", ctypes.c_uint32), ("gain", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("threshold", ctypes.c_double),
-                ("bias_slope", ctypes.c_double), ("own_scales_only", ctypes.c_int32)]
+                ("bias_slope", ctypes.c_double), ("own_scales_only", ctypes.c_int32),
+                ("first_cycle", ctypes.c_int32)]
 
 
 COMPONENT_DTYPE = np.dtype([("scale", "<i4"), ("iy", "<i4"), ("ix", "<i4"), ("reserved", "<i4"),
@@ -116,7 +119,7 @@ COMPONENT_DTYPE = np.dtype([("scale", "<i4"), ("iy", "<i4"), ("ix", "<i4"), ("re
 
 
 def msclean_params(scales, gain=0.1, niter=2000, threshold=0.0, bias_slope=0.6, active=None,
-                   own_scales_only=False):
+                   own_scales_only=False, first_cycle=0):
     if not 1 <= len(scales) <= MAX_SCALES:
         raise ImagerError(EINVAL, "between 1 and %d scales" % MAX_SCALES)
     p = MsCleanParams()
@@ -129,6 +132,7 @@ def msclean_params(scales, gain=0.1, niter=2000, threshold=0.0, bias_slope=0.6, 
     p.threshold = float(threshold)
     p.bias_slope = float(bias_slope)
     p.own_scales_only = 1 if own_scales_only else 0
+    p.first_cycle = int(first_cycle)
     return p
 
 
@@ -136,16 +140,18 @@ class FistaParams(ctypes.Structure):
     _fields_ = [("vanishing", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("n_iter", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("lam", ctypes.c_double), ("lambda_frac", ctypes.c_double),
-                ("gamma_n", ctypes.c_double), ("serial", ctypes.c_int32)]
+                ("gamma_n", ctypes.c_double), ("serial", ctypes.c_int32),
+                ("first_cycle", ctypes.c_int32)]
 
 
 def fista_params(vanishing=8, levels=3, n_iter=200, power_iters=30, lam=0.0, lam_frac=1e-3,
-                 gamma_n=0.0, serial=False):
+                 gamma_n=0.0, serial=False, first_cycle=0):
     p = FistaParams()
     p.vanishing, p.levels, p.n_iter, p.power_iters = int(vanishing), int(levels), int(n_iter), \
         int(power_iters)
     p.lam, p.lambda_frac, p.gamma_n = float(lam), float(lam_frac), float(gamma_n)
     p.serial = 1 if serial else 0
+    p.first_cycle = int(first_cycle)
     return p
 
 
@@ -436,15 +442,18 @@ class Imager:
         return delta, np.frombuffer(raw.tobytes(), dtype=COMPONENT_DTYPE), resid
 
     def reconstruct_msclean(self, n_cycles, scales, gain=0.1, niter=2000, threshold=0.0,
-                            bias_slope=0.6, active=None, models=None, rhos=None):
-        """The whole major/minor loop in the library.  Returns (final image
-        (float64), per-node models, per-node rho, components per cycle and node)."""
+                            bias_slope=0.6, active=None, models=None, rhos=None, first_cycle=0,
+                            final=None):
+        """The whole major/minor loop in the library (cycles first_cycle ..
+        first_cycle + n_cycles - 1).  Returns (final image (float64), per-node
+        models, per-node rho, components per cycle and node)."""
         n, k = self.n_pix, self.info.n_partitions
-        prm = msclean_params(scales, gain, niter, threshold, bias_slope, active)
+        prm = msclean_params(scales, gain, niter, threshold, bias_slope, active,
+                             first_cycle=first_cycle)
         import torch
         models = [torch.zeros((n, n), device="cuda") for _ in range(k)] if models is None else models
         rhos = [torch.zeros((n, n), device="cuda") for _ in range(k)] if rhos is None else rhos
-        final = self._empty((n, n), "float64")
+        final = self._empty((n, n), "float64") if final is None else final
         counts = np.zeros((n_cycles, k), np.int32)
         arr = lambda ts: (ctypes.c_void_p * k)(*[t.data_ptr() for t in ts])
         self._check(lib().imager_reconstruct_msclean(
@@ -470,15 +479,17 @@ class Imager:
         objective = None if obj is None else obj[:prm.n_iter].cpu().numpy()
         return delta, objective, L.value, lam.value
 
-    def reconstruct_fista(self, n_cycles, power_starts, models=None, rhos=None, **params):
-        """The whole loop with the sparsity-regularised minor cycle.  Returns
-        (final image (float64), models, rhos, L_hat and lambda per cycle and node)."""
+    def reconstruct_fista(self, n_cycles, power_starts, models=None, rhos=None, final=None,
+                          **params):
+        """The whole loop with the sparsity-regularised minor cycle (params may
+        hold first_cycle).  Returns (final image (float64), models, rhos, L_hat
+        and lambda per cycle and node)."""
         import torch
         n, k = self.n_pix, self.info.n_partitions
         prm = fista_params(**params)
         models = [torch.zeros((n, n), device="cuda") for _ in range(k)] if models is None else models
         rhos = [torch.zeros((n, n), device="cuda") for _ in range(k)] if rhos is None else rhos
-        final = self._empty((n, n), "float64")
+        final = self._empty((n, n), "float64") if final is None else final
         Ls = np.zeros((n_cycles, k))
         lams = np.zeros((n_cycles, k))
         arr = lambda ts: (ctypes.c_void_p * k)(*[t.data_ptr() for t in ts])
@@ -498,6 +509,22 @@ class Imager:
 
     def sync(self):
         self._check(lib().imager_sync(self._h))
+
+
+def footprint(n_pix, n_vis, n_partitions=1, support=8, tile=0, chunk=0, autotune=False,
+              tolerance=0.0, ell=-1.0, vis_on_host=False, n_scales=0, fista=False):
+    """(resident, peak) device bytes of a handle before it is built."""
+    c = Config()
+    c.n_pix, c.n_partitions, c.support = int(n_pix), int(n_partitions), int(support)
+    c.tile, c.chunk, c.autotune, c.tolerance = int(tile), int(chunk), int(bool(autotune)), \
+        float(tolerance)
+    c.ell_pix = float(ell)
+    r, p = ctypes.c_size_t(), ctypes.c_size_t()
+    st = lib().imager_footprint(ctypes.byref(c), int(n_vis), int(bool(vis_on_host)),
+                                int(n_scales), int(bool(fista)), ctypes.byref(r), ctypes.byref(p))
+    if st != OK:
+        raise ImagerError(st, "footprint: bad configuration")
+    return r.value, p.value
 
 
 def _ptr_array(ts):
