@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[2.0, 10.0, 50.0])
     ap.add_argument("--serve-workers", type=int, default=4)
-    ap.add_argument("--serve-budget-gib", type=float, default=48.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=12.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the steps, run a plain device copy of this many MiB three "
                          "times (a known-size kernel to scale hardware byte counters by)")
