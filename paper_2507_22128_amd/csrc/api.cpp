@@ -322,6 +322,20 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
       }
       h->tw64 = (double2 *)dev_alloc(h, kTwMax * sizeof(double2));
       IMGR_HIP(hipMemcpy(h->tw64, tw64.data(), kTwMax * sizeof(double2), hipMemcpyHostToDevice));
+      // per-length tables: entry L + m = w_L^m = the entry m kTwMax / L above
+      std::vector<float2> twr(2 * kTwMax, make_float2(0.f, 0.f));
+      std::vector<double2> twr64(2 * kTwMax, make_double2(0.0, 0.0));
+      for (int L = 2; L <= kTwMax; L *= 2)
+        for (int m = 0; m < L; ++m) {
+          twr[L + m] = tw[m * (kTwMax / L)];
+          twr64[L + m] = tw64[m * (kTwMax / L)];
+        }
+      h->twrow = (float2 *)dev_alloc(h, twr.size() * sizeof(float2));
+      h->twrow64 = (double2 *)dev_alloc(h, twr64.size() * sizeof(double2));
+      IMGR_HIP(hipMemcpy(h->twrow, twr.data(), twr.size() * sizeof(float2),
+                         hipMemcpyHostToDevice));
+      IMGR_HIP(hipMemcpy(h->twrow64, twr64.data(), twr64.size() * sizeof(double2),
+                         hipMemcpyHostToDevice));
     }
     const size_t ng2 = (size_t)h->Ng * h->Ng;
     for (int p = 0; p < h->n_parts; ++p) {
@@ -420,7 +434,7 @@ imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_
     const double nb2 = (ng / blk) * (ng / blk);
     return 28.0 * np_ + 4.0 * (3.0 * chunks(ng) + nb2 + 2.0);
   };
-  const double fixed = 4.0 * (N + 2 * N) + 24.0 * kTwMax + 4096.0;
+  const double fixed = 4.0 * (N + 2 * N) + 3 * 24.0 * kTwMax + 4096.0;
   double per = 2 * 8.0 * Ng * Ng + 8.0 * N * Ng + 4.0 * nn   // work grids, rows, image
                + tables(Ng) + 2048.0 * chunks(Ng)             // bins, chunk windows
                + 12.0 * 4 * nn;                               // PSF and its spectrum

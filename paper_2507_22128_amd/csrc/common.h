@@ -122,6 +122,8 @@ struct imgr_s {
   float *cinv2 = nullptr;      // [2N] 1 / psi_hat, 2N image on the 2 Ng grid
   float2 *tw = nullptr;        // [kTwMax]
   double2 *tw64 = nullptr;     // [kTwMax], FP64
+  float2 *twrow = nullptr;     // [2 kTwMax]: entry L + m = w_L^m (row passes)
+  double2 *twrow64 = nullptr;  // the same in FP64
   // per-node work buffers and streams: the two nodes' major cycles may run
   // concurrently (imager_major_cycle_nodes)
   imgr::Work work[2];

@@ -50,11 +50,6 @@ __device__ __forceinline__ float sum_rows(float v) {
   return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
-// slot of window column p in a row of the x-weight table: column 4s + q is
-// stored at 4q + s, so that the four columns q, 4 + q, 8 + q, 12 + q one
-// lane feeds to the four K-steps of G kx are one 16-byte read
-__device__ __forceinline__ int xslot(int p) { return ((p & 3) << 2) | (p >> 2); }
-
 template <int W, int BLK, int MODE>
 __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float *kx_t, float *ky_t,
                                              float2 *r_t) {
@@ -90,14 +85,16 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
   }
   constexpr float qc = -kC * kC;
 
-  // model window as the A operand of G kx: lane (c16, g) holds
-  // G[y = c16][x = 4 s + g] for the K-steps s = 0..3
+  // model window as the A operand of G kx.  The contraction over the 16
+  // window columns runs as 4 K-steps of 4; K-step s of lane group g takes
+  // column x = 4 g + s, so lane (c16, g) holds G[y = c16][x = 4 g + s] and
+  // feeds the weights of columns 4 g .. 4 g + 3, one 16-byte table read
   float gre[4], gim[4];
   if constexpr (kDegrid) {
     const int gy = (wy0 + c16) & (ng - 1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int gx = (wx0 + 4 * s + g) & (ng - 1);
+      const int gx = (wx0 + 4 * g + s) & (ng - 1);
       const float2 v = grid_in[(size_t)gy * ng + gx];
       gre[s] = v.x;
       gim[s] = v.y;
@@ -124,7 +121,8 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
     const float fx = pv.x - (float)ox, fy = pv.y - (float)oy;
 
     // tap weights: clear this lane's quarter of the two table rows of its
-    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis:
+    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis
+    // (both tables in natural window order):
     // phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1))
     *(floatx4 *)&kx_t[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
     *(floatx4 *)&ky_t[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -134,7 +132,7 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
       if (t < W) {
         const float sx = fmaxf(fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]), 0.0f);
         const float sy = fmaxf(fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]), 0.0f);
-        kx_t[c16 * 16 + xslot(ox + t)] =
+        kx_t[c16 * 16 + ox + t] =
             __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sx), -bl2e));
         ky_t[c16 * 16 + oy + t] =
             __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sy), -bl2e));
@@ -144,7 +142,7 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
 
     float pr = 0.f, pi = 0.f;
     if constexpr (kDegrid) {
-      // T[y][k] = sum_x G[y][x] kx_k[x]: B[x = 4 s + g][k = c16]
+      // T[y][k] = sum_x G[y][x] kx_k[x]: B[x = 4 g + s][k = c16]
       const floatx4 bx = *(const floatx4 *)&kx_t[c16 * 16 + 4 * g];
       floatx4 tre = {0.f, 0.f, 0.f, 0.f}, tim = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -184,7 +182,7 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
       for (int s = 0; s < 4; ++s) {
         const int k = 4 * s + g;
         const float kyv = ky_t[k * 16 + c16];
-        const float kxv = kx_t[k * 16 + xslot(c16)];
+        const float kxv = kx_t[k * 16 + c16];
         const float2 rk = r_t[k];
         acc_re = __builtin_amdgcn_mfma_f32_16x16x4f32(rk.x * kyv, kxv, acc_re, 0, 0, 0);
         if constexpr (kCplx)
@@ -208,14 +206,15 @@ template <int W, int BLK, int MODE>
 __global__ __launch_bounds__(64 * kWaves) void k_window(WinArgs a, const int32_t *__restrict__ order,
                                                        int n_chunks) {
   // per wave and batch: tap weights of the 16 visibilities over the 16
-  // window positions (x in xslot order, y in natural order), residuals
+  // window positions (natural order), and their residuals
   __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
   __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
   __shared__ float2 r_s[kWaves][16];
   const int wave = threadIdx.x >> 6;
-  const int slot = blockIdx.x * kWaves + wave;
-  if (slot >= n_chunks) return;  // the wave has no chunk; no other wave waits for it
-  window_chunk<W, BLK, MODE>(a, order[slot], kx_s[wave], ky_s[wave], r_s[wave]);
+  // with fewer workgroups than chunk groups each wave takes every
+  // (gridDim.x * kWaves)-th chunk of the order; no wave waits for another
+  for (int slot = blockIdx.x * kWaves + wave; slot < n_chunks; slot += gridDim.x * kWaves)
+    window_chunk<W, BLK, MODE>(a, order[slot], kx_s[wave], ky_s[wave], r_s[wave]);
 }
 
 // the chunks of many grids (channels) in one launch: order[slot] = (grid,
@@ -239,35 +238,65 @@ __global__ __launch_bounds__(64 * kWaves) void k_window_batch(const WinArgs *__r
 // One thread per grid cell, 16 x 16 cells per workgroup: FP64 sum over the
 // chunk windows of the blocks whose window covers the cell (fixed order:
 // block row offset, block column offset, chunk), times (-1)^(x + y) for the
-// centred inverse DFT that follows.
+// centred inverse DFT that follows.  The workgroup first stages the chunk
+// ranges of the blocks around its 16 x 16 cells in LDS; each thread then
+// issues the loads of the first chunk of every covering block at once (the
+// common case is one chunk per block) and adds the values, and any further
+// chunks, in the fixed order.
 template <int W, int BLK>
 __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
   constexpr int H = W / 2 - 1;
-  constexpr int R = kWin / BLK;
+  constexpr int R = kWin / BLK;       // block offsets -R .. R can cover a cell
+  constexpr int SB = kWin / BLK + 2 * R;  // staged blocks per axis
+  constexpr int KA = kWin / BLK;  // covering blocks per axis: exactly KA
+  __shared__ int2 rng[SB * SB];
   const int nb = a.nb, ng = a.ng;
   const int nq = ng / 16;
-  const int cx = (group % nq) * 16 + (threadIdx.x & 15);
-  const int cy = (group / nq) * 16 + (threadIdx.x >> 4);
-  const int bx = cx / BLK, by = cy / BLK, lx = cx % BLK, ly = cy % BLK;
+  const int gx0 = (group % nq) * 16, gy0 = (group / nq) * 16;
+  const int bx0 = gx0 / BLK - R, by0 = gy0 / BLK - R;
+  for (int i = threadIdx.x; i < SB * SB; i += 256) {
+    const int sy = i / SB, sx = i % SB;
+    const int n = ((by0 + sy + nb) % nb) * nb + (bx0 + sx + nb) % nb;
+    rng[i] = make_int2(a.block_chunk[n], a.block_chunk[n + 1]);
+  }
+  __syncthreads();
+  const int cx = gx0 + (threadIdx.x & 15);
+  const int cy = gy0 + (threadIdx.x >> 4);
+  const int lx = cx % BLK, ly = cy % BLK;
+  // the blocks whose window holds the cell: offsets d_lo .. d_lo + KA - 1
+  // per axis, d_lo = floor((l + H - 16) / BLK) + 1 (the shift by 8 BLK keeps
+  // the division on non-negative values)
+  const int dy_lo = (ly + H - kWin + 8 * BLK) / BLK - 8 + 1;
+  const int dx_lo = (lx + H - kWin + 8 * BLK) / BLK - 8 + 1;
+  const int sy0 = cy / BLK + dy_lo - by0, sx0 = cx / BLK + dx_lo - bx0;
+  const int wy0 = ly + H - dy_lo * BLK, wx0 = lx + H - dx_lo * BLK;
+  float2 first[KA * KA];
+#pragma unroll
+  for (int i = 0; i < KA; ++i)
+#pragma unroll
+    for (int j = 0; j < KA; ++j) {
+      const int2 r = rng[(sy0 + i) * SB + sx0 + j];
+      const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
+      first[i * KA + j] = (r.x < r.y) ? a.scratch[(size_t)r.x * (kWin * kWin) + off]
+                                      : make_float2(0.f, 0.f);
+    }
   double re = 0.0, im = 0.0;
 #pragma unroll
-  for (int dby = -R; dby <= R; ++dby) {
-    const int wy = ly + H - dby * BLK;
-    if (wy < 0 || wy >= kWin) continue;
-    const int nby = (by + dby + nb) % nb;
+  for (int i = 0; i < KA; ++i)
 #pragma unroll
-    for (int dbx = -R; dbx <= R; ++dbx) {
-      const int wx = lx + H - dbx * BLK;
-      if (wx < 0 || wx >= kWin) continue;
-      const int n = nby * nb + (bx + dbx + nb) % nb;
-      const int c0 = a.block_chunk[n], c1 = a.block_chunk[n + 1];
-      for (int c = c0; c < c1; ++c) {
-        const float2 v = a.scratch[(size_t)c * (kWin * kWin) + wy * kWin + wx];
-        re += (double)v.x;
-        im += (double)v.y;
+    for (int j = 0; j < KA; ++j) {
+      const int2 r = rng[(sy0 + i) * SB + sx0 + j];
+      if (r.x < r.y) {
+        re += (double)first[i * KA + j].x;
+        im += (double)first[i * KA + j].y;
+        const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
+        for (int c = r.x + 1; c < r.y; ++c) {
+          const float2 v = a.scratch[(size_t)c * (kWin * kWin) + off];
+          re += (double)v.x;
+          im += (double)v.y;
+        }
       }
     }
-  }
   const float sg = ((cx + cy) & 1) ? -1.f : 1.f;
   a.grid_out[(size_t)cy * ng + cx] = make_float2(sg * (float)re, sg * (float)im);
 }

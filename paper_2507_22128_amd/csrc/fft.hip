@@ -152,10 +152,11 @@ __device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, in
   }
 }
 
-// stage w_L^m, m < L, from the kTwMax-entry table into LDS
+// stage w_L^m, m < L, into LDS from the per-length tables (entry L + m of
+// twr holds w_L^m, so one row's twiddles are one contiguous read)
 template <int L, int NT, class C>
-__device__ __forceinline__ void stage_twiddles(C *twl, const C *__restrict__ tw) {
-  for (int m = threadIdx.x; m < L; m += NT) twl[m] = tw[m * (kTwMax / L)];
+__device__ __forceinline__ void stage_twiddles(C *twl, const C *__restrict__ twr) {
+  for (int m = threadIdx.x; m < L; m += NT) twl[m] = twr[L + m];
 }
 
 template <int L>
@@ -171,11 +172,11 @@ template <int L>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
     const float *__restrict__ model, const float *__restrict__ model_add,
     const float *__restrict__ cinv, int n, float2 *__restrict__ rows,
-    const float2 *__restrict__ tw) {
+    const float2 *__restrict__ twr) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  stage_twiddles<L, NT, float2>(twl, tw);
+  stage_twiddles<L, NT, float2>(twl, twr);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
@@ -201,11 +202,11 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
 template <int L>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
     const float2 *__restrict__ rows, const float *__restrict__ cinv, int n, float scale,
-    float *__restrict__ out, const float2 *__restrict__ tw) {
+    float *__restrict__ out, const float2 *__restrict__ twr) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  stage_twiddles<L, NT, float2>(twl, tw);
+  stage_twiddles<L, NT, float2>(twl, twr);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
@@ -224,11 +225,11 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
 // plain in-place complex row DFTs of an L x L buffer
 template <int L, int DIR, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__ buf,
-                                                                 const C *__restrict__ tw) {
+                                                                 const C *__restrict__ twr) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  stage_twiddles<L, NT, C>(twl, tw);
+  stage_twiddles<L, NT, C>(twl, twr);
   C *row = buf + (size_t)blockIdx.x * L;
   for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = row[x];
   __syncthreads();
@@ -309,12 +310,12 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
 template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
     const typename Real<C>::T *__restrict__ a, const typename Real<C>::T *__restrict__ b,
-    int n_in, C *__restrict__ out, const C *__restrict__ tw) {
+    int n_in, C *__restrict__ out, const C *__restrict__ twr) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  stage_twiddles<L, NT, C>(twl, tw);
+  stage_twiddles<L, NT, C>(twl, twr);
   const int r = blockIdx.x;
   for (int x = threadIdx.x; x < L; x += NT) {
     RT v = 0;
@@ -334,12 +335,12 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
 template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
     const C *__restrict__ in, int col0, int n_out, typename Real<C>::T *__restrict__ out,
-    int accumulate, const C *__restrict__ tw) {
+    int accumulate, const C *__restrict__ twr) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  stage_twiddles<L, NT, C>(twl, tw);
+  stage_twiddles<L, NT, C>(twl, twr);
   const int r = blockIdx.x;
   for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = in[(size_t)r * L + x];
   __syncthreads();
@@ -448,6 +449,9 @@ template <> struct Split<8192> { static constexpr int P = 64, Q = 128; };
 template <class C> const C *twiddles(const imgr_s *h);
 template <> const float2 *twiddles<float2>(const imgr_s *h) { return h->tw; }
 template <> const double2 *twiddles<double2>(const imgr_s *h) { return h->tw64; }
+template <class C> const C *row_twiddles(const imgr_s *h);
+template <> const float2 *row_twiddles<float2>(const imgr_s *h) { return h->twrow; }
+template <> const double2 *row_twiddles<double2>(const imgr_s *h) { return h->twrow64; }
 
 template <int L, int DIR, class C>
 void cols(const C *src, int src_row0, int y_lo, int y_hi, C *tmp, C *dst, int dst_row0, int k_lo,
@@ -464,7 +468,7 @@ void model_to_grid_t(imgr_s *h, const float *model, const float *model_add, cons
                      int n, float2 *rows, float2 *tmp, float2 *out, hipStream_t s) {
   const int o = (L - n) / 2;
   hipLaunchKernelGGL((k_rows_model<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, model, model_add,
-                     cinv, n, rows, h->tw);
+                     cinv, n, rows, h->twrow);
   cols<L, -1, float2>(rows, o, o, o + n, tmp, out, 0, 0, L, 1, h->tw, s);
 }
 
@@ -474,17 +478,18 @@ void grid_to_image_t(imgr_s *h, const float2 *in, const float *cinv, int n, floa
   const int o = (L - n) / 2;
   cols<L, 1, float2>(in, 0, 0, L, tmp, rows, o, o, o + n, 0, h->tw, s);
   hipLaunchKernelGGL((k_rows_image<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, rows, cinv, n,
-                     scale, out, h->tw);
+                     scale, out, h->twrow);
 }
 
 template <int L, class C>
 void plain_t(imgr_s *h, C *buf, C *tmp, int dir, hipStream_t s) {
   const C *tw = twiddles<C>(h);
+  const C *twr = row_twiddles<C>(h);
   if (dir < 0) {
-    hipLaunchKernelGGL((k_rows_plain<L, -1, C>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, tw);
+    hipLaunchKernelGGL((k_rows_plain<L, -1, C>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, twr);
     cols<L, -1, C>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, tw, s);
   } else {
-    hipLaunchKernelGGL((k_rows_plain<L, 1, C>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, tw);
+    hipLaunchKernelGGL((k_rows_plain<L, 1, C>), dim3(L), dim3(RowThreads<L>::v), 0, s, buf, twr);
     cols<L, 1, C>(buf, 0, 0, L, tmp, buf, 0, 0, L, 0, tw, s);
   }
 }
@@ -498,8 +503,9 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
               C *work, C *tmp, hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
   const C *tw = twiddles<C>(h);
+  const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
-                     n_in, work, tw);
+                     n_in, work, twr);
   hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(L / 64, Q), dim3(256), 0, s, work, 0, 0, n_in,
                      tmp, tw);
   if (mode == FILT_GAMMA)
@@ -511,7 +517,7 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
   hipLaunchKernelGGL((k_cols_fin<P, Q, C>), dim3(L / 64, Q), dim3(256), 0, s, tmp, work, k_lo,
                      k_hi, tw);
   hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
-                     work, col0, n_out, out, accumulate, tw);
+                     work, col0, n_out, out, accumulate, twr);
 }
 
 }  // namespace
