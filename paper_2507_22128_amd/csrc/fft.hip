@@ -342,7 +342,18 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
   __shared__ C twl[L];
   stage_twiddles<L, NT, C>(twl, twr);
   const int r = blockIdx.x;
-  for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = in[(size_t)r * L + x];
+  // the row is Hermitian (the 2-D spectrum it came from belongs to a real
+  // image): columns above L / 2 are the conjugates of those below
+  for (int x = threadIdx.x; x < L; x += NT) {
+    C v;
+    if (x <= L / 2) {
+      v = in[(size_t)r * L + x];
+    } else {
+      v = in[(size_t)r * L + (L - x)];
+      v.y = -v.y;
+    }
+    s[padi(x)] = v;
+  }
   __syncthreads();
   stockham_seq<L, NT, 1, 1, C>(s, twl, threadIdx.x);
   for (int c = threadIdx.x; c < n_out; c += NT) {
@@ -502,19 +513,24 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
               int k_lo, int k_hi, int col0, int n_out, typename Real<C>::T *out, int accumulate,
               C *work, C *tmp, hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  // the input is real, so its 2-D spectrum is Hermitian and the real
+  // spectral factors keep it so: the column passes only need the column
+  // blocks that hold frequencies 0 .. L / 2; the final row pass rebuilds
+  // the rest by conjugate symmetry
+  constexpr int CB = (L / 2) / 64 + 1 < L / 64 ? (L / 2) / 64 + 1 : L / 64;
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
                      n_in, work, twr);
-  hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(L / 64, Q), dim3(256), 0, s, work, 0, 0, n_in,
+  hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(CB, Q), dim3(256), 0, s, work, 0, 0, n_in,
                      tmp, tw);
   if (mode == FILT_GAMMA)
-    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_GAMMA, C>), dim3(L / 64, P), dim3(256), 0, s, tmp,
+    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_GAMMA, C>), dim3(CB, P), dim3(256), 0, s, tmp,
                        spec, h->ell, h->delta, gscale, own_low, coef, tw);
   else
-    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_SPEC, C>), dim3(L / 64, P), dim3(256), 0, s, tmp,
+    hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_SPEC, C>), dim3(CB, P), dim3(256), 0, s, tmp,
                        spec, h->ell, h->delta, gscale, own_low, coef, tw);
-  hipLaunchKernelGGL((k_cols_fin<P, Q, C>), dim3(L / 64, Q), dim3(256), 0, s, tmp, work, k_lo,
+  hipLaunchKernelGGL((k_cols_fin<P, Q, C>), dim3(CB, Q), dim3(256), 0, s, tmp, work, k_lo,
                      k_hi, tw);
   hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
                      work, col0, n_out, out, accumulate, twr);
