@@ -156,7 +156,12 @@ __device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, in
 // twr holds w_L^m, so one row's twiddles are one contiguous read)
 template <int L, int NT, class C>
 __device__ __forceinline__ void stage_twiddles(C *twl, const C *__restrict__ twr) {
-  for (int m = threadIdx.x; m < L; m += NT) twl[m] = twr[L + m];
+  constexpr int PER = L / NT;
+  C v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) v[q] = twr[L + threadIdx.x + q * NT];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) twl[threadIdx.x + q * NT] = v[q];
 }
 
 template <int L>
@@ -176,21 +181,37 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  stage_twiddles<L, NT, float2>(twl, twr);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
   const float cy = cinv[r];
-  for (int x = threadIdx.x; x < L; x += NT) {
-    float v = 0.f;
+  constexpr int PER = L / NT;
+  float v[PER], c[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int x = threadIdx.x + q * NT;
+    v[q] = 0.f;
+    c[q] = 0.f;
     if (x >= o && x < o + n) {
-      const int ix = x - o;
-      v = model[(size_t)r * n + ix];
-      if (model_add) v += model_add[(size_t)r * n + ix];
-      v *= cinv[ix] * cy;
-      if ((x + y) & 1) v = -v;
+      v[q] = model[(size_t)r * n + x - o];
+      c[q] = cinv[x - o];
     }
-    s[padi(x)] = make_float2(v, 0.f);
+  }
+  if (model_add) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int x = threadIdx.x + q * NT;
+      if (x >= o && x < o + n) v[q] += model_add[(size_t)r * n + x - o];
+    }
+  }
+  // the twiddle loads go out behind the row loads: one wait covers both
+  stage_twiddles<L, NT, float2>(twl, twr);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int x = threadIdx.x + q * NT;
+    float w = v[q] * (c[q] * cy);
+    if ((x + y) & 1) w = -w;
+    s[padi(x)] = make_float2(w, 0.f);
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
@@ -206,11 +227,18 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  stage_twiddles<L, NT, float2>(twl, twr);
   const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
-  for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = rows[(size_t)r * L + x];
+  {
+    constexpr int PER = L / NT;
+    float2 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = rows[(size_t)r * L + threadIdx.x + q * NT];
+    stage_twiddles<L, NT, float2>(twl, twr);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
+  }
   __syncthreads();
   stockham_seq<L, NT, 1, 1>(s, twl, threadIdx.x);
   const float cy = cinv[r] * scale;
@@ -229,9 +257,16 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  stage_twiddles<L, NT, C>(twl, twr);
   C *row = buf + (size_t)blockIdx.x * L;
-  for (int x = threadIdx.x; x < L; x += NT) s[padi(x)] = row[x];
+  {
+    constexpr int PER = L / NT;
+    C v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = row[threadIdx.x + q * NT];
+    stage_twiddles<L, NT, C>(twl, twr);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
+  }
   __syncthreads();
   stockham_seq<L, NT, 1, DIR, C>(s, twl, threadIdx.x);
   for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
@@ -315,15 +350,25 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  stage_twiddles<L, NT, C>(twl, twr);
   const int r = blockIdx.x;
-  for (int x = threadIdx.x; x < L; x += NT) {
-    RT v = 0;
-    if (x < n_in) {
-      v = a[(size_t)r * n_in + x];
-      if (b) v -= b[(size_t)r * n_in + x];
+  {
+    constexpr int PER = L / NT;
+    RT v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int x = threadIdx.x + q * NT;
+      v[q] = (x < n_in) ? a[(size_t)r * n_in + x] : RT(0);
     }
-    s[padi(x)] = mkc<C>(v, 0);
+    if (b) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int x = threadIdx.x + q * NT;
+        if (x < n_in) v[q] -= b[(size_t)r * n_in + x];
+      }
+    }
+    stage_twiddles<L, NT, C>(twl, twr);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = mkc<C>(v[q], 0);
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1, C>(s, twl, threadIdx.x);
@@ -340,26 +385,42 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  stage_twiddles<L, NT, C>(twl, twr);
   const int r = blockIdx.x;
   // the row is Hermitian (the 2-D spectrum it came from belongs to a real
   // image): columns above L / 2 are the conjugates of those below
-  for (int x = threadIdx.x; x < L; x += NT) {
-    C v;
-    if (x <= L / 2) {
-      v = in[(size_t)r * L + x];
-    } else {
-      v = in[(size_t)r * L + (L - x)];
-      v.y = -v.y;
+  {
+    constexpr int PER = L / NT;
+    C v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int x = threadIdx.x + q * NT;
+      v[q] = in[(size_t)r * L + (x <= L / 2 ? x : L - x)];
     }
-    s[padi(x)] = v;
+    stage_twiddles<L, NT, C>(twl, twr);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int x = threadIdx.x + q * NT;
+      if (x > L / 2) v[q].y = -v[q].y;
+      s[padi(x)] = v[q];
+    }
   }
   __syncthreads();
   stockham_seq<L, NT, 1, 1, C>(s, twl, threadIdx.x);
-  for (int c = threadIdx.x; c < n_out; c += NT) {
-    const RT v = s[padi(col0 + c)].x;
-    RT *o = out + (size_t)r * n_out + c;
-    *o = accumulate ? *o + v : v;
+  if (accumulate) {
+    constexpr int PO = (L + NT - 1) / NT;  // n_out <= L
+    RT prev[PO];
+#pragma unroll
+    for (int q = 0; q < PO; ++q) {
+      const int c = threadIdx.x + q * NT;
+      prev[q] = (c < n_out) ? out[(size_t)r * n_out + c] : RT(0);
+    }
+#pragma unroll
+    for (int q = 0; q < PO; ++q) {
+      const int c = threadIdx.x + q * NT;
+      if (c < n_out) out[(size_t)r * n_out + c] = prev[q] + s[padi(col0 + c)].x;
+    }
+  } else {
+    for (int c = threadIdx.x; c < n_out; c += NT) out[(size_t)r * n_out + c] = s[padi(col0 + c)].x;
   }
 }
 
