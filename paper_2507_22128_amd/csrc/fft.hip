@@ -290,19 +290,33 @@ __global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int 
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int y2 = blockIdx.y;
-  for (int i = t; i < P * 64; i += 256) {
-    const int y1 = i >> 6, c = i & 63;
-    const int y = Q * y1 + y2;
-    C v = mkc<C>(0, 0);
-    if (y >= y_lo && y < y_hi) v = src[(size_t)(y - src_row0) * L + x0 + c];
-    s[i] = v;
+  {
+    // every load of the thread goes out before the first is used
+    constexpr int PER = P * 64 / 256;
+    C v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = t + q * 256, y1 = i >> 6, c = i & 63;
+      const int y = Q * y1 + y2;
+      v[q] = (y >= y_lo && y < y_hi) ? src[(size_t)(y - src_row0) * L + x0 + c] : mkc<C>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
+  }
+  // the twiddles of the store, loaded while the transform runs
+  constexpr int PER = P * 64 / 256;
+  C w[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int k1 = (t + q * 256) >> 6;
+    w[q] = tw_get<DIR>(tw, ((y2 * k1) & (L - 1)) * (kTwMax / L));
   }
   __syncthreads();
   stockham_cols<P, 1, DIR>(s, tw, t);
-  for (int i = t; i < P * 64; i += 256) {
-    const int k1 = i >> 6, c = i & 63;
-    const int m = (y2 * k1) & (L - 1);
-    dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], tw_get<DIR>(tw, m * (kTwMax / L)));
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = t + q * 256, k1 = i >> 6, c = i & 63;
+    dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], w[q]);
   }
 }
 
@@ -316,9 +330,16 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int k1 = blockIdx.y;
-  for (int i = t; i < Q * 64; i += 256) {
-    const int y2 = i >> 6, c = i & 63;
-    s[i] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+  {
+    constexpr int PER = Q * 64 / 256;
+    C v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = t + q * 256, y2 = i >> 6, c = i & 63;
+      v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   __syncthreads();
   stockham_cols<Q, 1, DIR>(s, tw, t);
@@ -457,14 +478,32 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int k1 = blockIdx.y;
-  for (int i = t; i < Q * 64; i += 256) {
-    const int y2 = i >> 6, c = i & 63;
-    s[i] = buf[(size_t)(Q * k1 + y2) * L + x0 + c];
+  constexpr int PER = Q * 64 / 256;
+  // the column block and (for a spectral factor) the factors it is
+  // multiplied by: all loads issued before the first is used
+  C sp[MODE == FILT_SPEC ? PER : 1];
+  {
+    C v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = t + q * 256, y2 = i >> 6, c = i & 63;
+      v[q] = buf[(size_t)(Q * k1 + y2) * L + x0 + c];
+    }
+    if constexpr (MODE == FILT_SPEC) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = t + q * 256, k2 = i >> 6, c = i & 63;
+        sp[q] = spec[(size_t)(k1 + P * k2) * L + x0 + c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   __syncthreads();
   stockham_cols<Q, 1, -1>(s, tw, t);
-  for (int i = t; i < Q * 64; i += 256) {
-    const int k2 = i >> 6, c = i & 63;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = t + q * 256, k2 = i >> 6, c = i & 63;
     const int k = k1 + P * k2;
     C v = s[i];
     if constexpr (MODE == FILT_GAMMA) {
@@ -473,16 +512,22 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
       if (own_low & 2) g = g * g;
       v = cscale(v, g * coef);
     } else {
-      v = cscale(cmul(v, spec[(size_t)k * L + x0 + c]), coef);
+      v = cscale(cmul(v, sp[q]), coef);
     }
     s[i] = v;
   }
+  C w[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int y2 = (t + q * 256) >> 6;
+    w[q] = tw_get<1>(tw, ((y2 * k1) & (L - 1)) * (kTwMax / L));
+  }
   __syncthreads();
   stockham_cols<Q, 1, 1>(s, tw, t);
-  for (int i = t; i < Q * 64; i += 256) {
-    const int y2 = i >> 6, c = i & 63;
-    const int m = (y2 * k1) & (L - 1);
-    buf[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], tw_get<1>(tw, m * (kTwMax / L)));
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = t + q * 256, y2 = i >> 6, c = i & 63;
+    buf[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], w[q]);
   }
 }
 
@@ -494,9 +539,16 @@ __global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * 64;
   const int y2 = blockIdx.y;
-  for (int i = t; i < P * 64; i += 256) {
-    const int k1 = i >> 6, c = i & 63;
-    s[i] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+  {
+    constexpr int PER = P * 64 / 256;
+    C v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = t + q * 256, k1 = i >> 6, c = i & 63;
+      v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   __syncthreads();
   stockham_cols<P, 1, 1>(s, tw, t);
