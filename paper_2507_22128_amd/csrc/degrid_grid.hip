@@ -41,13 +41,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// sum of v over the four lanes c16 + 16 g (g = 0..3) of a wave, the same
-// value in all four (row swaps: rows 0<->1, 2<->3, then halves)
-__device__ __forceinline__ float sum_rows(float v) {
-  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-  auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
-  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+// sums over the four lanes c16 + 16 g (g = 0..3) of a wave: lanes with
+// even g receive (a_0 + a_1) + (a_2 + a_3), lanes with odd g the same sum of
+// b.  The first swap exchanges row 1 of a with row 0 of b and row 3 of a
+// with row 2 of b, so one add forms the row-pair sums of a in rows 0, 2 and
+// of b in rows 1, 3; the second swap adds the two halves.
+__device__ __forceinline__ float sum_rows2(float a, float b) {
+  auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  const float u = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(u), __float_as_uint(u), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
 template <int W, int BLK, int MODE>
@@ -116,8 +119,9 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
     const float w = valid ? w_next : 0.f;
     pv_next = posvis[min(v + 16, e - 1)];
     if constexpr (kGrid) w_next = wts[min(v + 16, e - 1)];
-    const int ox = min(max((int)floorf(pv.x), 0), BLK - 1);
-    const int oy = min(max((int)floorf(pv.y), 0), BLK - 1);
+    // offsets are >= 0, so truncation is the floor
+    const int ox = min(max((int)pv.x, 0), BLK - 1);
+    const int oy = min(max((int)pv.y, 0), BLK - 1);
     const float fx = pv.x - (float)ox, fy = pv.y - (float)oy;
 
     // tap weights: clear this lane's quarter of the two table rows of its
@@ -140,8 +144,9 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
     }
     wave_sync();
 
-    float pr = 0.f, pi = 0.f;
+    float val = 0.f;  // predicted visibility: real part in lanes of even g, imaginary in odd
     if constexpr (kDegrid) {
+      float pr = 0.f, pi = 0.f;
       // T[y][k] = sum_x G[y][x] kx_k[x]: B[x = 4 g + s][k = c16]
       const floatx4 bx = *(const floatx4 *)&kx_t[c16 * 16 + 4 * g];
       floatx4 tre = {0.f, 0.f, 0.f, 0.f}, tim = {0.f, 0.f, 0.f, 0.f};
@@ -157,18 +162,18 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
         pr = fmaf(by[r], tre[r], pr);
         pi = fmaf(by[r], tim[r], pi);
       }
-      pr = sum_rows(pr);
-      pi = sum_rows(pi);
+      val = sum_rows2(pr, pi);
     }
     if constexpr (MODE == MODE_DEGRID) {
-      if (valid && g == 0) vis_out[outpos[v]] = make_float2(pr, pi);
+      if (valid && g < 2) reinterpret_cast<float *>(vis_out)[2 * (size_t)outpos[v] + g] = val;
     }
     if constexpr (kGrid) {
-      if (g == 0) {
+      if constexpr (MODE == MODE_DEGRID_GRID) {
+        // lane g = 0 forms the real part of w (v - v_hat), lane g = 1 the imaginary
+        if (g < 2) reinterpret_cast<float *>(r_t)[2 * c16 + g] = w * ((g ? pv.w : pv.z) - val);
+      } else if (g == 0) {
         float2 r;
-        if constexpr (MODE == MODE_DEGRID_GRID) {
-          r = make_float2(w * (pv.z - pr), w * (pv.w - pi));
-        } else if constexpr (MODE == MODE_GRID) {
+        if constexpr (MODE == MODE_GRID) {
           const float2 x = valid ? vis_in[outpos[v]] : make_float2(0.f, 0.f);
           r = make_float2(w * x.x, w * x.y);
         } else {  // MODE_PSF: unit visibilities
