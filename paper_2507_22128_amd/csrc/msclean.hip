@@ -43,6 +43,7 @@ struct Cand {
   double v;     // bias_s |R_s(p)|
   int s, p;     // internal scale, flat pixel
   double peak0; // max |R_0|
+  double rv;    // R_s(p) itself
 };
 
 __device__ __forceinline__ bool better(double v1, int s1, int p1, double v2, int s2, int p2) {
@@ -64,10 +65,12 @@ __device__ __forceinline__ void reduce_cand(Cand &c, Cand *sh) {
     const double ov = __shfl_xor(c.v, off);
     const int os = __shfl_xor(c.s, off), op = __shfl_xor(c.p, off);
     const double o0 = __shfl_xor(c.peak0, off);
+    const double orv = __shfl_xor(c.rv, off);
     if (better(ov, os, op, c.v, c.s, c.p)) {
       c.v = ov;
       c.s = os;
       c.p = op;
+      c.rv = orv;
     }
     c.peak0 = fmax(c.peak0, o0);
   }
@@ -80,29 +83,110 @@ __device__ __forceinline__ void reduce_cand(Cand &c, Cand *sh) {
         c.v = sh[w].v;
         c.s = sh[w].s;
         c.p = sh[w].p;
+        c.rv = sh[w].rv;
       }
       c.peak0 = fmax(c.peak0, sh[w].peak0);
     }
   }
 }
 
-__global__ __launch_bounds__(kStepThreads) void k_clean_step(StepArgs a, CleanState *st,
-                                                              Cand *slots) {
+struct SelectArgs {
+  const double *B;
+  int pair[kMaxInt][kMaxInt];
+  const double *kern;   // scale kernels, concatenated
+  int koff[kMaxInt], krad[kMaxInt];
+  int user[kMaxInt];    // internal -> user scale index
+  int n, n_int;
+  double gain, threshold;
+};
+
+// One iteration.  Every workgroup reduces the previous iteration's
+// per-workgroup candidates itself (the same values in the same order, so
+// all reach the same decision): stop for good if max |R_0| < threshold, else
+// alpha = gain R_{s*}(p*) / B_{s*s*}(0).  Workgroup 0 records the component
+// and adds alpha phi_{s*} at p* to the model.  Then every workgroup applies
+// R_t -= alpha B_{s*t} (shifted to p*) to its pixels and posts its candidate
+// for the next iteration.  With first != 0 there is no previous candidate
+// set: the launch only posts the candidates of the initial residuals.
+__global__ __launch_bounds__(kStepThreads) void k_clean_iter(StepArgs a, SelectArgs se,
+                                                              CleanState *st, const Cand *prev,
+                                                              int n_prev, Cand *next, int first,
+                                                              imgr_component *comps,
+                                                              double *model) {
   __shared__ Cand sh[kStepThreads / 64];
+  __shared__ int go, s_s, s_p;
+  __shared__ double s_alpha;
   if (st->stop) return;
   const int n = a.n, nn = n * n, n2 = 2 * n;
-  const bool pend = st->pend != 0;
-  const int ps = st->s, pp = st->p;
-  const double alpha = st->alpha;
+  bool upd = false;
+  int ps = 0, pp = 0;
+  double alpha = 0.0;
+  if (!first) {
+    Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n_prev; i += kStepThreads) {
+      const Cand o = prev[i];
+      if (better(o.v, o.s, o.p, c.v, c.s, c.p)) {
+        c.v = o.v;
+        c.s = o.s;
+        c.p = o.p;
+        c.rv = o.rv;
+      }
+      c.peak0 = fmax(c.peak0, o.peak0);
+    }
+    reduce_cand(c, sh);
+    if (threadIdx.x == 0) {
+      go = 0;
+      if (!(c.peak0 >= se.threshold) || c.s >= se.n_int) {
+        if (blockIdx.x == 0) st->stop = 1;
+      } else {
+        const double bc = se.B[(size_t)se.pair[c.s][c.s] * n2 * n2 + (size_t)n * n2 + n];
+        const double al = __ddiv_rn(__dmul_rn(se.gain, c.rv), bc);
+        if (blockIdx.x == 0) {
+          const int k = st->n_comps;
+          imgr_component cp;
+          cp.scale = se.user[c.s];
+          cp.iy = c.p / n;
+          cp.ix = c.p % n;
+          cp.reserved = 0;
+          cp.amp = al;
+          if (comps) comps[k] = cp;
+          st->n_comps = k + 1;
+        }
+        s_alpha = al;
+        s_s = c.s;
+        s_p = c.p;
+        go = 1;
+      }
+    }
+    __syncthreads();
+    if (!go) return;
+    upd = true;
+    ps = s_s;
+    pp = s_p;
+    alpha = s_alpha;
+    if (blockIdx.x == 0) {
+      // model += alpha phi_s centred at p (clipped to the image)
+      const int r = se.krad[ps], w = 2 * r + 1;
+      const double *k = se.kern + se.koff[ps];
+      const int cy = pp / n, cx = pp % n;
+      for (int j = threadIdx.x; j < w * w; j += kStepThreads) {
+        const int y = cy + j / w - r, x = cx + j % w - r;
+        if (y >= 0 && y < n && x >= 0 && x < n) {
+          double *m = model + (size_t)y * n + x;
+          *m = __dadd_rn(*m, __dmul_rn(alpha, k[j]));
+        }
+      }
+    }
+  }
   const int py = pp / n, px = pp % n;
-  Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0};
+  Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0, 0.0};
   for (int i = blockIdx.x * kStepThreads + threadIdx.x; i < nn; i += gridDim.x * kStepThreads) {
     const int y = i / n, x = i % n;
     const size_t bi = (size_t)(n + y - py) * n2 + (n + x - px);
     for (int t = 0; t < a.n_int; ++t) {
       double *r = a.R + (size_t)t * nn + i;
       double v = *r;
-      if (pend) {
+      if (upd) {
         const double b = a.B[(size_t)a.pair[ps][t] * n2 * n2 + bi];
         v = __dsub_rn(v, __dmul_rn(alpha, b));
         *r = v;
@@ -113,87 +197,14 @@ __global__ __launch_bounds__(kStepThreads) void k_clean_step(StepArgs a, CleanSt
           c.v = bv;
           c.s = t;
           c.p = i;
+          c.rv = v;
         }
       }
       if (t == a.r0) c.peak0 = fmax(c.peak0, fabs(v));
     }
   }
   reduce_cand(c, sh);
-  if (threadIdx.x == 0) slots[blockIdx.x] = c;
-}
-
-struct SelectArgs {
-  const double *R;
-  const double *B;
-  int pair[kMaxInt][kMaxInt];
-  const double *kern;   // scale kernels, concatenated
-  int koff[kMaxInt], krad[kMaxInt];
-  int user[kMaxInt];    // internal -> user scale index
-  int n, n_int;
-  double gain, threshold;
-};
-
-__global__ __launch_bounds__(256) void k_clean_select(SelectArgs a, CleanState *st,
-                                                      const Cand *slots, int n_slots,
-                                                      imgr_component *comps, double *model) {
-  __shared__ Cand sh[4];
-  __shared__ int go;
-  __shared__ double s_alpha;
-  __shared__ int s_s, s_p;
-  if (st->stop) return;
-  Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0};
-  for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
-    const Cand o = slots[i];
-    if (better(o.v, o.s, o.p, c.v, c.s, c.p)) {
-      c.v = o.v;
-      c.s = o.s;
-      c.p = o.p;
-    }
-    c.peak0 = fmax(c.peak0, o.peak0);
-  }
-  reduce_cand(c, sh);
-  const int n = a.n, nn = n * n, n2 = 2 * n;
-  if (threadIdx.x == 0) {
-    st->pend = 0;
-    go = 0;
-    if (!(c.peak0 >= a.threshold) || c.s >= a.n_int) {
-      st->stop = 1;
-    } else {
-      const double rv = a.R[(size_t)c.s * nn + c.p];
-      const double bc = a.B[(size_t)a.pair[c.s][c.s] * n2 * n2 + (size_t)n * n2 + n];
-      const double alpha = __ddiv_rn(__dmul_rn(a.gain, rv), bc);
-      const int k = st->n_comps;
-      imgr_component cp;
-      cp.scale = a.user[c.s];
-      cp.iy = c.p / n;
-      cp.ix = c.p % n;
-      cp.reserved = 0;
-      cp.amp = alpha;
-      if (comps) comps[k] = cp;
-      st->n_comps = k + 1;
-      st->s = c.s;
-      st->p = c.p;
-      st->alpha = alpha;
-      st->pend = 1;
-      s_alpha = alpha;
-      s_s = c.s;
-      s_p = c.p;
-      go = 1;
-    }
-  }
-  __syncthreads();
-  if (!go) return;
-  // model += alpha phi_s centred at p (clipped to the image)
-  const int r = a.krad[s_s], w = 2 * r + 1;
-  const double *k = a.kern + a.koff[s_s];
-  const int cy = s_p / n, cx = s_p % n;
-  for (int j = threadIdx.x; j < w * w; j += blockDim.x) {
-    const int y = cy + j / w - r, x = cx + j % w - r;
-    if (y >= 0 && y < n && x >= 0 && x < n) {
-      double *m = model + (size_t)y * n + x;
-      *m = __dadd_rn(*m, __dmul_rn(s_alpha, k[j]));
-    }
-  }
+  if (threadIdx.x == 0) next[blockIdx.x] = c;
 }
 
 // out (n x n) = in * k (linear, zero outside), k of side 2r+1, centred
@@ -376,7 +387,7 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
     cw.kern = (double *)dev_alloc(h, kall.size() * sizeof(double));
     cw.model = (double *)dev_alloc(h, (size_t)nn * sizeof(double));
     cw.state = dev_alloc(h, sizeof(CleanState));
-    cw.slots = dev_alloc(h, (size_t)kStepBlocks * sizeof(Cand));
+    cw.slots = dev_alloc(h, (size_t)2 * kStepBlocks * sizeof(Cand));
     cw.R_elems = need_R;
     cw.B_elems = need_B;
     cw.k_elems = kall.size();
@@ -398,7 +409,6 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
   sa.R = cw.R;
   sa.B = cw.B;
   SelectArgs se;
-  se.R = cw.R;
   se.B = cw.B;
   se.kern = cw.kern;
   for (int a = 0; a < kMaxInt; ++a) {
@@ -424,11 +434,14 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
   const int nblk = std::min(kStepBlocks, (int)cdiv(nn, kStepThreads));
   CleanState *st = (CleanState *)cw.state;
   Cand *slots = (Cand *)cw.slots;
-  for (int k = 0; k < prm.max_iter; ++k) {
-    hipLaunchKernelGGL(k_clean_step, dim3(nblk), dim3(kStepThreads), 0, s, sa, st, slots);
-    hipLaunchKernelGGL(k_clean_select, dim3(1), dim3(256), 0, s, se, st, slots, nblk, comps,
-                       cw.model);
-  }
+  // candidates of iteration k live in slots[(k % 2) * kStepBlocks ...]: an
+  // iteration reads one half and writes the other
+  hipLaunchKernelGGL(k_clean_iter, dim3(nblk), dim3(kStepThreads), 0, s, sa, se, st,
+                     (const Cand *)nullptr, 0, slots, 1, comps, cw.model);
+  for (int k = 0; k < prm.max_iter; ++k)
+    hipLaunchKernelGGL(k_clean_iter, dim3(nblk), dim3(kStepThreads), 0, s, sa, se, st,
+                       (const Cand *)(slots + (k % 2) * kStepBlocks), nblk,
+                       slots + ((k + 1) % 2) * kStepBlocks, 0, comps, cw.model);
   IMGR_HIP(hipGetLastError());
   FinishArgs fa;
   for (int t = 0; t < kMaxInt; ++t) fa.pair_r0[t] = (t < n_int) ? pair[t][r0] : 0;
