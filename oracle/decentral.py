@@ -16,7 +16,7 @@ def gamma_low(n, ell, delta, scale=1.0):
 
     Section 4.1 asks the filters to keep only their own spatial frequencies
     and to have weights summing to one on the overlap L n H.  Reading
-    (DESIGN.md; shape parity unpinned): a radial linear ramp
+    (shape parity unpinned): a radial linear ramp
         Gamma_L(kappa) = clip((ell + delta - kappa) / (2 delta), 0, 1)
     with kappa the radius of the DFT frequency in Fourier pixels of the
     N x N image; for a 2N x 2N image the same physical frequency has twice

@@ -8,7 +8,7 @@ gridding work the paper cites in Section 2 (Barnett et al. 2019):
     phi(z) = exp(beta * (sqrt(1 - z^2) - 1))   for |z| <= 1, else 0,
 
 stretched over W grid cells: the weight of cell c for a visibility at grid
-coordinate x is phi((c - x) / (W/2)).  Reading (DESIGN.md): beta = 2.30 W,
+coordinate x is phi((c - x) / (W/2)).  Reading: beta = 2.30 W,
 the value that reference publishes for upsampling factor 2.
 
 The W cells used for coordinate x are floor(x) - W/2 + 1 ... floor(x) + W/2

@@ -3,7 +3,7 @@
 The paper states the measurement equation (Eq. 1, Section 2) in terms of
 baseline coordinates (u, v, w) in wavelengths and direction cosines (l, m);
 it gives no pixel or grid convention.  The conventions below are readings
-(listed in the design doc) and are applied identically by the GPU library:
+and are applied identically by the GPU library:
 
 * image of N x N pixels, row-major ``[iy][ix]``, pixel (ix, iy) at
   l = (ix - N/2) * cell, m = (iy - N/2) * cell; the phase centre is pixel

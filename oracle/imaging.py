@@ -16,7 +16,7 @@ from .geometry import fourier_pixels, grid_coord
 def uniform_weights(u, v, n_img, cell, w_in=None, valid=None):
     """Uniform weighting (Section 5.1 images every dataset with it).
 
-    Reading (DESIGN.md): the density cell of visibility k is the nearest
+    Reading: the density cell of visibility k is the nearest
     cell of the N x N image's Fourier grid,
         c_k = (floor(u_k N cell + 0.5), floor(v_k N cell + 0.5)) mod N,
     the density is the number n(c_k) of unflagged visibilities of the whole

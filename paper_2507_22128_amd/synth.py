@@ -8,7 +8,7 @@ sources, and evaluates each source's analytic Fourier transform plus
 complex Gaussian noise.  Both the HIP library (through the tests and the
 benchmark) and the CPU oracle consume exactly the arrays it returns.
 
-Recipe (also in DESIGN.md):
+Recipe:
 * antennas uniform over a disk (radius R sqrt(U), angle 2 pi U'), flat,
   at latitude -30.7 deg; all i < j baselines;
 * phase centre at declination -30 deg, hour angles at the midpoints of

@@ -193,6 +193,24 @@ def test_support_rule_error_bound(support):
     assert e_fwd > bound / 30 and e_adj > bound / 30
 
 
+def test_sparse_and_pointwise_sums_match_the_dense_definition():
+    """forward_points / adjoint_at (used at full size) against the dense
+    phase-matrix sums, on a case small enough for both."""
+    rng = np.random.default_rng(17)
+    n, cell = 32, 1e-3
+    u, v = _uv(rng, 700, 2 * n, cell)
+    iy, ix = rng.integers(0, n, 9), rng.integers(0, n, 9)
+    amp = rng.standard_normal(9)
+    img = np.zeros((n, n))
+    np.add.at(img, (iy, ix), amp)
+    assert np.allclose(dft.forward_points(amp, iy, ix, u, v, cell, n), dft.forward(img, u, v, cell),
+                       rtol=0, atol=1e-11)
+    y = rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))
+    dense = dft.adjoint(y, u, v, cell, n)
+    got = dft.adjoint_at(y, u, v, cell, n, iy, ix, chunk=128)
+    assert np.allclose(got, dense[iy, ix], rtol=0, atol=1e-10)
+
+
 def test_hermitian_symmetry_for_real_images():
     rng = np.random.default_rng(7)
     n, cell = 32, 1e-3
