@@ -285,3 +285,45 @@ def test_errors_are_reported(medium):
     with pytest.raises(imager.ImagerError) as e:
         imager.Imager.create(d, n_partitions=2, hbm_budget=1 << 20)
     assert e.value.code == imager.ENOMEM
+
+
+def test_all_flagged_is_refused():
+    d = workload("tiny", n_time=4)
+    imager = _imager()
+    with pytest.raises(imager.ImagerError) as e:
+        imager.Imager.create(d, n_partitions=1, flag=np.ones(len(d["vis"]), np.uint8))
+    assert e.value.code == imager.EINVAL
+
+
+@pytest.mark.parametrize("n_pix", [64, 2048])
+def test_smallest_and_largest_image_sizes(n_pix):
+    """N = 64 and N = 2048 (grids of 128 and 4096, PSF grids of 256 and 8192:
+    the smallest and largest transform lengths the library builds), against
+    the direct Fourier sums at sampled pixels."""
+    from oracle import dft
+    say("case: tiny array (10 time steps), N = %d" % n_pix)
+    d = workload("tiny", n_time=10)
+    h = _imager().Imager.create(d, n_pix=n_pix, n_partitions=1, weighting="uniform")
+    try:
+        n = n_pix
+        u, v = uv(d)
+        w = imaging.uniform_weights(u, v, n, d["cell"])
+        rng = np.random.default_rng(n)
+        iy = np.concatenate([[n // 2], rng.integers(0, n, 12)])
+        ix = np.concatenate([[n // 2], rng.integers(0, n, 12)])
+        q = (n // 2 + 5, n // 2 - 3)
+        model = np.zeros((n, n))
+        model[q] = 0.5
+        pred = dft.forward_points([0.5], [q[0]], [q[1]], u, v, d["cell"], n)
+        r = w * (d["vis"] - pred)
+        ref = dft.adjoint_at(r, u, v, d["cell"], n, iy, ix).real / w.sum()
+        got = to_np(h.major_cycle(0, to_dev(model)))[iy, ix].astype(np.float64)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        dy, dx = rng.integers(-8, 9, 10), rng.integers(-8, 9, 10)
+        pref = dft.adjoint_at(w, u, v, d["cell"], 2 * n, n + dy, n + dx).real / w.sum()
+        pgot = to_np(h.psf(0))[n + dy, n + dx].astype(np.float64)
+        perr = np.abs(pgot - pref).max() / np.abs(pref).max()
+        say("N = %d: residual max err %.3e, PSF max err %.3e" % (n, err, perr))
+        assert err < TOL and perr < TOL
+    finally:
+        h.destroy()
