@@ -150,6 +150,69 @@ def minor_cycles(h, info, model, rho, gammas, mus, n):
     return out
 
 
+def convex(args):
+    """The sparsity-regularised workload's shapes: 256 antennas x 1532 times
+    = 50,004,480 visibilities at 1.4 GHz, N = 2048, 2 partitions (median
+    split), support 8; point-source sky (500 sources) from the GPU
+    generator.  Times the two-node major cycle and node V_L's FISTA minor
+    cycle (db8, 3 levels, 200 iterations, 30 power iterations, lambda =
+    1e-3 max |i~|, gamma_n = 1)."""
+    import numpy as np
+    import torch
+    from paper_2507_22128_amd import imager, synth
+    t0 = time.perf_counter()
+    d = synth.make_channels(n_chan=1, n_time=1532, f_lo=1.4e9, f_hi=1.4e9, flag_max=0.0,
+                            sizes=(2048,), n_points=500, seed=3, device="cuda")
+    c = d["channels"][0]
+    h = imager.Imager.create(uvw=d["uvw"], vis=c["vis"], freq_hz=c["freq_hz"], cell=c["cell"],
+                             n_pix=2048, n_partitions=2, weighting="uniform")
+    info = h.info
+    del d, c
+    torch.cuda.empty_cache()
+    log("convex: %d visibilities, N = 2048, handle built in %.1f s (create %.0f ms)"
+        % (info.n_valid, time.perf_counter() - t0, info.create_ms))
+    n = 2048
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    model = [torch.zeros((n, n), device="cuda") for _ in range(2)]
+    rho = [1e-3 * torch.randn((n, n), generator=g, device="cuda") for _ in range(2)]
+    outs = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    locs = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    wsum = info.sum_w[0] + info.sum_w[1]
+    gm = [info.sum_w[0] / wsum, info.sum_w[1] / wsum]
+    mu = [gm[1], gm[0]]
+    for _ in range(2):
+        h.major_cycle_nodes(model, rho, gm, mu, outs=outs, local_outs=locs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 10
+    for _ in range(steps):
+        h.major_cycle_nodes(model, rho, gm, mu, outs=outs, local_outs=locs)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    start = torch.tensor(np.random.default_rng(7).standard_normal((n, n)), dtype=torch.float32,
+                         device="cuda")
+    h.minor_cycle_fista(0, locs[0], start, rho_other=rho[0], n_iter=2, power_iters=2, gamma_n=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, L, lam = h.minor_cycle_fista(0, locs[0], start, rho_other=rho[0], n_iter=200,
+                                       power_iters=30, gamma_n=1.0)
+    t_f = time.perf_counter() - t0
+    h.destroy()
+    torch.cuda.empty_cache()
+    log("convex: major cycle %.3f ms (%.0f Mvis/s), FISTA %.1f ms" % (
+        ms, info.n_valid / (ms / 1e3) / 1e6, 1e3 * t_f))
+    return {"workload": "256 antennas x 1532 times = %d visibilities (complex64), 1.40 GHz, "
+                        "2048^2 image, 2 partitions split at the median |uv|, uniform weighting, "
+                        "ES support 8; 500 point sources" % info.n_valid,
+            "n_vis_partitions": [int(info.n_vis[0]), int(info.n_vis[1])],
+            "major_cycle_ms": round(ms, 3),
+            "major_cycle_mvis_per_s": round(info.n_valid / (ms / 1e3) / 1e6, 1),
+            "fista_ms": round(1e3 * t_f, 1), "fista_ms_per_iteration": round(1e3 * t_f / 230, 3),
+            "fista_config": "node V_L, Eq. 5 with gamma_n = 1, db8 3 levels, 200 iterations + "
+                            "30 power iterations, lambda = 1e-3 max |i~|, FP64 transforms"}
+
+
 def batched_channels(args):
     """Batched-channel workload: the major cycle (Eq. 2) of every channel of
     a 64-channel observation (0.95 - 1.75 GHz, 256 antennas, 480 times,
@@ -347,6 +410,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-minor-cycles", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-convex", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
@@ -505,6 +569,8 @@ def main():
     if not args.no_minor_cycles:
         res["minor_cycles"] = minor_cycles(h, info, model, rho, gammas, mus, n)
     h.destroy()
+    if not args.no_convex:
+        res["convex"] = convex(args)
     if not args.no_batch:
         res["batched_channels"] = batched_channels(args)
     if not args.no_serve:
