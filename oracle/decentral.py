@@ -176,21 +176,25 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
 
 def reconstruct_fista(u, v, vis, w, n_img, cell, n_cycles, start_images, lam_frac=1e-3,
                       n_iter=200, power_iters=30, vanishing=8, levels=3, partitions=2, ell=None,
-                      delta=1.0, support=8):
+                      delta=1.0, support=8, dictionary=False):
     """The major/minor loop with the sparsity-regularised minor cycle (Eqs.
     4 and 5), serial (partitions = 1) or decentralized, in FP64.
 
     Per major cycle n and node: i~ = the node's residual (Eq. 2); lambda^n =
     lam_frac max |i~| (reading of "1e-3 x max |dirty|"); gamma_n = 0 at
     n = 1, else 1 (Eq. 5); L_hat by ``power_iters`` power iterations from
-    start_images[node]; alpha by ``n_iter`` FISTA iterations; ibar = W alpha;
+    start_images[node]; alpha by ``n_iter`` FISTA iterations; ibar = W alpha
+    (W one db_vanishing basis, or with ``dictionary`` the tight frame of db1 ..
+    db_vanishing);
     model += ibar (Eq. 3).  Then the Phi / rho exchange of Section 4.1 and,
     at the end, the equal-weight combination of Section 5.2.
     Returns (final image, per-node models, history of per-cycle dicts
     {node: (lambda, L_hat, objective list)}).
     """
     from . import fista as fs, imaging, wavelets
-    h = wavelets.daubechies(vanishing)
+    # one Daubechies basis, or the concatenation of the first `vanishing` ones
+    h = ([wavelets.daubechies(p) for p in range(1, vanishing + 1)] if dictionary
+         else wavelets.daubechies(vanishing))
     m = len(u)
     if partitions == 1:
         masks = {"L": np.ones(m, bool)}

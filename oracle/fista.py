@@ -7,7 +7,9 @@ the special case with Gamma_own = I and gamma_n = 0):
     f(alpha) = || Gamma_own (i~ - H W alpha) ||^2 + gamma_n || rho - Gamma_other W alpha ||^2
     alpha*   = argmin f(alpha) + lambda ||alpha||_1,     ibar = W alpha*
 
-with W the orthonormal periodized wavelet synthesis (``wavelets.idwt2``),
+with W the orthonormal periodized wavelet synthesis (``wavelets.idwt2``)
+or, for a list of filters, the tight frame of their concatenation
+(``wavelets.dict_synthesis``: the paper's first-8-Daubechies dictionary),
 H the convolution by the node's 2N x 2N PSF (``imaging.apply_psf``) and
 the filters Gamma of ``decentral``.  H and Gamma are self-adjoint (reading:
 the PSF is even and the filters are real and radial), so
@@ -21,7 +23,9 @@ FISTA (Beck and Teboulle 2009) with constant step 1/L_hat:
 from alpha_0 = y_1 = 0, t_1 = 1.  L_hat = 2 lambda_max of the image-space
 map x -> H Gamma_own^2 H x + gamma_n Gamma_other^2 x (W is orthonormal),
 estimated by power iteration from a given start image (the random start
-is an input, so both implementations can use the same one).
+is an input, so both implementations can use the same one).  For the tight
+frame W^T M W has the nonzero eigenvalues of M W W^T = M, so the same
+image-space estimate applies.
 """
 
 import numpy as np
@@ -51,9 +55,13 @@ class NodeProblem:
             self.g_own, self.g_other = decentral.filters(n, ell, delta, own)
 
     def W(self, a):
+        if isinstance(self.h, list):
+            return wavelets.dict_synthesis(a, self.h, self.levels)
         return wavelets.idwt2(a, self.h, self.levels)
 
     def Wt(self, x):
+        if isinstance(self.h, list):
+            return wavelets.dict_analysis(x, self.h, self.levels)
         return wavelets.dwt2(x, self.h, self.levels)
 
     def gam(self, x, g):
@@ -98,8 +106,7 @@ def power_iteration(prob, start, iters=30):
 
 def fista(prob, lam, n_iter, L_hat):
     """Returns (alpha, objective per iteration)."""
-    n = prob.dirty.shape[0]
-    a_prev = np.zeros((n, n))
+    a_prev = np.zeros(prob.Wt(np.zeros(prob.dirty.shape)).shape)
     y = a_prev.copy()
     t = 1.0
     obj = []

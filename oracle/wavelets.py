@@ -16,6 +16,11 @@ classical (1 + sqrt 3, 3 + sqrt 3, 3 - sqrt 3, 1 - sqrt 3) / (4 sqrt 2)
 (pinned in the tests).  Roots are polished by Newton's method in extended
 precision.  The high-pass filter is g_j = (-1)^j h_{L-1-j}.
 
+The paper's sparsity prior uses for W a concatenation of the first 8
+Daubechies wavelets (Section 5.1); as a tight frame each basis is scaled
+by 1/sqrt(P), P the number of bases, so that W W^T = I
+(``dict_analysis`` / ``dict_synthesis``; coefficients stacked [P][n][n]).
+
 Periodized analysis along one axis of length n (even):
     a[k] = sum_j h_j x[(2k + j) mod n],   d[k] = sum_j g_j x[(2k + j) mod n]
 and synthesis is its transpose.  Coefficients are stored in place (Mallat
@@ -122,3 +127,19 @@ def idwt2(c, h, levels):
         x[:n, :n] = blk
         n *= 2
     return x
+
+
+def dict_analysis(x, hs, levels):
+    """W^T for the dictionary of bases hs: stacked coefficients, each basis
+    scaled by 1 / sqrt(len(hs))."""
+    k = 1.0 / np.sqrt(len(hs))
+    return np.stack([k * dwt2(x, h, levels) for h in hs])
+
+
+def dict_synthesis(c, hs, levels):
+    """W: sum over the bases of their synthesis, scaled by 1 / sqrt(len(hs))."""
+    k = 1.0 / np.sqrt(len(hs))
+    out = np.zeros(c.shape[1:])
+    for p, h in enumerate(hs):
+        out += k * idwt2(c[p], h, levels)
+    return out

@@ -620,6 +620,48 @@ def test_fista_closed_form_identity_operator():
     assert max(obj) - min(obj) < 1e-9 * abs(obj[0])
 
 
+def test_dictionary_is_a_tight_frame_and_reduces_to_one_basis():
+    """The first-8-Daubechies dictionary: W W^T = I, W^T is the adjoint of
+    W, and a one-filter dictionary is that single basis."""
+    from oracle import wavelets
+    rng = np.random.default_rng(19)
+    n, levels = 64, 2
+    hs = [wavelets.daubechies(p) for p in range(1, 9)]
+    x = rng.standard_normal((n, n))
+    c = wavelets.dict_analysis(x, hs, levels)
+    assert c.shape == (8, n, n)
+    assert np.abs(wavelets.dict_synthesis(c, hs, levels) - x).max() < 1e-12
+    a = rng.standard_normal((8, n, n))
+    lhs = np.vdot(wavelets.dict_synthesis(a, hs, levels), x)
+    rhs = np.vdot(a, c)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(a) * np.linalg.norm(x)
+    # energy: ||W^T x|| = ||x|| (tight frame with bound 1), and not an orthonormal basis
+    assert abs(np.linalg.norm(c) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+    assert np.abs(wavelets.dict_analysis(wavelets.dict_synthesis(a, hs, levels), hs, levels)
+                  - a).max() > 1e-3
+    h4 = wavelets.daubechies(4)
+    assert np.array_equal(wavelets.dict_analysis(x, [h4], levels)[0], wavelets.dwt2(x, h4, levels))
+
+
+def test_fista_with_dictionary_decreases_objective():
+    from oracle import fista, wavelets
+    from oracle.imaging import apply_psf
+    psf, n = _small_psf()
+    rng = np.random.default_rng(20)
+    truth = np.zeros((n, n))
+    truth[rng.integers(4, n - 4, 6), rng.integers(4, n - 4, 6)] = rng.uniform(0.2, 1.0, 6)
+    dirty = apply_psf(psf, truth)
+    hs = [wavelets.daubechies(p) for p in range(1, 9)]
+    prob = fista.NodeProblem(dirty, psf, None, 0.0, 6.0, 1.0, "L", hs, 1, serial=True)
+    L_hat = fista.power_iteration(prob, rng.standard_normal((n, n)), 30)
+    single = fista.NodeProblem(dirty, psf, None, 0.0, 6.0, 1.0, "L", hs[7], 1, serial=True)
+    assert abs(L_hat - fista.power_iteration(single, rng.standard_normal((n, n)), 60)) < 1e-3 * L_hat
+    lam = 1e-3 * np.abs(dirty).max()
+    alpha, obj = fista.fista(prob, lam, 40, L_hat)
+    assert alpha.shape == (8, n, n)
+    assert obj[-1] < 0.5 * prob.objective(np.zeros((8, n, n)), lam)
+
+
 def test_fista_decreases_objective_and_respects_lipschitz_bound():
     """On a two-node problem: the power-iteration L_hat does not exceed the
     bound 2 max (Gamma_own^2 |psf_hat|^2 + gamma Gamma_other^2) of the
