@@ -140,7 +140,8 @@ typedef struct {
  * control: *resident (host) receives an upper estimate of device_bytes after
  * imager_create plus the reconstruction loop's buffers and the minor-cycle
  * work areas (multi-scale CLEAN with n_scales scales if n_scales > 0, FISTA
- * if fista != 0), *peak (host, may be NULL) one of device_peak_bytes, which
+ * over a dictionary of `fista` bases if fista > 0), *peak (host, may be
+ * NULL) one of device_peak_bytes, which
  * adds the temporaries of imager_create (host-staged inputs if vis_on_host,
  * sort and binning buffers, the PSF grid, the autotuner's trials).  With
  * two partitions and ell_pix < 0 (median split) each partition is taken to
@@ -324,6 +325,11 @@ typedef struct {
   double gamma_n;        /* weight of the rho term (Eq. 5: 0 at the first cycle, else 1) */
   int32_t serial;        /* 1: Eq. 4 (Gamma_own = identity, no rho term) */
   int32_t first_cycle;   /* imager_reconstruct_fista only: as in imgr_msclean_params */
+  int32_t dictionary;    /* 0: W is the one basis db_vanishing; 1: W is the concatenation of
+                            the first `vanishing` Daubechies bases db_1 .. db_vanishing, each
+                            scaled by 1 / sqrt(vanishing) (a tight frame, W W^T = I; the
+                            dictionary of Section 5.1), alpha then has vanishing x N^2
+                            coefficients */
 } imgr_fista_params;
 
 imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,

@@ -447,7 +447,9 @@ imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_
   }
   // FISTA: 11 FP64 images, 6 complex FP64 images of work, the FP64 PSF
   // spectrum and the temporary it is built in
-  if (fista) minor = std::max(minor, 8.0 * 11 * nn + 16.0 * 6 * nn + 2 * 16.0 * 4 * nn + 65536.0);
+  if (fista > 0)  // coefficients (3 x bases), 8 images, transform work, PSF spectrum + temp
+    minor = std::max(minor, 8.0 * (3.0 * fista + 8 + (fista > 1 ? 1 : 0)) * nn + 16.0 * 6 * nn +
+                                2 * 16.0 * 4 * nn + 65536.0);
   const double res = fixed + parts * (per + loop + minor);
   // create-time temporaries on top of the handle's work buffers and tables
   const double staged = vis_on_host ? (24.0 + 16.0 + 4.0 + 1.0) * m : 0.0;
@@ -707,6 +709,7 @@ static void check_fista(imgr_s *h, const imgr_fista_params &p) {
   IMGR_CHECK(std::isfinite(p.lambda) && std::isfinite(p.lambda_frac) && std::isfinite(p.gamma_n),
              "lambda / gamma_n");
   IMGR_CHECK(p.lambda > 0.0 || p.lambda_frac >= 0.0, "lambda_frac must be >= 0");
+  IMGR_CHECK(p.dictionary == 0 || p.dictionary == 1, "dictionary must be 0 or 1");
 }
 
 imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,

@@ -86,15 +86,16 @@ struct CleanWork {
 
 // device work area of one node's FISTA (kept between calls; FP64)
 struct FistaWork {
-  double *alpha_prev = nullptr, *y = nullptr;                    // N^2 coefficients
+  double *alpha_prev = nullptr, *y = nullptr, *coef = nullptr;   // P N^2 coefficients
   double *x = nullptr, *u1 = nullptr, *u2 = nullptr, *u3 = nullptr;  // N^2 images
-  double *cst = nullptr, *tmp = nullptr, *coef = nullptr;        // N^2
+  double *cst = nullptr, *tmp = nullptr, *xb = nullptr;          // N^2
   double *d64 = nullptr, *r64 = nullptr;                         // inputs in FP64
   double2 *work64 = nullptr, *tmp64 = nullptr;                   // transform buffers
   double *scal = nullptr;    // device scalars (L_hat, lambda, norms)
   double *part = nullptr;    // reduction partials
-  double *hlo = nullptr;     // wavelet filters (low, high)
-  int taps = 0, vanishing = 0;
+  double *hlo = nullptr;     // wavelet filters (low, high) of every basis, concatenated
+  std::vector<int> taps, hoff;  // per basis: filter length, offset in hlo
+  int vanishing = 0, n_bases = 0;
   size_t n = 0;
 };
 

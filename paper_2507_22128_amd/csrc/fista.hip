@@ -123,7 +123,7 @@ std::vector<double> daubechies(int p) {
 template <int AXIS>
 __global__ void k_dwt(const double *__restrict__ a, const double *__restrict__ b, int in_stride,
                       double *__restrict__ out, int out_stride, int n, const double *__restrict__ hg,
-                      int taps) {
+                      int taps, double sc) {
   const int half = n / 2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * half) return;
@@ -141,6 +141,7 @@ __global__ void k_dwt(const double *__restrict__ a, const double *__restrict__ b
     const size_t off = (AXIS == 1) ? (size_t)line * in_stride + m : (size_t)m * in_stride + line;
     double v = a[off];
     if (b) v -= b[off];
+    if (sc != 1.0) v *= sc;
     lo = fma(hg[j], v, lo);
     hi = fma(hg[taps + j], v, hi);
   }
@@ -204,6 +205,13 @@ __global__ void k_f32_to_f64(const float *__restrict__ a, double *__restrict__ b
 __global__ void k_copy_f64(const double *__restrict__ a, double *__restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
+}
+
+// out = k a (first) or out + k a
+__global__ void k_scale_add(const double *__restrict__ a, double k, double *__restrict__ out,
+                            int first, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = first ? k * a[i] : out[i] + k * a[i];
 }
 
 __global__ void k_add_to_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
@@ -299,7 +307,7 @@ inline dim3 g1(int64_t n) { return dim3(cdiv(n, 256)); }
 
 struct Ctx {
   imgr_s *h;
-  int part, n, levels, taps;
+  int part, n, levels, nb;  // nb: bases of the dictionary
   size_t nn;
   FistaWork *fw;
   const double2 *psf_hat;
@@ -308,32 +316,56 @@ struct Ctx {
   double gamma_n;
 };
 
-// W^T (a - b) -> out (coefficients), via fw->tmp
+// W^T (a - b) -> out (coefficients, nb stacked N^2 blocks), via fw->tmp; each
+// basis of a dictionary sees the input scaled by 1 / sqrt(nb)
 void dwt2(Ctx &c, const double *a, const double *b, double *out) {
   const int N = c.n;
-  int n = N;
-  for (int lev = 0; lev < c.levels; ++lev) {
-    const double *src = lev == 0 ? a : out;
-    const double *sb = lev == 0 ? b : nullptr;
-    hipLaunchKernelGGL(k_dwt<1>, g1((int64_t)n * (n / 2)), dim3(256), 0, c.s, src, sb, N,
-                       c.fw->tmp, N, n, c.fw->hlo, c.taps);
-    hipLaunchKernelGGL(k_dwt<0>, g1((int64_t)n * (n / 2)), dim3(256), 0, c.s, c.fw->tmp,
-                       (const double *)nullptr, N, out, N, n, c.fw->hlo, c.taps);
-    n /= 2;
+  const double sc = c.nb > 1 ? 1.0 / std::sqrt((double)c.nb) : 1.0;
+  for (int p = 0; p < c.nb; ++p) {
+    double *o = out + (size_t)p * c.nn;
+    const double *hg = c.fw->hlo + c.fw->hoff[p];
+    const int taps = c.fw->taps[p];
+    int n = N;
+    for (int lev = 0; lev < c.levels; ++lev) {
+      const double *src = lev == 0 ? a : o;
+      const double *sb = lev == 0 ? b : nullptr;
+      hipLaunchKernelGGL(k_dwt<1>, g1((int64_t)n * (n / 2)), dim3(256), 0, c.s, src, sb, N,
+                         c.fw->tmp, N, n, hg, taps, lev == 0 ? sc : 1.0);
+      hipLaunchKernelGGL(k_dwt<0>, g1((int64_t)n * (n / 2)), dim3(256), 0, c.s, c.fw->tmp,
+                         (const double *)nullptr, N, o, N, n, hg, taps, 1.0);
+      n /= 2;
+    }
   }
 }
 
-// W alpha -> out image, via fw->tmp
-void idwt2(Ctx &c, const double *alpha, double *out) {
+// one basis' synthesis of coefficients alpha -> out image, via fw->tmp
+void idwt2_one(Ctx &c, int p, const double *alpha, double *out) {
   const int N = c.n;
+  const double *hg = c.fw->hlo + c.fw->hoff[p];
+  const int taps = c.fw->taps[p];
   hipLaunchKernelGGL(k_copy_f64, g1((int64_t)c.nn), dim3(256), 0, c.s, alpha, out, (int64_t)c.nn);
   int n = N >> (c.levels - 1);
   for (int lev = 0; lev < c.levels; ++lev) {
     hipLaunchKernelGGL(k_idwt<0>, g1((int64_t)n * n), dim3(256), 0, c.s, out, N, c.fw->tmp, N, n,
-                       c.fw->hlo, c.taps);
+                       hg, taps);
     hipLaunchKernelGGL(k_idwt<1>, g1((int64_t)n * n), dim3(256), 0, c.s, c.fw->tmp, N, out, N, n,
-                       c.fw->hlo, c.taps);
+                       hg, taps);
     n *= 2;
+  }
+}
+
+// W alpha -> out image: one basis, or the sum over the dictionary's bases
+// of their synthesis times 1 / sqrt(nb), in basis order
+void idwt2(Ctx &c, const double *alpha, double *out) {
+  if (c.nb == 1) {
+    idwt2_one(c, 0, alpha, out);
+    return;
+  }
+  const double k = 1.0 / std::sqrt((double)c.nb);
+  for (int p = 0; p < c.nb; ++p) {
+    idwt2_one(c, p, alpha + (size_t)p * c.nn, c.fw->xb);
+    hipLaunchKernelGGL(k_scale_add, g1((int64_t)c.nn), dim3(256), 0, c.s, c.fw->xb, k, out,
+                       p == 0 ? 1 : 0, (int64_t)c.nn);
   }
 }
 
@@ -365,10 +397,10 @@ void normal_map(Ctx &c, const double *x, double *u3) {
 }
 
 void reduce(Ctx &c, const double *a, const double *b, const double *al, int mode, int op,
-            double mul, int dst) {
-  const int nb = std::min<int64_t>(kRedBlocks, cdiv((int64_t)c.nn, 256));
-  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(256), 0, c.s, a, b, al, (int64_t)c.nn, mode,
-                     c.fw->part);
+            double mul, int dst, int64_t count = 0) {
+  if (count == 0) count = (int64_t)c.nn;
+  const int nb = std::min<int64_t>(kRedBlocks, cdiv(count, 256));
+  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(256), 0, c.s, a, b, al, count, mode, c.fw->part);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c.s, c.fw->part, nb, op, mul, c.fw->scal,
                      dst);
 }
@@ -381,36 +413,43 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
   const int n = h->N;
   const size_t nn = (size_t)n * n;
   FistaWork &f = h->fista[part];
-  if (f.n != nn || f.vanishing != prm.vanishing) {
+  // bases: db_p alone, or the dictionary db_1 .. db_p
+  const int nbases = prm.dictionary ? prm.vanishing : 1;
+  if (f.n != nn || f.vanishing != prm.vanishing || f.n_bases != nbases) {
     for (void *q : {(void *)f.alpha_prev, (void *)f.y, (void *)f.x, (void *)f.u1, (void *)f.u2,
-                    (void *)f.u3, (void *)f.cst, (void *)f.tmp, (void *)f.coef, (void *)f.d64,
-                    (void *)f.r64, (void *)f.scal, (void *)f.part, (void *)f.hlo,
+                    (void *)f.u3, (void *)f.cst, (void *)f.tmp, (void *)f.coef, (void *)f.xb,
+                    (void *)f.d64, (void *)f.r64, (void *)f.scal, (void *)f.part, (void *)f.hlo,
                     (void *)f.work64, (void *)f.tmp64})
       dev_free(h, q);
     f = FistaWork();
-    for (double **b : {&f.alpha_prev, &f.y, &f.x, &f.u1, &f.u2, &f.u3, &f.cst, &f.tmp, &f.coef,
-                       &f.d64, &f.r64})
+    for (double **b : {&f.alpha_prev, &f.y, &f.coef})
+      *b = (double *)dev_alloc(h, (size_t)nbases * nn * sizeof(double));
+    for (double **b : {&f.x, &f.u1, &f.u2, &f.u3, &f.cst, &f.tmp, &f.d64, &f.r64})
       *b = (double *)dev_alloc(h, nn * sizeof(double));
+    if (nbases > 1) f.xb = (double *)dev_alloc(h, nn * sizeof(double));
     f.work64 = (double2 *)dev_alloc(h, 2 * nn * sizeof(double2));
     f.tmp64 = (double2 *)dev_alloc(h, 4 * nn * sizeof(double2));
     f.scal = (double *)dev_alloc(h, 16 * sizeof(double));
     f.part = (double *)dev_alloc(h, kRedBlocks * sizeof(double));
-    const std::vector<double> lo = daubechies(prm.vanishing);
-    const int L = (int)lo.size();
-    std::vector<double> hg(2 * L);
-    for (int j = 0; j < L; ++j) {
-      hg[j] = lo[j];
-      hg[L + j] = ((j & 1) ? -1.0 : 1.0) * lo[L - 1 - j];
+    std::vector<double> hg;
+    for (int b = 0; b < nbases; ++b) {
+      const std::vector<double> lo = daubechies(prm.dictionary ? b + 1 : prm.vanishing);
+      const int L = (int)lo.size();
+      f.hoff.push_back((int)hg.size());
+      f.taps.push_back(L);
+      for (int j = 0; j < L; ++j) hg.push_back(lo[j]);
+      for (int j = 0; j < L; ++j) hg.push_back(((j & 1) ? -1.0 : 1.0) * lo[L - 1 - j]);
     }
     f.hlo = (double *)dev_alloc(h, hg.size() * sizeof(double));
     IMGR_HIP(hipMemcpy(f.hlo, hg.data(), hg.size() * sizeof(double), hipMemcpyHostToDevice));
-    f.taps = L;
     f.vanishing = prm.vanishing;
+    f.n_bases = nbases;
     f.n = nn;
   }
   const double2 *spec = psf_spectrum64(h, part, s);
-  Ctx c{h, part, n, prm.levels, f.taps, nn, &f, spec, s, prm.serial != 0 || h->n_parts == 1,
+  Ctx c{h, part, n, prm.levels, nbases, nn, &f, spec, s, prm.serial != 0 || h->n_parts == 1,
         prm.gamma_n};
+  const int64_t NC = (int64_t)nbases * (int64_t)nn;  // coefficients
   if (c.serial) c.gamma_n = 0.0;
   const int64_t N2 = (int64_t)nn;
   IMGR_HIP(hipMemsetAsync(f.scal, 0, 16 * sizeof(double), s));
@@ -442,16 +481,16 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
     if (use_rho) gam(c, f.r64, nullptr, false, false, c.gamma_n, f.cst, 1);
   }
   // FISTA from alpha = y = 0, t = 1
-  IMGR_HIP(hipMemsetAsync(f.alpha_prev, 0, nn * sizeof(double), s));
-  IMGR_HIP(hipMemsetAsync(f.y, 0, nn * sizeof(double), s));
+  IMGR_HIP(hipMemsetAsync(f.alpha_prev, 0, NC * sizeof(double), s));
+  IMGR_HIP(hipMemsetAsync(f.y, 0, NC * sizeof(double), s));
   double t = 1.0;
   for (int k = 0; k < prm.n_iter; ++k) {
     idwt2(c, f.y, f.x);                 // x = W y
     normal_map(c, f.x, f.u3);           // u3 = (H Gamma^2 H + gamma Gamma_o^2) x
     dwt2(c, f.cst, f.u3, f.coef);       // v = W^T (c - u3) = -grad / 2
     const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-    hipLaunchKernelGGL(k_fista_update, g1(N2), dim3(256), 0, s, f.alpha_prev, f.y, f.coef,
-                       f.scal, (t - 1.0) / t_next, N2);
+    hipLaunchKernelGGL(k_fista_update, g1(NC), dim3(256), 0, s, f.alpha_prev, f.y, f.coef,
+                       f.scal, (t - 1.0) / t_next, NC);
     t = t_next;
     if (objective) {
       idwt2(c, f.alpha_prev, f.x);
@@ -467,7 +506,7 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
           reduce(c, f.u2, nullptr, nullptr, 0, 0, 1.0, 5);
         }
       }
-      reduce(c, nullptr, nullptr, f.alpha_prev, 2, 0, 1.0, 6);
+      reduce(c, nullptr, nullptr, f.alpha_prev, 2, 0, 1.0, 6, NC);
       hipLaunchKernelGGL(k_objective, dim3(1), dim3(64), 0, s, f.scal, c.gamma_n, objective, k);
     }
   }

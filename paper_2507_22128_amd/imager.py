@@ -141,17 +141,18 @@ class FistaParams(ctypes.Structure):
                 ("n_iter", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("lam", ctypes.c_double), ("lambda_frac", ctypes.c_double),
                 ("gamma_n", ctypes.c_double), ("serial", ctypes.c_int32),
-                ("first_cycle", ctypes.c_int32)]
+                ("first_cycle", ctypes.c_int32), ("dictionary", ctypes.c_int32)]
 
 
 def fista_params(vanishing=8, levels=3, n_iter=200, power_iters=30, lam=0.0, lam_frac=1e-3,
-                 gamma_n=0.0, serial=False, first_cycle=0):
+                 gamma_n=0.0, serial=False, first_cycle=0, dictionary=False):
     p = FistaParams()
     p.vanishing, p.levels, p.n_iter, p.power_iters = int(vanishing), int(levels), int(n_iter), \
         int(power_iters)
     p.lam, p.lambda_frac, p.gamma_n = float(lam), float(lam_frac), float(gamma_n)
     p.serial = 1 if serial else 0
     p.first_cycle = int(first_cycle)
+    p.dictionary = 1 if dictionary else 0
     return p
 
 
@@ -512,8 +513,9 @@ class Imager:
 
 
 def footprint(n_pix, n_vis, n_partitions=1, support=8, tile=0, chunk=0, autotune=False,
-              tolerance=0.0, ell=-1.0, vis_on_host=False, n_scales=0, fista=False):
-    """(resident, peak) device bytes of a handle before it is built."""
+              tolerance=0.0, ell=-1.0, vis_on_host=False, n_scales=0, fista=0):
+    """(resident, peak) device bytes of a handle before it is built; fista =
+    the number of dictionary bases of a FISTA minor cycle (0: none)."""
     c = Config()
     c.n_pix, c.n_partitions, c.support = int(n_pix), int(n_partitions), int(support)
     c.tile, c.chunk, c.autotune, c.tolerance = int(tile), int(chunk), int(bool(autotune)), \
@@ -521,7 +523,7 @@ def footprint(n_pix, n_vis, n_partitions=1, support=8, tile=0, chunk=0, autotune
     c.ell_pix = float(ell)
     r, p = ctypes.c_size_t(), ctypes.c_size_t()
     st = lib().imager_footprint(ctypes.byref(c), int(n_vis), int(bool(vis_on_host)),
-                                int(n_scales), int(bool(fista)), ctypes.byref(r), ctypes.byref(p))
+                                int(n_scales), int(fista), ctypes.byref(r), ctypes.byref(p))
     if st != OK:
         raise ImagerError(st, "footprint: bad configuration")
     return r.value, p.value

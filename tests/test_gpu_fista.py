@@ -43,10 +43,10 @@ def tiny2():
 
 
 def _oracle_run(dirty, psf, rho, gamma_n, ell, delta, own, start, n_iter, power_iters, serial,
-                lam_frac=1e-3):
+                lam_frac=1e-3, dictionary=False):
     from oracle import fista, wavelets
-    prob = fista.NodeProblem(dirty, psf, rho, gamma_n, ell, delta, own, wavelets.daubechies(8), 3,
-                             serial=serial)
+    h = [wavelets.daubechies(p) for p in range(1, 9)] if dictionary else wavelets.daubechies(8)
+    prob = fista.NodeProblem(dirty, psf, rho, gamma_n, ell, delta, own, h, 3, serial=serial)
     L = fista.power_iteration(prob, start, power_iters)
     lam = lam_frac * np.abs(dirty).max()
     alpha, obj = fista.fista(prob, lam, n_iter, L)
@@ -71,6 +71,45 @@ def test_fista_serial_teacher_forced(tiny1):
     assert abs(L / r_L - 1) < 1e-10 and abs(lam / r_lam - 1) < 1e-10
     assert e_obj < 1e-10
     assert e_img < 1e-6
+
+
+def test_fista_dictionary_teacher_forced(tiny1, tiny2):
+    """W = the concatenation of db1 .. db8 (the paper's dictionary), serial and
+    node H of the decentralized problem, 80 iterations."""
+    import torch
+    d, h = tiny1
+    n = d["n_img"]
+    dirty = h.major_cycle(0, torch.zeros((n, n), device="cuda"))
+    psf = h.psf(0)
+    start = to_dev(np.random.default_rng(41).standard_normal((n, n)))
+    delta, obj, L, lam = h.minor_cycle_fista(0, dirty, start, n_iter=80, power_iters=20,
+                                             serial=True, want_objective=True, dictionary=True)
+    r_img, r_obj, r_L, r_lam = _oracle_run(
+        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), None, 0.0, 0.0, 1.0, "L",
+        to_np(start).astype(np.float64), 80, 20, serial=True, dictionary=True)
+    e_img, e_obj = rel(to_np(delta), r_img), np.abs(obj / r_obj - 1).max()
+    say("dictionary FISTA (serial): L %.6g (oracle %.6g), image rel err %.3e, objective rel %.3e"
+        % (L, r_L, e_img, e_obj))
+    assert abs(L / r_L - 1) < 1e-10 and abs(lam / r_lam - 1) < 1e-10
+    assert e_obj < 1e-10 and e_img < 1e-6
+    d2, h2 = tiny2
+    rng = np.random.default_rng(42)
+    model = to_dev(0.3 * d2["truth"])
+    rho = to_dev(0.002 * rng.standard_normal((n, n)))
+    local = torch.empty((n, n), device="cuda")
+    h2.major_cycle(1, model, out=torch.empty((n, n), device="cuda"), local_out=local)
+    psf2 = h2.psf(1)
+    delta, obj, L, lam = h2.minor_cycle_fista(1, local, start, rho_other=rho, n_iter=60,
+                                              power_iters=20, gamma_n=1.0, want_objective=True,
+                                              dictionary=True)
+    r_img, r_obj, r_L, r_lam = _oracle_run(
+        to_np(local).astype(np.float64), to_np(psf2).astype(np.float64),
+        to_np(rho).astype(np.float64), 1.0, h2.info.ell_pix, h2.info.delta_pix, "H",
+        to_np(start).astype(np.float64), 60, 20, serial=False, dictionary=True)
+    e_img, e_obj = rel(to_np(delta), r_img), np.abs(obj / r_obj - 1).max()
+    say("dictionary FISTA (node H, Eq. 5): image rel err %.3e, objective rel %.3e" % (e_img, e_obj))
+    assert abs(L / r_L - 1) < 1e-10
+    assert e_obj < 1e-10 and e_img < 1e-6
 
 
 def test_fista_two_nodes_teacher_forced(tiny2):
