@@ -16,18 +16,33 @@ namespace imgr {
 
 void *dev_alloc(imgr_s *h, size_t bytes) {
   bytes = std::max<size_t>(bytes, 16);
-  if (h->budget && h->bytes + bytes > h->budget)
-    throw Error{IMGR_ENOMEM, "device footprint would exceed hbm_budget (" +
-                                 std::to_string(h->bytes + bytes) + " > " +
-                                 std::to_string(h->budget) + " bytes)"};
+  if (h->caching) bytes = (bytes + 4095) & ~(size_t)4095;
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{IMGR_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+  if (h->caching) {
+    // a block freed earlier in this build, of the same size: its last user
+    // was enqueued on the same stream, so reuse is ordered after it
+    for (size_t i = 0; i < h->cache.size(); ++i) {
+      if (h->cache[i].second == bytes) {
+        p = h->cache[i].first;
+        h->cache.erase(h->cache.begin() + i);
+        h->cached_bytes -= bytes;
+        break;
+      }
+    }
+  }
+  if (!p) {
+    if (h->budget && h->bytes + h->cached_bytes + bytes > h->budget)
+      throw Error{IMGR_ENOMEM, "device footprint would exceed hbm_budget (" +
+                                   std::to_string(h->bytes + h->cached_bytes + bytes) + " > " +
+                                   std::to_string(h->budget) + " bytes)"};
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{IMGR_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    }
   }
   h->bytes += bytes;
-  h->peak_bytes = std::max(h->peak_bytes, h->bytes);
+  h->peak_bytes = std::max(h->peak_bytes, h->bytes + h->cached_bytes);
   h->allocs.push_back(p);
   // remember the size in a parallel list for accounting on free
   h->alloc_sizes.push_back(bytes);
@@ -38,13 +53,27 @@ void dev_free(imgr_s *h, void *p) {
   if (!p) return;
   for (size_t i = 0; i < h->allocs.size(); ++i) {
     if (h->allocs[i] == p) {
-      h->bytes -= h->alloc_sizes[i];
+      const size_t bytes = h->alloc_sizes[i];
+      h->bytes -= bytes;
       h->allocs.erase(h->allocs.begin() + i);
       h->alloc_sizes.erase(h->alloc_sizes.begin() + i);
-      (void)hipFree(p);
+      if (h->caching) {
+        h->cache.emplace_back(p, bytes);
+        h->cached_bytes += bytes;
+      } else {
+        (void)hipFree(p);
+      }
       return;
     }
   }
+}
+
+// end of a build: release the blocks kept for reuse (the stream is idle)
+static void drop_cache(imgr_s *h) {
+  h->caching = false;
+  for (auto &c : h->cache) (void)hipFree(c.first);
+  h->cache.clear();
+  h->cached_bytes = 0;
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
@@ -153,6 +182,7 @@ static void release(imgr_s *h) {
     if (h->node_stream[p]) (void)hipStreamDestroy(h->node_stream[p]);
   }
   for (void *q : h->allocs) (void)hipFree(q);
+  for (auto &c : h->cache) (void)hipFree(c.first);
   delete h;
 }
 
@@ -346,6 +376,10 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
       wk.img = (float *)dev_alloc(h, (size_t)h->N * h->N * sizeof(float));
     }
 
+    // the build frees and re-requests many temporaries of equal size: keep
+    // freed blocks for reuse until it ends, instead of a hipFree (which
+    // waits for the device) and a hipMalloc each time
+    h->caching = true;
     prep_build(h, vis);
 
     for (int p = 0; p < h->n_parts; ++p) {
@@ -365,6 +399,7 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
       build_psf(h, p);
     }
     IMGR_HIP(hipStreamSynchronize(h->stream));
+    drop_cache(h);
   } catch (const Error &e) {
     g_create_error = e.msg;
     release(h);
@@ -447,9 +482,10 @@ imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_
   }
   // FISTA: 11 FP64 images, 6 complex FP64 images of work, the FP64 PSF
   // spectrum and the temporary it is built in
-  if (fista > 0)  // coefficients (3 x bases), 8 images, transform work, PSF spectrum + temp
-    minor = std::max(minor, 8.0 * (3.0 * fista + 8 + (fista > 1 ? 1 : 0)) * nn + 16.0 * 6 * nn +
-                                2 * 16.0 * 4 * nn + 65536.0);
+  if (fista > 0)  // 4 coefficient-sized arrays per basis (+1 for a dictionary), 7 images,
+                  // transform work, the FP64 PSF spectrum and its temporary
+    minor = std::max(minor, 8.0 * (7.0 + 4.0 * fista + (fista > 1 ? fista : 0)) * nn +
+                                16.0 * 6 * nn + 2 * 16.0 * 4 * nn + 65536.0);
   const double res = fixed + parts * (per + loop + minor);
   // create-time temporaries on top of the handle's work buffers and tables
   const double staged = vis_on_host ? (24.0 + 16.0 + 4.0 + 1.0) * m : 0.0;

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/imager.h"
@@ -87,8 +88,9 @@ struct CleanWork {
 // device work area of one node's FISTA (kept between calls; FP64)
 struct FistaWork {
   double *alpha_prev = nullptr, *y = nullptr, *coef = nullptr;   // P N^2 coefficients
+  double *tmp = nullptr, *xb = nullptr;  // P N^2 transform work (xb: dictionaries only)
   double *x = nullptr, *u1 = nullptr, *u2 = nullptr, *u3 = nullptr;  // N^2 images
-  double *cst = nullptr, *tmp = nullptr, *xb = nullptr;          // N^2
+  double *cst = nullptr;                                         // N^2
   double *d64 = nullptr, *r64 = nullptr;                         // inputs in FP64
   double2 *work64 = nullptr, *tmp64 = nullptr;                   // transform buffers
   double *scal = nullptr;    // device scalars (L_hat, lambda, norms)
@@ -156,6 +158,10 @@ struct imgr_s {
   std::vector<void *> allocs;
   std::vector<size_t> alloc_sizes;
   size_t bytes = 0, budget = 0, peak_bytes = 0;
+  // during imager_create: freed blocks kept for reuse (pointer, bytes)
+  bool caching = false;
+  std::vector<std::pair<void *, size_t>> cache;
+  size_t cached_bytes = 0;
   double create_ms = 0;
   bool broken = false;
   std::string err;

@@ -120,10 +120,22 @@ std::vector<double> daubechies(int p) {
 // analysis of the top-left n x n block along the rows (AXIS 1) or the
 // columns (AXIS 0): a[k] = sum_j h_j x[(2k + j) mod n], d[k] likewise with g;
 // the input is a - b (b may be NULL)
+constexpr int kMaxBases = 10;  // dictionary bases: db1 .. db10 at most
+
+// filters of the dictionary's bases (blockIdx.y = basis)
+struct Bases {
+  int hoff[kMaxBases], taps[kMaxBases];
+};
+
 template <int AXIS>
-__global__ void k_dwt(const double *__restrict__ a, const double *__restrict__ b, int in_stride,
-                      double *__restrict__ out, int out_stride, int n, const double *__restrict__ hg,
-                      int taps, double sc) {
+__global__ void k_dwt(const double *__restrict__ a, size_t a_bstride, const double *__restrict__ b,
+                      int in_stride, double *__restrict__ out, size_t out_bstride, int out_stride,
+                      int n, const double *__restrict__ hlo, Bases bs, double sc) {
+  const int p = blockIdx.y;
+  const double *__restrict__ hg = hlo + bs.hoff[p];
+  const int taps = bs.taps[p];
+  a += p * a_bstride;
+  out += p * out_bstride;
   const int half = n / 2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * half) return;
@@ -158,7 +170,13 @@ __global__ void k_dwt(const double *__restrict__ a, const double *__restrict__ b
 // h_j a[k] + g_j d[k], k = ((m - j) mod n) / 2
 template <int AXIS>
 __global__ void k_idwt(const double *__restrict__ in, int in_stride, double *__restrict__ out,
-                       int out_stride, int n, const double *__restrict__ hg, int taps) {
+                       int out_stride, size_t bstride, int n, const double *__restrict__ hlo,
+                       Bases bs) {
+  const int p = blockIdx.y;
+  const double *__restrict__ hg = hlo + bs.hoff[p];
+  const int taps = bs.taps[p];
+  in += p * bstride;
+  out += p * bstride;
   const int half = n / 2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
@@ -207,11 +225,14 @@ __global__ void k_copy_f64(const double *__restrict__ a, double *__restrict__ b,
   if (i < n) b[i] = a[i];
 }
 
-// out = k a (first) or out + k a
-__global__ void k_scale_add(const double *__restrict__ a, double k, double *__restrict__ out,
-                            int first, int64_t n) {
+// out = sum over the nb blocks of a (stride n) of k a_p, in block order
+__global__ void k_sum_bases(const double *__restrict__ a, int nb, double k,
+                            double *__restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = first ? k * a[i] : out[i] + k * a[i];
+  if (i >= n) return;
+  double acc = k * a[i];
+  for (int p = 1; p < nb; ++p) acc = acc + k * a[(size_t)p * n + i];
+  out[i] = acc;
 }
 
 __global__ void k_add_to_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
@@ -308,6 +329,7 @@ inline dim3 g1(int64_t n) { return dim3(cdiv(n, 256)); }
 struct Ctx {
   imgr_s *h;
   int part, n, levels, nb;  // nb: bases of the dictionary
+  Bases bases;
   size_t nn;
   FistaWork *fw;
   const double2 *psf_hat;
@@ -316,57 +338,45 @@ struct Ctx {
   double gamma_n;
 };
 
-// W^T (a - b) -> out (coefficients, nb stacked N^2 blocks), via fw->tmp; each
-// basis of a dictionary sees the input scaled by 1 / sqrt(nb)
+// W^T (a - b) -> out (coefficients, nb stacked N^2 blocks), via fw->tmp (nb
+// blocks); all bases in one launch per pass, each seeing the input scaled
+// by 1 / sqrt(nb) for a dictionary
 void dwt2(Ctx &c, const double *a, const double *b, double *out) {
   const int N = c.n;
   const double sc = c.nb > 1 ? 1.0 / std::sqrt((double)c.nb) : 1.0;
-  for (int p = 0; p < c.nb; ++p) {
-    double *o = out + (size_t)p * c.nn;
-    const double *hg = c.fw->hlo + c.fw->hoff[p];
-    const int taps = c.fw->taps[p];
-    int n = N;
-    for (int lev = 0; lev < c.levels; ++lev) {
-      const double *src = lev == 0 ? a : o;
-      const double *sb = lev == 0 ? b : nullptr;
-      hipLaunchKernelGGL(k_dwt<1>, g1((int64_t)n * (n / 2)), dim3(256), 0, c.s, src, sb, N,
-                         c.fw->tmp, N, n, hg, taps, lev == 0 ? sc : 1.0);
-      hipLaunchKernelGGL(k_dwt<0>, g1((int64_t)n * (n / 2)), dim3(256), 0, c.s, c.fw->tmp,
-                         (const double *)nullptr, N, o, N, n, hg, taps, 1.0);
-      n /= 2;
-    }
+  int n = N;
+  for (int lev = 0; lev < c.levels; ++lev) {
+    const double *src = lev == 0 ? a : out;
+    const size_t sstride = lev == 0 ? 0 : c.nn;
+    const double *sb = lev == 0 ? b : nullptr;
+    const dim3 grid(cdiv((int64_t)n * (n / 2), 256), c.nb);
+    hipLaunchKernelGGL(k_dwt<1>, grid, dim3(256), 0, c.s, src, sstride, sb, N, c.fw->tmp, c.nn,
+                       N, n, c.fw->hlo, c.bases, lev == 0 ? sc : 1.0);
+    hipLaunchKernelGGL(k_dwt<0>, grid, dim3(256), 0, c.s, (const double *)c.fw->tmp, c.nn,
+                       (const double *)nullptr, N, out, c.nn, N, n, c.fw->hlo, c.bases, 1.0);
+    n /= 2;
   }
 }
 
-// one basis' synthesis of coefficients alpha -> out image, via fw->tmp
-void idwt2_one(Ctx &c, int p, const double *alpha, double *out) {
+// W alpha -> out image: each basis' synthesis (all in one launch per pass),
+// then for a dictionary the sum over the bases times 1 / sqrt(nb)
+void idwt2(Ctx &c, const double *alpha, double *out) {
   const int N = c.n;
-  const double *hg = c.fw->hlo + c.fw->hoff[p];
-  const int taps = c.fw->taps[p];
-  hipLaunchKernelGGL(k_copy_f64, g1((int64_t)c.nn), dim3(256), 0, c.s, alpha, out, (int64_t)c.nn);
+  double *xs = c.nb > 1 ? c.fw->xb : out;
+  const int64_t tot = (int64_t)c.nb * (int64_t)c.nn;
+  hipLaunchKernelGGL(k_copy_f64, g1(tot), dim3(256), 0, c.s, alpha, xs, tot);
   int n = N >> (c.levels - 1);
   for (int lev = 0; lev < c.levels; ++lev) {
-    hipLaunchKernelGGL(k_idwt<0>, g1((int64_t)n * n), dim3(256), 0, c.s, out, N, c.fw->tmp, N, n,
-                       hg, taps);
-    hipLaunchKernelGGL(k_idwt<1>, g1((int64_t)n * n), dim3(256), 0, c.s, c.fw->tmp, N, out, N, n,
-                       hg, taps);
+    const dim3 grid(cdiv((int64_t)n * n, 256), c.nb);
+    hipLaunchKernelGGL(k_idwt<0>, grid, dim3(256), 0, c.s, (const double *)xs, N, c.fw->tmp, N,
+                       c.nn, n, c.fw->hlo, c.bases);
+    hipLaunchKernelGGL(k_idwt<1>, grid, dim3(256), 0, c.s, (const double *)c.fw->tmp, N, xs, N,
+                       c.nn, n, c.fw->hlo, c.bases);
     n *= 2;
   }
-}
-
-// W alpha -> out image: one basis, or the sum over the dictionary's bases
-// of their synthesis times 1 / sqrt(nb), in basis order
-void idwt2(Ctx &c, const double *alpha, double *out) {
-  if (c.nb == 1) {
-    idwt2_one(c, 0, alpha, out);
-    return;
-  }
-  const double k = 1.0 / std::sqrt((double)c.nb);
-  for (int p = 0; p < c.nb; ++p) {
-    idwt2_one(c, p, alpha + (size_t)p * c.nn, c.fw->xb);
-    hipLaunchKernelGGL(k_scale_add, g1((int64_t)c.nn), dim3(256), 0, c.s, c.fw->xb, k, out,
-                       p == 0 ? 1 : 0, (int64_t)c.nn);
-  }
+  if (c.nb > 1)
+    hipLaunchKernelGGL(k_sum_bases, g1((int64_t)c.nn), dim3(256), 0, c.s, (const double *)xs,
+                       c.nb, 1.0 / std::sqrt((double)c.nb), out, (int64_t)c.nn);
 }
 
 void psf_conv(Ctx &c, const double *a, double coef, double *out, int acc) {
@@ -422,11 +432,11 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
                     (void *)f.work64, (void *)f.tmp64})
       dev_free(h, q);
     f = FistaWork();
-    for (double **b : {&f.alpha_prev, &f.y, &f.coef})
+    for (double **b : {&f.alpha_prev, &f.y, &f.coef, &f.tmp})
       *b = (double *)dev_alloc(h, (size_t)nbases * nn * sizeof(double));
-    for (double **b : {&f.x, &f.u1, &f.u2, &f.u3, &f.cst, &f.tmp, &f.d64, &f.r64})
+    for (double **b : {&f.x, &f.u1, &f.u2, &f.u3, &f.cst, &f.d64, &f.r64})
       *b = (double *)dev_alloc(h, nn * sizeof(double));
-    if (nbases > 1) f.xb = (double *)dev_alloc(h, nn * sizeof(double));
+    if (nbases > 1) f.xb = (double *)dev_alloc(h, (size_t)nbases * nn * sizeof(double));
     f.work64 = (double2 *)dev_alloc(h, 2 * nn * sizeof(double2));
     f.tmp64 = (double2 *)dev_alloc(h, 4 * nn * sizeof(double2));
     f.scal = (double *)dev_alloc(h, 16 * sizeof(double));
@@ -447,8 +457,13 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
     f.n = nn;
   }
   const double2 *spec = psf_spectrum64(h, part, s);
-  Ctx c{h, part, n, prm.levels, nbases, nn, &f, spec, s, prm.serial != 0 || h->n_parts == 1,
-        prm.gamma_n};
+  Bases bs{};
+  for (int b = 0; b < nbases; ++b) {
+    bs.hoff[b] = f.hoff[b];
+    bs.taps[b] = f.taps[b];
+  }
+  Ctx c{h, part, n, prm.levels, nbases, bs, nn, &f, spec, s,
+        prm.serial != 0 || h->n_parts == 1, prm.gamma_n};
   const int64_t NC = (int64_t)nbases * (int64_t)nn;  // coefficients
   if (c.serial) c.gamma_n = 0.0;
   const int64_t N2 = (int64_t)nn;

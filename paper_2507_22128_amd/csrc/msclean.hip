@@ -231,6 +231,82 @@ __global__ __launch_bounds__(256) void k_conv_same(const T *__restrict__ in, int
   out[i] = acc;
 }
 
+// The same convolution on 16 x 64 output tiles: the workgroup stages the
+// input tile with its halo (zero outside the image) and the kernel, padded
+// with zero columns to a multiple of 4, in LDS; each thread forms 4
+// neighbouring outputs of one row, taking the kernel columns in groups of 4
+// (7 staged values serve the 16 products of a group).  Every output adds
+// k[a][b] in[y - a][x - b] in the order of k_conv_same (a, then b,
+// ascending); the extra products with padded zeros add nothing.
+constexpr int kConvTY = 16, kConvTX = 64;
+
+inline size_t conv_tile_lds(int r) {
+  const int wp = (2 * r + 1 + 3) / 4 * 4, pad = wp - (2 * r + 1);
+  return (size_t)(kConvTY + 2 * r) * (kConvTX + 2 * r + pad) * sizeof(float) +
+         (size_t)(2 * r + 1) * wp * sizeof(double);
+}
+
+__global__ __launch_bounds__(256) void k_conv_tile(const float *__restrict__ in, int n,
+                                                   const double *__restrict__ k, int r,
+                                                   double *__restrict__ out) {
+  extern __shared__ double conv_lds[];
+  const int w = 2 * r + 1;
+  const int wp = (w + 3) / 4 * 4, pad = wp - w;
+  const int th = kConvTY + 2 * r, tw = kConvTX + 2 * r + pad;
+  double *kw = conv_lds;                          // [w][wp]
+  float *tile = reinterpret_cast<float *>(kw + (size_t)w * wp);  // [th][tw]
+  const int x0 = blockIdx.x * kConvTX, y0 = blockIdx.y * kConvTY;
+  for (int i = threadIdx.x; i < w * wp; i += 256) {
+    const int a = i / wp, b = i % wp;
+    kw[i] = (b < w) ? k[a * w + b] : 0.0;
+  }
+  for (int i = threadIdx.x; i < th * tw; i += 256) {
+    const int ty = i / tw, tx = i % tw;
+    const int yy = y0 - r + ty, xx = x0 - r - pad + tx;
+    tile[i] = (yy >= 0 && yy < n && xx >= 0 && xx < n) ? in[(size_t)yy * n + xx] : 0.f;
+  }
+  __syncthreads();
+  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int a = 0; a < w; ++a) {
+    const float *row = tile + (size_t)(ly + 2 * r - a) * tw;
+    const double *kr = kw + (size_t)a * wp;
+    for (int g = 0; g < wp; g += 4) {
+      // columns lx + (2 r + pad - g) - 3 .. + 3 of the tile
+      const float *c = row + lx + (2 * r + pad - g) - 3;
+      float v[7];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) v[m] = c[m];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double kq = kr[g + q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fma(kq, (double)v[j - q + 3], acc[j]);
+      }
+    }
+  }
+  const int y = y0 + ly;
+  if (y < n) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = x0 + lx + j;
+      if (x < n) out[(size_t)y * n + x] = acc[j];
+    }
+  }
+}
+
+// out = in * k (same as k_conv_same), tiled when the tile fits in LDS
+void conv_same(const float *in, int n, const double *k, int r, double *out, hipStream_t s) {
+  const size_t lds = conv_tile_lds(r);
+  if (lds <= 64 * 1024) {
+    hipLaunchKernelGGL(k_conv_tile, dim3(cdiv(n, kConvTX), cdiv(n, kConvTY)), dim3(256), lds, s,
+                       in, n, k, r, out);
+  } else {
+    hipLaunchKernelGGL(k_conv_same<float>, dim3(cdiv((int64_t)n * n, 256)), dim3(256), 0, s, in,
+                       n, k, r, out);
+  }
+}
+
 // pending update on R_0 only, then the f32 outputs
 struct FinishArgs {
   int pair_r0[kMaxInt];  // pair index of (t, r0) for each internal scale t
@@ -398,11 +474,9 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
   IMGR_HIP(hipMemsetAsync(cw.state, 0, sizeof(CleanState), s));
   // R_s = phi_s * D, B_ab = phi_a phi_b * P
   for (int i = 0; i < n_int; ++i)
-    hipLaunchKernelGGL(k_conv_same<float>, dim3(cdiv(nn, 256)), dim3(256), 0, s, dirty, n,
-                       cw.kern + koff[i], rad[i], cw.R + (size_t)i * nn);
+    conv_same(dirty, n, cw.kern + koff[i], rad[i], cw.R + (size_t)i * nn, s);
   for (int q = 0; q < n_pairs; ++q)
-    hipLaunchKernelGGL(k_conv_same<float>, dim3(cdiv((int64_t)n2 * n2, 256)), dim3(256), 0, s,
-                       psf, n2, cw.kern + poff[q], prad[q], cw.B + (size_t)q * n2 * n2);
+    conv_same(psf, n2, cw.kern + poff[q], prad[q], cw.B + (size_t)q * n2 * n2, s);
   IMGR_HIP(hipGetLastError());
 
   StepArgs sa;
