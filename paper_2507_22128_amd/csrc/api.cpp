@@ -465,9 +465,9 @@ imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_
   const double m = (double)n_vis;
   const double np_ = parts == 2 ? (cfg->ell_pix < 0 ? 0.6 * m : m) : m;
   auto chunks = [&](double ng) { return np_ / C + (ng / blk) * (ng / blk); };
-  auto tables = [&](double ng) {  // posvis, w, orig, outpos + chunk tables
+  auto tables = [&](double ng) {  // posvis, w, orig, outpos + chunk tables (with row counts)
     const double nb2 = (ng / blk) * (ng / blk);
-    return 28.0 * np_ + 4.0 * (3.0 * chunks(ng) + nb2 + 2.0);
+    return 28.0 * np_ + 4.0 * (11.0 * chunks(ng) + nb2 + 2.0);
   };
   const double fixed = 4.0 * (N + 2 * N) + 3 * 24.0 * kTwMax + 4096.0;
   double per = 2 * 8.0 * Ng * Ng + 8.0 * N * Ng + 4.0 * nn   // work grids, rows, image

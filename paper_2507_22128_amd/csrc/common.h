@@ -47,9 +47,10 @@ constexpr int kTwMax = 16384;
 
 // Visibilities of one partition binned for one grid: sorted by the
 // blk x blk block of grid cells that holds the first tap of their footprint
-// shifted by W/2 - 1, and cut into chunks of at most C visibilities of one
-// block.  Every footprint of a block lies in a 16 x 16 window of the grid
-// whose origin is the block origin minus W/2 - 1.
+// shifted by W/2 - 1, then by the row of that tap inside the block, and cut
+// into chunks of at most C visibilities of one block.  Every footprint of a
+// block lies in a 16 x 16 window of the grid whose origin is the block origin
+// minus W/2 - 1.
 struct Bins {
   int64_t n = 0;               // members
   int n_chunks = 0;
@@ -61,6 +62,7 @@ struct Bins {
   int32_t *outpos = nullptr;   // [n] member rank (position in member order)
   int32_t *chunk_block = nullptr;  // [n_chunks] block of each chunk
   int32_t *chunk_begin = nullptr;  // [n_chunks + 1]
+  int32_t *chunk_rows = nullptr;   // [n_chunks][8] visibilities of the chunk with row <= j
   int32_t *block_chunk = nullptr;  // [nb * nb + 1] first chunk of each block
   int32_t *order = nullptr;        // [n_chunks] launch order: largest chunk first
 };
@@ -265,6 +267,7 @@ struct WinArgs {
   const int32_t *outpos;
   const int32_t *chunk_block;
   const int32_t *chunk_begin;
+  const int32_t *chunk_rows;
   int nb, ng;
   float bl2e;
   const float2 *grid_in;

@@ -20,6 +20,17 @@
 // its window once.  The flush then adds, for every grid cell, the windows of
 // the chunks of the neighbouring blocks in a fixed order in FP64, so the
 // grid is reproducible bit for bit.
+//
+// For W <= 8 the kernel uses a row-group form with half the matrix work: the
+// visibilities of a chunk are sorted by the row oy of their first tap in the
+// block, and a batch of 16 visibilities of one row group touches only the W
+// rows oy .. oy + W - 1 of the window.  Eight of those rows (padded with
+// zero weights) times {real, imaginary} make the 16 rows of both operands:
+//   T[8 c + y][k]   = sum_x G_c[oy + y][x] kx_k[x]          (c = 0 re, 1 im)
+//   v_hat_k         = sum_y ky_k[y] (T[y][k] + i T[8 + y][k])
+//   A_oy[8 c + y][x] += sum_k part_c(r_k) ky_k[y] kx_k[x]
+// so each product is 4 MFMAs per batch instead of 8; A_oy is added into the
+// residual window (LDS) at row offset oy when the group ends.
 #include "common.h"
 
 namespace imgr {
@@ -206,20 +217,217 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
   }
 }
 
+// LDS of one wave in the row-group form
+struct RowsLds {
+  float kx[16 * 16];     // [visibility][window column] tap weights
+  float ky[16 * 8];      // [visibility][footprint row] tap weights
+  float r[16 * 2];       // weighted residual (re, im) per visibility
+  float g[2][16 * 16];   // model window: real, imaginary planes [row][column]
+  float acc[2][16 * 16]; // residual window: real, imaginary planes
+};
+
+template <int W, int BLK, int MODE>
+__device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, RowsLds &s) {
+  static_assert(W <= 8 && BLK + 7 <= kWin, "the row groups must fit the window");
+  constexpr int H = W / 2 - 1;
+  constexpr int TPL = (W + 3) / 4;  // taps per lane and axis
+  constexpr float kC = 2.0f / W;    // z = (t - H - f) * kC for tap t at fraction f
+  constexpr bool kDegrid = (MODE == MODE_DEGRID_GRID || MODE == MODE_DEGRID);
+  constexpr bool kGrid = (MODE != MODE_DEGRID);
+  const float4 *__restrict__ posvis = a.posvis;
+  const float *__restrict__ wts = a.wts;
+  const int nb = a.nb, ng = a.ng;
+  const float bl2e = a.bl2e;
+
+  const int l = threadIdx.x & 63, c16 = l & 15, g = l >> 4;
+  chunk = __builtin_amdgcn_readfirstlane(chunk);
+  const int blk = a.chunk_block[chunk];
+  const int wx0 = (blk % nb) * BLK - H, wy0 = (blk / nb) * BLK - H;
+  const int b = a.chunk_begin[chunk];
+  const int32_t *__restrict__ rows = a.chunk_rows + 8 * chunk;
+
+  float qa[TPL], qb[TPL];
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    const float t0 = (float)(g * TPL + q - H);
+    qa[q] = 1.0f - kC * kC * t0 * t0;
+    qb[q] = 2.0f * kC * kC * t0;
+  }
+  constexpr float qc = -kC * kC;
+
+  // chunk set-up: the model window in LDS (two planes), a zero residual
+  // window, and zero footprint rows (taps W .. 7 are never written)
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int y = 4 * g + r;
+    if constexpr (kDegrid) {
+      const float2 v = a.grid_in[(size_t)((wy0 + y) & (ng - 1)) * ng + ((wx0 + c16) & (ng - 1))];
+      s.g[0][y * 16 + c16] = v.x;
+      s.g[1][y * 16 + c16] = v.y;
+    }
+    if constexpr (kGrid) {
+      s.acc[0][y * 16 + c16] = 0.f;
+      s.acc[1][y * 16 + c16] = 0.f;
+    }
+  }
+  *(float2 *)&s.ky[c16 * 8 + 2 * g] = make_float2(0.f, 0.f);
+  wave_sync();
+
+  // row groups: group j holds the chunk's visibilities [b + rows[j-1], b + rows[j])
+  int oy = 0, ge = b + rows[0];
+  while (ge == b && oy < BLK - 1) ge = b + rows[++oy];
+  float foy = (float)oy;
+  // A operand of the group: lane (c16, g) holds G_c[oy + y][4 g + s], c16 = 8 c + y
+  floatx4 ga = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (kDegrid) ga = *(const floatx4 *)&s.g[c16 >> 3][(oy + (c16 & 7)) * 16 + 4 * g];
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+
+  // lane (c16, g) works on visibility c16 of each batch; the record of the
+  // next batch is loaded while the current one is processed (indices past
+  // the group are clamped to its last visibility and masked by `valid`)
+  // (chunks are never empty; the guard keeps every read inside the chunk)
+  float4 pv_next = make_float4(0.f, 0.f, 0.f, 0.f);
+  float w_next = 0.f;
+  if (ge > b) {
+    pv_next = posvis[min(b + c16, ge - 1)];
+    if constexpr (kGrid) w_next = wts[min(b + c16, ge - 1)];
+  }
+  for (int base = b; ge > b;) {
+    const int v = base + c16;
+    const bool valid = v < ge;
+    const float4 pv = pv_next;
+    const float w = valid ? w_next : 0.f;
+    // the next batch: the rest of this group, else the next nonempty group
+    int nbase = base + 16, nge = ge, noy = oy;
+    const bool group_end = nbase >= ge;
+    if (group_end) {
+      nbase = ge;
+      while (nge == ge && noy < BLK - 1) nge = b + rows[++noy];
+    }
+    // (without a next batch, nbase == nge and the load re-reads the last
+    // record of the chunk, which keeps it unconditional)
+    const bool more = nbase < nge;
+    pv_next = posvis[min(nbase + c16, nge - 1)];
+    if constexpr (kGrid) w_next = wts[min(nbase + c16, nge - 1)];
+    // offsets are >= 0, so truncation is the floor; the row is the group's
+    const int ox = min(max((int)pv.x, 0), BLK - 1);
+    const float fx = pv.x - (float)ox, fy = pv.y - foy;
+
+    // tap weights: clear this lane's quarter of the column table row of its
+    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis:
+    // phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1))
+    *(floatx4 *)&s.kx[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < TPL; ++q) {
+      const int t = g * TPL + q;
+      if (t < W) {
+        const float sx = fmaxf(fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]), 0.0f);
+        const float sy = fmaxf(fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]), 0.0f);
+        s.kx[c16 * 16 + ox + t] =
+            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sx), -bl2e));
+        s.ky[c16 * 8 + t] = __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sy), -bl2e));
+      }
+    }
+    wave_sync();
+
+    float val = 0.f;  // predicted visibility: real part in lanes g = 0, 1, imaginary in g = 2, 3
+    if constexpr (kDegrid) {
+      // T[m][k] = sum_x Gs[m][x] kx_k[x]: B[x = 4 g + s][k = c16]
+      const floatx4 bx = *(const floatx4 *)&s.kx[c16 * 16 + 4 * g];
+      floatx4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[q], bx[q], t, 0, 0, 0);
+      // lane (c16, g) holds T[4 g + r][c16]: part g >> 1, rows 4 (g & 1) + r
+      const floatx4 by = *(const floatx4 *)&s.ky[c16 * 8 + 4 * (g & 1)];
+      float p = by[0] * t[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) p = fmaf(by[r], t[r], p);
+      // rows 0 + 1 and 2 + 3 of the wave: both lanes of a pair get the same sum
+      auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(p), __float_as_uint(p), false,
+                                                false);
+      val = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    }
+    if constexpr (MODE == MODE_DEGRID) {
+      if (valid && !(g & 1))
+        reinterpret_cast<float *>(a.vis_out)[2 * (size_t)a.outpos[v] + (g >> 1)] = val;
+    }
+    if constexpr (kGrid) {
+      if constexpr (MODE == MODE_DEGRID_GRID) {
+        // lane g = 0 forms the real part of w (v - v_hat), lane g = 2 the imaginary
+        if (!(g & 1)) s.r[2 * c16 + (g >> 1)] = w * ((g ? pv.w : pv.z) - val);
+      } else if (g == 0) {
+        float2 r;
+        if constexpr (MODE == MODE_GRID) {
+          const float2 x = valid ? a.vis_in[a.outpos[v]] : make_float2(0.f, 0.f);
+          r = make_float2(w * x.x, w * x.y);
+        } else {  // MODE_PSF: unit visibilities
+          r = make_float2(w, 0.f);
+        }
+        *(float2 *)&s.r[2 * c16] = r;
+      }
+      wave_sync();
+      // A_oy[m][x] += sum_k part_c(r_k) ky_k[y] kx_k[x], m = c16 = 8 c + y;
+      // K-step q covers k = 4 q + g
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 4 * q + g;
+        const float kyv = s.ky[k * 8 + (c16 & 7)];
+        const float kxv = s.kx[k * 16 + c16];
+        const float rc = s.r[2 * k + (c16 >> 3)];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(rc * kyv, kxv, acc, 0, 0, 0);
+      }
+    }
+    wave_sync();  // the tables are rewritten by the next batch
+
+    if (group_end) {
+      if constexpr (kGrid) {
+        // lane (c16, g) holds A_oy[4 g + r][c16]: part g >> 1, window row oy + 4 (g & 1) + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s.acc[g >> 1][(oy + 4 * (g & 1) + r) * 16 + c16] += acc[r];
+        acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        wave_sync();
+      }
+      if (!more) break;
+      oy = noy;
+      foy = (float)oy;
+      if constexpr (kDegrid) ga = *(const floatx4 *)&s.g[c16 >> 3][(oy + (c16 & 7)) * 16 + 4 * g];
+    }
+    base = nbase;
+    ge = nge;
+  }
+
+  if constexpr (kGrid) {
+    // lane (c16, g) writes window rows 4 g .. 4 g + 3 of column c16
+    float2 *out = a.scratch + (size_t)chunk * (kWin * kWin);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int y = 4 * g + r;
+      out[y * kWin + c16] = make_float2(s.acc[0][y * 16 + c16], s.acc[1][y * 16 + c16]);
+    }
+  }
+}
+
 // one partition's chunks, launch order `order` (largest first)
 template <int W, int BLK, int MODE>
 __global__ __launch_bounds__(64 * kWaves) void k_window(WinArgs a, const int32_t *__restrict__ order,
                                                        int n_chunks) {
-  // per wave and batch: tap weights of the 16 visibilities over the 16
-  // window positions (natural order), and their residuals
-  __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
-  __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
-  __shared__ float2 r_s[kWaves][16];
   const int wave = threadIdx.x >> 6;
   // with fewer workgroups than chunk groups each wave takes every
   // (gridDim.x * kWaves)-th chunk of the order; no wave waits for another
-  for (int slot = blockIdx.x * kWaves + wave; slot < n_chunks; slot += gridDim.x * kWaves)
-    window_chunk<W, BLK, MODE>(a, order[slot], kx_s[wave], ky_s[wave], r_s[wave]);
+  if constexpr (W <= 8) {
+    __shared__ __attribute__((aligned(16))) RowsLds lds[kWaves];
+    for (int slot = blockIdx.x * kWaves + wave; slot < n_chunks; slot += gridDim.x * kWaves)
+      window_chunk_rows<W, BLK, MODE>(a, order[slot], lds[wave]);
+  } else {
+    // per wave and batch: tap weights of the 16 visibilities over the 16
+    // window positions (natural order), and their residuals
+    __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
+    __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
+    __shared__ float2 r_s[kWaves][16];
+    for (int slot = blockIdx.x * kWaves + wave; slot < n_chunks; slot += gridDim.x * kWaves)
+      window_chunk<W, BLK, MODE>(a, order[slot], kx_s[wave], ky_s[wave], r_s[wave]);
+  }
 }
 
 // the chunks of many grids (channels) in one launch: order[slot] = (grid,
@@ -228,16 +436,21 @@ template <int W, int BLK, int MODE>
 __global__ __launch_bounds__(64 * kWaves) void k_window_batch(const WinArgs *__restrict__ grids,
                                                              const int2 *__restrict__ order,
                                                              int n_slots) {
-  __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
-  __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
-  __shared__ float2 r_s[kWaves][16];
   const int wave = threadIdx.x >> 6;
   // wave-uniform, so the descriptor is read through scalar loads
   const int slot = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
   if (slot >= n_slots) return;
   const int2 gc = order[slot];
   const WinArgs a = grids[gc.x];
-  window_chunk<W, BLK, MODE>(a, gc.y, kx_s[wave], ky_s[wave], r_s[wave]);
+  if constexpr (W <= 8) {
+    __shared__ __attribute__((aligned(16))) RowsLds lds[kWaves];
+    window_chunk_rows<W, BLK, MODE>(a, gc.y, lds[wave]);
+  } else {
+    __shared__ __attribute__((aligned(16))) float kx_s[kWaves][16 * 16];
+    __shared__ __attribute__((aligned(16))) float ky_s[kWaves][16 * 16];
+    __shared__ float2 r_s[kWaves][16];
+    window_chunk<W, BLK, MODE>(a, gc.y, kx_s[wave], ky_s[wave], r_s[wave]);
+  }
 }
 
 // One thread per grid cell, 16 x 16 cells per workgroup: FP64 sum over the
@@ -400,6 +613,7 @@ WinArgs win_args(const imgr_s *h, const Bins &B, const float2 *grid_in, const fl
   a.outpos = B.outpos;
   a.chunk_block = B.chunk_block;
   a.chunk_begin = B.chunk_begin;
+  a.chunk_rows = B.chunk_rows;
   a.nb = B.nb;
   a.ng = B.ng;
   a.bl2e = (float)(h->beta * 1.4426950408889634);

@@ -115,18 +115,27 @@ __global__ void k_member(int64_t m, const double *__restrict__ rho,
   member[i] = in ? 1 : 0;
 }
 
-// block of the first tap: floor(scale * g) / blk (scale 1 or 2 is exact);
-// non-members get key nb * nb and sort last
+// row of the first tap inside its block, from the FP32 offset the packed
+// stream stores (so the window kernel, which reads that offset, agrees)
+__device__ __forceinline__ int row_in_block(float dy, int blk) {
+  return min(max((int)dy, 0), blk - 1);
+}
+
+// sort key: block of the first tap, floor(scale * g) / blk (scale 1 or 2 is
+// exact), times 8 plus the tap's row in the block; non-members get key
+// 8 nb^2 and sort last
 __global__ void k_block_keys(int64_t m, const double *__restrict__ gx,
                              const double *__restrict__ gy, const int32_t *__restrict__ member,
                              double scale, int blk, int nb, uint32_t *__restrict__ keys,
                              int32_t *__restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  uint32_t key = (uint32_t)nb * (uint32_t)nb;
+  uint32_t key = (uint32_t)nb * (uint32_t)nb * 8u;
   if (member[i]) {
     const int cx = (int)floor(gx[i] * scale), cy = (int)floor(gy[i] * scale);
-    key = (uint32_t)((cy / blk) * nb + (cx / blk));
+    const int by = cy / blk;
+    const int row = row_in_block((float)(gy[i] * scale - (double)(by * blk)), blk);
+    key = (uint32_t)(by * nb + (cx / blk)) * 8u + (uint32_t)row;
   }
   keys[i] = key;
   vals[i] = (int32_t)i;
@@ -281,7 +290,7 @@ void radix_sort(imgr_s *h, uint32_t *&keys, int32_t *&vals, uint32_t *&ktmp, int
 __global__ void k_block_hist(int64_t n, const uint32_t *__restrict__ keys, int n_blocks,
                              int32_t *__restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && keys[i] < (uint32_t)n_blocks) atomicAdd(&cnt[keys[i]], 1);
+  if (i < n && (keys[i] >> 3) < (uint32_t)n_blocks) atomicAdd(&cnt[keys[i] >> 3], 1);
 }
 
 __global__ void k_chunk_count(int n_blocks, const int32_t *__restrict__ cnt, int cap,
@@ -305,6 +314,25 @@ __global__ void k_make_chunks(int n_blocks, const int32_t *__restrict__ cnt,
   }
 }
 
+// rows[8 c + j]: visibilities of chunk c whose first tap lies in rows
+// 0 .. j of the block (the sort keeps them first); binary search over the
+// chunk's packed offsets
+__global__ void k_chunk_rows(int n_chunks, const int32_t *__restrict__ cbegin,
+                             const float4 *__restrict__ posvis, int blk,
+                             int32_t *__restrict__ rows) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_chunks * 8) return;
+  const int c = t >> 3, j = t & 7;
+  const int b = cbegin[c], e = cbegin[c + 1];
+  int lo = b, hi = e;  // first index with row > j
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if (row_in_block(posvis[mid].y, blk) <= j) lo = mid + 1;
+    else hi = mid;
+  }
+  rows[t] = lo - b;
+}
+
 __global__ void k_pack(int64_t n, const uint32_t *__restrict__ keys,
                        const int32_t *__restrict__ idx, const double *__restrict__ gx,
                        const double *__restrict__ gy, double scale, const void *__restrict__ vis,
@@ -314,7 +342,7 @@ __global__ void k_pack(int64_t n, const uint32_t *__restrict__ keys,
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = idx[s];
-  const int t = (int)keys[s];
+  const int t = (int)(keys[s] >> 3);
   const int bx = t % nb, by = t / nb;
   float re, im;
   if (c128) {
@@ -383,6 +411,16 @@ double lower_median_rho(imgr_s *h, int64_t m, const double *rho, const uint8_t *
   return med;
 }
 
+// (re)build B.chunk_rows from the chunk table and the packed stream
+void chunk_rows(imgr_s *h, Bins &B, hipStream_t s) {
+  dev_free(h, B.chunk_rows);
+  B.chunk_rows = alloc_n<int32_t>(h, 8 * (int64_t)B.n_chunks);
+  if (B.n_chunks > 0)
+    hipLaunchKernelGGL(k_chunk_rows, dim3(cdiv(8 * (int64_t)B.n_chunks, 256)), dim3(256), 0, s,
+                       B.n_chunks, B.chunk_begin, B.posvis, h->blk, B.chunk_rows);
+  IMGR_HIP(hipGetLastError());
+}
+
 // Sort the members of a partition by block of the (scale * g) grid of side
 // ng, cut chunks, and pack the 20-byte per-visibility stream.
 void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member,
@@ -399,9 +437,9 @@ void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member
   hipLaunchKernelGGL(k_block_keys, dim3(nbk), dim3(256), 0, s, m, gx, gy, member, scale, blk,
                      B.nb, keys, vals);
   IMGR_HIP(hipGetLastError());
-  // stable sort by block; non-members (key n_blocks) go last
+  // stable sort by block and row; non-members (key 8 n_blocks) go last
   int key_bits = 0;
-  while ((1ll << key_bits) <= n_blocks) key_bits += 8;
+  while ((1ll << key_bits) <= 8ll * n_blocks) key_bits += 8;
   radix_sort(h, keys, vals, ktmp, vtmp, m, key_bits, s);
   // block counts, starts, chunks
   int32_t *cnt = alloc_n<int32_t>(h, n_blocks + 1);
@@ -451,6 +489,7 @@ void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member
     hipLaunchKernelGGL(k_pack, dim3(cdiv(n, 256)), dim3(256), 0, s, n, keys, vals, gx, gy, scale,
                        vis_dev, c128, w64, rank, blk, B.nb, B.posvis, B.w, B.orig, B.outpos);
   IMGR_HIP(hipGetLastError());
+  chunk_rows(h, B, s);
   IMGR_HIP(hipStreamSynchronize(s));
   for (void *q : {(void *)keys, (void *)ktmp, (void *)vals, (void *)vtmp, (void *)cnt,
                   (void *)bstart, (void *)nch})
@@ -586,8 +625,8 @@ int support_for_tolerance(double tol) {
 
 void free_bins(imgr_s *h, Bins &B) {
   for (void *q : {(void *)B.posvis, (void *)B.w, (void *)B.orig, (void *)B.outpos,
-                  (void *)B.chunk_block, (void *)B.chunk_begin, (void *)B.block_chunk,
-                  (void *)B.order})
+                  (void *)B.chunk_block, (void *)B.chunk_begin, (void *)B.chunk_rows,
+                  (void *)B.block_chunk, (void *)B.order})
     dev_free(h, q);
   B = Bins();
 }
@@ -634,6 +673,7 @@ void rechunk(imgr_s *h, Bins &B, int C, hipStream_t s) {
   }
   IMGR_HIP(hipMemcpyAsync(B.chunk_begin, ncb.data(), (nc + 1) * sizeof(int32_t),
                           hipMemcpyHostToDevice, s));
+  chunk_rows(h, B, s);
   IMGR_HIP(hipStreamSynchronize(s));
 }
 
