@@ -47,8 +47,8 @@ constexpr int kTwMax = 16384;
 
 // Visibilities of one partition binned for one grid: sorted by the
 // blk x blk block of grid cells that holds the first tap of their footprint
-// shifted by W/2 - 1, then by the row of that tap inside the block, and cut
-// into chunks of at most C visibilities of one block.  Every footprint of a
+// shifted by W/2 - 1, then by the row and column of that tap inside the
+// block, and cut into chunks of at most C visibilities of one block.  Every footprint of a
 // block lies in a 16 x 16 window of the grid whose origin is the block origin
 // minus W/2 - 1.
 struct Bins {
@@ -268,6 +268,7 @@ struct WinArgs {
   const int32_t *chunk_block;
   const int32_t *chunk_begin;
   const int32_t *chunk_rows;
+  int n;  // visibilities in the stream
   int nb, ng;
   float bl2e;
   const float2 *grid_in;

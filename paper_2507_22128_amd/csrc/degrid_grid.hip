@@ -22,21 +22,25 @@
 // grid is reproducible bit for bit.
 //
 // For W <= 8 the kernel uses a row-group form with half the matrix work: the
-// visibilities of a chunk are sorted by the row oy of their first tap in the
-// block, and a batch of 16 visibilities of one row group touches only the W
-// rows oy .. oy + W - 1 of the window.  Eight of those rows (padded with
+// visibilities of a chunk are sorted by the row oy (then the column) of their
+// first tap in the block, and a batch of 16 visibilities of one row group
+// touches only the W rows oy .. oy + W - 1 of the window.  Eight of those rows (padded with
 // zero weights) times {real, imaginary} make the 16 rows of both operands:
 //   T[8 c + y][k]   = sum_x G_c[oy + y][x] kx_k[x]          (c = 0 re, 1 im)
 //   v_hat_k         = sum_y ky_k[y] (T[y][k] + i T[8 + y][k])
 //   A_oy[8 c + y][x] += sum_k part_c(r_k) ky_k[y] kx_k[x]
-// so each product is 4 MFMAs per batch instead of 8; A_oy is added into the
-// residual window (LDS) at row offset oy when the group ends.
+// so each product is 4 MFMAs per batch instead of 8 (the first one skips the
+// K-steps of window columns no footprint of the batch reaches); A_oy is
+// added into the residual window (LDS) at row offset oy when the group ends.
 #include "common.h"
 
 namespace imgr {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// word 3 of a raw (untyped) buffer descriptor on gfx9-family chips
+constexpr int kBufferWord3 = 0x00020000;
 
 #ifndef IMGR_WIN_WAVES
 #define IMGR_WIN_WAVES 4
@@ -218,9 +222,12 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
 }
 
 // LDS of one wave in the row-group form
+// row strides of the tap tables: 20 and 12 floats keep the 16-byte reads
+// of eight consecutive lanes on distinct banks
+constexpr int kKx = 20, kKy = 12;
 struct RowsLds {
-  float kx[16 * 16];     // [visibility][window column] tap weights
-  float ky[16 * 8];      // [visibility][footprint row] tap weights
+  float kx[16 * kKx];    // [visibility][window column] tap weights
+  float ky[16 * kKy];    // [visibility][footprint row] tap weights
   float r[16 * 2];       // weighted residual (re, im) per visibility
   float g[2][16 * 16];   // model window: real, imaginary planes [row][column]
   float acc[2][16 * 16]; // residual window: real, imaginary planes
@@ -271,33 +278,57 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       s.acc[1][y * 16 + c16] = 0.f;
     }
   }
-  *(float2 *)&s.ky[c16 * 8 + 2 * g] = make_float2(0.f, 0.f);
+  *(float2 *)&s.ky[c16 * kKy + 2 * g] = make_float2(0.f, 0.f);
   wave_sync();
 
   // row groups: group j holds the chunk's visibilities [b + rows[j-1], b + rows[j])
   int oy = 0, ge = b + rows[0];
   while (ge == b && oy < BLK - 1) ge = b + rows[++oy];
   float foy = (float)oy;
-  // A operand of the group: lane (c16, g) holds G_c[oy + y][4 g + s], c16 = 8 c + y
+  // A operand of the group: in K-step q lane (c16, g) holds G_c[oy + y][4 q + g],
+  // c16 = 8 c + y
   floatx4 ga = {0.f, 0.f, 0.f, 0.f};
-  if constexpr (kDegrid) ga = *(const floatx4 *)&s.g[c16 >> 3][(oy + (c16 & 7)) * 16 + 4 * g];
+  auto load_ga = [&]() {
+    const float *row = &s.g[c16 >> 3][(oy + (c16 & 7)) * 16 + g];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ga[q] = row[4 * q];
+  };
+  if constexpr (kDegrid) load_ga();
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 
   // lane (c16, g) works on visibility c16 of each batch; the record of the
   // next batch is loaded while the current one is processed (indices past
   // the group are clamped to its last visibility and masked by `valid`)
-  // (chunks are never empty; the guard keeps every read inside the chunk)
+  // (chunks are never empty; the guard keeps every read inside the chunk).
+  // The stream is read through buffer descriptors with 32-bit offsets.  The
+  // record index of a lane past the batch's group is clamped to the group's
+  // last visibility; its weight is read through a descriptor that ends at
+  // the group, so the hardware returns 0 for it and masks its residual
+  const __amdgpu_buffer_rsrc_t pv_rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)posvis, (short)0, a.n * 16, kBufferWord3);
+  auto load_pv = [&](int first, int end) {  // record first + c16 (clamped to end - 1)
+    const u32x4 r = __builtin_amdgcn_raw_buffer_load_b128(
+        pv_rs, (unsigned)min(first + c16, end - 1) * 16u, 0, 0);
+    return make_float4(__uint_as_float(r[0]), __uint_as_float(r[1]), __uint_as_float(r[2]),
+                       __uint_as_float(r[3]));
+  };
+  auto load_w = [&](int first, int end) {  // weight of record first + c16, 0 from end on
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)wts, (short)0, end * 4, kBufferWord3);
+    return __uint_as_float(
+        __builtin_amdgcn_raw_buffer_load_b32(rs, (unsigned)(first + c16) * 4u, 0, 0));
+  };
   float4 pv_next = make_float4(0.f, 0.f, 0.f, 0.f);
   float w_next = 0.f;
   if (ge > b) {
-    pv_next = posvis[min(b + c16, ge - 1)];
-    if constexpr (kGrid) w_next = wts[min(b + c16, ge - 1)];
+    pv_next = load_pv(b, ge);
+    if constexpr (kGrid) w_next = load_w(b, ge);
   }
   for (int base = b; ge > b;) {
     const int v = base + c16;
-    const bool valid = v < ge;
+    const bool valid = c16 < ge - base;
     const float4 pv = pv_next;
-    const float w = valid ? w_next : 0.f;
+    const float w = w_next;  // 0 for lanes past the group
     // the next batch: the rest of this group, else the next nonempty group
     int nbase = base + 16, nge = ge, noy = oy;
     const bool group_end = nbase >= ge;
@@ -305,11 +336,11 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       nbase = ge;
       while (nge == ge && noy < BLK - 1) nge = b + rows[++noy];
     }
-    // (without a next batch, nbase == nge and the load re-reads the last
-    // record of the chunk, which keeps it unconditional)
+    // (without a next batch, nbase == nge: the loads re-read the last record
+    // and return zero weights, which keeps them unconditional)
     const bool more = nbase < nge;
-    pv_next = posvis[min(nbase + c16, nge - 1)];
-    if constexpr (kGrid) w_next = wts[min(nbase + c16, nge - 1)];
+    pv_next = load_pv(nbase, nge);
+    if constexpr (kGrid) w_next = load_w(nbase, nge);
     // offsets are >= 0, so truncation is the floor; the row is the group's
     const int ox = min(max((int)pv.x, 0), BLK - 1);
     const float fx = pv.x - (float)ox, fy = pv.y - foy;
@@ -317,29 +348,52 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
     // tap weights: clear this lane's quarter of the column table row of its
     // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis:
     // phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1))
-    *(floatx4 *)&s.kx[c16 * 16 + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    *(floatx4 *)&s.kx[c16 * kKx + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < TPL; ++q) {
       const int t = g * TPL + q;
       if (t < W) {
-        const float sx = fmaxf(fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]), 0.0f);
-        const float sy = fmaxf(fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]), 0.0f);
-        s.kx[c16 * 16 + ox + t] =
-            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sx), -bl2e));
-        s.ky[c16 * 8 + t] = __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(sy), -bl2e));
+        // 1 - z^2 >= 0 on the support; rounding can leave -1e-8 at |z| = 1,
+        // so the root takes the magnitude (a free source modifier)
+        const float sx = fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]);
+        const float sy = fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]);
+        s.kx[c16 * kKx + ox + t] =
+            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(fabsf(sx)), -bl2e));
+        s.ky[c16 * kKy + t] =
+            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(fabsf(sy)), -bl2e));
       }
     }
     wave_sync();
 
     float val = 0.f;  // predicted visibility: real part in lanes g = 0, 1, imaginary in g = 2, 3
     if constexpr (kDegrid) {
-      // T[m][k] = sum_x Gs[m][x] kx_k[x]: B[x = 4 g + s][k = c16]
-      const floatx4 bx = *(const floatx4 *)&s.kx[c16 * 16 + 4 * g];
+      // T[m][k] = sum_x Gs[m][x] kx_k[x]: K-step q takes window columns
+      // 4 q .. 4 q + 3, B[x = 4 q + g][k = c16].  The stream is sorted by
+      // column inside a row group, so lane 0 holds the batch's first column
+      // and lane 15 (the last visibility, or a copy of it) the last: K-steps
+      // whose four columns no footprint reaches have all-zero weights and
+      // are skipped, which leaves the sums unchanged
+      const int s_lo = __builtin_amdgcn_readfirstlane(ox) >> 2;
+      const int s_hi = (__builtin_amdgcn_readlane(ox, 15) + W - 1) >> 2;
+      const float *kxr = &s.kx[c16 * kKx + g];
+      const floatx4 kq = {kxr[0], kxr[4], kxr[8], kxr[12]};
       floatx4 t = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[q], bx[q], t, 0, 0, 0);
+#define MF_(q) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[q], kq[q], t, 0, 0, 0)
+      switch (s_lo * 4 + s_hi) {  // (first, last) K-step
+        case 0: MF_(0); break;
+        case 1: MF_(0); MF_(1); break;
+        case 2: MF_(0); MF_(1); MF_(2); break;
+        case 5: MF_(1); break;
+        case 6: MF_(1); MF_(2); break;
+        case 7: MF_(1); MF_(2); MF_(3); break;
+        case 10: MF_(2); break;
+        case 11: MF_(2); MF_(3); break;
+        case 15: MF_(3); break;
+        default: MF_(0); MF_(1); MF_(2); MF_(3); break;
+      }
+#undef MF_
       // lane (c16, g) holds T[4 g + r][c16]: part g >> 1, rows 4 (g & 1) + r
-      const floatx4 by = *(const floatx4 *)&s.ky[c16 * 8 + 4 * (g & 1)];
+      const floatx4 by = *(const floatx4 *)&s.ky[c16 * kKy + 4 * (g & 1)];
       float p = by[0] * t[0];
 #pragma unroll
       for (int r = 1; r < 4; ++r) p = fmaf(by[r], t[r], p);
@@ -372,8 +426,8 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = 4 * q + g;
-        const float kyv = s.ky[k * 8 + (c16 & 7)];
-        const float kxv = s.kx[k * 16 + c16];
+        const float kyv = s.ky[k * kKy + (c16 & 7)];
+        const float kxv = s.kx[k * kKx + c16];
         const float rc = s.r[2 * k + (c16 >> 3)];
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(rc * kyv, kxv, acc, 0, 0, 0);
       }
@@ -391,7 +445,7 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       if (!more) break;
       oy = noy;
       foy = (float)oy;
-      if constexpr (kDegrid) ga = *(const floatx4 *)&s.g[c16 >> 3][(oy + (c16 & 7)) * 16 + 4 * g];
+      if constexpr (kDegrid) load_ga();
     }
     base = nbase;
     ge = nge;
@@ -614,6 +668,9 @@ WinArgs win_args(const imgr_s *h, const Bins &B, const float2 *grid_in, const fl
   a.chunk_block = B.chunk_block;
   a.chunk_begin = B.chunk_begin;
   a.chunk_rows = B.chunk_rows;
+  // buffer descriptors address the stream with 32-bit byte offsets
+  IMGR_CHECK(B.n < (int64_t)1 << 27, "a partition holds at most 2^27 visibilities");
+  a.n = (int)B.n;
   a.nb = B.nb;
   a.ng = B.ng;
   a.bl2e = (float)(h->beta * 1.4426950408889634);

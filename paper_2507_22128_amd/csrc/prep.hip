@@ -115,27 +115,28 @@ __global__ void k_member(int64_t m, const double *__restrict__ rho,
   member[i] = in ? 1 : 0;
 }
 
-// row of the first tap inside its block, from the FP32 offset the packed
-// stream stores (so the window kernel, which reads that offset, agrees)
-__device__ __forceinline__ int row_in_block(float dy, int blk) {
-  return min(max((int)dy, 0), blk - 1);
+// row (column) of the first tap inside its block, from the FP32 offset the
+// packed stream stores (so the window kernel, which reads that offset, agrees)
+__device__ __forceinline__ int row_in_block(float d, int blk) {
+  return min(max((int)d, 0), blk - 1);
 }
 
 // sort key: block of the first tap, floor(scale * g) / blk (scale 1 or 2 is
-// exact), times 8 plus the tap's row in the block; non-members get key
-// 8 nb^2 and sort last
+// exact), then the tap's row and column in the block: 64 block + 8 row +
+// column; non-members get key 64 nb^2 and sort last
 __global__ void k_block_keys(int64_t m, const double *__restrict__ gx,
                              const double *__restrict__ gy, const int32_t *__restrict__ member,
                              double scale, int blk, int nb, uint32_t *__restrict__ keys,
                              int32_t *__restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  uint32_t key = (uint32_t)nb * (uint32_t)nb * 8u;
+  uint32_t key = (uint32_t)nb * (uint32_t)nb * 64u;
   if (member[i]) {
     const int cx = (int)floor(gx[i] * scale), cy = (int)floor(gy[i] * scale);
-    const int by = cy / blk;
+    const int bx = cx / blk, by = cy / blk;
     const int row = row_in_block((float)(gy[i] * scale - (double)(by * blk)), blk);
-    key = (uint32_t)(by * nb + (cx / blk)) * 8u + (uint32_t)row;
+    const int col = row_in_block((float)(gx[i] * scale - (double)(bx * blk)), blk);
+    key = (uint32_t)(by * nb + bx) * 64u + (uint32_t)(row * 8 + col);
   }
   keys[i] = key;
   vals[i] = (int32_t)i;
@@ -287,10 +288,30 @@ void radix_sort(imgr_s *h, uint32_t *&keys, int32_t *&vals, uint32_t *&ktmp, int
 
 // ---------------------------------------------------------------- blocks, chunks, pack
 
-__global__ void k_block_hist(int64_t n, const uint32_t *__restrict__ keys, int n_blocks,
-                             int32_t *__restrict__ cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && (keys[i] >> 3) < (uint32_t)n_blocks) atomicAdd(&cnt[keys[i] >> 3], 1);
+// first index of the sorted keys[0, n) with key >= k
+__device__ __forceinline__ int64_t lower_bound_key(const uint32_t *keys, int64_t n, uint32_t k) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// visibilities per block from the sorted keys (block = key / 64); entry
+// n_blocks is 0.  Binary searches instead of a histogram: sorted keys would
+// send every atomic of a run to one counter
+__global__ void k_block_count(int64_t n, const uint32_t *__restrict__ keys, int n_blocks,
+                              int32_t *__restrict__ cnt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > n_blocks) return;
+  if (t == n_blocks) {
+    cnt[t] = 0;
+    return;
+  }
+  const uint32_t k0 = (uint32_t)t * 64u;
+  cnt[t] = (int32_t)(lower_bound_key(keys, n, k0 + 64u) - lower_bound_key(keys, n, k0));
 }
 
 __global__ void k_chunk_count(int n_blocks, const int32_t *__restrict__ cnt, int cap,
@@ -342,7 +363,7 @@ __global__ void k_pack(int64_t n, const uint32_t *__restrict__ keys,
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = idx[s];
-  const int t = (int)(keys[s] >> 3);
+  const int t = (int)(keys[s] >> 6);
   const int bx = t % nb, by = t / nb;
   float re, im;
   if (c128) {
@@ -437,17 +458,17 @@ void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member
   hipLaunchKernelGGL(k_block_keys, dim3(nbk), dim3(256), 0, s, m, gx, gy, member, scale, blk,
                      B.nb, keys, vals);
   IMGR_HIP(hipGetLastError());
-  // stable sort by block and row; non-members (key 8 n_blocks) go last
+  // stable sort by block, row and column; non-members (key 64 n_blocks) go last
+  IMGR_CHECK(n_blocks < (1 << 25), "grid too large for the 32-bit sort key");
   int key_bits = 0;
-  while ((1ll << key_bits) <= 8ll * n_blocks) key_bits += 8;
+  while ((1ll << key_bits) <= 64ll * n_blocks) key_bits += 8;
   radix_sort(h, keys, vals, ktmp, vtmp, m, key_bits, s);
   // block counts, starts, chunks
   int32_t *cnt = alloc_n<int32_t>(h, n_blocks + 1);
   int32_t *bstart = alloc_n<int32_t>(h, n_blocks + 1);
   int32_t *nch = alloc_n<int32_t>(h, n_blocks + 1);
-  IMGR_HIP(hipMemsetAsync(cnt, 0, (n_blocks + 1) * sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_block_hist, dim3(cdiv(std::max<int64_t>(n, 1), 256)), dim3(256), 0, s, n,
-                     keys, n_blocks, cnt);
+  hipLaunchKernelGGL(k_block_count, dim3(cdiv(n_blocks + 1, 256)), dim3(256), 0, s, n, keys,
+                     n_blocks, cnt);
   IMGR_HIP(hipGetLastError());
   scan_exclusive(h, cnt, bstart, n_blocks + 1, s);
   hipLaunchKernelGGL(k_chunk_count, dim3(cdiv(n_blocks + 1, 256)), dim3(256), 0, s, n_blocks + 1,
