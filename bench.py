@@ -33,8 +33,8 @@ FP32_PEAK_MATRIX = 157.3
 # (profiles/k_window_decentral_hbm_traffic.md), valid only for the kernel
 # source the counters were taken on.
 KWINDOW_TRAFFIC = {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
-                   "sha256_16": "6e90fbd56d4d56de",
-                   "bytes_per_launch": (98286.4 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)}
+                   "sha256_16": "5e0af2c049652809",
+                   "bytes_per_launch": (99139.3 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)}
 
 
 def measured_traffic():
@@ -314,6 +314,7 @@ def batched_channels(args):
         "image_sizes": {str(x): sizes.count(x) for x in sorted(set(sizes))},
         "support": i0.support, "tile": i0.tile, "chunk": chosen,
         "n_chunks_fused": int(info.n_chunks),
+        "n_sets": int(b.info().n_sets),
         "create_tuner": [{"tile": t, "chunk": c, "ms": round(x, 4)} for t, c, x in tune_log],
         "batch_tuner_ms": {str(k): round(v, 4) for k, v in cap_ms.items()},
         "fused_window_flush_ms": round(cap_ms[chosen], 4),

@@ -405,10 +405,11 @@ imgr_status imager_set_chunk(imgr_t h, int32_t chunk);
  * Frequency channels are the axis along which imaging work is usually
  * spread (Section 1); a batch runs the major cycles (Eq. 2) of many
  * single-partition handles, e.g. one per channel with its own image size,
- * cell and flags, with the de/gridding of ALL of them as one fused launch
- * over every channel's chunks (largest chunks first across channels) and
- * one fused flush, while the FFT stages run per channel on the same
- * stream.  Members must have one partition, equal support and tile, and
+ * cell and flags, with the de/gridding of many of them as one fused launch
+ * over their chunks (largest chunks first across channels) and one fused
+ * flush, while the FFT stages run per channel on the same stream.  Members
+ * are taken in consecutive sets sized to the last-level cache, one fused
+ * launch per set (imgr_batch_info.n_sets).  Members must have one partition, equal support and tile, and
  * one stream, on which the batch enqueues its work.  The caller owns the
  * members; they must outlive the batch.  The batch uses the members' work
  * buffers, so a member's own calls and batch calls must be ordered (they
@@ -426,8 +427,10 @@ enum {
 typedef struct {
   int32_t n_members, support, tile, chunk;
   int64_t n_vis;        /* member visibilities over all members */
-  int64_t n_chunks;     /* chunks of the fused launch */
+  int64_t n_chunks;     /* chunks of the fused launches */
   int32_t graph_ready;  /* 1 if a captured graph is held */
+  int32_t n_sets;       /* consecutive member sets, one fused launch each (their grids and
+                           chunk windows stay within half of the last-level cache) */
 } imgr_batch_info;
 
 /* members: host array of n >= 1 handles.  Synchronous. */

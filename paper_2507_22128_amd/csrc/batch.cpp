@@ -13,6 +13,13 @@
 // single-handle path, so results match it bit for bit.  The whole cycle
 // (per-channel FFTs, fused de/gridding, flush, per-channel inverse FFTs) can
 // be captured into a HIP graph and replayed; it holds no memset nodes.
+//
+// The members are taken in consecutive sets whose model grids and chunk
+// windows together stay within half of the 256 MB last-level cache: for each
+// set the model transforms, one fused de/gridding launch, one fused flush and
+// the inverse transforms run back to back, so a grid written by one stage is
+// still cached when the next reads it (one launch over every channel at once
+// would push each grid out to HBM between the stages).
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -30,6 +37,12 @@ struct imgr_batch_s {
   int2 *d_order = nullptr;
   int32_t *d_gstart = nullptr;
   int n_slots = 0, n_groups = 0;
+  // consecutive member sets: members [g0, g1), slots [slot0, slot0 + n_slots)
+  // of d_order, flush-group offsets d_gstart[gs0 .. gs0 + g1 - g0] (relative)
+  struct Set {
+    int g0, g1, slot0, n_slots, gs0, n_groups;
+  };
+  std::vector<Set> sets;
   int64_t n_vis = 0;
   std::vector<uint64_t> versions;  // member layout versions the tables were built for
   // captured graph and the pointers it was captured with
@@ -68,6 +81,10 @@ T *upload(const std::vector<T> &v, hipStream_t s) {
   return d;
 }
 
+// bytes of a member set's grids and chunk windows that should stay cached
+// between its stages: half of the 256 MB last-level cache
+constexpr size_t kSetBytes = (size_t)128 << 20;
+
 // (Re)build the device tables from the members' current bins and buffers.
 void build_tables(imgr_batch_s *b) {
   hipStream_t s = b->stream;
@@ -77,21 +94,43 @@ void build_tables(imgr_batch_s *b) {
   const int n = (int)b->m.size();
   std::vector<WinArgs> win(n);
   std::vector<FlushArgs> fl(n);
-  std::vector<int32_t> gstart(n + 1, 0);
-  // (size, grid, chunk) of every chunk, grids in member order
+  std::vector<int32_t> gstart;
+  // (size, grid, chunk) of every chunk of a set, grids in member order
   struct Item {
     int32_t size, grid, chunk;
   };
   std::vector<Item> items;
+  std::vector<int2> order;
+  b->sets.clear();
   b->n_vis = 0;
   b->versions.resize(n);
+  size_t set_bytes = 0;
+  auto close_set = [&](int g1) {
+    imgr_batch_s::Set &st = b->sets.back();
+    st.g1 = g1;
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &x, const Item &y) { return x.size > y.size; });
+    for (const Item &it : items) order.push_back(make_int2(it.grid, it.chunk));
+    st.n_slots = (int)items.size();
+    st.n_groups = gstart.back();
+    items.clear();
+  };
   for (int g = 0; g < n; ++g) {
     imgr_s *h = b->m[g];
     const Bins &B = h->part[0].bins;
     Work &wk = h->work[0];
+    const size_t bytes = (size_t)B.ng * B.ng * sizeof(float2) + (size_t)B.n_chunks * kWin * kWin *
+                                                                   sizeof(float2);
+    if (g == 0 || set_bytes + bytes > kSetBytes) {
+      if (g > 0) close_set(g);
+      b->sets.push_back({g, g, (int)order.size(), 0, (int)gstart.size(), 0});
+      gstart.push_back(0);
+      set_bytes = 0;
+    }
+    set_bytes += bytes;
     win[g] = win_args(h, B, wk.grid_a, nullptr, nullptr, wk.scratch);
     fl[g] = FlushArgs{wk.scratch, B.block_chunk, B.nb, B.ng, wk.grid_a};
-    gstart[g + 1] = gstart[g] + (B.ng / 16) * (B.ng / 16);
+    gstart.push_back(gstart.back() + (B.ng / 16) * (B.ng / 16));
     std::vector<int32_t> cb(B.n_chunks + 1);
     IMGR_HIP(hipMemcpyAsync(cb.data(), B.chunk_begin, (B.n_chunks + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
@@ -100,13 +139,11 @@ void build_tables(imgr_batch_s *b) {
     b->n_vis += B.n;
     b->versions[g] = h->layout_version;
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const Item &x, const Item &y) { return x.size > y.size; });
-  std::vector<int2> order(items.size());
-  for (size_t i = 0; i < items.size(); ++i) order[i] = make_int2(items[i].grid, items[i].chunk);
-  IMGR_CHECK(items.size() < (size_t)INT32_MAX, "too many chunks for one launch");
-  b->n_slots = (int)items.size();
-  b->n_groups = gstart[n];
+  if (n > 0) close_set(n);
+  IMGR_CHECK(order.size() < (size_t)INT32_MAX, "too many chunks for one launch");
+  b->n_slots = (int)order.size();
+  b->n_groups = 0;
+  for (const imgr_batch_s::Set &st : b->sets) b->n_groups += st.n_groups;
   b->d_win = upload(win, s);
   b->d_flush = upload(fl, s);
   b->d_order = upload(order, s);
@@ -123,27 +160,34 @@ void refresh(imgr_batch_s *b) {
   if (stale) build_tables(b);
 }
 
-// fused de/gridding and flush of every member (model grids already in
-// work[0].grid_a; residual grids left there)
+// fused de/gridding and flush of the members of one set (model grids
+// already in work[0].grid_a; residual grids left there)
+void fused_set(imgr_batch_s *b, const imgr_batch_s::Set &st, hipStream_t s) {
+  degrid_grid_batch(b->W, b->blk, b->d_win, b->d_order + st.slot0, st.n_slots, s);
+  flush_batch(b->W, b->blk, b->d_flush + st.g0, b->d_gstart + st.gs0, st.g1 - st.g0,
+              st.n_groups, s);
+}
+
 void fused_window(imgr_batch_s *b, hipStream_t s) {
-  degrid_grid_batch(b->W, b->blk, b->d_win, b->d_order, b->n_slots, s);
-  flush_batch(b->W, b->blk, b->d_flush, b->d_gstart, (int)b->m.size(), b->n_groups, s);
+  for (const imgr_batch_s::Set &st : b->sets) fused_set(b, st, s);
 }
 
 void enqueue_cycle(imgr_batch_s *b, const float *const *model, float *const *residual,
                    hipStream_t s) {
-  for (size_t g = 0; g < b->m.size(); ++g) {
-    imgr_s *h = b->m[g];
-    Work &wk = h->work[0];
-    fft_model_to_grid(h, model[g], nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b, wk.grid_a,
-                      s);
-  }
-  fused_window(b, s);
-  for (size_t g = 0; g < b->m.size(); ++g) {
-    imgr_s *h = b->m[g];
-    Work &wk = h->work[0];
-    fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / h->part[0].sum_w),
-                      wk.rows, wk.grid_b, residual[g], s);
+  for (const imgr_batch_s::Set &st : b->sets) {
+    for (int g = st.g0; g < st.g1; ++g) {
+      imgr_s *h = b->m[g];
+      Work &wk = h->work[0];
+      fft_model_to_grid(h, model[g], nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b,
+                        wk.grid_a, s);
+    }
+    fused_set(b, st, s);
+    for (int g = st.g0; g < st.g1; ++g) {
+      imgr_s *h = b->m[g];
+      Work &wk = h->work[0];
+      fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / h->part[0].sum_w),
+                        wk.rows, wk.grid_b, residual[g], s);
+    }
   }
 }
 
@@ -245,6 +289,7 @@ imgr_status imager_batch_info(imgr_batch_t b, imgr_batch_info *o) {
   o->n_vis = b->n_vis;
   o->n_chunks = b->n_slots;
   o->graph_ready = b->exec != nullptr;
+  o->n_sets = (int32_t)b->sets.size();
   return IMGR_OK;
 }
 

@@ -48,6 +48,37 @@ constexpr int kBufferWord3 = 0x00020000;
 // independent waves per workgroup (each owns one chunk and an LDS slice)
 constexpr int kWaves = IMGR_WIN_WAVES;
 
+// Address-space views of the argument pointers.  The batched kernels read
+// their arguments from a device table, and pointers loaded from memory are
+// generic to the compiler: flat accesses, which also count against the LDS
+// wait counter and may alias LDS.  Global (1) and constant (4) views give
+// plain global and, for wave-uniform table reads, scalar loads.
+// (The host pass only parses device code, so the qualifiers are empty there.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AS_GLOBAL __attribute__((address_space(1)))
+#define AS_CONST __attribute__((address_space(4)))
+#else
+#define AS_GLOBAL
+#define AS_CONST
+#endif
+template <class T>
+__device__ __forceinline__ AS_GLOBAL T *glb(T *p) {
+  return (AS_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ const AS_CONST T *cst(const T *p) {
+  return (const AS_CONST T *)p;
+}
+// complex values through the global view (as native two-float vectors)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld2(const float2 *p, size_t i) {
+  const f32x2 v = ((const AS_GLOBAL f32x2 *)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(float2 *p, size_t i, float2 v) {
+  ((AS_GLOBAL f32x2 *)p)[i] = f32x2{v.x, v.y};
+}
+
 // orders the LDS traffic of one wave around a point where its lanes
 // exchange data (no other wave shares the data)
 __device__ __forceinline__ void wave_sync() {
@@ -248,10 +279,10 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
 
   const int l = threadIdx.x & 63, c16 = l & 15, g = l >> 4;
   chunk = __builtin_amdgcn_readfirstlane(chunk);
-  const int blk = a.chunk_block[chunk];
+  const int blk = cst(a.chunk_block)[chunk];
   const int wx0 = (blk % nb) * BLK - H, wy0 = (blk / nb) * BLK - H;
-  const int b = a.chunk_begin[chunk];
-  const int32_t *__restrict__ rows = a.chunk_rows + 8 * chunk;
+  const int b = cst(a.chunk_begin)[chunk];
+  const AS_CONST int32_t *__restrict__ rows = cst(a.chunk_rows) + 8 * chunk;
 
   float qa[TPL], qb[TPL];
 #pragma unroll
@@ -269,7 +300,7 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
   for (int r = 0; r < 4; ++r) {
     const int y = 4 * g + r;
     if constexpr (kDegrid) {
-      const float2 v = a.grid_in[(size_t)((wy0 + y) & (ng - 1)) * ng + ((wx0 + c16) & (ng - 1))];
+      const float2 v = ld2(a.grid_in, (size_t)((wy0 + y) & (ng - 1)) * ng + ((wx0 + c16) & (ng - 1)));
       s.g[0][y * 16 + c16] = v.x;
       s.g[1][y * 16 + c16] = v.y;
     }
@@ -404,7 +435,7 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
     }
     if constexpr (MODE == MODE_DEGRID) {
       if (valid && !(g & 1))
-        reinterpret_cast<float *>(a.vis_out)[2 * (size_t)a.outpos[v] + (g >> 1)] = val;
+        glb(reinterpret_cast<float *>(a.vis_out))[2 * (size_t)glb(a.outpos)[v] + (g >> 1)] = val;
     }
     if constexpr (kGrid) {
       if constexpr (MODE == MODE_DEGRID_GRID) {
@@ -413,7 +444,8 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       } else if (g == 0) {
         float2 r;
         if constexpr (MODE == MODE_GRID) {
-          const float2 x = valid ? a.vis_in[a.outpos[v]] : make_float2(0.f, 0.f);
+          float2 x = make_float2(0.f, 0.f);
+          if (valid) x = ld2(a.vis_in, glb(a.outpos)[v]);
           r = make_float2(w * x.x, w * x.y);
         } else {  // MODE_PSF: unit visibilities
           r = make_float2(w, 0.f);
@@ -457,7 +489,7 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int y = 4 * g + r;
-      out[y * kWin + c16] = make_float2(s.acc[0][y * 16 + c16], s.acc[1][y * 16 + c16]);
+      st2(out, y * kWin + c16, make_float2(s.acc[0][y * 16 + c16], s.acc[1][y * 16 + c16]));
     }
   }
 }
@@ -529,7 +561,7 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
   for (int i = threadIdx.x; i < SB * SB; i += 256) {
     const int sy = i / SB, sx = i % SB;
     const int n = ((by0 + sy + nb) % nb) * nb + (bx0 + sx + nb) % nb;
-    rng[i] = make_int2(a.block_chunk[n], a.block_chunk[n + 1]);
+    rng[i] = make_int2(glb(a.block_chunk)[n], glb(a.block_chunk)[n + 1]);
   }
   __syncthreads();
   const int cx = gx0 + (threadIdx.x & 15);
@@ -549,8 +581,8 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
     for (int j = 0; j < KA; ++j) {
       const int2 r = rng[(sy0 + i) * SB + sx0 + j];
       const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
-      first[i * KA + j] = (r.x < r.y) ? a.scratch[(size_t)r.x * (kWin * kWin) + off]
-                                      : make_float2(0.f, 0.f);
+      first[i * KA + j] = make_float2(0.f, 0.f);
+      if (r.x < r.y) first[i * KA + j] = ld2(a.scratch, (size_t)r.x * (kWin * kWin) + off);
     }
   double re = 0.0, im = 0.0;
 #pragma unroll
@@ -563,14 +595,14 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
         im += (double)first[i * KA + j].y;
         const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
         for (int c = r.x + 1; c < r.y; ++c) {
-          const float2 v = a.scratch[(size_t)c * (kWin * kWin) + off];
+          const float2 v = ld2(a.scratch, (size_t)c * (kWin * kWin) + off);
           re += (double)v.x;
           im += (double)v.y;
         }
       }
     }
   const float sg = ((cx + cy) & 1) ? -1.f : 1.f;
-  a.grid_out[(size_t)cy * ng + cx] = make_float2(sg * (float)re, sg * (float)im);
+  st2(a.grid_out, (size_t)cy * ng + cx, make_float2(sg * (float)re, sg * (float)im));
 }
 
 template <int W, int BLK>

@@ -64,7 +64,8 @@ class Info(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_members", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("n_vis", ctypes.c_int64),
-                ("n_chunks", ctypes.c_int64), ("graph_ready", ctypes.c_int32)]
+                ("n_chunks", ctypes.c_int64), ("graph_ready", ctypes.c_int32),
+                ("n_sets", ctypes.c_int32)]
 
 
 BATCH_GRAPH, BATCH_LOOP = 1, 2

@@ -57,6 +57,7 @@ def test_batch_equals_single_handles_bitwise(chans):
         assert info.n_members == len(members)
         assert info.n_vis == sum(m.n_vis(0) for m in members)
         assert info.n_chunks == sum(m.info.n_chunks[0] for m in members)
+        assert info.n_sets == 1  # small grids: one fused launch
         for mode in (dict(), dict(loop=True), dict(graph=True)):
             got = [to_np(r) for r in b.major_cycle(models, **mode)]
             say("batch mode %s: max |diff| %.3e" % (mode, max(np.abs(g - r).max()
@@ -116,6 +117,33 @@ def test_batch_members_against_oracle(chans):
         err = rel(got[k], ref)
         say("channel %d (N=%d, %.0f%% flagged): rel err %.3e" % (k, n, 100 * c["flag_frac"], err))
         assert err < TOL
+
+
+def test_batch_member_sets_bitwise():
+    """Members whose grids and chunk windows together exceed the cache budget
+    of one fused launch run in several consecutive sets; every mode still
+    equals each member's own cycle bit for bit."""
+    from paper_2507_22128_amd import synth
+    say("case: 3 channels of N = 2048 (4096^2 grids of 134 MB each: one set per member)")
+    d = synth.make_channels(n_chan=3, n_ant=24, n_time=8, sizes=(2048,), seed=9)
+    members = [_create(d, c, chunk=256) for c in d["channels"]]
+    try:
+        rng = np.random.default_rng(22)
+        models = [to_dev(random_model(c["n_img"], rng, n_points=12, smooth=False))
+                  for c in d["channels"]]
+        ref = _singles(members, models)
+        b = _imager().Batch(members)
+        try:
+            assert b.info().n_sets == 3
+            for mode in (dict(), dict(graph=True)):
+                got = [to_np(r) for r in b.major_cycle(models, **mode)]
+                for g, r in zip(got, ref):
+                    assert np.array_equal(g, r)
+        finally:
+            b.destroy()
+    finally:
+        for m in members:
+            m.destroy()
 
 
 def test_set_chunk_equals_fresh_create(chans):
