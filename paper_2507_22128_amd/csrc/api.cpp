@@ -141,7 +141,8 @@ static void build_psf(imgr_s *h, int p) {
       h, (size_t)std::max(P.psf_bins.n_chunks, 1) * kWin * kWin * sizeof(float2));
   degrid_grid(h, P.psf_bins, MODE_PSF, nullptr, nullptr, nullptr, scr, s);
   flush_chunks(h, P.psf_bins, scr, grid, s);
-  fft_grid_to_image(h, grid, h->cinv2, n2, ng2, (float)(1.0 / P.sum_w), rows, tmp, P.psf, s);
+  fft_grid_to_image(h, grid, h->cinv2, n2, ng2, (float)(1.0 / P.sum_w), rows, tmp, P.psf,
+                    P.psf_bins.box, s);
   IMGR_HIP(hipStreamSynchronize(s));
   dev_free(h, scr);
   dev_free(h, rows);
@@ -214,7 +215,7 @@ void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other,
   mark(0);
   // a1: model -> model grid
   fft_model_to_grid(h, model, (flags & IMGR_DEGRID_COMPOSITE) ? rho_other : nullptr, h->cinv, h->N,
-                    h->Ng, wk.rows, wk.grid_b, wk.grid_a, s);
+                    h->Ng, wk.rows, wk.grid_b, wk.grid_a, P.bins.box, s);
   mark(1);
   // a2 + a3: degrid, residual, grid (one pass per chunk), flush
   degrid_grid(h, P.bins, MODE_DEGRID_GRID, wk.grid_a, nullptr, nullptr, wk.scratch, s);
@@ -223,7 +224,7 @@ void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other,
   mark(3);
   // a4: residual grid -> residual image
   fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), wk.rows,
-                    wk.grid_b, local, s);
+                    wk.grid_b, local, P.bins.box, s);
   mark(4);
   // a6: pseudo-full-resolution composition
   if (h->n_parts == 2) {
@@ -560,7 +561,8 @@ imgr_status imager_degrid(imgr_t h, int32_t part, const float *model, void *vis_
   IMGR_CHECK(model && vis_out, "null pointer");
   hipStream_t s = h->stream;
   Work &wk = h->work[part];
-  fft_model_to_grid(h, model, nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b, wk.grid_a, s);
+  fft_model_to_grid(h, model, nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b, wk.grid_a,
+                    h->part[part].bins.box, s);
   degrid_grid(h, h->part[part].bins, MODE_DEGRID, wk.grid_a, nullptr, (float2 *)vis_out, nullptr,
               s);
   API_END(h)
@@ -578,7 +580,8 @@ imgr_status imager_grid(imgr_t h, int32_t part, const void *vis_in, float *image
   degrid_grid(h, B, MODE_GRID, nullptr, (const float2 *)vis_in, nullptr, wk.scratch, s);
   flush_chunks(h, B, wk.scratch, wk.grid_a, s);
   const float scale = mode == IMGR_GRID_DIRTY ? (float)(1.0 / h->part[part].sum_w) : 1.f;
-  fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, scale, wk.rows, wk.grid_b, image_out, s);
+  fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, scale, wk.rows, wk.grid_b, image_out,
+                    B.box, s);
   API_END(h)
 }
 

@@ -129,8 +129,8 @@ void build_tables(imgr_batch_s *b) {
     }
     set_bytes += bytes;
     win[g] = win_args(h, B, wk.grid_a, nullptr, nullptr, wk.scratch);
-    fl[g] = FlushArgs{wk.scratch, B.block_chunk, B.nb, B.ng, wk.grid_a};
-    gstart.push_back(gstart.back() + (B.ng / 16) * (B.ng / 16));
+    fl[g] = flush_args(B, wk.scratch, wk.grid_a);
+    gstart.push_back(gstart.back() + flush_groups(B));
     std::vector<int32_t> cb(B.n_chunks + 1);
     IMGR_HIP(hipMemcpyAsync(cb.data(), B.chunk_begin, (B.n_chunks + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
@@ -179,14 +179,14 @@ void enqueue_cycle(imgr_batch_s *b, const float *const *model, float *const *res
       imgr_s *h = b->m[g];
       Work &wk = h->work[0];
       fft_model_to_grid(h, model[g], nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b,
-                        wk.grid_a, s);
+                        wk.grid_a, h->part[0].bins.box, s);
     }
     fused_set(b, st, s);
     for (int g = st.g0; g < st.g1; ++g) {
       imgr_s *h = b->m[g];
       Work &wk = h->work[0];
       fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / h->part[0].sum_w),
-                        wk.rows, wk.grid_b, residual[g], s);
+                        wk.rows, wk.grid_b, residual[g], h->part[0].bins.box, s);
     }
   }
 }

@@ -51,6 +51,14 @@ constexpr int kTwMax = 16384;
 // block, and cut into chunks of at most C visibilities of one block.  Every footprint of a
 // block lies in a 16 x 16 window of the grid whose origin is the block origin
 // minus W/2 - 1.
+// Grid cells the chunk windows of a partition cover: columns [x0, x1)
+// (multiples of 64), rows [y0, y1) (multiples of 16).  The de/gridding reads
+// and the flush writes nothing outside, so the transforms skip the rest.
+// The whole grid when some window wraps around the grid's edge.
+struct Box {
+  int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+};
+
 struct Bins {
   int64_t n = 0;               // members
   int n_chunks = 0;
@@ -65,6 +73,7 @@ struct Bins {
   int32_t *chunk_rows = nullptr;   // [n_chunks][8] visibilities of the chunk with row <= j
   int32_t *block_chunk = nullptr;  // [nb * nb + 1] first chunk of each block
   int32_t *order = nullptr;        // [n_chunks] launch order: largest chunk first
+  Box box;                         // cells the chunk windows cover
 };
 
 // work buffers of one node's major cycle
@@ -217,12 +226,15 @@ int support_for_tolerance(double tol);
 // ----------------------------------------------------------------- FFT
 // centred forward transform of an N x N real image (times 1/psi_hat on both
 // axes, plus optional second image) into the Ng x Ng grid `out`
+// (box: the grid cells the following de/gridding reads; nothing else is formed)
 void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, const float *cinv,
-                       int n, int ng, float2 *rows, float2 *tmp, float2 *out, hipStream_t s);
+                       int n, int ng, float2 *rows, float2 *tmp, float2 *out, const Box &box,
+                       hipStream_t s);
 // centred inverse transform of the Ng x Ng grid `in` (already multiplied by
 // (-1)^(gx+gy)) cropped to N x N, times (-1)^(px+py)/psi_hat^2 * scale, real part
+// (box: the cells of `in` that the flush wrote; the rest is taken as zero)
 void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
-                       float2 *rows, float2 *tmp, float *out, hipStream_t s);
+                       float2 *rows, float2 *tmp, float *out, const Box &box, hipStream_t s);
 // out (+)= Re F_N^-1 (Gamma_own . F_N (a - b)) * coef for N x N images
 // (b may be NULL; plain DFTs; own_low: bit 0 set = Gamma_L, else Gamma_H;
 // bit 1 set = the filter squared);
@@ -282,7 +294,13 @@ struct FlushArgs {
   const int32_t *block_chunk;
   int nb, ng;
   float2 *grid_out;
+  int gx0, gy0, gnx;  // 16 x 16 cell groups of the box: first column, first row, per row
 };
+FlushArgs flush_args(const Bins &B, const float2 *scratch, float2 *grid_out);
+// 16 x 16 cell groups of the flush of bins B
+inline int flush_groups(const Bins &B) {
+  return ((B.box.x1 - B.box.x0) / 16) * ((B.box.y1 - B.box.y0) / 16);
+}
 WinArgs win_args(const imgr_s *h, const Bins &B, const float2 *grid_in, const float2 *vis_in,
                  float2 *vis_out, float2 *scratch);
 // fused degrid / residual / grid over the chunks of many grids: order[i] =

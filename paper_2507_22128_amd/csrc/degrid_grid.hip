@@ -75,6 +75,11 @@ __device__ __forceinline__ float2 ld2(const float2 *p, size_t i) {
   const f32x2 v = ((const AS_GLOBAL f32x2 *)p)[i];
   return make_float2(v.x, v.y);
 }
+// element index below 2^32 (the chunk-window arrays hold fewer than 2^24 windows)
+__device__ __forceinline__ float2 ld2u(const float2 *p, unsigned i) {
+  const f32x2 v = ((const AS_GLOBAL f32x2 *)p)[i];
+  return make_float2(v.x, v.y);
+}
 __device__ __forceinline__ void st2(float2 *p, size_t i, float2 v) {
   ((AS_GLOBAL f32x2 *)p)[i] = f32x2{v.x, v.y};
 }
@@ -555,8 +560,7 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
   constexpr int KA = kWin / BLK;  // covering blocks per axis: exactly KA
   __shared__ int2 rng[SB * SB];
   const int nb = a.nb, ng = a.ng;
-  const int nq = ng / 16;
-  const int gx0 = (group % nq) * 16, gy0 = (group / nq) * 16;
+  const int gx0 = (a.gx0 + group % a.gnx) * 16, gy0 = (a.gy0 + group / a.gnx) * 16;
   const int bx0 = gx0 / BLK - R, by0 = gy0 / BLK - R;
   for (int i = threadIdx.x; i < SB * SB; i += 256) {
     const int sy = i / SB, sx = i % SB;
@@ -582,7 +586,7 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
       const int2 r = rng[(sy0 + i) * SB + sx0 + j];
       const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
       first[i * KA + j] = make_float2(0.f, 0.f);
-      if (r.x < r.y) first[i * KA + j] = ld2(a.scratch, (size_t)r.x * (kWin * kWin) + off);
+      if (r.x < r.y) first[i * KA + j] = ld2u(a.scratch, (unsigned)(r.x * (kWin * kWin) + off));
     }
   double re = 0.0, im = 0.0;
 #pragma unroll
@@ -595,7 +599,7 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
         im += (double)first[i * KA + j].y;
         const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
         for (int c = r.x + 1; c < r.y; ++c) {
-          const float2 v = ld2(a.scratch, (size_t)c * (kWin * kWin) + off);
+          const float2 v = ld2u(a.scratch, (unsigned)(c * (kWin * kWin) + off));
           re += (double)v.x;
           im += (double)v.y;
         }
@@ -644,9 +648,9 @@ void launch_window(imgr_s *h, const Bins &B, int mode, const float2 *grid_in,
 
 template <int W, int BLK>
 void launch_flush(const Bins &B, const float2 *scratch, float2 *out, hipStream_t s) {
-  const int nq = B.ng / 16;
-  FlushArgs a{scratch, B.block_chunk, B.nb, B.ng, out};
-  hipLaunchKernelGGL((k_flush<W, BLK>), dim3(nq * nq), dim3(256), 0, s, a);
+  const int n_groups = flush_groups(B);
+  if (n_groups == 0) return;
+  hipLaunchKernelGGL((k_flush<W, BLK>), dim3(n_groups), dim3(256), 0, s, flush_args(B, scratch, out));
 }
 
 template <int W, int BLK>
@@ -691,6 +695,13 @@ void degrid_grid(imgr_s *h, const Bins &B, int mode, const float2 *grid_in, cons
   throw Error{IMGR_EINVAL, "unsupported support / block combination"};
 }
 
+FlushArgs flush_args(const Bins &B, const float2 *scratch, float2 *grid_out) {
+  IMGR_CHECK(B.n_chunks < (1 << 24), "too many chunk windows for 32-bit element offsets");
+  FlushArgs a{scratch, B.block_chunk, B.nb, B.ng, grid_out, B.box.x0 / 16, B.box.y0 / 16,
+              (B.box.x1 - B.box.x0) / 16};
+  return a;
+}
+
 WinArgs win_args(const imgr_s *h, const Bins &B, const float2 *grid_in, const float2 *vis_in,
                  float2 *vis_out, float2 *scratch) {
   WinArgs a;
@@ -729,6 +740,7 @@ void degrid_grid_batch(int W, int blk, const WinArgs *grids, const int2 *order, 
 
 void flush_batch(int W, int blk, const FlushArgs *grids, const int32_t *group_start, int n_grids,
                  int n_groups, hipStream_t s) {
+  if (n_groups == 0) return;
 #define C_(w, b)                                                              \
   if (W == w && blk == b) {                                                   \
     launch_flush_batch<w, b>(grids, group_start, n_grids, n_groups, s);       \

@@ -177,7 +177,7 @@ template <int L>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
     const float *__restrict__ model, const float *__restrict__ model_add,
     const float *__restrict__ cinv, int n, float2 *__restrict__ rows,
-    const float2 *__restrict__ twr) {
+    const float2 *__restrict__ twr, int c_lo, int c_hi) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
@@ -215,15 +215,17 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
-  for (int x = threadIdx.x; x < L; x += NT) rows[(size_t)r * L + x] = s[padi(x)];
+  // only the columns [c_lo, c_hi) are ever read
+  for (int x = c_lo + threadIdx.x; x < c_hi; x += NT) rows[(size_t)r * L + x] = s[padi(x)];
 }
 
 // rows (n x L complex) -> image (n x n f32): inverse row DFT, crop of the
 // centre, (-1)^(x+y), correction 1/psi on both axes, real part, scale.
+// Columns outside [c_lo, c_hi) are zero and not read.
 template <int L>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
     const float2 *__restrict__ rows, const float *__restrict__ cinv, int n, float scale,
-    float *__restrict__ out, const float2 *__restrict__ twr) {
+    float *__restrict__ out, const float2 *__restrict__ twr, int c_lo, int c_hi) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
@@ -234,7 +236,10 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
     constexpr int PER = L / NT;
     float2 v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) v[q] = rows[(size_t)r * L + threadIdx.x + q * NT];
+    for (int q = 0; q < PER; ++q) {
+      const int x = threadIdx.x + q * NT;
+      v[q] = (x >= c_lo && x < c_hi) ? rows[(size_t)r * L + x] : make_float2(0.f, 0.f);
+    }
     stage_twiddles<L, NT, float2>(twl, twr);
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
@@ -284,11 +289,11 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
 template <int P, int Q, int DIR, class C>
 __global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int src_row0,
                                                  int y_lo, int y_hi, C *__restrict__ dst,
-                                                 const C *__restrict__ tw) {
+                                                 const C *__restrict__ tw, int cb0) {
   constexpr int L = P * Q;
   __shared__ C s[P * 64];
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * 64;
+  const int x0 = (blockIdx.x + cb0) * 64;
   const int y2 = blockIdx.y;
   {
     // every load of the thread goes out before the first is used
@@ -324,11 +329,11 @@ template <int P, int Q, int DIR, class C>
 __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
                                                  C *__restrict__ dst, int dst_row0, int k_lo,
                                                  int k_hi, int modulate,
-                                                 const C *__restrict__ tw) {
+                                                 const C *__restrict__ tw, int cb0) {
   constexpr int L = P * Q;
   __shared__ C s[Q * 64];
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * 64;
+  const int x0 = (blockIdx.x + cb0) * 64;
   const int k1 = blockIdx.y;
   {
     constexpr int PER = Q * 64 / 256;
@@ -577,32 +582,40 @@ template <class C> const C *row_twiddles(const imgr_s *h);
 template <> const float2 *row_twiddles<float2>(const imgr_s *h) { return h->twrow; }
 template <> const double2 *row_twiddles<double2>(const imgr_s *h) { return h->twrow64; }
 
+// column blocks [cb0, cb1) of 64 columns
 template <int L, int DIR, class C>
 void cols(const C *src, int src_row0, int y_lo, int y_hi, C *tmp, C *dst, int dst_row0, int k_lo,
-          int k_hi, int modulate, const C *tw, hipStream_t s) {
+          int k_hi, int modulate, const C *tw, hipStream_t s, int cb0 = 0, int cb1 = L / 64) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
-  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR, C>), dim3(L / 64, Q), dim3(256), 0, s, src, src_row0,
-                     y_lo, y_hi, tmp, tw);
-  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR, C>), dim3(L / 64, P), dim3(256), 0, s, tmp, dst,
-                     dst_row0, k_lo, k_hi, modulate, tw);
+  if (cb1 <= cb0) return;
+  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR, C>), dim3(cb1 - cb0, Q), dim3(256), 0, s, src,
+                     src_row0, y_lo, y_hi, tmp, tw, cb0);
+  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR, C>), dim3(cb1 - cb0, P), dim3(256), 0, s, tmp, dst,
+                     dst_row0, k_lo, k_hi, modulate, tw, cb0);
 }
 
+// the transforms touch only the box of grid cells the partition's chunk
+// windows cover: the de/gridding reads and the flush writes nothing else,
+// so the rest of the grid is never formed (model side) and is zero (residual
+// side)
 template <int L>
 void model_to_grid_t(imgr_s *h, const float *model, const float *model_add, const float *cinv,
-                     int n, float2 *rows, float2 *tmp, float2 *out, hipStream_t s) {
+                     int n, float2 *rows, float2 *tmp, float2 *out, const Box &b, hipStream_t s) {
   const int o = (L - n) / 2;
   hipLaunchKernelGGL((k_rows_model<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, model, model_add,
-                     cinv, n, rows, h->twrow);
-  cols<L, -1, float2>(rows, o, o, o + n, tmp, out, 0, 0, L, 1, h->tw, s);
+                     cinv, n, rows, h->twrow, b.x0, b.x1);
+  cols<L, -1, float2>(rows, o, o, o + n, tmp, out, 0, b.y0, b.y1, 1, h->tw, s, b.x0 / 64,
+                      b.x1 / 64);
 }
 
 template <int L>
 void grid_to_image_t(imgr_s *h, const float2 *in, const float *cinv, int n, float scale,
-                     float2 *rows, float2 *tmp, float *out, hipStream_t s) {
+                     float2 *rows, float2 *tmp, float *out, const Box &b, hipStream_t s) {
   const int o = (L - n) / 2;
-  cols<L, 1, float2>(in, 0, 0, L, tmp, rows, o, o, o + n, 0, h->tw, s);
+  cols<L, 1, float2>(in, 0, b.y0, b.y1, tmp, rows, o, o, o + n, 0, h->tw, s, b.x0 / 64,
+                     b.x1 / 64);
   hipLaunchKernelGGL((k_rows_image<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, rows, cinv, n,
-                     scale, out, h->twrow);
+                     scale, out, h->twrow, b.x0, b.x1);
 }
 
 template <int L, class C>
@@ -636,7 +649,7 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
                      n_in, work, twr);
   hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(CB, Q), dim3(256), 0, s, work, 0, 0, n_in,
-                     tmp, tw);
+                     tmp, tw, 0);
   if (mode == FILT_GAMMA)
     hipLaunchKernelGGL((k_cols_mid<P, Q, FILT_GAMMA, C>), dim3(CB, P), dim3(256), 0, s, tmp,
                        spec, h->ell, h->delta, gscale, own_low, coef, tw);
@@ -653,11 +666,19 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
 
 #define IMGR_FFT_SIZES(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
+static void check_box(const Box &b, int ng) {
+  IMGR_CHECK(b.x0 >= 0 && b.x0 <= b.x1 && b.x1 <= ng && b.x0 % 64 == 0 && b.x1 % 64 == 0 &&
+                 b.y0 >= 0 && b.y0 <= b.y1 && b.y1 <= ng,
+             "transform box outside the grid");
+}
+
 void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, const float *cinv,
-                       int n, int ng, float2 *rows, float2 *tmp, float2 *out, hipStream_t s) {
+                       int n, int ng, float2 *rows, float2 *tmp, float2 *out, const Box &box,
+                       hipStream_t s) {
+  check_box(box, ng);
   switch (ng) {
 #define X(L) \
-  case L: model_to_grid_t<L>(h, model, model_add, cinv, n, rows, tmp, out, s); break;
+  case L: model_to_grid_t<L>(h, model, model_add, cinv, n, rows, tmp, out, box, s); break;
     IMGR_FFT_SIZES(X)
 #undef X
     default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
@@ -666,10 +687,11 @@ void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, co
 }
 
 void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
-                       float2 *rows, float2 *tmp, float *out, hipStream_t s) {
+                       float2 *rows, float2 *tmp, float *out, const Box &box, hipStream_t s) {
+  check_box(box, ng);
   switch (ng) {
 #define X(L) \
-  case L: grid_to_image_t<L>(h, in, cinv, n, scale, rows, tmp, out, s); break;
+  case L: grid_to_image_t<L>(h, in, cinv, n, scale, rows, tmp, out, box, s); break;
     IMGR_FFT_SIZES(X)
 #undef X
     default: throw Error{IMGR_EINVAL, "unsupported FFT size"};

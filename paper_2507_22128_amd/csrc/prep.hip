@@ -432,6 +432,38 @@ double lower_median_rho(imgr_s *h, int64_t m, const double *rho, const uint8_t *
   return med;
 }
 
+// B.box from the blocks that hold visibilities: the union of their 16 x 16
+// windows (origin block origin - (W/2 - 1)), columns widened to multiples of
+// 64 and rows to multiples of 16; the whole grid when a window wraps
+void cover_box(imgr_s *h, Bins &B, hipStream_t s) {
+  const int n_blocks = B.nb * B.nb, blk = h->blk, H = h->W / 2 - 1, ng = B.ng;
+  std::vector<int32_t> bc(n_blocks + 1);
+  IMGR_HIP(hipMemcpyAsync(bc.data(), B.block_chunk, (n_blocks + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+  IMGR_HIP(hipStreamSynchronize(s));
+  int x0 = ng, x1 = 0, y0 = ng, y1 = 0;
+  bool wraps = false;
+  for (int b = 0; b < n_blocks; ++b) {
+    if (bc[b + 1] == bc[b]) continue;
+    const int wx = (b % B.nb) * blk - H, wy = (b / B.nb) * blk - H;
+    if (wx < 0 || wy < 0 || wx + kWin > ng || wy + kWin > ng) wraps = true;
+    x0 = std::min(x0, wx);
+    x1 = std::max(x1, wx + kWin);
+    y0 = std::min(y0, wy);
+    y1 = std::max(y1, wy + kWin);
+  }
+  Box box;
+  if (wraps) {
+    box = Box{0, ng, 0, ng};
+  } else if (x1 > x0) {
+    box.x0 = x0 / 64 * 64;
+    box.x1 = std::min(ng, (x1 + 63) / 64 * 64);
+    box.y0 = y0 / 16 * 16;
+    box.y1 = std::min(ng, (y1 + 15) / 16 * 16);
+  }
+  B.box = box;
+}
+
 // (re)build B.chunk_rows from the chunk table and the packed stream
 void chunk_rows(imgr_s *h, Bins &B, hipStream_t s) {
   dev_free(h, B.chunk_rows);
@@ -511,6 +543,7 @@ void bin_members(imgr_s *h, Bins &B, int64_t m, int64_t n, const int32_t *member
                        vis_dev, c128, w64, rank, blk, B.nb, B.posvis, B.w, B.orig, B.outpos);
   IMGR_HIP(hipGetLastError());
   chunk_rows(h, B, s);
+  cover_box(h, B, s);
   IMGR_HIP(hipStreamSynchronize(s));
   for (void *q : {(void *)keys, (void *)ktmp, (void *)vals, (void *)vtmp, (void *)cnt,
                   (void *)bstart, (void *)nch})
