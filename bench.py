@@ -33,8 +33,8 @@ FP32_PEAK_MATRIX = 157.3
 # (profiles/k_window_decentral_hbm_traffic.md), valid only for the kernel
 # source the counters were taken on.
 KWINDOW_TRAFFIC = {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
-                   "sha256_16": "5e0af2c049652809",
-                   "bytes_per_launch": (99139.3 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)}
+                   "sha256_16": "77d023a885a28790",
+                   "bytes_per_launch": (99263.4 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)}
 
 
 def measured_traffic():
