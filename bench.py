@@ -578,6 +578,11 @@ def main():
         "stage_ms_per_node_cycle": {k: round(v, 4) for k, v in stage_avg.items()},
         "stage_ms_per_node_cycle_concurrent": {k: round(v, 4) for k, v in stage_conc.items()},
         "cycle_hbm_frac": round(cycle_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the partitions' members summed (visibilities of the overlap ring counted in both)
+        "mvis_per_s_partition_sum": round((info.n_vis[0] + info.n_vis[1]) /
+                                          (ms_per_step / 1e3) / 1e6, 1),
+        # the fused degrid / residual / grid kernel alone, one launch per partition
+        "degrid_grid_kernel_mvis_per_s": round(m_avg / t_launch / 1e6, 1),
         "roofline": roofline,
     }
     if not args.no_minor_cycles:
