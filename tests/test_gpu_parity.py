@@ -10,8 +10,8 @@ agree bit for bit.
 import numpy as np
 import pytest
 
-from helpers import (decentral, imaging, oracle_weights, random_model, rel, say, to_dev,
-                     to_np, uv, workload)
+from helpers import (decentral, geometry, imaging, oracle_weights, random_model, rel, say,
+                     to_dev, to_np, uv, workload)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -325,5 +325,32 @@ def test_smallest_and_largest_image_sizes(n_pix):
         perr = np.abs(pgot - pref).max() / np.abs(pref).max()
         say("N = %d: residual max err %.3e, PSF max err %.3e" % (n, err, perr))
         assert err < TOL and perr < TOL
+    finally:
+        h.destroy()
+
+
+def test_windows_wrapping_the_grid_edge():
+    """A cell size that puts the outermost visibilities within half a support
+    of the grid's edge: their footprints wrap around (the oracle's gridding
+    takes cell indices modulo Ng), and the transforms and flush must cover the
+    whole grid instead of the box of the chunk windows."""
+    say("case: tiny array (6 time steps), N = 64, cell 0.499 / max |u|: footprints wrap")
+    d = workload("tiny", n_time=6)
+    u, v = uv(d)
+    cell = 0.499 / max(np.abs(u).max(), np.abs(v).max())
+    n = 64
+    h = _imager().Imager.create(uvw=d["uvw"], vis=d["vis"], freq_hz=d["freq_hz"], cell=cell,
+                                n_pix=n, n_partitions=1, weighting="uniform")
+    try:
+        w = imaging.uniform_weights(u, v, n, cell)
+        model = random_model(n, np.random.default_rng(41), n_points=8)
+        ref, _ = imaging.residual_image(u, v, d["vis"], w, model, cell)
+        got = to_np(h.major_cycle(0, to_dev(model)))
+        err = rel(got, ref)
+        g = geometry.grid_coord(u, 2 * n, cell)
+        say("max |grid coordinate - Ng/2| = %.2f of %d: residual rel err %.3e"
+            % (np.abs(g - n).max(), n, err))
+        assert np.abs(g - n).max() > n - 4  # some footprints cross the edge
+        assert err < TOL
     finally:
         h.destroy()
