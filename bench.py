@@ -438,7 +438,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build images on a single GPU; --gpus %d is not supported "
+        print("bench.py: the imager runs on a single GPU; --gpus %d is not supported "
               "(the two partitions run on one device)" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
 

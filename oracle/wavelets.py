@@ -1,7 +1,7 @@
 """Orthonormal Daubechies wavelets and the periodized 2-D transform W, FP64.
 
 The sparsity-regularised reconstruction (Section 4.1, Eqs. 4 and 5) uses a
-wavelet operator W; the configuration read for this build is the
+wavelet operator W; the configuration read here is the
 Daubechies wavelet with p = 8 vanishing moments (16 taps, extremal phase),
 3 levels, periodized boundaries, with the l1 norm on every coefficient.
 

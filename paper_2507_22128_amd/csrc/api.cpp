@@ -19,7 +19,7 @@ void *dev_alloc(imgr_s *h, size_t bytes) {
   if (h->caching) bytes = (bytes + 4095) & ~(size_t)4095;
   void *p = nullptr;
   if (h->caching) {
-    // a block freed earlier in this build, of the same size: its last user
+    // a block freed earlier during handle creation, of the same size: its last user
     // was enqueued on the same stream, so reuse is ordered after it
     for (size_t i = 0; i < h->cache.size(); ++i) {
       if (h->cache[i].second == bytes) {
