@@ -417,8 +417,8 @@ def serving(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="decentral")
     ap.add_argument("--cpu-sample-times", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -484,20 +484,30 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    h.set_timing(True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    # the timed steps: nothing but the steps between the two synchronizations
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the same number of steps again with an event pair around each (p50 / p99 of
+    # the per-step device time), then again with the handle's stage events
+    # (per-stage breakdown); both add event packets to the streams, so neither
+    # is part of the timed steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     for k in range(args.steps):
         ev[k][0].record()
         step()
         ev[k][1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    cycles, stage_ms = h.get_timing()
     per_step = sorted(a.elapsed_time(b) for a, b in ev)
+    h.set_timing(True)
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    cycles, stage_ms = h.get_timing()
     ms_per_step = 1e3 * wall / args.steps
     n_valid = info.n_valid
     value = n_valid / (ms_per_step / 1e3) / 1e6
