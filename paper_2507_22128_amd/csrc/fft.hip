@@ -367,7 +367,12 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
 // and a real-output row pass.
 
 // rows r < gridDim.x: (a - b) (n_in real values, zero padded to L) -> plain
-// forward row DFT -> out[r][0..L)
+// forward row DFT -> out[r][0..CH): the column passes that follow read only
+// the column blocks holding frequencies 0 .. L / 2 (the row is Hermitian)
+template <int L>
+constexpr int half_spectrum_cols() {
+  return ((L / 2) / 64 + 1) * 64 < L ? ((L / 2) / 64 + 1) * 64 : L;
+}
 template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
     const typename Real<C>::T *__restrict__ a, const typename Real<C>::T *__restrict__ b,
@@ -398,7 +403,8 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1, C>(s, twl, threadIdx.x);
-  for (int x = threadIdx.x; x < L; x += NT) out[(size_t)r * L + x] = s[padi(x)];
+  for (int x = threadIdx.x; x < half_spectrum_cols<L>(); x += NT)
+    out[(size_t)r * L + x] = s[padi(x)];
 }
 
 // rows r < gridDim.x: inverse plain row DFT of in[r][0..L), then
@@ -643,7 +649,7 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
   // spectral factors keep it so: the column passes only need the column
   // blocks that hold frequencies 0 .. L / 2; the final row pass rebuilds
   // the rest by conjugate symmetry
-  constexpr int CB = (L / 2) / 64 + 1 < L / 64 ? (L / 2) / 64 + 1 : L / 64;
+  constexpr int CB = half_spectrum_cols<L>() / 64;
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
