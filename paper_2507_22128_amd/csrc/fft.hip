@@ -367,8 +367,9 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
 // and a real-output row pass.
 
 // rows r < gridDim.x: (a - b) (n_in real values, zero padded to L) -> plain
-// forward row DFT -> out[r][0..CH): the column passes that follow read only
-// the column blocks holding frequencies 0 .. L / 2 (the row is Hermitian)
+// forward row DFT -> out[r][0..c_hi): the column passes that follow read
+// only the column blocks holding frequencies 0 .. L / 2 (the row is
+// Hermitian), fewer when the spectral factor vanishes beyond a frequency
 template <int L>
 constexpr int half_spectrum_cols() {
   return ((L / 2) / 64 + 1) * 64 < L ? ((L / 2) / 64 + 1) * 64 : L;
@@ -376,7 +377,7 @@ constexpr int half_spectrum_cols() {
 template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
     const typename Real<C>::T *__restrict__ a, const typename Real<C>::T *__restrict__ b,
-    int n_in, C *__restrict__ out, const C *__restrict__ twr) {
+    int n_in, C *__restrict__ out, const C *__restrict__ twr, int c_hi) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
@@ -403,16 +404,15 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1, C>(s, twl, threadIdx.x);
-  for (int x = threadIdx.x; x < half_spectrum_cols<L>(); x += NT)
-    out[(size_t)r * L + x] = s[padi(x)];
+  for (int x = threadIdx.x; x < c_hi; x += NT) out[(size_t)r * L + x] = s[padi(x)];
 }
 
-// rows r < gridDim.x: inverse plain row DFT of in[r][0..L), then
-// out[r][c] (+)= Re s[col0 + c] for c < n_out
+// rows r < gridDim.x: inverse plain row DFT of in[r][0..L) (columns x and
+// L - x at or above c_hi zero), then out[r][c] (+)= Re s[col0 + c], c < n_out
 template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
     const C *__restrict__ in, int col0, int n_out, typename Real<C>::T *__restrict__ out,
-    int accumulate, const C *__restrict__ twr) {
+    int accumulate, const C *__restrict__ twr, int c_hi) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
@@ -426,7 +426,8 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int x = threadIdx.x + q * NT;
-      v[q] = in[(size_t)r * L + (x <= L / 2 ? x : L - x)];
+      const int xs = x <= L / 2 ? x : L - x;  // columns from c_hi on are zero
+      v[q] = xs < c_hi ? in[(size_t)r * L + xs] : mkc<C>(0, 0);
     }
     stage_twiddles<L, NT, C>(twl, twr);
 #pragma unroll
@@ -649,11 +650,16 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
   // spectral factors keep it so: the column passes only need the column
   // blocks that hold frequencies 0 .. L / 2; the final row pass rebuilds
   // the rest by conjugate symmetry
-  constexpr int CB = half_spectrum_cols<L>() / 64;
+  int CB = half_spectrum_cols<L>() / 64;
+  // Gamma_L (own_low odd) vanishes for |kx| >= (ell + delta) scale: the column
+  // blocks from there on are zero after the product, so they are never formed
+  if (mode == FILT_GAMMA && (own_low & 1))
+    CB = std::min(CB, std::max(1, (int)std::ceil((h->ell + h->delta) * gscale / 64.0)));
+  const int c_hi = CB * 64;
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
-                     n_in, work, twr);
+                     n_in, work, twr, c_hi);
   hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(CB, Q), dim3(256), 0, s, work, 0, 0, n_in,
                      tmp, tw, 0);
   if (mode == FILT_GAMMA)
@@ -665,7 +671,7 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
   hipLaunchKernelGGL((k_cols_fin<P, Q, C>), dim3(CB, Q), dim3(256), 0, s, tmp, work, k_lo,
                      k_hi, tw);
   hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
-                     work, col0, n_out, out, accumulate, twr);
+                     work, col0, n_out, out, accumulate, twr, c_hi);
 }
 
 }  // namespace
