@@ -196,44 +196,61 @@ static void check_cycle_args(imgr_s *h, int part, const float *model, const floa
 }
 
 // One node's major cycle (Eq. 2 then Eq. 7) enqueued on stream s with the
-// node's own work buffers; stage events are recorded on s when timing is on.
+// node's own work buffers, stage by stage (node_stage); stage events are
+// recorded on s when timing is on.
+NodeCall node_begin(imgr_s *h, int part, const float *model, const float *rho_other,
+                    double gamma, double mu, float *residual_out, float *residual_local_out,
+                    int flags, hipStream_t s) {
+  NodeCall c{part, model, rho_other, gamma, mu, residual_out,
+             residual_local_out ? residual_local_out : h->work[part].img, flags, s, -1};
+  if (h->timing) {
+    c.ev_set = (int)h->ev_sets.size();
+    h->ev_sets.emplace_back();
+    for (int k = 0; k <= IMGR_N_STAGES; ++k) h->ev_sets.back().push_back(take_event(h));
+    IMGR_HIP(hipEventRecord(h->ev_sets[c.ev_set][0], s));
+  }
+  return c;
+}
+
+void node_stage(imgr_s *h, const NodeCall &c, int stage) {
+  const Partition &P = h->part[c.part];
+  Work &wk = h->work[c.part];
+  hipStream_t s = c.s;
+  switch (stage) {
+    case 0:  // a1: model -> model grid
+      fft_model_to_grid(h, c.model, (c.flags & IMGR_DEGRID_COMPOSITE) ? c.rho_other : nullptr,
+                        h->cinv, h->N, h->Ng, wk.rows, wk.grid_b, wk.grid_a, P.bins.box, s);
+      break;
+    case 1:  // a2 + a3: degrid, residual, grid (one pass per chunk)
+      degrid_grid(h, P.bins, MODE_DEGRID_GRID, wk.grid_a, nullptr, nullptr, wk.scratch, s);
+      break;
+    case 2:  // flush of the chunk windows
+      flush_chunks(h, P.bins, wk.scratch, wk.grid_a, s);
+      break;
+    case 3:  // a4: residual grid -> residual image
+      fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), wk.rows,
+                        wk.grid_b, c.local, P.bins.box, s);
+      break;
+    case 4:  // a6: pseudo-full-resolution composition
+      if (h->n_parts == 2) {
+        compose(h, c.part, c.local, c.rho_other, c.gamma, c.mu, c.residual_out, s);
+      } else if (c.residual_out != c.local) {
+        IMGR_HIP(hipMemcpyAsync(c.residual_out, c.local, (size_t)h->N * h->N * sizeof(float),
+                                hipMemcpyDeviceToDevice, s));
+      }
+      break;
+    default:
+      throw Error{IMGR_EINVAL, "unknown cycle stage"};
+  }
+  if (c.ev_set >= 0) IMGR_HIP(hipEventRecord(h->ev_sets[c.ev_set][stage + 1], s));
+}
+
 void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other,
                        double gamma, double mu, float *residual_out, float *residual_local_out,
                        int flags, hipStream_t s) {
-  const Partition &P = h->part[part];
-  Work &wk = h->work[part];
-  float *local = residual_local_out ? residual_local_out : wk.img;
-  std::vector<hipEvent_t> *ev = nullptr;
-  if (h->timing) {
-    h->ev_sets.emplace_back();
-    ev = &h->ev_sets.back();
-    for (int k = 0; k <= IMGR_N_STAGES; ++k) ev->push_back(take_event(h));
-  }
-  auto mark = [&](int k) {
-    if (ev) IMGR_HIP(hipEventRecord((*ev)[k], s));
-  };
-  mark(0);
-  // a1: model -> model grid
-  fft_model_to_grid(h, model, (flags & IMGR_DEGRID_COMPOSITE) ? rho_other : nullptr, h->cinv, h->N,
-                    h->Ng, wk.rows, wk.grid_b, wk.grid_a, P.bins.box, s);
-  mark(1);
-  // a2 + a3: degrid, residual, grid (one pass per chunk), flush
-  degrid_grid(h, P.bins, MODE_DEGRID_GRID, wk.grid_a, nullptr, nullptr, wk.scratch, s);
-  mark(2);
-  flush_chunks(h, P.bins, wk.scratch, wk.grid_a, s);
-  mark(3);
-  // a4: residual grid -> residual image
-  fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), wk.rows,
-                    wk.grid_b, local, P.bins.box, s);
-  mark(4);
-  // a6: pseudo-full-resolution composition
-  if (h->n_parts == 2) {
-    compose(h, part, local, rho_other, gamma, mu, residual_out, s);
-  } else if (residual_out != local) {
-    IMGR_HIP(hipMemcpyAsync(residual_out, local, (size_t)h->N * h->N * sizeof(float),
-                            hipMemcpyDeviceToDevice, s));
-  }
-  mark(5);
+  const NodeCall c = node_begin(h, part, model, rho_other, gamma, mu, residual_out,
+                                residual_local_out, flags, s);
+  for (int stage = 0; stage < IMGR_N_STAGES; ++stage) node_stage(h, c, stage);
 }
 
 // re-cut every partition's chunks for cap C and grow the chunk-window
@@ -619,14 +636,22 @@ imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
     node_cycle(h, 0, model[0], ro(0), gamma[0], mu[0], residual_out[0], lo(0), flags, h->stream);
   } else {
     // fork both nodes off the caller's stream, join them back into it
+    // the two nodes' stages are enqueued alternately, so both streams have
+    // work from the start (enqueueing one node's whole cycle first would hold
+    // the other back by the host's launch time)
     IMGR_HIP(hipEventRecord(h->ev_fork, h->stream));
+    NodeCall c[2];
     for (int p = 0; p < 2; ++p) {
       IMGR_HIP(hipStreamWaitEvent(h->node_stream[p], h->ev_fork, 0));
-      node_cycle(h, p, model[p], ro(p), gamma[p], mu[p], residual_out[p], lo(p), flags,
-                 h->node_stream[p]);
-      IMGR_HIP(hipEventRecord(h->ev_join[p], h->node_stream[p]));
+      c[p] = node_begin(h, p, model[p], ro(p), gamma[p], mu[p], residual_out[p], lo(p), flags,
+                        h->node_stream[p]);
     }
-    for (int p = 0; p < 2; ++p) IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[p], 0));
+    for (int stage = 0; stage < IMGR_N_STAGES; ++stage)
+      for (int p = 0; p < 2; ++p) node_stage(h, c[p], stage);
+    for (int p = 0; p < 2; ++p) {
+      IMGR_HIP(hipEventRecord(h->ev_join[p], h->node_stream[p]));
+      IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[p], 0));
+    }
   }
   API_END(h)
 }

@@ -210,6 +210,23 @@ void prep_build(imgr_s *h, const imgr_vis *vis);
 void free_bins(imgr_s *h, Bins &B);
 // rechunk every partition of h for cap C (imager_set_chunk)
 void set_chunk(imgr_s *h, int C);
+// one node's major cycle: its arguments, and the index of its stage-event set
+// (-1 without timing)
+struct NodeCall {
+  int part;
+  const float *model, *rho_other;
+  double gamma, mu;
+  float *residual_out, *local;
+  int flags;
+  hipStream_t s;
+  int ev_set;
+};
+NodeCall node_begin(imgr_s *h, int part, const float *model, const float *rho_other,
+                    double gamma, double mu, float *residual_out, float *residual_local_out,
+                    int flags, hipStream_t s);
+// enqueue stage 0 .. IMGR_N_STAGES - 1 of the cycle (model transform,
+// de/gridding, flush, inverse transform, composition)
+void node_stage(imgr_s *h, const NodeCall &c, int stage);
 // one node's major cycle enqueued on s (imager_major_cycle)
 void node_cycle(imgr_s *h, int part, const float *model, const float *rho_other, double gamma,
                 double mu, float *residual_out, float *residual_local_out, int flags,
