@@ -231,7 +231,8 @@ void node_stage(imgr_s *h, const NodeCall &c, int stage) {
       fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / P.sum_w), wk.rows,
                         wk.grid_b, c.local, P.bins.box, s);
       break;
-    case 4:  // a6: pseudo-full-resolution composition
+    case 4:  // a6: pseudo-full-resolution composition (none without an output)
+      if (!c.residual_out) break;
       if (h->n_parts == 2) {
         compose(h, c.part, c.local, c.rho_other, c.gamma, c.mu, c.residual_out, s);
       } else if (c.residual_out != c.local) {
@@ -731,6 +732,8 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
                       nullptr, nullptr, s);
     } else {
       IMGR_HIP(hipEventRecord(h->ev_fork, h->stream));
+      // the major cycles of both nodes, their stages enqueued alternately
+      NodeCall nc[2];
       for (int k = 0; k < 2; ++k) {
         hipStream_t s = h->node_stream[k];
         IMGR_HIP(hipStreamWaitEvent(s, h->ev_fork, 0));
@@ -738,7 +741,13 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
         // then the partitions' shares of the summed imaging weights
         const double gamma = (cyc == 1) ? 1.0 : h->part[k].sum_w / wsum;
         const double mu = (cyc == 1) ? 0.0 : h->part[1 - k].sum_w / wsum;
-        node_cycle(h, k, model[k], rho[k], gamma, mu, h->loop_dirty[k], nullptr, 0, s);
+        nc[k] = node_begin(h, k, model[k], rho[k], gamma, mu, h->loop_dirty[k], nullptr, 0, s);
+      }
+      for (int stage = 0; stage < IMGR_N_STAGES; ++stage)
+        for (int k = 0; k < 2; ++k) node_stage(h, nc[k], stage);
+      for (int k = 0; k < 2; ++k) {
+        hipStream_t s = h->node_stream[k];
+        const double gamma = nc[k].gamma, mu = nc[k].mu;
         composed_psf(h, k, gamma, mu, h->loop_psf[k], s);
         imgr_msclean_params q = p;
         if (cyc == 1) q.active_mask = (p.active_mask ? p.active_mask : ~0u) &
@@ -828,11 +837,18 @@ imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fist
       q.serial = 0;
       q.gamma_n = (cyc == 1) ? 0.0 : 1.0;  // Eq. 5
       IMGR_HIP(hipEventRecord(h->ev_fork, h->stream));
+      // the node's own residual i~ (Eq. 2) on both nodes, stages enqueued
+      // alternately; the composition is not used here
+      NodeCall nc[2];
+      for (int k = 0; k < 2; ++k) {
+        IMGR_HIP(hipStreamWaitEvent(h->node_stream[k], h->ev_fork, 0));
+        nc[k] = node_begin(h, k, model[k], nullptr, 1.0, 0.0, nullptr, h->loop_dirty[k], 0,
+                           h->node_stream[k]);
+      }
+      for (int stage = 0; stage < IMGR_N_STAGES; ++stage)
+        for (int k = 0; k < 2; ++k) node_stage(h, nc[k], stage);
       for (int k = 0; k < 2; ++k) {
         hipStream_t s = h->node_stream[k];
-        IMGR_HIP(hipStreamWaitEvent(s, h->ev_fork, 0));
-        // the node's own residual i~ (Eq. 2); the composition is not used here
-        node_cycle(h, k, model[k], nullptr, 1.0, 0.0, h->loop_psf[k], h->loop_dirty[k], 0, s);
         fista_enqueue(h, k, q, h->loop_dirty[k], rho[k], power_start[k], h->loop_delta[k],
                       model[k], nullptr, s);
         IMGR_HIP(hipEventRecord(h->ev_join[k], s));
