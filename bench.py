@@ -226,26 +226,32 @@ def convex(args):
                             "30 power iterations, lambda = 1e-3 max |i~|, FP64 transforms"}
 
 
-def batched_channels(args):
+def batched_channels(args, small=False):
     """Batched-channel workload: the major cycle (Eq. 2) of every channel of
     a 64-channel observation (0.95 - 1.75 GHz, 256 antennas, 480 times,
     flags 0-60 % per channel, images 512 / 1024 / 2048), one partition per
-    channel.  Support from the 1e-5 accuracy rule, tile and chunk cap from
-    the create-time autotuner on the largest channel, then the chunk cap
-    re-tuned over the fused launch.  Times the fused batch as a replayed HIP
-    graph, the same eagerly, and the per-channel launch loop."""
+    channel; with ``small``, 256 short channels of the same array (16 times,
+    images 256 / 512), where one channel's launch cannot fill the chip.
+    Support from the 1e-5 accuracy rule, tile and chunk cap from the
+    create-time autotuner on the largest channel, then the chunk cap re-tuned
+    over the fused launch.  Times the fused batch as a replayed HIP graph,
+    the same eagerly, and the per-channel launch loop."""
     import numpy as np
     import torch
     from paper_2507_22128_amd import imager, synth
     t0 = time.perf_counter()
     cfg = dict(synth.CHANNELS)
-    cfg["n_chan"] = args.batch_channels
+    if small:
+        cfg.update(n_chan=args.batch_small_channels, n_time=16, sizes=(256, 512))
+    else:
+        cfg["n_chan"] = args.batch_channels
     d = synth.make_channels(device="cuda", **cfg)
     torch.cuda.synchronize()
     chans = d["channels"]
     n_ok = [int((c["flag"] == 0).sum().item()) for c in chans]
-    log("batch: %d channels generated in %.1f s, %d - %d unflagged visibilities per channel"
-        % (len(chans), time.perf_counter() - t0, min(n_ok), max(n_ok)))
+    tag = "batch (small channels)" if small else "batch"
+    log("%s: %d channels generated in %.1f s, %d - %d unflagged visibilities per channel"
+        % (tag, len(chans), time.perf_counter() - t0, min(n_ok), max(n_ok)))
 
     def mk(c, **kw):
         return imager.Imager.create(uvw=d["uvw"], vis=c["vis"], freq_hz=c["freq_hz"],
@@ -268,8 +274,8 @@ def batched_channels(args):
     b = imager.Batch(members)
     chosen, cap_ms = b.autotune()
     info = b.info()
-    log("batch: %d members created in %.1f s (support %d, tile %d from the create tuner), "
-        "chunk cap %d from the batch tuner %s" % (len(members), create_s, i0.support, i0.tile,
+    log("%s: %d members created in %.1f s (support %d, tile %d from the create tuner), "
+        "chunk cap %d from the batch tuner %s" % (tag, len(members), create_s, i0.support, i0.tile,
                                                  chosen, cap_ms))
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
@@ -296,8 +302,8 @@ def batched_channels(args):
         out[name] = {"ms_per_cycle": round(ms, 3),
                      "mvis_per_s": round(info.n_vis / (ms / 1e3) / 1e6, 1)}
         last[name] = [r.clone() for r in res]
-        log("batch %s: %.3f ms per cycle of all channels, %.0f Mvis/s"
-            % (name, ms, info.n_vis / (ms / 1e3) / 1e6))
+        log("%s %s: %.3f ms per cycle of all channels, %.0f Mvis/s"
+            % (tag, name, ms, info.n_vis / (ms / 1e3) / 1e6))
     same = all(torch.equal(a, c) for a, c in zip(last["fused_graph"], last["per_channel_loop"]))
     sizes = [m.n_pix for m in members]
     t_win = cap_ms[chosen] / 1e3
@@ -426,6 +432,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-convex", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=64)
+    ap.add_argument("--batch-small-channels", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16)
@@ -602,6 +609,7 @@ def main():
         res["convex"] = convex(args)
     if not args.no_batch:
         res["batched_channels"] = batched_channels(args)
+        res["batched_small_channels"] = batched_channels(args, small=True)
     if not args.no_serve:
         res["serving"] = serving(args)
     if not args.no_cpu_baseline:
