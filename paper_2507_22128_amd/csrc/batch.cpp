@@ -43,6 +43,16 @@ struct imgr_batch_s {
     int g0, g1, slot0, n_slots, gs0, n_groups;
   };
   std::vector<Set> sets;
+  // members of one set with one grid and image side: their model / residual
+  // transforms run as one batched launch per pass, arguments in
+  // d_fft[off .. off + count) (member pointers of the last call)
+  struct FftGroup {
+    int set, ng, n, off, count, max_cb;
+    std::vector<int> members;
+  };
+  std::vector<FftGroup> fft_groups;
+  imgr::FftMember *d_fft = nullptr;
+  std::vector<const void *> fft_key;  // model / residual pointers d_fft was filled for
   int64_t n_vis = 0;
   std::vector<uint64_t> versions;  // member layout versions the tables were built for
   // captured graph and the pointers it was captured with
@@ -65,12 +75,15 @@ void free_graph(imgr_batch_s *b) {
 }
 
 void free_tables(imgr_batch_s *b) {
-  for (void *q : {(void *)b->d_win, (void *)b->d_flush, (void *)b->d_order, (void *)b->d_gstart})
+  for (void *q : {(void *)b->d_win, (void *)b->d_flush, (void *)b->d_order, (void *)b->d_gstart,
+                  (void *)b->d_fft})
     if (q) (void)hipFree(q);
   b->d_win = nullptr;
   b->d_flush = nullptr;
   b->d_order = nullptr;
   b->d_gstart = nullptr;
+  b->d_fft = nullptr;
+  b->fft_key.clear();
 }
 
 template <typename T>
@@ -144,6 +157,33 @@ void build_tables(imgr_batch_s *b) {
   b->n_slots = (int)order.size();
   b->n_groups = 0;
   for (const imgr_batch_s::Set &st : b->sets) b->n_groups += st.n_groups;
+  // transform groups: per set, members of equal (Ng, N) in member order
+  b->fft_groups.clear();
+  int off = 0;
+  for (int si = 0; si < (int)b->sets.size(); ++si) {
+    const imgr_batch_s::Set &st = b->sets[si];
+    const size_t first = b->fft_groups.size();
+    for (int g = st.g0; g < st.g1; ++g) {
+      imgr_s *h = b->m[g];
+      const Box &box = h->part[0].bins.box;
+      imgr_batch_s::FftGroup *grp = nullptr;
+      for (size_t k = first; k < b->fft_groups.size(); ++k)
+        if (b->fft_groups[k].ng == h->Ng && b->fft_groups[k].n == h->N) grp = &b->fft_groups[k];
+      if (!grp) {
+        b->fft_groups.push_back({si, h->Ng, h->N, 0, 0, 0, {}});
+        grp = &b->fft_groups.back();
+      }
+      grp->members.push_back(g);
+      grp->max_cb = std::max(grp->max_cb, (box.x1 - box.x0) / 64);
+    }
+    for (size_t k = first; k < b->fft_groups.size(); ++k) {
+      b->fft_groups[k].off = off;
+      b->fft_groups[k].count = (int)b->fft_groups[k].members.size();
+      off += b->fft_groups[k].count;
+    }
+  }
+  IMGR_HIP(hipMalloc((void **)&b->d_fft, std::max(off, 1) * sizeof(FftMember)));
+  b->fft_key.clear();
   b->d_win = upload(win, s);
   b->d_flush = upload(fl, s);
   b->d_order = upload(order, s);
@@ -172,22 +212,44 @@ void fused_window(imgr_batch_s *b, hipStream_t s) {
   for (const imgr_batch_s::Set &st : b->sets) fused_set(b, st, s);
 }
 
-void enqueue_cycle(imgr_batch_s *b, const float *const *model, float *const *residual,
-                   hipStream_t s) {
-  for (const imgr_batch_s::Set &st : b->sets) {
-    for (int g = st.g0; g < st.g1; ++g) {
+// the transform arguments of every member for the model / residual
+// pointers of this call (uploaded when they change; the stream is drained
+// first, since earlier cycles may still read the table)
+void fill_fft_table(imgr_batch_s *b, const float *const *model, float *const *residual) {
+  const int n = (int)b->m.size();
+  std::vector<const void *> key(2 * n);
+  for (int g = 0; g < n; ++g) {
+    key[g] = model[g];
+    key[n + g] = residual[g];
+  }
+  if (key == b->fft_key) return;
+  std::vector<FftMember> tab;
+  for (const imgr_batch_s::FftGroup &grp : b->fft_groups)
+    for (int g : grp.members) {
       imgr_s *h = b->m[g];
       Work &wk = h->work[0];
-      fft_model_to_grid(h, model[g], nullptr, h->cinv, h->N, h->Ng, wk.rows, wk.grid_b,
-                        wk.grid_a, h->part[0].bins.box, s);
+      const Box &box = h->part[0].bins.box;
+      tab.push_back(FftMember{model[g], residual[g], wk.rows, wk.grid_b, wk.grid_a, h->cinv,
+                              (float)(1.0 / h->part[0].sum_w), box.x0, box.x1, box.y0, box.y1});
     }
-    fused_set(b, st, s);
-    for (int g = st.g0; g < st.g1; ++g) {
-      imgr_s *h = b->m[g];
-      Work &wk = h->work[0];
-      fft_grid_to_image(h, wk.grid_a, h->cinv, h->N, h->Ng, (float)(1.0 / h->part[0].sum_w),
-                        wk.rows, wk.grid_b, residual[g], h->part[0].bins.box, s);
-    }
+  IMGR_HIP(hipStreamSynchronize(b->stream));
+  if (!tab.empty())
+    IMGR_HIP(hipMemcpy(b->d_fft, tab.data(), tab.size() * sizeof(FftMember),
+                       hipMemcpyHostToDevice));
+  b->fft_key = key;
+}
+
+void enqueue_cycle(imgr_batch_s *b, hipStream_t s) {
+  for (int si = 0; si < (int)b->sets.size(); ++si) {
+    for (const imgr_batch_s::FftGroup &grp : b->fft_groups)
+      if (grp.set == si)
+        fft_model_to_grid_batch(b->m[grp.members[0]], grp.ng, grp.n, b->d_fft + grp.off,
+                                grp.count, grp.max_cb, s);
+    fused_set(b, b->sets[si], s);
+    for (const imgr_batch_s::FftGroup &grp : b->fft_groups)
+      if (grp.set == si)
+        fft_grid_to_image_batch(b->m[grp.members[0]], grp.ng, grp.n, b->d_fft + grp.off,
+                                grp.count, grp.max_cb, s);
   }
 }
 
@@ -307,8 +369,9 @@ imgr_status imager_batch_major_cycle(imgr_batch_t b, const float *const *model,
       node_cycle(b->m[g], 0, model[g], nullptr, 1.0, 0.0, residual[g], residual[g], 0, b->stream);
     return IMGR_OK;
   }
+  fill_fft_table(b, model, residual);
   if (!(flags & IMGR_BATCH_GRAPH)) {
-    enqueue_cycle(b, model, residual, b->stream);
+    enqueue_cycle(b, b->stream);
     return IMGR_OK;
   }
   std::vector<const void *> key(2 * n);
@@ -320,7 +383,7 @@ imgr_status imager_batch_major_cycle(imgr_batch_t b, const float *const *model,
     free_graph(b);
     IMGR_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     try {
-      enqueue_cycle(b, model, residual, b->cap_stream);
+      enqueue_cycle(b, b->cap_stream);
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(b->cap_stream, &g);

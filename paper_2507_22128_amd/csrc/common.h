@@ -249,6 +249,25 @@ void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, co
                        hipStream_t s);
 // centred inverse transform of the Ng x Ng grid `in` (already multiplied by
 // (-1)^(gx+gy)) cropped to N x N, times (-1)^(px+py)/psi_hat^2 * scale, real part
+// One member's model and residual transforms in a batched launch (members of
+// one grid side Ng and image side N): model -> rows -> tmp -> grid on the
+// model side, grid -> tmp -> rows -> image on the residual side, over the
+// member's covered box.
+struct FftMember {
+  const float *model;  // N x N model image
+  float *image;        // N x N residual image
+  float2 *rows, *tmp, *grid;
+  const float *cinv;   // gridding correction (N)
+  float scale;         // residual image scale (1 / sum of weights)
+  int x0, x1, y0, y1;  // covered box
+};
+// the model / residual transforms of `count` members (device table) in one
+// launch per pass; max_cb: the most 64-column blocks of any member's box;
+// h supplies the twiddle tables (equal for every handle)
+void fft_model_to_grid_batch(const imgr_s *h, int ng, int n, const FftMember *members, int count,
+                             int max_cb, hipStream_t s);
+void fft_grid_to_image_batch(const imgr_s *h, int ng, int n, const FftMember *members, int count,
+                             int max_cb, hipStream_t s);
 // (box: the cells of `in` that the flush wrote; the rest is taken as zero)
 void fft_grid_to_image(imgr_s *h, const float2 *in, const float *cinv, int n, int ng, float scale,
                        float2 *rows, float2 *tmp, float *out, const Box &box, hipStream_t s);

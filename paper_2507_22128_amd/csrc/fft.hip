@@ -174,14 +174,15 @@ struct RowThreads {
 // model (n x n f32) [+ model_add] -> rows (n x L complex): correction 1/psi on
 // both axes, centred zero-padding, (-1)^(x+y) modulation, forward row DFT.
 template <int L>
-__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
-    const float *__restrict__ model, const float *__restrict__ model_add,
-    const float *__restrict__ cinv, int n, float2 *__restrict__ rows,
-    const float2 *__restrict__ twr, int c_lo, int c_hi) {
+__device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
+                                                const float *__restrict__ model_add,
+                                                const float *__restrict__ cinv, int n,
+                                                float2 *__restrict__ rows,
+                                                const float2 *__restrict__ twr, int c_lo,
+                                                int c_hi, int r) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
   const float cy = cinv[r];
@@ -219,17 +220,26 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
   for (int x = c_lo + threadIdx.x; x < c_hi; x += NT) rows[(size_t)r * L + x] = s[padi(x)];
 }
 
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model(
+    const float *__restrict__ model, const float *__restrict__ model_add,
+    const float *__restrict__ cinv, int n, float2 *__restrict__ rows,
+    const float2 *__restrict__ twr, int c_lo, int c_hi) {
+  rows_model_body<L>(model, model_add, cinv, n, rows, twr, c_lo, c_hi, blockIdx.x);
+}
+
 // rows (n x L complex) -> image (n x n f32): inverse row DFT, crop of the
 // centre, (-1)^(x+y), correction 1/psi on both axes, real part, scale.
 // Columns outside [c_lo, c_hi) are zero and not read.
 template <int L>
-__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
-    const float2 *__restrict__ rows, const float *__restrict__ cinv, int n, float scale,
-    float *__restrict__ out, const float2 *__restrict__ twr, int c_lo, int c_hi) {
+__device__ __forceinline__ void rows_image_body(const float2 *__restrict__ rows,
+                                                const float *__restrict__ cinv, int n,
+                                                float scale, float *__restrict__ out,
+                                                const float2 *__restrict__ twr, int c_lo,
+                                                int c_hi, int r) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
-  const int r = blockIdx.x;
   const int o = (L - n) / 2;
   const int y = o + r;
   {
@@ -253,6 +263,13 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
     if ((x + y) & 1) v = -v;
     out[(size_t)r * n + ix] = v * cinv[ix] * cy;
   }
+}
+
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image(
+    const float2 *__restrict__ rows, const float *__restrict__ cinv, int n, float scale,
+    float *__restrict__ out, const float2 *__restrict__ twr, int c_lo, int c_hi) {
+  rows_image_body<L>(rows, cinv, n, scale, out, twr, c_lo, c_hi, blockIdx.x);
 }
 
 // plain in-place complex row DFTs of an L x L buffer
@@ -287,14 +304,12 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
 // stored at dst row (k - dst_row0), optionally times (-1)^(k + x).
 
 template <int P, int Q, int DIR, class C>
-__global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int src_row0,
-                                                 int y_lo, int y_hi, C *__restrict__ dst,
-                                                 const C *__restrict__ tw, int cb0) {
+__device__ __forceinline__ void cols_p1_body(const C *__restrict__ src, int src_row0, int y_lo,
+                                             int y_hi, C *__restrict__ dst,
+                                             const C *__restrict__ tw, int x0, int y2) {
   constexpr int L = P * Q;
   __shared__ C s[P * 64];
   const int t = threadIdx.x;
-  const int x0 = (blockIdx.x + cb0) * 64;
-  const int y2 = blockIdx.y;
   {
     // every load of the thread goes out before the first is used
     constexpr int PER = P * 64 / 256;
@@ -326,15 +341,20 @@ __global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int 
 }
 
 template <int P, int Q, int DIR, class C>
-__global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
-                                                 C *__restrict__ dst, int dst_row0, int k_lo,
-                                                 int k_hi, int modulate,
+__global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int src_row0,
+                                                 int y_lo, int y_hi, C *__restrict__ dst,
                                                  const C *__restrict__ tw, int cb0) {
+  cols_p1_body<P, Q, DIR, C>(src, src_row0, y_lo, y_hi, dst, tw, (blockIdx.x + cb0) * 64,
+                             blockIdx.y);
+}
+
+template <int P, int Q, int DIR, class C>
+__device__ __forceinline__ void cols_p2_body(const C *__restrict__ src, C *__restrict__ dst,
+                                             int dst_row0, int k_lo, int k_hi, int modulate,
+                                             const C *__restrict__ tw, int x0, int k1) {
   constexpr int L = P * Q;
   __shared__ C s[Q * 64];
   const int t = threadIdx.x;
-  const int x0 = (blockIdx.x + cb0) * 64;
-  const int k1 = blockIdx.y;
   {
     constexpr int PER = Q * 64 / 256;
     C v[PER];
@@ -357,6 +377,65 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
       dst[(size_t)(k - dst_row0) * L + x0 + c] = v;
     }
   }
+}
+
+template <int P, int Q, int DIR, class C>
+__global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
+                                                 C *__restrict__ dst, int dst_row0, int k_lo,
+                                                 int k_hi, int modulate,
+                                                 const C *__restrict__ tw, int cb0) {
+  cols_p2_body<P, Q, DIR, C>(src, dst, dst_row0, k_lo, k_hi, modulate, tw,
+                             (blockIdx.x + cb0) * 64, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- batched transforms
+// The model / residual transforms of many members (same L and N) per launch:
+// the member is the last grid dimension; blocks past a member's own row or
+// column-block count return at once.
+
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_model_batch(
+    const FftMember *__restrict__ m, int n, const float2 *__restrict__ twr) {
+  const FftMember &a = m[blockIdx.y];
+  rows_model_body<L>(a.model, nullptr, a.cinv, n, a.rows, twr, a.x0, a.x1, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_image_batch(
+    const FftMember *__restrict__ m, int n, const float2 *__restrict__ twr) {
+  const FftMember &a = m[blockIdx.y];
+  rows_image_body<L>(a.rows, a.cinv, n, a.scale, a.image, twr, a.x0, a.x1, blockIdx.x);
+}
+
+// SIDE 0: model side (rows -> tmp), 1: residual side (grid -> tmp)
+template <int P, int Q, int DIR, int SIDE>
+__global__ __launch_bounds__(256) void k_cols_p1_batch(const FftMember *__restrict__ m, int n,
+                                                       const float2 *__restrict__ tw) {
+  constexpr int L = P * Q;
+  const FftMember &a = m[blockIdx.z];
+  if ((int)blockIdx.x >= (a.x1 - a.x0) / 64) return;
+  const int x0 = a.x0 + blockIdx.x * 64;
+  const int o = (L - n) / 2;
+  if constexpr (SIDE == 0)
+    cols_p1_body<P, Q, DIR, float2>(a.rows, o, o, o + n, a.tmp, tw, x0, blockIdx.y);
+  else
+    cols_p1_body<P, Q, DIR, float2>(a.grid, 0, a.y0, a.y1, a.tmp, tw, x0, blockIdx.y);
+}
+
+// SIDE 0: model side (tmp -> grid rows of the box, modulated), 1: residual
+// side (tmp -> rows of the crop)
+template <int P, int Q, int DIR, int SIDE>
+__global__ __launch_bounds__(256) void k_cols_p2_batch(const FftMember *__restrict__ m, int n,
+                                                       const float2 *__restrict__ tw) {
+  constexpr int L = P * Q;
+  const FftMember &a = m[blockIdx.z];
+  if ((int)blockIdx.x >= (a.x1 - a.x0) / 64) return;
+  const int x0 = a.x0 + blockIdx.x * 64;
+  const int o = (L - n) / 2;
+  if constexpr (SIDE == 0)
+    cols_p2_body<P, Q, DIR, float2>(a.tmp, a.grid, 0, a.y0, a.y1, 1, tw, x0, blockIdx.y);
+  else
+    cols_p2_body<P, Q, DIR, float2>(a.tmp, a.rows, o, o, o + n, 0, tw, x0, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- image-domain filters
@@ -682,6 +761,63 @@ static void check_box(const Box &b, int ng) {
   IMGR_CHECK(b.x0 >= 0 && b.x0 <= b.x1 && b.x1 <= ng && b.x0 % 64 == 0 && b.x1 % 64 == 0 &&
                  b.y0 >= 0 && b.y0 <= b.y1 && b.y1 <= ng,
              "transform box outside the grid");
+}
+
+namespace {
+template <int L>
+void model_to_grid_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
+                           hipStream_t s) {
+  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  hipLaunchKernelGGL((k_rows_model_batch<L>), dim3(n, count), dim3(RowThreads<L>::v), 0, s, m, n,
+                     h->twrow);
+  if (max_cb == 0) return;
+  hipLaunchKernelGGL((k_cols_p1_batch<P, Q, -1, 0>), dim3(max_cb, Q, count), dim3(256), 0, s, m,
+                     n, h->tw);
+  hipLaunchKernelGGL((k_cols_p2_batch<P, Q, -1, 0>), dim3(max_cb, P, count), dim3(256), 0, s, m,
+                     n, h->tw);
+}
+
+template <int L>
+void grid_to_image_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
+                           hipStream_t s) {
+  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  if (max_cb > 0) {
+    hipLaunchKernelGGL((k_cols_p1_batch<P, Q, 1, 1>), dim3(max_cb, Q, count), dim3(256), 0, s, m,
+                       n, h->tw);
+    hipLaunchKernelGGL((k_cols_p2_batch<P, Q, 1, 1>), dim3(max_cb, P, count), dim3(256), 0, s, m,
+                       n, h->tw);
+  }
+  hipLaunchKernelGGL((k_rows_image_batch<L>), dim3(n, count), dim3(RowThreads<L>::v), 0, s, m, n,
+                     h->twrow);
+}
+}  // namespace
+
+void fft_model_to_grid_batch(const imgr_s *h, int ng, int n, const FftMember *members, int count,
+                             int max_cb, hipStream_t s) {
+  if (count == 0) return;
+  IMGR_CHECK(count <= 65535 && max_cb >= 0 && max_cb <= ng / 64, "batched transform shape");
+  switch (ng) {
+#define X(L) \
+  case L: model_to_grid_batch_t<L>(h, n, members, count, max_cb, s); break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void fft_grid_to_image_batch(const imgr_s *h, int ng, int n, const FftMember *members, int count,
+                             int max_cb, hipStream_t s) {
+  if (count == 0) return;
+  IMGR_CHECK(count <= 65535 && max_cb >= 0 && max_cb <= ng / 64, "batched transform shape");
+  switch (ng) {
+#define X(L) \
+  case L: grid_to_image_batch_t<L>(h, n, members, count, max_cb, s); break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
 }
 
 void fft_model_to_grid(imgr_s *h, const float *model, const float *model_add, const float *cinv,
