@@ -406,10 +406,10 @@ imgr_status imager_set_chunk(imgr_t h, int32_t chunk);
  * spread (Section 1); a batch runs the major cycles (Eq. 2) of many
  * single-partition handles, e.g. one per channel with its own image size,
  * cell and flags, with the de/gridding of many of them as one fused launch
- * over their chunks (largest chunks first across channels) and one fused
- * flush, while the FFT stages run per channel on the same stream.  Members
- * are taken in consecutive sets sized to the last-level cache, one fused
- * launch per set (imgr_batch_info.n_sets).  Members must have one partition, equal support and tile, and
+ * over their chunks (largest chunks first across channels), one fused
+ * flush, and the model / residual transforms of the members with one image
+ * size as one launch per pass.  Members are taken in consecutive sets sized
+ * to the last-level cache, one fused launch each (imgr_batch_info.n_sets).  Members must have one partition, equal support and tile, and
  * one stream, on which the batch enqueues its work.  The caller owns the
  * members; they must outlive the batch.  The batch uses the members' work
  * buffers, so a member's own calls and batch calls must be ordered (they

@@ -1,18 +1,20 @@
 // Batched channels: the major cycles (Eq. 2) of many single-partition
-// handles with the de/gridding of all of them in one fused launch.
+// handles with the de/gridding of many of them in one fused launch.
 //
 // Frequency channels share the array but not their uv coordinates, flags,
 // cell or image size, so their visibility counts and chunk counts differ
 // widely; launched one by one, each small channel leaves most of the 256
 // compute units idle at the head and tail of its launch.  The batch keeps
 // one device table of per-grid kernel arguments (bins, model grid, chunk
-// windows) and one (grid, chunk) list in decreasing chunk size over all
-// grids, so a single k_window_batch launch spreads every channel's chunks
-// over the whole chip, and a single k_flush_batch covers every grid.  The
-// per-chunk and per-cell arithmetic is the same device code as the
-// single-handle path, so results match it bit for bit.  The whole cycle
-// (per-channel FFTs, fused de/gridding, flush, per-channel inverse FFTs) can
-// be captured into a HIP graph and replayed; it holds no memset nodes.
+// windows) and, per member set, one (grid, chunk) list in decreasing chunk
+// size, so a single k_window_batch launch spreads the set's chunks over the
+// whole chip, and a single k_flush_batch covers the set's grids.  The
+// members of a set with one image size also run each pass of their model
+// and residual transforms as one launch (k_*_batch in the FFT source).  The
+// per-chunk, per-cell, per-row and per-column-block arithmetic is the same
+// device code as the single-handle path, so results match it bit for bit.
+// The whole cycle can be captured into a HIP graph and replayed; it holds no
+// memset nodes.
 //
 // The members are taken in consecutive sets whose model grids and chunk
 // windows together stay within half of the 256 MB last-level cache: for each
