@@ -175,13 +175,18 @@ static void release(imgr_s *h) {
   (void)hipStreamSynchronize(h->stream);
   for (int p = 0; p < 2; ++p)
     if (h->node_stream[p]) (void)hipStreamSynchronize(h->node_stream[p]);
+  if (h->psf_stream) (void)hipStreamSynchronize(h->psf_stream);
   recycle_events(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   for (int p = 0; p < 2; ++p) {
     if (h->ev_join[p]) (void)hipEventDestroy(h->ev_join[p]);
     if (h->node_stream[p]) (void)hipStreamDestroy(h->node_stream[p]);
+    if (h->ev_psf[p]) (void)hipEventDestroy(h->ev_psf[p]);
+    if (h->ev_win[p]) (void)hipEventDestroy(h->ev_win[p]);
   }
+  if (h->ev_psf_join) (void)hipEventDestroy(h->ev_psf_join);
+  if (h->psf_stream) (void)hipStreamDestroy(h->psf_stream);
   for (void *q : h->allocs) (void)hipFree(q);
   for (auto &c : h->cache) (void)hipFree(c.first);
   delete h;
@@ -202,7 +207,7 @@ NodeCall node_begin(imgr_s *h, int part, const float *model, const float *rho_ot
                     double gamma, double mu, float *residual_out, float *residual_local_out,
                     int flags, hipStream_t s) {
   NodeCall c{part, model, rho_other, gamma, mu, residual_out,
-             residual_local_out ? residual_local_out : h->work[part].img, flags, s, -1};
+             residual_local_out ? residual_local_out : h->work[part].img, flags, s, -1, false};
   if (h->timing) {
     c.ev_set = (int)h->ev_sets.size();
     h->ev_sets.emplace_back();
@@ -234,7 +239,7 @@ void node_stage(imgr_s *h, const NodeCall &c, int stage) {
     case 4:  // a6: pseudo-full-resolution composition (none without an output)
       if (!c.residual_out) break;
       if (h->n_parts == 2) {
-        compose(h, c.part, c.local, c.rho_other, c.gamma, c.mu, c.residual_out, s);
+        compose(h, c.part, c.local, c.rho_other, c.gamma, c.mu, c.residual_out, c.psf_pre, s);
       } else if (c.residual_out != c.local) {
         IMGR_HIP(hipMemcpyAsync(c.residual_out, c.local, (size_t)h->N * h->N * sizeof(float),
                                 hipMemcpyDeviceToDevice, s));
@@ -411,7 +416,13 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
       for (int p = 0; p < 2; ++p) {
         IMGR_HIP(hipStreamCreateWithFlags(&h->node_stream[p], hipStreamNonBlocking));
         IMGR_HIP(hipEventCreateWithFlags(&h->ev_join[p], hipEventDisableTiming));
+        IMGR_HIP(hipEventCreateWithFlags(&h->ev_psf[p], hipEventDisableTiming));
+        IMGR_HIP(hipEventCreateWithFlags(&h->ev_win[p], hipEventDisableTiming));
+        h->psf_work[p] = (float2 *)dev_alloc(h, (size_t)h->N * h->Ng * sizeof(float2));
       }
+      IMGR_HIP(hipStreamCreateWithFlags(&h->psf_stream, hipStreamNonBlocking));
+      IMGR_HIP(hipEventCreateWithFlags(&h->ev_psf_join, hipEventDisableTiming));
+      h->psf_tmp = (float2 *)dev_alloc(h, (size_t)h->Ng * h->Ng * sizeof(float2));
     }
     for (int p = 0; p < h->n_parts; ++p) {
       IMGR_CHECK(h->part[p].bins.n > 0, "a partition is empty (check ell / delta)");
@@ -505,7 +516,10 @@ imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_
                   // transform work, the FP64 PSF spectrum and its temporary
     minor = std::max(minor, 8.0 * (7.0 + 4.0 * fista + (fista > 1 ? fista : 0)) * nn +
                                 16.0 * 6 * nn + 2 * 16.0 * 4 * nn + 65536.0);
-  const double res = fixed + parts * (per + loop + minor);
+  // two partitions: the PSF terms' work (N x 2N complex per node) and their
+  // shared (2N)^2 complex temporary
+  const double psf_terms = parts == 2 ? 2 * 8.0 * N * Ng + 8.0 * Ng * Ng : 0.0;
+  const double res = fixed + parts * (per + loop + minor) + psf_terms;
   // create-time temporaries on top of the handle's work buffers and tables
   const double staged = vis_on_host ? (24.0 + 16.0 + 4.0 + 1.0) * m : 0.0;
   const double prep = 45.0 * m + 4.0 * nn;                   // coordinates, weights, keys
@@ -513,8 +527,8 @@ imgr_status imager_footprint(const imgr_config *cfg, int64_t n_vis, int32_t vis_
   const double psf_build = tables(2 * Ng) + 2 * 8.0 * 4 * Ng * Ng + 8.0 * 2 * N * 2 * Ng +
                            2048.0 * chunks(2 * Ng) + 16.0 * 4 * nn;
   const double tune = cfg->autotune ? 2 * 8.0 * Ng * Ng + tables(Ng) + 2048.0 * chunks(Ng) : 0.0;
-  const double create_peak = fixed + parts * (per - 12.0 * 4 * nn) + staged + prep + sortb +
-                             std::max(psf_build + 12.0 * 4 * nn, tune);
+  const double create_peak = fixed + psf_terms + parts * (per - 12.0 * 4 * nn) + staged + prep +
+                             sortb + std::max(psf_build + 12.0 * 4 * nn, tune);
   *resident = (size_t)res;
   if (peak) *peak = (size_t)std::max(res, create_peak + parts * 12.0 * 4 * nn);
   return IMGR_OK;
@@ -647,11 +661,28 @@ imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
       c[p] = node_begin(h, p, model[p], ro(p), gamma[p], mu[p], residual_out[p], lo(p), flags,
                         h->node_stream[p]);
     }
+    // the PSF term of Eq. 7 reads only the cycle's inputs: its front runs on
+    // the PSF stream beside the node's memory-bound stages, from the end of
+    // the node's de/gridding on (earlier, it takes the de/gridding's compute
+    // units), and the node's composition waits for it before its last pass
+    bool pre[2];
+    for (int p = 0; p < 2; ++p) c[p].psf_pre = pre[p] = residual_out[p] && mu[p] != 0.0 && ro(p);
     for (int stage = 0; stage < IMGR_N_STAGES; ++stage)
-      for (int p = 0; p < 2; ++p) node_stage(h, c[p], stage);
+      for (int p = 0; p < 2; ++p) {
+        node_stage(h, c[p], stage);
+        if (stage == 1 && pre[p]) {
+          IMGR_HIP(hipEventRecord(h->ev_win[p], h->node_stream[p]));
+          IMGR_HIP(hipStreamWaitEvent(h->psf_stream, h->ev_win[p], 0));
+          compose_psf_front(h, p, ro(p), mu[p], h->psf_stream);
+        }
+      }
     for (int p = 0; p < 2; ++p) {
       IMGR_HIP(hipEventRecord(h->ev_join[p], h->node_stream[p]));
       IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[p], 0));
+    }
+    if (pre[0] || pre[1]) {
+      IMGR_HIP(hipEventRecord(h->ev_psf_join, h->psf_stream));
+      IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_psf_join, 0));
     }
   }
   API_END(h)

@@ -151,6 +151,15 @@ struct imgr_s {
   hipStream_t node_stream[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[2] = {nullptr, nullptr};
+  // the PSF terms of Eq. 7 of both nodes depend only on the cycle's inputs:
+  // imager_major_cycle_nodes runs their fronts on a stream of their own,
+  // into psf_work[p] (N x 2N complex, tmp (2N)^2)
+  hipStream_t psf_stream = nullptr;
+  hipEvent_t ev_psf[2] = {nullptr, nullptr};
+  hipEvent_t ev_win[2] = {nullptr, nullptr};  // end of node p's de/gridding
+  hipEvent_t ev_psf_join = nullptr;
+  float2 *psf_work[2] = {nullptr, nullptr};
+  float2 *psf_tmp = nullptr;
   // stage timing (imager_set_timing): one set of events per recorded cycle
   bool timing = false;
   std::vector<std::vector<hipEvent_t>> ev_sets;
@@ -220,6 +229,7 @@ struct NodeCall {
   int flags;
   hipStream_t s;
   int ev_set;
+  bool psf_pre;  // the PSF term's front already enqueued (compose_psf_front)
 };
 NodeCall node_begin(imgr_s *h, int part, const float *model, const float *rho_other,
                     double gamma, double mu, float *residual_out, float *residual_local_out,
@@ -281,6 +291,13 @@ void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float c
 // the 2N x 2N PSF with spectrum psf_hat (centre (N, N)), cropped to N x N
 void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef, float *out,
                     int accumulate, float2 *work, float2 *tmp, hipStream_t s);
+// its two parts, for callers that run them on different streams: the front
+// leaves N rows of 2N complex values in work (tmp: (2N)^2 complex), the back
+// (+)= them into out
+void image_psf_conv_front(imgr_s *h, const float *a, const float2 *psf_hat, float coef,
+                          float2 *work, float2 *tmp, hipStream_t s);
+void image_psf_conv_back(imgr_s *h, const float2 *work, float *out, int accumulate,
+                         hipStream_t s);
 // FP64 versions of the two filters (work: N x 2N, tmp: (2N)^2 double2)
 void image_gamma64(imgr_s *h, const double *a, const double *b, int own_low, double coef,
                    double *out, int accumulate, double2 *work, double2 *tmp, hipStream_t s);
@@ -350,8 +367,13 @@ void flush_batch(int W, int blk, const FlushArgs *grids, const int32_t *group_st
 void rechunk(imgr_s *h, Bins &B, int C, hipStream_t s);
 
 // ----------------------------------------------------------------- composition
+// Eq. 7 for node p on stream s; with psf_pre, the PSF term's front was
+// enqueued by compose_psf_front and only its back runs here (after ev_psf[p])
 void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma, double mu,
-             float *out, hipStream_t s);
+             float *out, bool psf_pre, hipStream_t s);
+// the front of node p's PSF term, mu H_other rho_other, into psf_work[p] on
+// stream s, then ev_psf[p] recorded on s
+void compose_psf_front(imgr_s *h, int p, const float *rho_other, double mu, hipStream_t s);
 void composed_psf(imgr_s *h, int p, double gamma, double mu, float *out, hipStream_t s);
 void exchange(imgr_s *h, const float *a, const float *b, float *rho_a, float *rho_b, hipStream_t s);
 void combine_final(imgr_s *h, const float *a, const float *b, double wa, double wb, double *out,

@@ -114,15 +114,28 @@ const double2 *psf_spectrum64(imgr_s *h, int p, hipStream_t s) {
 
 // Eq. 7: out = gamma Gamma_own resid + mu H_other rho_other
 void compose(imgr_s *h, int p, const float *resid, const float *rho_other, double gamma,
-             double mu, float *out, hipStream_t s) {
+             double mu, float *out, bool psf_pre, hipStream_t s) {
   const int n = h->N, nd = 2 * n;
   // both grids are free once the residual image is out
   float2 *work = h->work[p].grid_a, *tmp = h->work[p].grid_b;
   image_gamma(h, resid, nullptr, p == IMGR_PART_LOW ? 1 : 0, (float)(gamma / ((double)n * n)),
               out, 0, work, tmp, s);
-  if (mu != 0.0 && rho_other)
-    image_psf_conv(h, rho_other, h->part[1 - p].psf_hat, (float)(mu / ((double)nd * nd)), out, 1,
-                   work, tmp, s);
+  if (mu == 0.0 || !rho_other) return;
+  if (psf_pre) {
+    IMGR_HIP(hipStreamWaitEvent(s, h->ev_psf[p], 0));
+    image_psf_conv_back(h, h->psf_work[p], out, 1, s);
+  } else {
+    image_psf_conv_front(h, rho_other, h->part[1 - p].psf_hat, (float)(mu / ((double)nd * nd)),
+                         work, tmp, s);
+    image_psf_conv_back(h, work, out, 1, s);
+  }
+}
+
+void compose_psf_front(imgr_s *h, int p, const float *rho_other, double mu, hipStream_t s) {
+  const int nd = 2 * h->N;
+  image_psf_conv_front(h, rho_other, h->part[1 - p].psf_hat, (float)(mu / ((double)nd * nd)),
+                       h->psf_work[p], h->psf_tmp, s);
+  IMGR_HIP(hipEventRecord(h->ev_psf[p], s));
 }
 
 void composed_psf(imgr_s *h, int p, double gamma, double mu, float *out, hipStream_t s) {

@@ -718,13 +718,13 @@ void plain_t(imgr_s *h, C *buf, C *tmp, int dir, hipStream_t s) {
 }
 
 // n_in rows of n_in pixels in (zero padded to L x L), rows [k_lo, k_hi) x
-// cols [col0, col0 + n_out) out; work: n_in x L, tmp: L x L
-template <int L, class C>
-void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T *b, int n_in,
-              int mode, const C *spec, int own_low, double gscale, typename Real<C>::T coef,
-              int k_lo, int k_hi, int col0, int n_out, typename Real<C>::T *out, int accumulate,
-              C *work, C *tmp, hipStream_t s) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+// cols [col0, col0 + n_out) out; work: n_in x L, tmp: L x L.
+// The filter is two parts: the front (real-input row pass and the three
+// column passes) leaves rows [k_lo, k_hi) of the filtered spectrum's inverse
+// column transform in work; the back (real-output row pass) turns them into
+// the output.  Either part may run on its own stream.
+template <int L>
+int filter_cols(const imgr_s *h, int mode, int own_low, double gscale) {
   // the input is real, so its 2-D spectrum is Hermitian and the real
   // spectral factors keep it so: the column passes only need the column
   // blocks that hold frequencies 0 .. L / 2; the final row pass rebuilds
@@ -734,7 +734,16 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
   // blocks from there on are zero after the product, so they are never formed
   if (mode == FILT_GAMMA && (own_low & 1))
     CB = std::min(CB, std::max(1, (int)std::ceil((h->ell + h->delta) * gscale / 64.0)));
-  const int c_hi = CB * 64;
+  return CB * 64;
+}
+
+template <int L, class C>
+void filter_front_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T *b,
+                    int n_in, int mode, const C *spec, int own_low, double gscale,
+                    typename Real<C>::T coef, int k_lo, int k_hi, C *work, C *tmp,
+                    hipStream_t s) {
+  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  const int c_hi = filter_cols<L>(h, mode, own_low, gscale), CB = c_hi / 64;
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
@@ -749,8 +758,26 @@ void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T
                        spec, h->ell, h->delta, gscale, own_low, coef, tw);
   hipLaunchKernelGGL((k_cols_fin<P, Q, C>), dim3(CB, Q), dim3(256), 0, s, tmp, work, k_lo,
                      k_hi, tw);
+}
+
+template <int L, class C>
+void filter_back_t(imgr_s *h, int mode, int own_low, double gscale, int k_lo, int k_hi, int col0,
+                   int n_out, typename Real<C>::T *out, int accumulate, const C *work,
+                   hipStream_t s) {
+  const int c_hi = filter_cols<L>(h, mode, own_low, gscale);
   hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
-                     work, col0, n_out, out, accumulate, twr, c_hi);
+                     work, col0, n_out, out, accumulate, row_twiddles<C>(h), c_hi);
+}
+
+template <int L, class C>
+void filter_t(imgr_s *h, const typename Real<C>::T *a, const typename Real<C>::T *b, int n_in,
+              int mode, const C *spec, int own_low, double gscale, typename Real<C>::T coef,
+              int k_lo, int k_hi, int col0, int n_out, typename Real<C>::T *out, int accumulate,
+              C *work, C *tmp, hipStream_t s) {
+  filter_front_t<L, C>(h, a, b, n_in, mode, spec, own_low, gscale, coef, k_lo, k_hi, work, tmp,
+                       s);
+  filter_back_t<L, C>(h, mode, own_low, gscale, k_lo, k_hi, col0, n_out, out, accumulate, work,
+                      s);
 }
 
 }  // namespace
@@ -871,6 +898,39 @@ void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef
   case L:                                                                                      \
     filter_t<L, float2>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, n, n, out,  \
                         accumulate, work, tmp, s);                                             \
+    break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+// the two parts of image_psf_conv: the front leaves N rows of 2N complex
+// values in work (tmp: (2N)^2 complex), the back (+)= them into out
+void image_psf_conv_front(imgr_s *h, const float *a, const float2 *psf_hat, float coef,
+                          float2 *work, float2 *tmp, hipStream_t s) {
+  const int n = h->N, nd = 2 * n;
+  switch (nd) {
+#define X(L)                                                                                  \
+  case L:                                                                                     \
+    filter_front_t<L, float2>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, work, \
+                              tmp, s);                                                        \
+    break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void image_psf_conv_back(imgr_s *h, const float2 *work, float *out, int accumulate,
+                         hipStream_t s) {
+  const int n = h->N, nd = 2 * n;
+  switch (nd) {
+#define X(L)                                                                              \
+  case L:                                                                                 \
+    filter_back_t<L, float2>(h, FILT_SPEC, 1, 1.0, n, nd, n, n, out, accumulate, work, s); \
     break;
     IMGR_FFT_SIZES(X)
 #undef X

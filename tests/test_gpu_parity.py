@@ -229,6 +229,12 @@ def test_concurrent_nodes_equal_single_calls(medium):
         both = h.major_cycle_nodes(models, rhos, gam, mus)
         for p in (0, 1):
             assert torch.equal(both[p], single[p]), "node %d differs" % p
+    # one node with the PSF term of Eq. 7, the other without
+    mus = [0.0, 0.6]
+    single = [h.major_cycle(p, models[p], rhos[p], gam[p], mus[p]) for p in (0, 1)]
+    both = h.major_cycle_nodes(models, rhos, gam, mus)
+    for p in (0, 1):
+        assert torch.equal(both[p], single[p]), "node %d differs (mu = %g)" % (p, mus[p])
 
 
 def test_composite_degrid(medium):
