@@ -5,9 +5,10 @@
 //     points, padded one slot per 32 against bank conflicts of the
 //     strided Stockham stores);
 //   * column passes: a four-step split L = P * Q done in two kernels over
-//     blocks of 64 adjacent columns (512-byte coalesced row segments); in
-//     LDS each wave owns 64 columns, so every lane of a wave uses the same
-//     row index and twiddle (no bank conflicts, scalar twiddle loads).
+//     blocks of CW = 32 adjacent columns (256-byte coalesced row segments in
+//     FP32; 64 columns halve the workgroup count, which leaves much of the
+//     chip idle at these sizes, and 16 columns measured slower); in LDS each
+//     group of CW threads owns the block's columns, one lane per column.
 // Zero rows of a padded input are never read and rows outside a crop are
 // never written.  The centred transform of the gridder (grid cell g holds
 // frequency g - Ng/2) is the plain DFT with (-1)^index modulation on both
@@ -18,6 +19,9 @@ namespace imgr {
 namespace {
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }
+
+// width of the column passes' blocks where the split allows it (ColWidth)
+constexpr int kColWant = 32;
 
 template <int DIR, class C>
 __device__ __forceinline__ C tw_get(const C *__restrict__ tw, int idx) {
@@ -111,29 +115,32 @@ __device__ __forceinline__ void stockham_seq(C *s, const C *tw, int t) {
   }
 }
 
-// 64 sequences of length LEN stored as s[pos][64] (column c = lane), 256
-// threads: wave w does butterflies j = w, w + 4, ...
-template <int LEN, int NS, int DIR, class C>
+// CW sequences of length LEN stored as s[pos][CW] (column c = t % CW), 256
+// threads in G = 256 / CW groups: group g does butterflies j = g, g + G, ...
+// (with CW = 64 a group is a wave, and its row index and twiddles are
+// wave-uniform)
+template <int LEN, int NS, int DIR, class C, int CW>
 __device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, int t) {
   if constexpr (NS < LEN) {
     constexpr int R = (LEN / NS >= 8) ? 8 : (LEN / NS);
     constexpr int NB = LEN / R;
-    constexpr int PER = (NB + 3) / 4;
-    const int c = t & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    constexpr int G = 256 / CW;
+    constexpr int PER = (NB + G - 1) / G;
+    const int c = t % CW;
+    const int wv = CW == 64 ? __builtin_amdgcn_readfirstlane(t >> 6) : t / CW;
     C x[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int j = wv + 4 * q;
+      const int j = wv + G * q;
       if (j < NB) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[q][r] = s[(j + r * NB) * 64 + c];
+        for (int r = 0; r < R; ++r) x[q][r] = s[(j + r * NB) * CW + c];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int j = wv + 4 * q;
+      const int j = wv + G * q;
       if (j < NB) {
         const int k = j & (NS - 1);
         if constexpr (NS > 1) {
@@ -144,11 +151,11 @@ __device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, in
         dft<R, DIR>(x[q]);
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) s[(base + r * NS) * 64 + c] = x[q][r];
+        for (int r = 0; r < R; ++r) s[(base + r * NS) * CW + c] = x[q][r];
       }
     }
     __syncthreads();
-    stockham_cols<LEN, NS * R, DIR, C>(s, tw, t);
+    stockham_cols<LEN, NS * R, DIR, C, CW>(s, tw, t);
   }
 }
 
@@ -295,6 +302,14 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
 }
 
 // ---------------------------------------------------------------- column kernels
+// Width of the column blocks for a transform of length L = P * Q: every
+// pass keeps P or Q rows of CW columns in LDS, 256 threads, at least one
+// element each.  Narrower blocks give more workgroups for the same data.
+template <int P, int Q>
+struct ColWidth {
+  static constexpr int lo = 256 / (P < Q ? P : Q);  // one element per thread
+  static constexpr int v = kColWant > lo ? kColWant : lo;
+};
 // Column DFT of length L = P * Q over an L x L array (row stride L):
 //   pass 1 (block (cb, y2)): A[k1] = sum_y1 x[Q y1 + y2] w_P^(y1 k1), times
 //          w_L^(y2 k1), stored at row Q k1 + y2 of dst;
@@ -307,16 +322,16 @@ template <int P, int Q, int DIR, class C>
 __device__ __forceinline__ void cols_p1_body(const C *__restrict__ src, int src_row0, int y_lo,
                                              int y_hi, C *__restrict__ dst,
                                              const C *__restrict__ tw, int x0, int y2) {
-  constexpr int L = P * Q;
-  __shared__ C s[P * 64];
+  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  __shared__ C s[P * CW];
   const int t = threadIdx.x;
   {
     // every load of the thread goes out before the first is used
-    constexpr int PER = P * 64 / 256;
+    constexpr int PER = P * CW / 256;
     C v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int i = t + q * 256, y1 = i >> 6, c = i & 63;
+      const int i = t + q * 256, y1 = i / CW, c = i % CW;
       const int y = Q * y1 + y2;
       v[q] = (y >= y_lo && y < y_hi) ? src[(size_t)(y - src_row0) * L + x0 + c] : mkc<C>(0, 0);
     }
@@ -324,18 +339,18 @@ __device__ __forceinline__ void cols_p1_body(const C *__restrict__ src, int src_
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   // the twiddles of the store, loaded while the transform runs
-  constexpr int PER = P * 64 / 256;
+  constexpr int PER = P * CW / 256;
   C w[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int k1 = (t + q * 256) >> 6;
+    const int k1 = (t + q * 256) / CW;
     w[q] = tw_get<DIR>(tw, ((y2 * k1) & (L - 1)) * (kTwMax / L));
   }
   __syncthreads();
-  stockham_cols<P, 1, DIR>(s, tw, t);
+  stockham_cols<P, 1, DIR, C, CW>(s, tw, t);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int i = t + q * 256, k1 = i >> 6, c = i & 63;
+    const int i = t + q * 256, k1 = i / CW, c = i % CW;
     dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], w[q]);
   }
 }
@@ -344,32 +359,32 @@ template <int P, int Q, int DIR, class C>
 __global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int src_row0,
                                                  int y_lo, int y_hi, C *__restrict__ dst,
                                                  const C *__restrict__ tw, int cb0) {
-  cols_p1_body<P, Q, DIR, C>(src, src_row0, y_lo, y_hi, dst, tw, (blockIdx.x + cb0) * 64,
-                             blockIdx.y);
+  cols_p1_body<P, Q, DIR, C>(src, src_row0, y_lo, y_hi, dst, tw,
+                             (blockIdx.x + cb0) * ColWidth<P, Q>::v, blockIdx.y);
 }
 
 template <int P, int Q, int DIR, class C>
 __device__ __forceinline__ void cols_p2_body(const C *__restrict__ src, C *__restrict__ dst,
                                              int dst_row0, int k_lo, int k_hi, int modulate,
                                              const C *__restrict__ tw, int x0, int k1) {
-  constexpr int L = P * Q;
-  __shared__ C s[Q * 64];
+  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  __shared__ C s[Q * CW];
   const int t = threadIdx.x;
   {
-    constexpr int PER = Q * 64 / 256;
+    constexpr int PER = Q * CW / 256;
     C v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int i = t + q * 256, y2 = i >> 6, c = i & 63;
+      const int i = t + q * 256, y2 = i / CW, c = i % CW;
       v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   __syncthreads();
-  stockham_cols<Q, 1, DIR>(s, tw, t);
-  for (int i = t; i < Q * 64; i += 256) {
-    const int k2 = i >> 6, c = i & 63;
+  stockham_cols<Q, 1, DIR, C, CW>(s, tw, t);
+  for (int i = t; i < Q * CW; i += 256) {
+    const int k2 = i / CW, c = i % CW;
     const int k = k1 + P * k2;
     if (k >= k_lo && k < k_hi) {
       C v = s[i];
@@ -385,7 +400,7 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
                                                  int k_hi, int modulate,
                                                  const C *__restrict__ tw, int cb0) {
   cols_p2_body<P, Q, DIR, C>(src, dst, dst_row0, k_lo, k_hi, modulate, tw,
-                             (blockIdx.x + cb0) * 64, blockIdx.y);
+                             (blockIdx.x + cb0) * ColWidth<P, Q>::v, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- batched transforms
@@ -413,8 +428,9 @@ __global__ __launch_bounds__(256) void k_cols_p1_batch(const FftMember *__restri
                                                        const float2 *__restrict__ tw) {
   constexpr int L = P * Q;
   const FftMember &a = m[blockIdx.z];
-  if ((int)blockIdx.x >= (a.x1 - a.x0) / 64) return;
-  const int x0 = a.x0 + blockIdx.x * 64;
+  constexpr int CW = ColWidth<P, Q>::v;
+  if ((int)blockIdx.x >= (a.x1 - a.x0) / CW) return;
+  const int x0 = a.x0 + blockIdx.x * CW;
   const int o = (L - n) / 2;
   if constexpr (SIDE == 0)
     cols_p1_body<P, Q, DIR, float2>(a.rows, o, o, o + n, a.tmp, tw, x0, blockIdx.y);
@@ -429,8 +445,9 @@ __global__ __launch_bounds__(256) void k_cols_p2_batch(const FftMember *__restri
                                                        const float2 *__restrict__ tw) {
   constexpr int L = P * Q;
   const FftMember &a = m[blockIdx.z];
-  if ((int)blockIdx.x >= (a.x1 - a.x0) / 64) return;
-  const int x0 = a.x0 + blockIdx.x * 64;
+  constexpr int CW = ColWidth<P, Q>::v;
+  if ((int)blockIdx.x >= (a.x1 - a.x0) / CW) return;
+  const int x0 = a.x0 + blockIdx.x * CW;
   const int o = (L - n) / 2;
   if constexpr (SIDE == 0)
     cols_p2_body<P, Q, DIR, float2>(a.tmp, a.grid, 0, a.y0, a.y1, 1, tw, x0, blockIdx.y);
@@ -537,7 +554,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
 }
 
 // Spectral product between a forward and an inverse column DFT, four-step
-// form (L = P * Q, blocks of 64 columns):
+// form (L = P * Q, blocks of CW columns):
 //   forward pass 1 (k_cols_p1) leaves A[Q k1 + y2];
 //   mid (block (cb, k1)): X[k1 + P k2] = sum_y2 A[Q k1 + y2] w_Q^(y2 k2)
 //          (forward), times the spectral factor, then
@@ -564,12 +581,12 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
                                                   int own_low, typename Real<C>::T coef,
                                                   const C *__restrict__ tw) {
   typedef typename Real<C>::T RT;
-  constexpr int L = P * Q;
-  __shared__ C s[Q * 64];
+  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  __shared__ C s[Q * CW];
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * 64;
+  const int x0 = blockIdx.x * CW;
   const int k1 = blockIdx.y;
-  constexpr int PER = Q * 64 / 256;
+  constexpr int PER = Q * CW / 256;
   // the column block and (for a spectral factor) the factors it is
   // multiplied by: all loads issued before the first is used
   C sp[MODE == FILT_SPEC ? PER : 1];
@@ -577,13 +594,13 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
     C v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int i = t + q * 256, y2 = i >> 6, c = i & 63;
+      const int i = t + q * 256, y2 = i / CW, c = i % CW;
       v[q] = buf[(size_t)(Q * k1 + y2) * L + x0 + c];
     }
     if constexpr (MODE == FILT_SPEC) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int i = t + q * 256, k2 = i >> 6, c = i & 63;
+        const int i = t + q * 256, k2 = i / CW, c = i % CW;
         sp[q] = spec[(size_t)(k1 + P * k2) * L + x0 + c];
       }
     }
@@ -591,10 +608,10 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   __syncthreads();
-  stockham_cols<Q, 1, -1>(s, tw, t);
+  stockham_cols<Q, 1, -1, C, CW>(s, tw, t);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int i = t + q * 256, k2 = i >> 6, c = i & 63;
+    const int i = t + q * 256, k2 = i / CW, c = i % CW;
     const int k = k1 + P * k2;
     C v = s[i];
     if constexpr (MODE == FILT_GAMMA) {
@@ -610,14 +627,14 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
   C w[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int y2 = (t + q * 256) >> 6;
+    const int y2 = (t + q * 256) / CW;
     w[q] = tw_get<1>(tw, ((y2 * k1) & (L - 1)) * (kTwMax / L));
   }
   __syncthreads();
-  stockham_cols<Q, 1, 1>(s, tw, t);
+  stockham_cols<Q, 1, 1, C, CW>(s, tw, t);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int i = t + q * 256, y2 = i >> 6, c = i & 63;
+    const int i = t + q * 256, y2 = i / CW, c = i % CW;
     buf[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], w[q]);
   }
 }
@@ -625,26 +642,26 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
 template <int P, int Q, class C>
 __global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *__restrict__ dst,
                                                   int k_lo, int k_hi, const C *__restrict__ tw) {
-  constexpr int L = P * Q;
-  __shared__ C s[P * 64];
+  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  __shared__ C s[P * CW];
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * 64;
+  const int x0 = blockIdx.x * CW;
   const int y2 = blockIdx.y;
   {
-    constexpr int PER = P * 64 / 256;
+    constexpr int PER = P * CW / 256;
     C v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int i = t + q * 256, k1 = i >> 6, c = i & 63;
+      const int i = t + q * 256, k1 = i / CW, c = i % CW;
       v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
   }
   __syncthreads();
-  stockham_cols<P, 1, 1>(s, tw, t);
-  for (int i = t; i < P * 64; i += 256) {
-    const int y1 = i >> 6, c = i & 63;
+  stockham_cols<P, 1, 1, C, CW>(s, tw, t);
+  for (int i = t; i < P * CW; i += 256) {
+    const int y1 = i / CW, c = i % CW;
     const int y = y2 + Q * y1;
     if (y >= k_lo && y < k_hi) dst[(size_t)(y - k_lo) * L + x0 + c] = s[i];
   }
@@ -668,16 +685,16 @@ template <class C> const C *row_twiddles(const imgr_s *h);
 template <> const float2 *row_twiddles<float2>(const imgr_s *h) { return h->twrow; }
 template <> const double2 *row_twiddles<double2>(const imgr_s *h) { return h->twrow64; }
 
-// column blocks [cb0, cb1) of 64 columns
+// column blocks [cb0, cb1) of 64 columns (F = 64 / CW launch blocks each)
 template <int L, int DIR, class C>
 void cols(const C *src, int src_row0, int y_lo, int y_hi, C *tmp, C *dst, int dst_row0, int k_lo,
           int k_hi, int modulate, const C *tw, hipStream_t s, int cb0 = 0, int cb1 = L / 64) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
   if (cb1 <= cb0) return;
-  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR, C>), dim3(cb1 - cb0, Q), dim3(256), 0, s, src,
-                     src_row0, y_lo, y_hi, tmp, tw, cb0);
-  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR, C>), dim3(cb1 - cb0, P), dim3(256), 0, s, tmp, dst,
-                     dst_row0, k_lo, k_hi, modulate, tw, cb0);
+  hipLaunchKernelGGL((k_cols_p1<P, Q, DIR, C>), dim3((cb1 - cb0) * F, Q), dim3(256), 0, s, src,
+                     src_row0, y_lo, y_hi, tmp, tw, cb0 * F);
+  hipLaunchKernelGGL((k_cols_p2<P, Q, DIR, C>), dim3((cb1 - cb0) * F, P), dim3(256), 0, s, tmp,
+                     dst, dst_row0, k_lo, k_hi, modulate, tw, cb0 * F);
 }
 
 // the transforms touch only the box of grid cells the partition's chunk
@@ -743,7 +760,8 @@ void filter_front_t(imgr_s *h, const typename Real<C>::T *a, const typename Real
                     typename Real<C>::T coef, int k_lo, int k_hi, C *work, C *tmp,
                     hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
-  const int c_hi = filter_cols<L>(h, mode, own_low, gscale), CB = c_hi / 64;
+  const int c_hi = filter_cols<L>(h, mode, own_low, gscale);
+  const int CB = c_hi / ColWidth<P, Q>::v;  // launch blocks
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
@@ -794,25 +812,25 @@ namespace {
 template <int L>
 void model_to_grid_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
                            hipStream_t s) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
   hipLaunchKernelGGL((k_rows_model_batch<L>), dim3(n, count), dim3(RowThreads<L>::v), 0, s, m, n,
                      h->twrow);
   if (max_cb == 0) return;
-  hipLaunchKernelGGL((k_cols_p1_batch<P, Q, -1, 0>), dim3(max_cb, Q, count), dim3(256), 0, s, m,
-                     n, h->tw);
-  hipLaunchKernelGGL((k_cols_p2_batch<P, Q, -1, 0>), dim3(max_cb, P, count), dim3(256), 0, s, m,
-                     n, h->tw);
+  hipLaunchKernelGGL((k_cols_p1_batch<P, Q, -1, 0>), dim3(max_cb * F, Q, count), dim3(256), 0, s,
+                     m, n, h->tw);
+  hipLaunchKernelGGL((k_cols_p2_batch<P, Q, -1, 0>), dim3(max_cb * F, P, count), dim3(256), 0, s,
+                     m, n, h->tw);
 }
 
 template <int L>
 void grid_to_image_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
                            hipStream_t s) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
   if (max_cb > 0) {
-    hipLaunchKernelGGL((k_cols_p1_batch<P, Q, 1, 1>), dim3(max_cb, Q, count), dim3(256), 0, s, m,
-                       n, h->tw);
-    hipLaunchKernelGGL((k_cols_p2_batch<P, Q, 1, 1>), dim3(max_cb, P, count), dim3(256), 0, s, m,
-                       n, h->tw);
+    hipLaunchKernelGGL((k_cols_p1_batch<P, Q, 1, 1>), dim3(max_cb * F, Q, count), dim3(256), 0, s,
+                       m, n, h->tw);
+    hipLaunchKernelGGL((k_cols_p2_batch<P, Q, 1, 1>), dim3(max_cb * F, P, count), dim3(256), 0, s,
+                       m, n, h->tw);
   }
   hipLaunchKernelGGL((k_rows_image_batch<L>), dim3(n, count), dim3(RowThreads<L>::v), 0, s, m, n,
                      h->twrow);
