@@ -235,6 +235,17 @@ def test_concurrent_nodes_equal_single_calls(medium):
     both = h.major_cycle_nodes(models, rhos, gam, mus)
     for p in (0, 1):
         assert torch.equal(both[p], single[p]), "node %d differs (mu = %g)" % (p, mus[p])
+    # two calls in a row with different rho, no synchronisation between them:
+    # each call's PSF term reads its own rho (the terms' work buffers are reused)
+    mus = [0.4, 0.6]
+    rhos_b = [to_dev(0.02 * random_model(n, rng)) for _ in range(2)]
+    single_a = [h.major_cycle(p, models[p], rhos[p], gam[p], mus[p]) for p in (0, 1)]
+    single_b = [h.major_cycle(p, models[p], rhos_b[p], gam[p], mus[p]) for p in (0, 1)]
+    out_a = h.major_cycle_nodes(models, rhos, gam, mus)
+    out_b = h.major_cycle_nodes(models, rhos_b, gam, mus)
+    for p in (0, 1):
+        assert torch.equal(out_a[p], single_a[p]), "first of two calls, node %d" % p
+        assert torch.equal(out_b[p], single_b[p]), "second of two calls, node %d" % p
 
 
 def test_composite_degrid(medium):
