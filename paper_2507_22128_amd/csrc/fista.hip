@@ -127,6 +127,46 @@ struct Bases {
   int hoff[kMaxBases], taps[kMaxBases];
 };
 
+// The tap count T is a template argument (each basis' launch dispatches on
+// it), so every tap's load is issued before the first product: the sums
+// themselves run in the same order as a plain loop over the taps.
+__device__ __forceinline__ int wrap_hi(int m, int n) {  // m mod n for m >= 0
+  while (m >= n) m -= n;
+  return m;
+}
+
+template <int AXIS, int T>
+__device__ __forceinline__ void dwt_body(const double *__restrict__ a,
+                                         const double *__restrict__ b, int in_stride,
+                                         double *__restrict__ out, int out_stride, int n,
+                                         const double *__restrict__ hg, double sc, int line,
+                                         int k) {
+  const int half = n / 2;
+  double v[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int m = wrap_hi(2 * k + j, n);
+    const size_t off = (AXIS == 1) ? (size_t)line * in_stride + m : (size_t)m * in_stride + line;
+    v[j] = a[off];
+    if (b) v[j] -= b[off];
+  }
+  double lo = 0.0, hi = 0.0;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    double x = v[j];
+    if (sc != 1.0) x *= sc;
+    lo = fma(hg[j], x, lo);
+    hi = fma(hg[T + j], x, hi);
+  }
+  if (AXIS == 1) {
+    out[(size_t)line * out_stride + k] = lo;
+    out[(size_t)line * out_stride + half + k] = hi;
+  } else {
+    out[(size_t)k * out_stride + line] = lo;
+    out[(size_t)(half + k) * out_stride + line] = hi;
+  }
+}
+
 template <int AXIS>
 __global__ void k_dwt(const double *__restrict__ a, size_t a_bstride, const double *__restrict__ b,
                       int in_stride, double *__restrict__ out, size_t out_bstride, int out_stride,
@@ -147,27 +187,55 @@ __global__ void k_dwt(const double *__restrict__ a, size_t a_bstride, const doub
     line = (int)(idx % n);
     k = (int)(idx / n);
   }
-  double lo = 0.0, hi = 0.0;
-  for (int j = 0; j < taps; ++j) {
-    const int m = (2 * k + j) % n;
-    const size_t off = (AXIS == 1) ? (size_t)line * in_stride + m : (size_t)m * in_stride + line;
-    double v = a[off];
-    if (b) v -= b[off];
-    if (sc != 1.0) v *= sc;
-    lo = fma(hg[j], v, lo);
-    hi = fma(hg[taps + j], v, hi);
-  }
-  if (AXIS == 1) {
-    out[(size_t)line * out_stride + k] = lo;
-    out[(size_t)line * out_stride + half + k] = hi;
-  } else {
-    out[(size_t)k * out_stride + line] = lo;
-    out[(size_t)(half + k) * out_stride + line] = hi;
+  switch (taps) {
+#define TAPS_(T) \
+  case T: dwt_body<AXIS, T>(a, b, in_stride, out, out_stride, n, hg, sc, line, k); break;
+    TAPS_(2) TAPS_(4) TAPS_(6) TAPS_(8) TAPS_(10) TAPS_(12) TAPS_(14) TAPS_(16) TAPS_(18)
+    TAPS_(20)
+#undef TAPS_
+    default: break;  // the host admits db1 .. db10 only
   }
 }
 
 // synthesis (the transpose): x[m] = sum over j with m - j even of
 // h_j a[k] + g_j d[k], k = ((m - j) mod n) / 2
+template <int AXIS, int T>
+__device__ __forceinline__ void idwt_body(const double *__restrict__ in, int in_stride,
+                                          double *__restrict__ out, int out_stride, int n,
+                                          const double *__restrict__ hg, int line, int m) {
+  const int half = n / 2;
+  const int j0 = m & 1;
+  double va[T / 2], vd[T / 2];
+#pragma unroll
+  for (int i = 0; i < T / 2; ++i) {
+    const int j = j0 + 2 * i;
+    int t = m - j;
+    while (t < 0) t += n;
+    const int k = t / 2;
+    size_t oa, od;
+    if (AXIS == 1) {
+      oa = (size_t)line * in_stride + k;
+      od = oa + half;
+    } else {
+      oa = (size_t)k * in_stride + line;
+      od = (size_t)(half + k) * in_stride + line;
+    }
+    va[i] = in[oa];
+    vd[i] = in[od];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < T / 2; ++i) {
+    const int j = j0 + 2 * i;
+    acc = fma(hg[j], va[i], acc);
+    acc = fma(hg[T + j], vd[i], acc);
+  }
+  if (AXIS == 1)
+    out[(size_t)line * out_stride + m] = acc;
+  else
+    out[(size_t)m * out_stride + line] = acc;
+}
+
 template <int AXIS>
 __global__ void k_idwt(const double *__restrict__ in, int in_stride, double *__restrict__ out,
                        int out_stride, size_t bstride, int n, const double *__restrict__ hlo,
@@ -177,7 +245,6 @@ __global__ void k_idwt(const double *__restrict__ in, int in_stride, double *__r
   const int taps = bs.taps[p];
   in += p * bstride;
   out += p * bstride;
-  const int half = n / 2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   int line, m;
@@ -188,24 +255,14 @@ __global__ void k_idwt(const double *__restrict__ in, int in_stride, double *__r
     line = (int)(idx % n);
     m = (int)(idx / n);
   }
-  double acc = 0.0;
-  for (int j = (m & 1); j < taps; j += 2) {
-    const int k = (((m - j) % n + n) % n) / 2;
-    size_t oa, od;
-    if (AXIS == 1) {
-      oa = (size_t)line * in_stride + k;
-      od = oa + half;
-    } else {
-      oa = (size_t)k * in_stride + line;
-      od = (size_t)(half + k) * in_stride + line;
-    }
-    acc = fma(hg[j], in[oa], acc);
-    acc = fma(hg[taps + j], in[od], acc);
+  switch (taps) {
+#define TAPS_(T) \
+  case T: idwt_body<AXIS, T>(in, in_stride, out, out_stride, n, hg, line, m); break;
+    TAPS_(2) TAPS_(4) TAPS_(6) TAPS_(8) TAPS_(10) TAPS_(12) TAPS_(14) TAPS_(16) TAPS_(18)
+    TAPS_(20)
+#undef TAPS_
+    default: break;
   }
-  if (AXIS == 1)
-    out[(size_t)line * out_stride + m] = acc;
-  else
-    out[(size_t)m * out_stride + line] = acc;
 }
 
 // ------------------------------------------------------------------ elementwise / reductions
