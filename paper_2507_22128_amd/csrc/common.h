@@ -303,6 +303,11 @@ void image_gamma64(imgr_s *h, const double *a, const double *b, int own_low, dou
                    double *out, int accumulate, double2 *work, double2 *tmp, hipStream_t s);
 void image_psf_conv64(imgr_s *h, const double *a, const double2 *psf_hat, double coef, double *out,
                       int accumulate, double2 *work, double2 *tmp, hipStream_t s);
+// two FP64 Gamma filters (own_low, coef, accumulate as in image_gamma64) of
+// different images in one launch per pass; work: 2 N^2, tmp: 2 N^2 double2
+void image_gamma64_pair(imgr_s *h, const double *a0, int own0, double coef0, double *out0,
+                        int acc0, const double *a1, int own1, double coef1, double *out1,
+                        int acc1, double2 *work, double2 *tmp, hipStream_t s);
 // plain FP64 2-D DFT of an n x n complex buffer in place
 void fft2_plain64(imgr_s *h, double2 *buf, double2 *tmp, int n, int dir, hipStream_t s);
 // the partition's FP64 PSF spectrum (built on first use, kept)

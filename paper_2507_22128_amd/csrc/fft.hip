@@ -471,14 +471,14 @@ constexpr int half_spectrum_cols() {
   return ((L / 2) / 64 + 1) * 64 < L ? ((L / 2) / 64 + 1) * 64 : L;
 }
 template <int L, class C>
-__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
-    const typename Real<C>::T *__restrict__ a, const typename Real<C>::T *__restrict__ b,
-    int n_in, C *__restrict__ out, const C *__restrict__ twr, int c_hi) {
+__device__ __forceinline__ void rows_real_fwd_body(const typename Real<C>::T *__restrict__ a,
+                                                   const typename Real<C>::T *__restrict__ b,
+                                                   int n_in, C *__restrict__ out,
+                                                   const C *__restrict__ twr, int c_hi, int r) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  const int r = blockIdx.x;
   {
     constexpr int PER = L / NT;
     RT v[PER];
@@ -503,17 +503,24 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
   for (int x = threadIdx.x; x < c_hi; x += NT) out[(size_t)r * L + x] = s[padi(x)];
 }
 
+template <int L, class C>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
+    const typename Real<C>::T *__restrict__ a, const typename Real<C>::T *__restrict__ b,
+    int n_in, C *__restrict__ out, const C *__restrict__ twr, int c_hi) {
+  rows_real_fwd_body<L, C>(a, b, n_in, out, twr, c_hi, blockIdx.x);
+}
+
 // rows r < gridDim.x: inverse plain row DFT of in[r][0..L) (columns x and
 // L - x at or above c_hi zero), then out[r][c] (+)= Re s[col0 + c], c < n_out
 template <int L, class C>
-__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
-    const C *__restrict__ in, int col0, int n_out, typename Real<C>::T *__restrict__ out,
-    int accumulate, const C *__restrict__ twr, int c_hi) {
+__device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int col0, int n_out,
+                                                   typename Real<C>::T *__restrict__ out,
+                                                   int accumulate, const C *__restrict__ twr,
+                                                   int c_hi, int r) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  const int r = blockIdx.x;
   // the row is Hermitian (the 2-D spectrum it came from belongs to a real
   // image): columns above L / 2 are the conjugates of those below
   {
@@ -553,6 +560,13 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
   }
 }
 
+template <int L, class C>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
+    const C *__restrict__ in, int col0, int n_out, typename Real<C>::T *__restrict__ out,
+    int accumulate, const C *__restrict__ twr, int c_hi) {
+  rows_inv_real_body<L, C>(in, col0, n_out, out, accumulate, twr, c_hi, blockIdx.x);
+}
+
 // Spectral product between a forward and an inverse column DFT, four-step
 // form (L = P * Q, blocks of CW columns):
 //   forward pass 1 (k_cols_p1) leaves A[Q k1 + y2];
@@ -576,16 +590,14 @@ __device__ __forceinline__ double gamma_low_at(int kx, int ky, int nd, double el
 }
 
 template <int P, int Q, int MODE, class C>
-__global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *__restrict__ spec,
-                                                  double ell, double delta, double gscale,
-                                                  int own_low, typename Real<C>::T coef,
-                                                  const C *__restrict__ tw) {
+__device__ __forceinline__ void cols_mid_body(C *__restrict__ buf, const C *__restrict__ spec,
+                                              double ell, double delta, double gscale,
+                                              int own_low, typename Real<C>::T coef,
+                                              const C *__restrict__ tw, int x0, int k1) {
   typedef typename Real<C>::T RT;
   constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
   __shared__ C s[Q * CW];
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * CW;
-  const int k1 = blockIdx.y;
   constexpr int PER = Q * CW / 256;
   // the column block and (for a spectral factor) the factors it is
   // multiplied by: all loads issued before the first is used
@@ -639,14 +651,22 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
   }
 }
 
+template <int P, int Q, int MODE, class C>
+__global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *__restrict__ spec,
+                                                  double ell, double delta, double gscale,
+                                                  int own_low, typename Real<C>::T coef,
+                                                  const C *__restrict__ tw) {
+  cols_mid_body<P, Q, MODE, C>(buf, spec, ell, delta, gscale, own_low, coef, tw,
+                               blockIdx.x * ColWidth<P, Q>::v, blockIdx.y);
+}
+
 template <int P, int Q, class C>
-__global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *__restrict__ dst,
-                                                  int k_lo, int k_hi, const C *__restrict__ tw) {
+__device__ __forceinline__ void cols_fin_body(const C *__restrict__ src, C *__restrict__ dst,
+                                              int k_lo, int k_hi, const C *__restrict__ tw,
+                                              int x0, int y2) {
   constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
   __shared__ C s[P * CW];
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * CW;
-  const int y2 = blockIdx.y;
   {
     constexpr int PER = P * CW / 256;
     C v[PER];
@@ -665,6 +685,12 @@ __global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *
     const int y = y2 + Q * y1;
     if (y >= k_lo && y < k_hi) dst[(size_t)(y - k_lo) * L + x0 + c] = s[i];
   }
+}
+
+template <int P, int Q, class C>
+__global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *__restrict__ dst,
+                                                  int k_lo, int k_hi, const C *__restrict__ tw) {
+  cols_fin_body<P, Q, C>(src, dst, k_lo, k_hi, tw, blockIdx.x * ColWidth<P, Q>::v, blockIdx.y);
 }
 
 template <int L>
@@ -785,6 +811,82 @@ void filter_back_t(imgr_s *h, int mode, int own_low, double gscale, int k_lo, in
   const int c_hi = filter_cols<L>(h, mode, own_low, gscale);
   hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
                      work, col0, n_out, out, accumulate, row_twiddles<C>(h), c_hi);
+}
+
+// Two Gamma filters of the same length L = N in one launch per pass: the
+// member is the last grid dimension; column blocks past a member's own
+// column count return at once.  Each member computes exactly what filter_t
+// computes for it alone.
+template <class C>
+struct GammaMember {
+  const typename Real<C>::T *a;
+  typename Real<C>::T *out;
+  C *work, *tmp;
+  typename Real<C>::T coef;
+  int own_low, accumulate, c_hi;
+};
+template <class C>
+struct GammaPair {
+  GammaMember<C> m[2];
+};
+template <class C>
+__device__ __forceinline__ GammaMember<C> pick(const GammaPair<C> &g, unsigned k) {
+  GammaMember<C> m = g.m[0];  // a select, not an indexed copy of the arguments
+  if (k) m = g.m[1];
+  return m;
+}
+
+template <int L, class C>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_gamma_pair_rows_fwd(GammaPair<C> g,
+                                                                          const C *twr) {
+  const GammaMember<C> m = pick(g, blockIdx.y);
+  rows_real_fwd_body<L, C>(m.a, nullptr, L, m.work, twr, m.c_hi, blockIdx.x);
+}
+template <int P, int Q, class C>
+__global__ __launch_bounds__(256) void k_gamma_pair_p1(GammaPair<C> g, const C *tw) {
+  constexpr int CW = ColWidth<P, Q>::v;
+  const GammaMember<C> m = pick(g, blockIdx.z);
+  if ((int)blockIdx.x * CW >= m.c_hi) return;
+  cols_p1_body<P, Q, -1, C>(m.work, 0, 0, P * Q, m.tmp, tw, blockIdx.x * CW, blockIdx.y);
+}
+template <int P, int Q, class C>
+__global__ __launch_bounds__(256) void k_gamma_pair_mid(GammaPair<C> g, double ell, double delta,
+                                                        const C *tw) {
+  constexpr int CW = ColWidth<P, Q>::v;
+  const GammaMember<C> m = pick(g, blockIdx.z);
+  if ((int)blockIdx.x * CW >= m.c_hi) return;
+  cols_mid_body<P, Q, FILT_GAMMA, C>(m.tmp, nullptr, ell, delta, 1.0, m.own_low, m.coef, tw,
+                                     blockIdx.x * CW, blockIdx.y);
+}
+template <int P, int Q, class C>
+__global__ __launch_bounds__(256) void k_gamma_pair_fin(GammaPair<C> g, const C *tw) {
+  constexpr int CW = ColWidth<P, Q>::v;
+  const GammaMember<C> m = pick(g, blockIdx.z);
+  if ((int)blockIdx.x * CW >= m.c_hi) return;
+  cols_fin_body<P, Q, C>(m.tmp, m.work, 0, P * Q, tw, blockIdx.x * CW, blockIdx.y);
+}
+template <int L, class C>
+__global__ __launch_bounds__(RowThreads<L>::v) void k_gamma_pair_rows_inv(GammaPair<C> g,
+                                                                          const C *twr) {
+  const GammaMember<C> m = pick(g, blockIdx.y);
+  rows_inv_real_body<L, C>(m.work, 0, L, m.out, m.accumulate, twr, m.c_hi, blockIdx.x);
+}
+
+template <int L, class C>
+void gamma_pair_t(imgr_s *h, GammaPair<C> g, hipStream_t s) {
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, CW = ColWidth<P, Q>::v;
+  for (int k = 0; k < 2; ++k) g.m[k].c_hi = filter_cols<L>(h, FILT_GAMMA, g.m[k].own_low, 1.0);
+  const int cb = std::max(g.m[0].c_hi, g.m[1].c_hi) / CW;
+  const C *tw = twiddles<C>(h);
+  const C *twr = row_twiddles<C>(h);
+  hipLaunchKernelGGL((k_gamma_pair_rows_fwd<L, C>), dim3(L, 2), dim3(RowThreads<L>::v), 0, s, g,
+                     twr);
+  hipLaunchKernelGGL((k_gamma_pair_p1<P, Q, C>), dim3(cb, Q, 2), dim3(256), 0, s, g, tw);
+  hipLaunchKernelGGL((k_gamma_pair_mid<P, Q, C>), dim3(cb, P, 2), dim3(256), 0, s, g, h->ell,
+                     h->delta, tw);
+  hipLaunchKernelGGL((k_gamma_pair_fin<P, Q, C>), dim3(cb, Q, 2), dim3(256), 0, s, g, tw);
+  hipLaunchKernelGGL((k_gamma_pair_rows_inv<L, C>), dim3(L, 2), dim3(RowThreads<L>::v), 0, s, g,
+                     twr);
 }
 
 template <int L, class C>
@@ -996,6 +1098,24 @@ void image_psf_conv64(imgr_s *h, const double *a, const double2 *psf_hat, double
     filter_t<L, double2>(h, a, nullptr, n, FILT_SPEC, psf_hat, 1, 1.0, coef, n, nd, n, n, out, \
                          accumulate, work, tmp, s);                                            \
     break;
+    IMGR_FFT64_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void image_gamma64_pair(imgr_s *h, const double *a0, int own0, double coef0, double *out0,
+                        int acc0, const double *a1, int own1, double coef1, double *out1,
+                        int acc1, double2 *work, double2 *tmp, hipStream_t s) {
+  const int n = h->N;
+  const size_t nn = (size_t)n * n;
+  GammaPair<double2> g;
+  g.m[0] = GammaMember<double2>{a0, out0, work, tmp, coef0, own0, acc0, 0};
+  g.m[1] = GammaMember<double2>{a1, out1, work + nn, tmp + nn, coef1, own1, acc1, 0};
+  switch (n) {
+#define X(L) \
+  case L: gamma_pair_t<L, double2>(h, g, s); break;
     IMGR_FFT64_SIZES(X)
 #undef X
     default: throw Error{IMGR_EINVAL, "unsupported FFT size"};

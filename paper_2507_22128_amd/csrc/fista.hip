@@ -454,13 +454,21 @@ void gam(Ctx &c, const double *a, const double *b, bool own, bool squared, doubl
 void normal_map(Ctx &c, const double *x, double *u3) {
   FistaWork &f = *c.fw;
   psf_conv(c, x, 1.0, f.u1, 0);
-  const double *t = f.u1;
-  if (!c.serial) {
+  if (c.serial) {
+    psf_conv(c, f.u1, 1.0, u3, 0);
+  } else if (c.gamma_n == 0.0) {
     gam(c, f.u1, nullptr, true, true, 1.0, f.u2, 0);
-    t = f.u2;
+    psf_conv(c, f.u2, 1.0, u3, 0);
+  } else {
+    // Gamma_own^2 H x -> u2 and gamma_n Gamma_other^2 x -> u3 as one pair of
+    // filters (one launch per pass), then u3 += H u2: the same sum, term for
+    // term, as H u2 + gamma_n Gamma_other^2 x
+    const bool low = c.part == IMGR_PART_LOW;  // Gamma_own = Gamma_L at node L
+    const double nn = (double)c.n * c.n;
+    image_gamma64_pair(c.h, f.u1, (low ? 1 : 0) | 2, 1.0 / nn, f.u2, 0, x, (low ? 0 : 1) | 2,
+                       c.gamma_n / nn, u3, 0, c.fw->work64, c.fw->tmp64, c.s);
+    psf_conv(c, f.u2, 1.0, u3, 1);
   }
-  psf_conv(c, t, 1.0, u3, 0);
-  if (!c.serial && c.gamma_n != 0.0) gam(c, x, nullptr, false, true, c.gamma_n, u3, 1);
 }
 
 void reduce(Ctx &c, const double *a, const double *b, const double *al, int mode, int op,
