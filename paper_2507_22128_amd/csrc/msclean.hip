@@ -108,6 +108,9 @@ struct SelectArgs {
 // R_t -= alpha B_{s*t} (shifted to p*) to its pixels and posts its candidate
 // for the next iteration.  With first != 0 there is no previous candidate
 // set: the launch only posts the candidates of the initial residuals.
+// NI = a.n_int (internal scales), a template argument so the per-pixel
+// arrays hold exactly the scales in use.
+template <int NI>
 __global__ __launch_bounds__(kStepThreads) void k_clean_iter(StepArgs a, SelectArgs se,
                                                               CleanState *st, const Cand *prev,
                                                               int n_prev, Cand *next, int first,
@@ -180,27 +183,52 @@ __global__ __launch_bounds__(kStepThreads) void k_clean_iter(StepArgs a, SelectA
   }
   const int py = pp / n, px = pp % n;
   Cand c{-1.0, 0x7fffffff, 0x7fffffff, 0.0, 0.0};
-  for (int i = blockIdx.x * kStepThreads + threadIdx.x; i < nn; i += gridDim.x * kStepThreads) {
-    const int y = i / n, x = i % n;
-    const size_t bi = (size_t)(n + y - py) * n2 + (n + x - px);
-    for (int t = 0; t < a.n_int; ++t) {
-      double *r = a.R + (size_t)t * nn + i;
-      double v = *r;
+  // two pixels per pass, every load of both issued before the first use;
+  // the candidate order (`better`) is total and peak0 a maximum, so the
+  // result does not depend on the order pixels and scales are visited in
+  const int lg = 31 - __clz(n);  // n is a power of two
+  double *__restrict__ R = a.R;
+  const double *__restrict__ Bs[NI];
+#pragma unroll
+  for (int t = 0; t < NI; ++t) Bs[t] = a.B + (size_t)a.pair[upd ? ps : 0][t] * n2 * n2;
+  const int stride = gridDim.x * kStepThreads;
+  for (int i0 = blockIdx.x * kStepThreads + threadIdx.x; i0 < nn; i0 += 2 * stride) {
+    const int i1 = i0 + stride;
+    const bool has1 = i1 < nn;
+    double v0[NI], v1[NI], b0[NI], b1[NI];
+    const size_t bi0 = (size_t)(n + (i0 >> lg) - py) * n2 + (n + (i0 & (n - 1)) - px);
+    const size_t bi1 = (size_t)(n + (i1 >> lg) - py) * n2 + (n + (i1 & (n - 1)) - px);
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      v0[t] = R[(size_t)t * nn + i0];
+      if (has1) v1[t] = R[(size_t)t * nn + i1];
       if (upd) {
-        const double b = a.B[(size_t)a.pair[ps][t] * n2 * n2 + bi];
-        v = __dsub_rn(v, __dmul_rn(alpha, b));
-        *r = v;
+        b0[t] = Bs[t][bi0];
+        if (has1) b1[t] = Bs[t][bi1];
       }
-      if (a.selectable[t]) {
-        const double bv = __dmul_rn(a.bias[t], fabs(v));
-        if (better(bv, t, i, c.v, c.s, c.p)) {
-          c.v = bv;
-          c.s = t;
-          c.p = i;
-          c.rv = v;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !has1) break;
+      const int i = h ? i1 : i0;
+#pragma unroll
+      for (int t = 0; t < NI; ++t) {
+        double v = h ? v1[t] : v0[t];
+        if (upd) {
+          v = __dsub_rn(v, __dmul_rn(alpha, h ? b1[t] : b0[t]));
+          R[(size_t)t * nn + i] = v;
         }
+        if (a.selectable[t]) {
+          const double bv = __dmul_rn(a.bias[t], fabs(v));
+          if (better(bv, t, i, c.v, c.s, c.p)) {
+            c.v = bv;
+            c.s = t;
+            c.p = i;
+            c.rv = v;
+          }
+        }
+        if (t == a.r0) c.peak0 = fmax(c.peak0, fabs(v));
       }
-      if (t == a.r0) c.peak0 = fmax(c.peak0, fabs(v));
     }
   }
   reduce_cand(c, sh);
@@ -510,10 +538,25 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
   Cand *slots = (Cand *)cw.slots;
   // candidates of iteration k live in slots[(k % 2) * kStepBlocks ...]: an
   // iteration reads one half and writes the other
-  hipLaunchKernelGGL(k_clean_iter, dim3(nblk), dim3(kStepThreads), 0, s, sa, se, st,
+  static_assert(kMaxInt == 9, "one instantiation per internal scale count");
+  void (*iter)(StepArgs, SelectArgs, CleanState *, const Cand *, int, Cand *, int,
+               imgr_component *, double *) = nullptr;
+  switch (n_int) {
+    case 1: iter = k_clean_iter<1>; break;
+    case 2: iter = k_clean_iter<2>; break;
+    case 3: iter = k_clean_iter<3>; break;
+    case 4: iter = k_clean_iter<4>; break;
+    case 5: iter = k_clean_iter<5>; break;
+    case 6: iter = k_clean_iter<6>; break;
+    case 7: iter = k_clean_iter<7>; break;
+    case 8: iter = k_clean_iter<8>; break;
+    case 9: iter = k_clean_iter<9>; break;
+    default: throw Error{IMGR_EINVAL, "internal scale count out of range"};
+  }
+  hipLaunchKernelGGL(iter, dim3(nblk), dim3(kStepThreads), 0, s, sa, se, st,
                      (const Cand *)nullptr, 0, slots, 1, comps, cw.model);
   for (int k = 0; k < prm.max_iter; ++k)
-    hipLaunchKernelGGL(k_clean_iter, dim3(nblk), dim3(kStepThreads), 0, s, sa, se, st,
+    hipLaunchKernelGGL(iter, dim3(nblk), dim3(kStepThreads), 0, s, sa, se, st,
                        (const Cand *)(slots + (k % 2) * kStepBlocks), nblk,
                        slots + ((k + 1) % 2) * kStepBlocks, 0, comps, cw.model);
   IMGR_HIP(hipGetLastError());
