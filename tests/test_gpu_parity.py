@@ -346,6 +346,51 @@ def test_smallest_and_largest_image_sizes(n_pix):
         h.destroy()
 
 
+@pytest.mark.parametrize("n_pix", [64, 128])
+def test_two_partitions_small_images(n_pix):
+    """The two-node cycle at the smallest image sizes (Gamma filters of 64 and
+    128 points, PSF convolutions of 128 and 256): each node's composed
+    residual (Eq. 7) against the oracle, and equal bit for bit to the
+    single-node call."""
+    import torch
+    say("case: tiny array (10 time steps), N = %d, 2 partitions" % n_pix)
+    d = workload("tiny", n_time=10)
+    n = n_pix
+    h = _imager().Imager.create(d, n_pix=n, n_partitions=2, weighting="uniform")
+    try:
+        u, v = uv(d)
+        w = imaging.uniform_weights(u, v, n, d["cell"])
+        low, high, ell = imaging.partition(u, v, n, d["cell"])
+        assert h.info.ell_pix == ell
+        rng = np.random.default_rng(n + 1)
+        model = random_model(n, rng, n_points=6)
+        rho = 0.01 * random_model(n, rng, n_points=6)
+        psfs, locals_ = {}, {}
+        for p, mask in ((0, low), (1, high)):
+            psfs[p] = imaging.psf2(u[mask], v[mask], w[mask], n, d["cell"])
+            locals_[p], _ = imaging.residual_image(u[mask], v[mask], d["vis"][mask], w[mask],
+                                                   model, d["cell"])
+        wl, wh = w[low].sum(), w[high].sum()
+        gm, mus = [], []
+        for p in (0, 1):
+            g, m = decentral.weights_schedule(2, (wl, wh)[p], (wh, wl)[p])
+            gm.append(g)
+            mus.append(m)
+        models = [to_dev(model), to_dev(model)]
+        rhos = [to_dev(rho), to_dev(rho)]
+        both = h.major_cycle_nodes(models, rhos, gm, mus)
+        for p, own in ((0, "L"), (1, "H")):
+            ref = decentral.compose_dirty(locals_[p], rho, psfs[1 - p], ell, 1.0, own, gm[p],
+                                          mus[p])
+            err = rel(to_np(both[p]), ref)
+            say("N = %d part %d composed residual rel err %.3e" % (n, p, err))
+            assert err < TOL
+            single = h.major_cycle(p, models[p], rhos[p], gm[p], mus[p])
+            assert torch.equal(both[p], single), "node %d differs from its single call" % p
+    finally:
+        h.destroy()
+
+
 def test_windows_wrapping_the_grid_edge():
     """A cell size that puts the outermost visibilities within half a support
     of the grid's edge: their footprints wrap around (the oracle's gridding
