@@ -291,6 +291,11 @@ void image_gamma(imgr_s *h, const float *a, const float *b, int own_low, float c
 // the 2N x 2N PSF with spectrum psf_hat (centre (N, N)), cropped to N x N
 void image_psf_conv(imgr_s *h, const float *a, const float2 *psf_hat, float coef, float *out,
                     int accumulate, float2 *work, float2 *tmp, hipStream_t s);
+// out = gamma Gamma_own a (own_low as in image_gamma, bit 0 only): Gamma_H a
+// is formed as gamma a - gamma Gamma_L a, whose spectral factor vanishes
+// beyond (ell + delta), so only those column blocks are transformed
+void image_gamma_scaled(imgr_s *h, const float *a, int own_low, float gamma, float *out,
+                        float2 *work, float2 *tmp, hipStream_t s);
 // its two parts, for callers that run them on different streams: the front
 // leaves N rows of 2N complex values in work (tmp: (2N)^2 complex), the back
 // (+)= them into out

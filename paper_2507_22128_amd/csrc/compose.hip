@@ -118,8 +118,7 @@ void compose(imgr_s *h, int p, const float *resid, const float *rho_other, doubl
   const int n = h->N, nd = 2 * n;
   // both grids are free once the residual image is out
   float2 *work = h->work[p].grid_a, *tmp = h->work[p].grid_b;
-  image_gamma(h, resid, nullptr, p == IMGR_PART_LOW ? 1 : 0, (float)(gamma / ((double)n * n)),
-              out, 0, work, tmp, s);
+  image_gamma_scaled(h, resid, p == IMGR_PART_LOW ? 1 : 0, (float)gamma, out, work, tmp, s);
   if (mu == 0.0 || !rho_other) return;
   if (psf_pre) {
     IMGR_HIP(hipStreamWaitEvent(s, h->ev_psf[p], 0));

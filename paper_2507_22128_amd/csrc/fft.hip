@@ -516,7 +516,10 @@ template <int L, class C>
 __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int col0, int n_out,
                                                    typename Real<C>::T *__restrict__ out,
                                                    int accumulate, const C *__restrict__ twr,
-                                                   int c_hi, int r) {
+                                                   int c_hi, int r,
+                                                   const typename Real<C>::T *__restrict__ add =
+                                                       nullptr,
+                                                   typename Real<C>::T add_scale = 0) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
@@ -555,6 +558,10 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
       const int c = threadIdx.x + q * NT;
       if (c < n_out) out[(size_t)r * n_out + c] = prev[q] + s[padi(col0 + c)].x;
     }
+  } else if (add) {
+    // out = add_scale add + the row (add: n_out columns per row, like out)
+    for (int c = threadIdx.x; c < n_out; c += NT)
+      out[(size_t)r * n_out + c] = add_scale * add[(size_t)r * n_out + c] + s[padi(col0 + c)].x;
   } else {
     for (int c = threadIdx.x; c < n_out; c += NT) out[(size_t)r * n_out + c] = s[padi(col0 + c)].x;
   }
@@ -563,8 +570,10 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
 template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_inv_real(
     const C *__restrict__ in, int col0, int n_out, typename Real<C>::T *__restrict__ out,
-    int accumulate, const C *__restrict__ twr, int c_hi) {
-  rows_inv_real_body<L, C>(in, col0, n_out, out, accumulate, twr, c_hi, blockIdx.x);
+    int accumulate, const C *__restrict__ twr, int c_hi,
+    const typename Real<C>::T *__restrict__ add = nullptr, typename Real<C>::T add_scale = 0) {
+  rows_inv_real_body<L, C>(in, col0, n_out, out, accumulate, twr, c_hi, blockIdx.x, add,
+                           add_scale);
 }
 
 // Spectral product between a forward and an inverse column DFT, four-step
@@ -1051,6 +1060,31 @@ void image_psf_conv_back(imgr_s *h, const float2 *work, float *out, int accumula
 #define X(L)                                                                              \
   case L:                                                                                 \
     filter_back_t<L, float2>(h, FILT_SPEC, 1, 1.0, n, nd, n, n, out, accumulate, work, s); \
+    break;
+    IMGR_FFT_SIZES(X)
+#undef X
+    default: throw Error{IMGR_EINVAL, "unsupported FFT size"};
+  }
+  IMGR_HIP(hipGetLastError());
+}
+
+void image_gamma_scaled(imgr_s *h, const float *a, int own_low, float gamma, float *out,
+                        float2 *work, float2 *tmp, hipStream_t s) {
+  const int n = h->N;
+  const float inv = (float)(1.0 / ((double)n * n));
+  switch (n) {
+#define X(L)                                                                                 \
+  case L:                                                                                    \
+    if (own_low & 1) {                                                                       \
+      filter_t<L, float2>(h, a, nullptr, n, FILT_GAMMA, nullptr, own_low, 1.0, gamma * inv, \
+                          0, n, 0, n, out, 0, work, tmp, s);                                 \
+    } else {                                                                                 \
+      filter_front_t<L, float2>(h, a, nullptr, n, FILT_GAMMA, nullptr, 1, 1.0, -gamma * inv, \
+                                0, n, work, tmp, s);                                         \
+      hipLaunchKernelGGL((k_rows_inv_real<L, float2>), dim3(n), dim3(RowThreads<L>::v), 0, s, \
+                         work, 0, n, out, 0, h->twrow,                                      \
+                         filter_cols<L>(h, FILT_GAMMA, 1, 1.0), a, gamma);                  \
+    }                                                                                        \
     break;
     IMGR_FFT_SIZES(X)
 #undef X
