@@ -203,8 +203,9 @@ imgr_status imager_major_cycle(imgr_t h, int32_t part, const float *model,
  * the meaning of the same argument of imager_major_cycle for part = p, and
  * rho_other / residual_local_out may be NULL (all entries absent).  The
  * nodes run concurrently on library-owned streams with their own work
- * buffers, forked from and joined back into the handle's stream, so the
- * call is ordered on that stream like any other.  Results equal those of
+ * buffers (the PSF terms mu H_other rho_other of Eq. 7, which read only the
+ * inputs, on a third one), forked from and joined back into the handle's
+ * stream, so the call is ordered on that stream like any other.  Results equal those of
  * imager_major_cycle for each node, bit for bit.  Output buffers of
  * different nodes must not overlap. */
 imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
