@@ -183,9 +183,9 @@ static void release(imgr_s *h) {
     if (h->ev_join[p]) (void)hipEventDestroy(h->ev_join[p]);
     if (h->node_stream[p]) (void)hipStreamDestroy(h->node_stream[p]);
     if (h->ev_psf[p]) (void)hipEventDestroy(h->ev_psf[p]);
-    if (h->ev_win[p]) (void)hipEventDestroy(h->ev_win[p]);
   }
   if (h->ev_psf_join) (void)hipEventDestroy(h->ev_psf_join);
+  if (h->ev_win) (void)hipEventDestroy(h->ev_win);
   if (h->psf_stream) (void)hipStreamDestroy(h->psf_stream);
   for (void *q : h->allocs) (void)hipFree(q);
   for (auto &c : h->cache) (void)hipFree(c.first);
@@ -417,11 +417,11 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
         IMGR_HIP(hipStreamCreateWithFlags(&h->node_stream[p], hipStreamNonBlocking));
         IMGR_HIP(hipEventCreateWithFlags(&h->ev_join[p], hipEventDisableTiming));
         IMGR_HIP(hipEventCreateWithFlags(&h->ev_psf[p], hipEventDisableTiming));
-        IMGR_HIP(hipEventCreateWithFlags(&h->ev_win[p], hipEventDisableTiming));
         h->psf_work[p] = (float2 *)dev_alloc(h, (size_t)h->N * h->Ng * sizeof(float2));
       }
       IMGR_HIP(hipStreamCreateWithFlags(&h->psf_stream, hipStreamNonBlocking));
       IMGR_HIP(hipEventCreateWithFlags(&h->ev_psf_join, hipEventDisableTiming));
+      IMGR_HIP(hipEventCreateWithFlags(&h->ev_win, hipEventDisableTiming));
       h->psf_tmp = (float2 *)dev_alloc(h, (size_t)h->Ng * h->Ng * sizeof(float2));
     }
     for (int p = 0; p < h->n_parts; ++p) {
@@ -661,19 +661,21 @@ imgr_status imager_major_cycle_nodes(imgr_t h, const float *const *model,
       c[p] = node_begin(h, p, model[p], ro(p), gamma[p], mu[p], residual_out[p], lo(p), flags,
                         h->node_stream[p]);
     }
-    // the PSF term of Eq. 7 reads only the cycle's inputs: its front runs on
-    // the PSF stream beside the node's memory-bound stages, from the end of
-    // the node's de/gridding on (earlier, it takes the de/gridding's compute
-    // units), and the node's composition waits for it before its last pass
+    // the PSF terms of Eq. 7 read only the cycle's inputs: their fronts run
+    // on the PSF stream, one after the other, from the end of node V_L's
+    // de/gridding on (the smaller partition's, which ends first; earlier,
+    // they take the de/gridding's compute units), beside the memory-bound
+    // stages; each node's composition waits for its own before its last pass
     bool pre[2];
     for (int p = 0; p < 2; ++p) c[p].psf_pre = pre[p] = residual_out[p] && mu[p] != 0.0 && ro(p);
     for (int stage = 0; stage < IMGR_N_STAGES; ++stage)
       for (int p = 0; p < 2; ++p) {
         node_stage(h, c[p], stage);
-        if (stage == 1 && pre[p]) {
-          IMGR_HIP(hipEventRecord(h->ev_win[p], h->node_stream[p]));
-          IMGR_HIP(hipStreamWaitEvent(h->psf_stream, h->ev_win[p], 0));
-          compose_psf_front(h, p, ro(p), mu[p], h->psf_stream);
+        if (stage == 1 && p == IMGR_PART_LOW && (pre[0] || pre[1])) {
+          IMGR_HIP(hipEventRecord(h->ev_win, h->node_stream[p]));
+          IMGR_HIP(hipStreamWaitEvent(h->psf_stream, h->ev_win, 0));
+          for (int k = 0; k < 2; ++k)
+            if (pre[k]) compose_psf_front(h, k, ro(k), mu[k], h->psf_stream);
         }
       }
     for (int p = 0; p < 2; ++p) {

@@ -156,7 +156,7 @@ struct imgr_s {
   // into psf_work[p] (N x 2N complex, tmp (2N)^2)
   hipStream_t psf_stream = nullptr;
   hipEvent_t ev_psf[2] = {nullptr, nullptr};
-  hipEvent_t ev_win[2] = {nullptr, nullptr};  // end of node p's de/gridding
+  hipEvent_t ev_win = nullptr;  // end of node V_L's de/gridding
   hipEvent_t ev_psf_join = nullptr;
   float2 *psf_work[2] = {nullptr, nullptr};
   float2 *psf_tmp = nullptr;
