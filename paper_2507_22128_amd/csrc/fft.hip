@@ -180,28 +180,33 @@ struct RowThreads {
 
 // model (n x n f32) [+ model_add] -> rows (n x L complex): correction 1/psi on
 // both axes, centred zero-padding, (-1)^(x+y) modulation, forward row DFT.
+// The rows are real, so one workgroup transforms rows 2p and 2p + 1 at
+// once as the real and imaginary parts of one complex sequence z = a + i b,
+// and separates them by the symmetry of real spectra:
+// A[k] = (Z[k] + conj Z[L-k]) / 2, B[k] = (Z[k] - conj Z[L-k]) / 2i.
 template <int L>
 __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
                                                 const float *__restrict__ model_add,
                                                 const float *__restrict__ cinv, int n,
                                                 float2 *__restrict__ rows,
                                                 const float2 *__restrict__ twr, int c_lo,
-                                                int c_hi, int r) {
+                                                int c_hi, int pair) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
   __shared__ float2 twl[L];
   const int o = (L - n) / 2;
-  const int y = o + r;
-  const float cy = cinv[r];
+  const int ra = 2 * pair, rb = ra + 1;
+  const int ya = o + ra;
+  const float cya = cinv[ra], cyb = cinv[rb];
   constexpr int PER = L / NT;
-  float v[PER], c[PER];
+  float va[PER], vb[PER], c[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int x = threadIdx.x + q * NT;
-    v[q] = 0.f;
-    c[q] = 0.f;
+    va[q] = vb[q] = c[q] = 0.f;
     if (x >= o && x < o + n) {
-      v[q] = model[(size_t)r * n + x - o];
+      va[q] = model[(size_t)ra * n + x - o];
+      vb[q] = model[(size_t)rb * n + x - o];
       c[q] = cinv[x - o];
     }
   }
@@ -209,7 +214,10 @@ __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int x = threadIdx.x + q * NT;
-      if (x >= o && x < o + n) v[q] += model_add[(size_t)r * n + x - o];
+      if (x >= o && x < o + n) {
+        va[q] += model_add[(size_t)ra * n + x - o];
+        vb[q] += model_add[(size_t)rb * n + x - o];
+      }
     }
   }
   // the twiddle loads go out behind the row loads: one wait covers both
@@ -217,14 +225,20 @@ __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int x = threadIdx.x + q * NT;
-    float w = v[q] * (c[q] * cy);
-    if ((x + y) & 1) w = -w;
-    s[padi(x)] = make_float2(w, 0.f);
+    float wa = va[q] * (c[q] * cya), wb = vb[q] * (c[q] * cyb);
+    // (-1)^(x + y): rows ra and rb = ra + 1 have opposite signs
+    if ((x + ya) & 1) wa = -wa;
+    else wb = -wb;
+    s[padi(x)] = make_float2(wa, wb);
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
   // only the columns [c_lo, c_hi) are ever read
-  for (int x = c_lo + threadIdx.x; x < c_hi; x += NT) rows[(size_t)r * L + x] = s[padi(x)];
+  for (int x = c_lo + threadIdx.x; x < c_hi; x += NT) {
+    const float2 zx = s[padi(x)], zm = s[padi((L - x) & (L - 1))];
+    rows[(size_t)ra * L + x] = make_float2(0.5f * (zx.x + zm.x), 0.5f * (zx.y - zm.y));
+    rows[(size_t)rb * L + x] = make_float2(0.5f * (zx.y + zm.y), 0.5f * (zm.x - zx.x));
+  }
 }
 
 template <int L>
@@ -740,8 +754,9 @@ template <int L>
 void model_to_grid_t(imgr_s *h, const float *model, const float *model_add, const float *cinv,
                      int n, float2 *rows, float2 *tmp, float2 *out, const Box &b, hipStream_t s) {
   const int o = (L - n) / 2;
-  hipLaunchKernelGGL((k_rows_model<L>), dim3(n), dim3(RowThreads<L>::v), 0, s, model, model_add,
-                     cinv, n, rows, h->twrow, b.x0, b.x1);
+  // one workgroup per pair of rows (n is even)
+  hipLaunchKernelGGL((k_rows_model<L>), dim3(n / 2), dim3(RowThreads<L>::v), 0, s, model,
+                     model_add, cinv, n, rows, h->twrow, b.x0, b.x1);
   cols<L, -1, float2>(rows, o, o, o + n, tmp, out, 0, b.y0, b.y1, 1, h->tw, s, b.x0 / 64,
                       b.x1 / 64);
 }
@@ -924,8 +939,8 @@ template <int L>
 void model_to_grid_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
                            hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
-  hipLaunchKernelGGL((k_rows_model_batch<L>), dim3(n, count), dim3(RowThreads<L>::v), 0, s, m, n,
-                     h->twrow);
+  hipLaunchKernelGGL((k_rows_model_batch<L>), dim3(n / 2, count), dim3(RowThreads<L>::v), 0, s,
+                     m, n, h->twrow);
   if (max_cb == 0) return;
   hipLaunchKernelGGL((k_cols_p1_batch<P, Q, -1, 0>), dim3(max_cb * F, Q, count), dim3(256), 0, s,
                      m, n, h->tw);
