@@ -476,8 +476,9 @@ __global__ __launch_bounds__(256) void k_cols_p2_batch(const FftMember *__restri
 // that transforms, multiplies and transforms back with whole columns in LDS,
 // and a real-output row pass.
 
-// rows r < gridDim.x: (a - b) (n_in real values, zero padded to L) -> plain
-// forward row DFT -> out[r][0..c_hi): the column passes that follow read
+// rows r < 2 gridDim.x (two per workgroup): (a - b) (n_in real values, zero
+// padded to L) -> plain forward row DFT -> out[r][0..c_hi): the column passes
+// that follow read
 // only the column blocks holding frequencies 0 .. L / 2 (the row is
 // Hermitian), fewer when the spectral factor vanishes beyond a frequency
 template <int L>
@@ -488,33 +489,48 @@ template <int L, class C>
 __device__ __forceinline__ void rows_real_fwd_body(const typename Real<C>::T *__restrict__ a,
                                                    const typename Real<C>::T *__restrict__ b,
                                                    int n_in, C *__restrict__ out,
-                                                   const C *__restrict__ twr, int c_hi, int r) {
+                                                   const C *__restrict__ twr, int c_hi,
+                                                   int pair) {
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
+  // rows 2 pair and 2 pair + 1 as the real and imaginary parts of one
+  // complex sequence z = u + i v; their spectra are separated below by the
+  // symmetry of real spectra: U[k] = (Z[k] + conj Z[L-k]) / 2,
+  // V[k] = (Z[k] - conj Z[L-k]) / 2i
+  const int ra = 2 * pair, rb = ra + 1;
   {
     constexpr int PER = L / NT;
-    RT v[PER];
+    RT u[PER], v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int x = threadIdx.x + q * NT;
-      v[q] = (x < n_in) ? a[(size_t)r * n_in + x] : RT(0);
+      u[q] = (x < n_in) ? a[(size_t)ra * n_in + x] : RT(0);
+      v[q] = (x < n_in) ? a[(size_t)rb * n_in + x] : RT(0);
     }
     if (b) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int x = threadIdx.x + q * NT;
-        if (x < n_in) v[q] -= b[(size_t)r * n_in + x];
+        if (x < n_in) {
+          u[q] -= b[(size_t)ra * n_in + x];
+          v[q] -= b[(size_t)rb * n_in + x];
+        }
       }
     }
     stage_twiddles<L, NT, C>(twl, twr);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = mkc<C>(v[q], 0);
+    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = mkc<C>(u[q], v[q]);
   }
   __syncthreads();
   stockham_seq<L, NT, 1, -1, C>(s, twl, threadIdx.x);
-  for (int x = threadIdx.x; x < c_hi; x += NT) out[(size_t)r * L + x] = s[padi(x)];
+  const RT h = RT(0.5);
+  for (int x = threadIdx.x; x < c_hi; x += NT) {
+    const C zx = s[padi(x)], zm = s[padi((L - x) & (L - 1))];
+    out[(size_t)ra * L + x] = mkc<C>(h * (zx.x + zm.x), h * (zx.y - zm.y));
+    out[(size_t)rb * L + x] = mkc<C>(h * (zx.y + zm.y), h * (zm.x - zx.x));
+  }
 }
 
 template <int L, class C>
@@ -814,7 +830,7 @@ void filter_front_t(imgr_s *h, const typename Real<C>::T *a, const typename Real
   const int CB = c_hi / ColWidth<P, Q>::v;  // launch blocks
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
-  hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in), dim3(RowThreads<L>::v), 0, s, a, b,
+  hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in / 2), dim3(RowThreads<L>::v), 0, s, a, b,
                      n_in, work, twr, c_hi);
   hipLaunchKernelGGL((k_cols_p1<P, Q, -1, C>), dim3(CB, Q), dim3(256), 0, s, work, 0, 0, n_in,
                      tmp, tw, 0);
@@ -903,8 +919,8 @@ void gamma_pair_t(imgr_s *h, GammaPair<C> g, hipStream_t s) {
   const int cb = std::max(g.m[0].c_hi, g.m[1].c_hi) / CW;
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
-  hipLaunchKernelGGL((k_gamma_pair_rows_fwd<L, C>), dim3(L, 2), dim3(RowThreads<L>::v), 0, s, g,
-                     twr);
+  hipLaunchKernelGGL((k_gamma_pair_rows_fwd<L, C>), dim3(L / 2, 2), dim3(RowThreads<L>::v), 0, s,
+                     g, twr);
   hipLaunchKernelGGL((k_gamma_pair_p1<P, Q, C>), dim3(cb, Q, 2), dim3(256), 0, s, g, tw);
   hipLaunchKernelGGL((k_gamma_pair_mid<P, Q, C>), dim3(cb, P, 2), dim3(256), 0, s, g, h->ell,
                      h->delta, tw);
