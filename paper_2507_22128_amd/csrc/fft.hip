@@ -540,13 +540,14 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_real_fwd(
   rows_real_fwd_body<L, C>(a, b, n_in, out, twr, c_hi, blockIdx.x);
 }
 
-// rows r < gridDim.x: inverse plain row DFT of in[r][0..L) (columns x and
-// L - x at or above c_hi zero), then out[r][c] (+)= Re s[col0 + c], c < n_out
+// rows r < 2 gridDim.x (two per workgroup): inverse plain row DFT of
+// in[r][0..L) (columns x and L - x at or above c_hi zero), then
+// out[r][c] (+)= Re s[col0 + c], c < n_out
 template <int L, class C>
 __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int col0, int n_out,
                                                    typename Real<C>::T *__restrict__ out,
                                                    int accumulate, const C *__restrict__ twr,
-                                                   int c_hi, int r,
+                                                   int c_hi, int pair,
                                                    const typename Real<C>::T *__restrict__ add =
                                                        nullptr,
                                                    typename Real<C>::T add_scale = 0) {
@@ -554,46 +555,70 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
   __shared__ C twl[L];
-  // the row is Hermitian (the 2-D spectrum it came from belongs to a real
-  // image): columns above L / 2 are the conjugates of those below
+  // rows 2 pair and 2 pair + 1 in one transform: each row is Hermitian (the
+  // 2-D spectrum it came from belongs to a real image), columns above L / 2
+  // being the conjugates of those below, so the inverse DFT of
+  // Z = U + i V is u + i v with both u and v real.  The imaginary parts at
+  // columns 0 and L / 2, which do not reach the real part of a row's own
+  // inverse, are dropped so that they do not reach the other row's.
+  const int ra = 2 * pair, rb = ra + 1;
   {
     constexpr int PER = L / NT;
-    C v[PER];
+    C u[PER], v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int x = threadIdx.x + q * NT;
       const int xs = x <= L / 2 ? x : L - x;  // columns from c_hi on are zero
-      v[q] = xs < c_hi ? in[(size_t)r * L + xs] : mkc<C>(0, 0);
+      u[q] = xs < c_hi ? in[(size_t)ra * L + xs] : mkc<C>(0, 0);
+      v[q] = xs < c_hi ? in[(size_t)rb * L + xs] : mkc<C>(0, 0);
     }
     stage_twiddles<L, NT, C>(twl, twr);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int x = threadIdx.x + q * NT;
-      if (x > L / 2) v[q].y = -v[q].y;
-      s[padi(x)] = v[q];
+      if (x > L / 2) {
+        u[q].y = -u[q].y;
+        v[q].y = -v[q].y;
+      } else if (x == 0 || x == L / 2) {
+        u[q].y = 0;
+        v[q].y = 0;
+      }
+      s[padi(x)] = mkc<C>(u[q].x - v[q].y, u[q].y + v[q].x);
     }
   }
   __syncthreads();
   stockham_seq<L, NT, 1, 1, C>(s, twl, threadIdx.x);
   if (accumulate) {
     constexpr int PO = (L + NT - 1) / NT;  // n_out <= L
-    RT prev[PO];
+    RT pa[PO], pb[PO];
 #pragma unroll
     for (int q = 0; q < PO; ++q) {
       const int c = threadIdx.x + q * NT;
-      prev[q] = (c < n_out) ? out[(size_t)r * n_out + c] : RT(0);
+      pa[q] = (c < n_out) ? out[(size_t)ra * n_out + c] : RT(0);
+      pb[q] = (c < n_out) ? out[(size_t)rb * n_out + c] : RT(0);
     }
 #pragma unroll
     for (int q = 0; q < PO; ++q) {
       const int c = threadIdx.x + q * NT;
-      if (c < n_out) out[(size_t)r * n_out + c] = prev[q] + s[padi(col0 + c)].x;
+      if (c < n_out) {
+        const C z = s[padi(col0 + c)];
+        out[(size_t)ra * n_out + c] = pa[q] + z.x;
+        out[(size_t)rb * n_out + c] = pb[q] + z.y;
+      }
     }
   } else if (add) {
     // out = add_scale add + the row (add: n_out columns per row, like out)
-    for (int c = threadIdx.x; c < n_out; c += NT)
-      out[(size_t)r * n_out + c] = add_scale * add[(size_t)r * n_out + c] + s[padi(col0 + c)].x;
+    for (int c = threadIdx.x; c < n_out; c += NT) {
+      const C z = s[padi(col0 + c)];
+      out[(size_t)ra * n_out + c] = add_scale * add[(size_t)ra * n_out + c] + z.x;
+      out[(size_t)rb * n_out + c] = add_scale * add[(size_t)rb * n_out + c] + z.y;
+    }
   } else {
-    for (int c = threadIdx.x; c < n_out; c += NT) out[(size_t)r * n_out + c] = s[padi(col0 + c)].x;
+    for (int c = threadIdx.x; c < n_out; c += NT) {
+      const C z = s[padi(col0 + c)];
+      out[(size_t)ra * n_out + c] = z.x;
+      out[(size_t)rb * n_out + c] = z.y;
+    }
   }
 }
 
@@ -849,8 +874,8 @@ void filter_back_t(imgr_s *h, int mode, int own_low, double gscale, int k_lo, in
                    int n_out, typename Real<C>::T *out, int accumulate, const C *work,
                    hipStream_t s) {
   const int c_hi = filter_cols<L>(h, mode, own_low, gscale);
-  hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3(k_hi - k_lo), dim3(RowThreads<L>::v), 0, s,
-                     work, col0, n_out, out, accumulate, row_twiddles<C>(h), c_hi);
+  hipLaunchKernelGGL((k_rows_inv_real<L, C>), dim3((k_hi - k_lo) / 2), dim3(RowThreads<L>::v),
+                     0, s, work, col0, n_out, out, accumulate, row_twiddles<C>(h), c_hi);
 }
 
 // Two Gamma filters of the same length L = N in one launch per pass: the
@@ -925,8 +950,8 @@ void gamma_pair_t(imgr_s *h, GammaPair<C> g, hipStream_t s) {
   hipLaunchKernelGGL((k_gamma_pair_mid<P, Q, C>), dim3(cb, P, 2), dim3(256), 0, s, g, h->ell,
                      h->delta, tw);
   hipLaunchKernelGGL((k_gamma_pair_fin<P, Q, C>), dim3(cb, Q, 2), dim3(256), 0, s, g, tw);
-  hipLaunchKernelGGL((k_gamma_pair_rows_inv<L, C>), dim3(L, 2), dim3(RowThreads<L>::v), 0, s, g,
-                     twr);
+  hipLaunchKernelGGL((k_gamma_pair_rows_inv<L, C>), dim3(L / 2, 2), dim3(RowThreads<L>::v), 0, s,
+                     g, twr);
 }
 
 template <int L, class C>
@@ -1112,8 +1137,8 @@ void image_gamma_scaled(imgr_s *h, const float *a, int own_low, float gamma, flo
     } else {                                                                                 \
       filter_front_t<L, float2>(h, a, nullptr, n, FILT_GAMMA, nullptr, 1, 1.0, -gamma * inv, \
                                 0, n, work, tmp, s);                                         \
-      hipLaunchKernelGGL((k_rows_inv_real<L, float2>), dim3(n), dim3(RowThreads<L>::v), 0, s, \
-                         work, 0, n, out, 0, h->twrow,                                      \
+      hipLaunchKernelGGL((k_rows_inv_real<L, float2>), dim3(n / 2), dim3(RowThreads<L>::v), 0, \
+                         s, work, 0, n, out, 0, h->twrow,                                   \
                          filter_cols<L>(h, FILT_GAMMA, 1, 1.0), a, gamma);                  \
     }                                                                                        \
     break;
