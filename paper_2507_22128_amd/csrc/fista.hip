@@ -200,10 +200,14 @@ __global__ void k_dwt(const double *__restrict__ a, size_t a_bstride, const doub
 // synthesis (the transpose): x[m] = sum over j with m - j even of
 // h_j a[k] + g_j d[k], k = ((m - j) mod n) / 2
 template <int AXIS, int T>
-__device__ __forceinline__ void idwt_body(const double *__restrict__ in, int in_stride,
+__device__ __forceinline__ void idwt_body(const double *__restrict__ in,
+                                          const double *__restrict__ ll, int in_stride,
                                           double *__restrict__ out, int out_stride, int n,
                                           const double *__restrict__ hg, int line, int m) {
   const int half = n / 2;
+  // the approximation quadrant (rows and columns below half) comes from ll
+  // when given; the detail quadrants always come from in
+  const double *__restrict__ lo_src = (ll && line < half) ? ll : in;
   const int j0 = m & 1;
   double va[T / 2], vd[T / 2];
 #pragma unroll
@@ -220,7 +224,7 @@ __device__ __forceinline__ void idwt_body(const double *__restrict__ in, int in_
       oa = (size_t)k * in_stride + line;
       od = (size_t)(half + k) * in_stride + line;
     }
-    va[i] = in[oa];
+    va[i] = lo_src[oa];
     vd[i] = in[od];
   }
   double acc = 0.0;
@@ -236,14 +240,17 @@ __device__ __forceinline__ void idwt_body(const double *__restrict__ in, int in_
     out[(size_t)m * out_stride + line] = acc;
 }
 
+// (AXIS 0 only: ll, when given, holds the approximation quadrant in place of
+// in, with in's layout)
 template <int AXIS>
-__global__ void k_idwt(const double *__restrict__ in, int in_stride, double *__restrict__ out,
-                       int out_stride, size_t bstride, int n, const double *__restrict__ hlo,
-                       Bases bs) {
+__global__ void k_idwt(const double *__restrict__ in, const double *__restrict__ ll,
+                       int in_stride, double *__restrict__ out, int out_stride, size_t bstride,
+                       int n, const double *__restrict__ hlo, Bases bs) {
   const int p = blockIdx.y;
   const double *__restrict__ hg = hlo + bs.hoff[p];
   const int taps = bs.taps[p];
   in += p * bstride;
+  if (ll) ll += p * bstride;
   out += p * bstride;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
@@ -257,7 +264,7 @@ __global__ void k_idwt(const double *__restrict__ in, int in_stride, double *__r
   }
   switch (taps) {
 #define TAPS_(T) \
-  case T: idwt_body<AXIS, T>(in, in_stride, out, out_stride, n, hg, line, m); break;
+  case T: idwt_body<AXIS, T>(in, ll, in_stride, out, out_stride, n, hg, line, m); break;
     TAPS_(2) TAPS_(4) TAPS_(6) TAPS_(8) TAPS_(10) TAPS_(12) TAPS_(14) TAPS_(16) TAPS_(18)
     TAPS_(20)
 #undef TAPS_
@@ -420,15 +427,17 @@ void dwt2(Ctx &c, const double *a, const double *b, double *out) {
 void idwt2(Ctx &c, const double *alpha, double *out) {
   const int N = c.n;
   double *xs = c.nb > 1 ? c.fw->xb : out;
-  const int64_t tot = (int64_t)c.nb * (int64_t)c.nn;
-  hipLaunchKernelGGL(k_copy_f64, g1(tot), dim3(256), 0, c.s, alpha, xs, tot);
+  // the detail quadrants are read from alpha itself; the approximation of
+  // each finer level is the previous level's synthesis in xs (the coarsest
+  // level's is alpha's own)
   int n = N >> (c.levels - 1);
   for (int lev = 0; lev < c.levels; ++lev) {
     const dim3 grid(cdiv((int64_t)n * n, 256), c.nb);
-    hipLaunchKernelGGL(k_idwt<0>, grid, dim3(256), 0, c.s, (const double *)xs, N, c.fw->tmp, N,
+    hipLaunchKernelGGL(k_idwt<0>, grid, dim3(256), 0, c.s, alpha,
+                       lev == 0 ? (const double *)nullptr : (const double *)xs, N, c.fw->tmp, N,
                        c.nn, n, c.fw->hlo, c.bases);
-    hipLaunchKernelGGL(k_idwt<1>, grid, dim3(256), 0, c.s, (const double *)c.fw->tmp, N, xs, N,
-                       c.nn, n, c.fw->hlo, c.bases);
+    hipLaunchKernelGGL(k_idwt<1>, grid, dim3(256), 0, c.s, (const double *)c.fw->tmp,
+                       (const double *)nullptr, N, xs, N, c.nn, n, c.fw->hlo, c.bases);
     n *= 2;
   }
   if (c.nb > 1)
