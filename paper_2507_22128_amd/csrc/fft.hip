@@ -319,10 +319,12 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
 // Width of the column blocks for a transform of length L = P * Q: every
 // pass keeps P or Q rows of CW columns in LDS, 256 threads, at least one
 // element each.  Narrower blocks give more workgroups for the same data.
-template <int P, int Q>
+template <int P, int Q, class C>
 struct ColWidth {
   static constexpr int lo = 256 / (P < Q ? P : Q);  // one element per thread
-  static constexpr int v = kColWant > lo ? kColWant : lo;
+  // FP64 elements are twice as wide: the same bytes per row segment
+  static constexpr int want = sizeof(C) > 8 ? kColWant / 2 : kColWant;
+  static constexpr int v = want > lo ? want : lo;
 };
 // Column DFT of length L = P * Q over an L x L array (row stride L):
 //   pass 1 (block (cb, y2)): A[k1] = sum_y1 x[Q y1 + y2] w_P^(y1 k1), times
@@ -336,7 +338,7 @@ template <int P, int Q, int DIR, class C>
 __device__ __forceinline__ void cols_p1_body(const C *__restrict__ src, int src_row0, int y_lo,
                                              int y_hi, C *__restrict__ dst,
                                              const C *__restrict__ tw, int x0, int y2) {
-  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  constexpr int L = P * Q, CW = ColWidth<P, Q, C>::v;
   __shared__ C s[P * CW];
   const int t = threadIdx.x;
   {
@@ -374,14 +376,14 @@ __global__ __launch_bounds__(256) void k_cols_p1(const C *__restrict__ src, int 
                                                  int y_lo, int y_hi, C *__restrict__ dst,
                                                  const C *__restrict__ tw, int cb0) {
   cols_p1_body<P, Q, DIR, C>(src, src_row0, y_lo, y_hi, dst, tw,
-                             (blockIdx.x + cb0) * ColWidth<P, Q>::v, blockIdx.y);
+                             (blockIdx.x + cb0) * ColWidth<P, Q, C>::v, blockIdx.y);
 }
 
 template <int P, int Q, int DIR, class C>
 __device__ __forceinline__ void cols_p2_body(const C *__restrict__ src, C *__restrict__ dst,
                                              int dst_row0, int k_lo, int k_hi, int modulate,
                                              const C *__restrict__ tw, int x0, int k1) {
-  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  constexpr int L = P * Q, CW = ColWidth<P, Q, C>::v;
   __shared__ C s[Q * CW];
   const int t = threadIdx.x;
   {
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(256) void k_cols_p2(const C *__restrict__ src,
                                                  int k_hi, int modulate,
                                                  const C *__restrict__ tw, int cb0) {
   cols_p2_body<P, Q, DIR, C>(src, dst, dst_row0, k_lo, k_hi, modulate, tw,
-                             (blockIdx.x + cb0) * ColWidth<P, Q>::v, blockIdx.y);
+                             (blockIdx.x + cb0) * ColWidth<P, Q, C>::v, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- batched transforms
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(256) void k_cols_p1_batch(const FftMember *__restri
                                                        const float2 *__restrict__ tw) {
   constexpr int L = P * Q;
   const FftMember &a = m[blockIdx.z];
-  constexpr int CW = ColWidth<P, Q>::v;
+  constexpr int CW = ColWidth<P, Q, float2>::v;
   if ((int)blockIdx.x >= (a.x1 - a.x0) / CW) return;
   const int x0 = a.x0 + blockIdx.x * CW;
   const int o = (L - n) / 2;
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(256) void k_cols_p2_batch(const FftMember *__restri
                                                        const float2 *__restrict__ tw) {
   constexpr int L = P * Q;
   const FftMember &a = m[blockIdx.z];
-  constexpr int CW = ColWidth<P, Q>::v;
+  constexpr int CW = ColWidth<P, Q, float2>::v;
   if ((int)blockIdx.x >= (a.x1 - a.x0) / CW) return;
   const int x0 = a.x0 + blockIdx.x * CW;
   const int o = (L - n) / 2;
@@ -659,7 +661,7 @@ __device__ __forceinline__ void cols_mid_body(C *__restrict__ buf, const C *__re
                                               int own_low, typename Real<C>::T coef,
                                               const C *__restrict__ tw, int x0, int k1) {
   typedef typename Real<C>::T RT;
-  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  constexpr int L = P * Q, CW = ColWidth<P, Q, C>::v;
   __shared__ C s[Q * CW];
   const int t = threadIdx.x;
   constexpr int PER = Q * CW / 256;
@@ -721,14 +723,14 @@ __global__ __launch_bounds__(256) void k_cols_mid(C *__restrict__ buf, const C *
                                                   int own_low, typename Real<C>::T coef,
                                                   const C *__restrict__ tw) {
   cols_mid_body<P, Q, MODE, C>(buf, spec, ell, delta, gscale, own_low, coef, tw,
-                               blockIdx.x * ColWidth<P, Q>::v, blockIdx.y);
+                               blockIdx.x * ColWidth<P, Q, C>::v, blockIdx.y);
 }
 
 template <int P, int Q, class C>
 __device__ __forceinline__ void cols_fin_body(const C *__restrict__ src, C *__restrict__ dst,
                                               int k_lo, int k_hi, const C *__restrict__ tw,
                                               int x0, int y2) {
-  constexpr int L = P * Q, CW = ColWidth<P, Q>::v;
+  constexpr int L = P * Q, CW = ColWidth<P, Q, C>::v;
   __shared__ C s[P * CW];
   const int t = threadIdx.x;
   {
@@ -754,7 +756,8 @@ __device__ __forceinline__ void cols_fin_body(const C *__restrict__ src, C *__re
 template <int P, int Q, class C>
 __global__ __launch_bounds__(256) void k_cols_fin(const C *__restrict__ src, C *__restrict__ dst,
                                                   int k_lo, int k_hi, const C *__restrict__ tw) {
-  cols_fin_body<P, Q, C>(src, dst, k_lo, k_hi, tw, blockIdx.x * ColWidth<P, Q>::v, blockIdx.y);
+  cols_fin_body<P, Q, C>(src, dst, k_lo, k_hi, tw, blockIdx.x * ColWidth<P, Q, C>::v,
+                         blockIdx.y);
 }
 
 template <int L>
@@ -779,7 +782,7 @@ template <> const double2 *row_twiddles<double2>(const imgr_s *h) { return h->tw
 template <int L, int DIR, class C>
 void cols(const C *src, int src_row0, int y_lo, int y_hi, C *tmp, C *dst, int dst_row0, int k_lo,
           int k_hi, int modulate, const C *tw, hipStream_t s, int cb0 = 0, int cb1 = L / 64) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q, C>::v;
   if (cb1 <= cb0) return;
   hipLaunchKernelGGL((k_cols_p1<P, Q, DIR, C>), dim3((cb1 - cb0) * F, Q), dim3(256), 0, s, src,
                      src_row0, y_lo, y_hi, tmp, tw, cb0 * F);
@@ -852,7 +855,7 @@ void filter_front_t(imgr_s *h, const typename Real<C>::T *a, const typename Real
                     hipStream_t s) {
   constexpr int P = Split<L>::P, Q = Split<L>::Q;
   const int c_hi = filter_cols<L>(h, mode, own_low, gscale);
-  const int CB = c_hi / ColWidth<P, Q>::v;  // launch blocks
+  const int CB = c_hi / ColWidth<P, Q, C>::v;  // launch blocks
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
   hipLaunchKernelGGL((k_rows_real_fwd<L, C>), dim3(n_in / 2), dim3(RowThreads<L>::v), 0, s, a, b,
@@ -909,7 +912,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_gamma_pair_rows_fwd(GammaP
 }
 template <int P, int Q, class C>
 __global__ __launch_bounds__(256) void k_gamma_pair_p1(GammaPair<C> g, const C *tw) {
-  constexpr int CW = ColWidth<P, Q>::v;
+  constexpr int CW = ColWidth<P, Q, C>::v;
   const GammaMember<C> m = pick(g, blockIdx.z);
   if ((int)blockIdx.x * CW >= m.c_hi) return;
   cols_p1_body<P, Q, -1, C>(m.work, 0, 0, P * Q, m.tmp, tw, blockIdx.x * CW, blockIdx.y);
@@ -917,7 +920,7 @@ __global__ __launch_bounds__(256) void k_gamma_pair_p1(GammaPair<C> g, const C *
 template <int P, int Q, class C>
 __global__ __launch_bounds__(256) void k_gamma_pair_mid(GammaPair<C> g, double ell, double delta,
                                                         const C *tw) {
-  constexpr int CW = ColWidth<P, Q>::v;
+  constexpr int CW = ColWidth<P, Q, C>::v;
   const GammaMember<C> m = pick(g, blockIdx.z);
   if ((int)blockIdx.x * CW >= m.c_hi) return;
   cols_mid_body<P, Q, FILT_GAMMA, C>(m.tmp, nullptr, ell, delta, 1.0, m.own_low, m.coef, tw,
@@ -925,7 +928,7 @@ __global__ __launch_bounds__(256) void k_gamma_pair_mid(GammaPair<C> g, double e
 }
 template <int P, int Q, class C>
 __global__ __launch_bounds__(256) void k_gamma_pair_fin(GammaPair<C> g, const C *tw) {
-  constexpr int CW = ColWidth<P, Q>::v;
+  constexpr int CW = ColWidth<P, Q, C>::v;
   const GammaMember<C> m = pick(g, blockIdx.z);
   if ((int)blockIdx.x * CW >= m.c_hi) return;
   cols_fin_body<P, Q, C>(m.tmp, m.work, 0, P * Q, tw, blockIdx.x * CW, blockIdx.y);
@@ -939,7 +942,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_gamma_pair_rows_inv(GammaP
 
 template <int L, class C>
 void gamma_pair_t(imgr_s *h, GammaPair<C> g, hipStream_t s) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q, CW = ColWidth<P, Q>::v;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, CW = ColWidth<P, Q, C>::v;
   for (int k = 0; k < 2; ++k) g.m[k].c_hi = filter_cols<L>(h, FILT_GAMMA, g.m[k].own_low, 1.0);
   const int cb = std::max(g.m[0].c_hi, g.m[1].c_hi) / CW;
   const C *tw = twiddles<C>(h);
@@ -979,7 +982,7 @@ namespace {
 template <int L>
 void model_to_grid_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
                            hipStream_t s) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q, float2>::v;
   hipLaunchKernelGGL((k_rows_model_batch<L>), dim3(n / 2, count), dim3(RowThreads<L>::v), 0, s,
                      m, n, h->twrow);
   if (max_cb == 0) return;
@@ -992,7 +995,7 @@ void model_to_grid_batch_t(const imgr_s *h, int n, const FftMember *m, int count
 template <int L>
 void grid_to_image_batch_t(const imgr_s *h, int n, const FftMember *m, int count, int max_cb,
                            hipStream_t s) {
-  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q>::v;
+  constexpr int P = Split<L>::P, Q = Split<L>::Q, F = 64 / ColWidth<P, Q, float2>::v;
   if (max_cb > 0) {
     hipLaunchKernelGGL((k_cols_p1_batch<P, Q, 1, 1>), dim3(max_cb * F, Q, count), dim3(256), 0, s,
                        m, n, h->tw);
