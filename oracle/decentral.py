@@ -112,7 +112,8 @@ def combine(images, weights=None):
 
 
 def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, niter=2000,
-                        threshold=0.0, partitions=2, ell=None, delta=1.0, support=8):
+                        threshold=0.0, partitions=2, ell=None, delta=1.0, support=8,
+                        record_gaps=False):
     """The major/minor loop with multi-scale CLEAN, serial (partitions = 1)
     or decentralized over V_L / V_H (partitions = 2), in FP64.
 
@@ -127,7 +128,9 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
     Serially the loop is Eq. 2 -> ms-CLEAN(i~, H, S, K) -> Eq. 3.
 
     Returns (final image, per-node models, history) with history a list of
-    per-cycle dicts {node: (dirty D, psf P, components)}.
+    per-cycle dicts {node: (dirty D, psf P, components, ibar, gaps)}; gaps
+    is the per-iteration near-tie margin of ``msclean.msclean`` with
+    ``record_gaps``, else None.
     """
     from . import imaging, msclean as msc
     m = len(u)
@@ -158,9 +161,11 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
                 d_img = compose_dirty(resid, rho[k], psf[other[k]], ell, delta, k, gamma, mu)
                 p_img = compose_psf(psf[k], psf[other[k]], ell, delta, k, gamma, mu)
                 active = msc.scale_subset(scales, n_img, ell, delta, k) if cyc == 1 else None
-            ibar, _, comps = msc.msclean(d_img, p_img, scales, gain, niter, threshold, active)
+            st = {} if record_gaps else None
+            ibar, _, comps = msc.msclean(d_img, p_img, scales, gain, niter, threshold, active,
+                                         state=st)
             deltas[k] = ibar
-            step[k] = (d_img, p_img, comps)
+            step[k] = (d_img, p_img, comps, ibar, st["gaps"] if record_gaps else None)
         for k in nodes:
             models[k] = models[k] + deltas[k]
         if partitions == 2:

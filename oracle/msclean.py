@@ -24,7 +24,10 @@ The PSF is the 2N x 2N image of imaging.psf2 (centre (N, N)), so a unit
 source at pixel q of the N x N image contributes psf2[N + p - q] at p.
 
 Parity: pinned by the Hogbom reduction, the single-source closed form, the
-consistency R_0 = dirty - psf * model and flux conservation (tests).
+consistency R_0 = dirty - psf * model, flux conservation, and the
+invariant R_t = phi_t * R_0 on pixels at least the kernel radius from the
+edge, which holds only if every cross PSF B_st and every R_t update is
+right (tests).
 """
 
 import numpy as np
@@ -84,7 +87,7 @@ def add_component(model, kern, iy, ix, amp):
 
 
 def msclean(dirty, psf2, scales, gain=0.1, niter=2000, threshold=0.0, active=None,
-            bias_slope=0.6):
+            bias_slope=0.6, state=None):
     """Run the minor cycle.  Returns (model, residual R_0, components) with
     components a list of (scale index, iy, ix, alpha) in iteration order.
 
@@ -92,6 +95,12 @@ def msclean(dirty, psf2, scales, gain=0.1, niter=2000, threshold=0.0, active=Non
     indices of S the peak search may pick (psi^n of Eq. 7); scale 0 need not
     be in S - the unsmoothed residual R_0 is tracked for the threshold
     anyway.
+
+    ``state`` (optional dict) receives, without changing any result:
+    "resid", the smoothed residuals R_t after the last iteration, and
+    "gaps", per iteration the margin between the chosen candidate's biased
+    value and the best value of every other (scale, pixel) candidate (a
+    margin near zero marks a near-tie that rounding could reorder).
     """
     dirty = np.asarray(dirty, np.float64)
     psf2 = np.asarray(psf2, np.float64)
@@ -106,6 +115,7 @@ def msclean(dirty, psf2, scales, gain=0.1, niter=2000, threshold=0.0, active=Non
     psf_plain = [convolve_same(psf2, k) for k in kern]  # phi_t * psf2 for the R_0 update
     model = np.zeros((n, n))
     comps = []
+    gaps = []
     for _ in range(niter):
         if np.abs(r0).max() < threshold:
             break
@@ -115,6 +125,16 @@ def msclean(dirty, psf2, scales, gain=0.1, niter=2000, threshold=0.0, active=Non
             p = int(np.argmax(v))  # first occurrence: smallest flat index
             if v.flat[p] > best_v:
                 best_v, best_s, best_p = v.flat[p], si, p
+        if state is not None:
+            second = -1.0
+            for si in active:
+                v = (bias[si] * np.abs(resid[si])).ravel()
+                if si == best_s:
+                    if v.size > 1:
+                        second = max(second, np.partition(v, -2)[-2])
+                else:
+                    second = max(second, v.max())
+            gaps.append(best_v - second)
         iy, ix = divmod(best_p, n)
         b_ss = cross[(best_s, best_s)]
         alpha = gain * resid[best_s][iy, ix] / b_ss[n, n]
@@ -125,6 +145,9 @@ def msclean(dirty, psf2, scales, gain=0.1, niter=2000, threshold=0.0, active=Non
             resid[t] -= alpha * b[win]
         r0 -= alpha * psf_plain[best_s][win]
         comps.append((best_s, iy, ix, alpha))
+    if state is not None:
+        state["resid"] = resid
+        state["gaps"] = gaps
     return model, r0, comps
 
 

@@ -1,0 +1,364 @@
+"""Pins of the oracle's decentralized pieces that the basic pins leave open
+(no GPU).
+
+* Multi-scale CLEAN (Eq. 6): every smoothed residual obeys
+  R_t = phi_t * R_0 on pixels at least the kernel radius from the edge, at
+  any iteration.  The identity holds only if every cross PSF B_st
+  (s != t included) and every update of an R_t with t != s* is right.
+* FISTA (Eqs. 4, 5): the gradient agrees with central differences of the
+  smooth objective (exact for a quadratic up to rounding), and with H = I
+  and lambda = 0 the iterates reach the minimiser of Eq. 5, which is
+  diagonal in the Fourier domain.
+* Composition (Eq. 7): for (u, v) on the Fourier lattice of the N x N image
+  the direct-sum PSFs are exact cosine sums, a filter Gamma multiplies each
+  term by its value at that sample's radius, and the mu term is the normal
+  operator of the other partition.  That gives closed forms for the
+  composed dirty image and PSF with mu != 0.
+
+Every pin is shown to fail on planted mistakes (a swapped filter, a wrong
+cross PSF, a flipped sign) patched into the oracle for the duration of one
+test.
+"""
+
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import decentral, dft, fista, imaging, msclean, wavelets
+from oracle.imaging import apply_psf
+
+
+def _small_psf(n=48, m=400, seed=31):
+    rng = np.random.default_rng(seed)
+    cell = 1.0 / (3.0 * 40.0)
+    u, v = rng.uniform(-40.0, 40.0, (2, m))
+    return imaging.psf2(u, v, np.ones(m), n, cell)
+
+
+# ------------------------------------------------------------------ msCLEAN
+
+SCALES = [0, 2, 4]
+
+
+def _msclean_invariant():
+    """Largest |R_t - phi_t * R_0| over interior pixels and t, relative to
+    max |R_t|, after 150 iterations on a field of points and blobs; and the
+    scales the components used."""
+    n = 48
+    psf = _small_psf(n)
+    rng = np.random.default_rng(32)
+    truth = np.zeros((n, n))
+    truth[rng.integers(6, n - 6, 8), rng.integers(6, n - 6, 8)] = rng.uniform(0.3, 1.0, 8)
+    yy, xx = np.mgrid[0:n, 0:n]
+    for cy, cx, s, a in ((14, 30, 3.0, 2.0), (33, 16, 2.0, 1.5)):
+        truth += a * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * s * s))
+    dirty = apply_psf(psf, truth)
+    err, used = 0.0, set()
+    # the peak search over all scales, then over one larger scale at a time,
+    # so that every B_st (s* in S, t in S) enters some update
+    for active in (None, [1], [2]):
+        st = {}
+        _, r0, comps = msclean.msclean(dirty, psf, SCALES, gain=0.1, niter=150, active=active,
+                                       state=st)
+        used |= {c[0] for c in comps}
+        for t, s in enumerate(SCALES):
+            k = msclean.scale_kernel(s)
+            r = k.shape[0] // 2
+            ref = signal.convolve2d(r0, k, mode="same")
+            got = st["resid"][t]
+            inner = (slice(r, n - r), slice(r, n - r))
+            err = max(err, np.abs(got[inner] - ref[inner]).max() / np.abs(got).max())
+    return err, used
+
+
+def test_msclean_smoothed_residuals_stay_consistent():
+    err, used = _msclean_invariant()
+    assert used == {0, 1, 2}, used  # components at every scale
+    assert err < 1e-12, err
+
+
+def _cross_same_scale(psf2, scales):
+    """Planted: B_ab = phi_a * phi_a * psf for every b (wrong off-diagonal)."""
+    ker = [msclean.scale_kernel(s) for s in scales]
+    return {(a, b): msclean.convolve_same(psf2, signal.convolve2d(ker[a], ker[a]))
+            for a in range(len(scales)) for b in range(a, len(scales))}
+
+
+def _cross_one_kernel(psf2, scales):
+    """Planted: B_ab = phi_b * psf (one smoothing missing)."""
+    ker = [msclean.scale_kernel(s) for s in scales]
+    return {(a, b): msclean.convolve_same(psf2, ker[b])
+            for a in range(len(scales)) for b in range(a, len(scales))}
+
+
+def _cross_no_offdiag(psf2, scales):
+    """Planted: only R_{s*} is updated (zero off-diagonal cross PSFs)."""
+    good = _ORIG_CROSS(psf2, scales)
+    return {k: (v if k[0] == k[1] else np.zeros_like(v)) for k, v in good.items()}
+
+
+_ORIG_CROSS = msclean.cross_psfs
+
+
+@pytest.mark.parametrize("planted", [_cross_same_scale, _cross_one_kernel, _cross_no_offdiag])
+def test_msclean_invariant_catches_planted_cross_psf_mistakes(monkeypatch, planted):
+    monkeypatch.setattr(msclean, "cross_psfs", planted)
+    err, _ = _msclean_invariant()
+    assert err > 1e-6, err
+
+
+def test_msclean_gaps_are_margins_of_the_chosen_candidate():
+    """The recorded near-tie margins are >= 0 and equal the distance to the
+    runner-up recomputed by brute force at the first iteration."""
+    n = 24
+    psf = _small_psf(n, 200, 33)
+    rng = np.random.default_rng(34)
+    dirty = apply_psf(psf, rng.standard_normal((n, n)))
+    st = {}
+    msclean.msclean(dirty, psf, SCALES, niter=20, state=st)
+    assert len(st["gaps"]) == 20 and min(st["gaps"]) >= 0.0
+    bias = msclean.scale_bias(SCALES)
+    vals = np.concatenate([(bias[i] * np.abs(msclean.convolve_same(dirty, msclean.scale_kernel(s))))
+                           .ravel() for i, s in enumerate(SCALES)])
+    top2 = np.sort(vals)[-2:]
+    assert abs(st["gaps"][0] - (top2[1] - top2[0])) < 1e-15 * top2[1]
+
+
+# ------------------------------------------------------------------ FISTA
+
+def _problems():
+    n = 32
+    psf = _small_psf(n, 300, 11)
+    rng = np.random.default_rng(40)
+    dirty = apply_psf(psf, rng.standard_normal((n, n)))
+    rho = 0.3 * rng.standard_normal((n, n))
+    h = wavelets.daubechies(4)
+    yield "serial", fista.NodeProblem(dirty, psf, None, 0.0, 6.0, 1.0, "L", h, 2, serial=True)
+    for own in ("L", "H"):
+        yield own, fista.NodeProblem(dirty, psf, rho, 1.0, 6.0, 1.0, own, h, 2)
+
+
+def _fd_errors():
+    """Relative gap between <grad f(a), d> and the central difference of the
+    smooth objective (lambda = 0) along random d, for each problem."""
+    rng = np.random.default_rng(41)
+    out = {}
+    for name, prob in _problems():
+        a = rng.standard_normal((32, 32))
+        g = prob.grad(a)
+        worst = 0.0
+        for _ in range(3):
+            d = rng.standard_normal((32, 32))
+            eps = 1e-2  # f is quadratic: the central difference has no truncation error
+            fd = (prob.objective(a + eps * d, 0.0) - prob.objective(a - eps * d, 0.0)) / (2 * eps)
+            worst = max(worst, abs(fd - np.vdot(g, d)) / (np.linalg.norm(g) * np.linalg.norm(d)))
+        out[name] = worst
+    return out
+
+
+def test_fista_gradient_matches_central_differences():
+    errs = _fd_errors()
+    assert max(errs.values()) < 1e-10, errs
+
+
+def _grad_rho_sign(self, a):
+    x = self.W(a)
+    t = apply_psf(self.psf, self.gam(self.gam(self.dirty - apply_psf(self.psf, x), self.g_own),
+                                     self.g_own))
+    if self.gamma_n != 0.0:
+        t = t - self.gamma_n * self.gam(self.rho - self.gam(x, self.g_other), self.g_other)
+    return -2.0 * self.Wt(t)
+
+
+def _grad_rho_own_filter(self, a):
+    x = self.W(a)
+    t = apply_psf(self.psf, self.gam(self.gam(self.dirty - apply_psf(self.psf, x), self.g_own),
+                                     self.g_own))
+    if self.gamma_n != 0.0:
+        t = t + self.gamma_n * self.gam(self.rho - self.gam(x, self.g_other), self.g_own)
+    return -2.0 * self.Wt(t)
+
+
+def _grad_single_filter(self, a):
+    x = self.W(a)
+    t = apply_psf(self.psf, self.gam(self.dirty - apply_psf(self.psf, x), self.g_own))
+    if self.gamma_n != 0.0:
+        t = t + self.gamma_n * self.gam(self.rho - self.gam(x, self.g_other), self.g_other)
+    return -2.0 * self.Wt(t)
+
+
+@pytest.mark.parametrize("planted", [_grad_rho_sign, _grad_rho_own_filter, _grad_single_filter])
+def test_fista_gradient_check_catches_planted_mistakes(monkeypatch, planted):
+    monkeypatch.setattr(fista.NodeProblem, "grad", planted)
+    errs = _fd_errors()
+    assert max(errs["L"], errs["H"]) > 1e-4, errs
+
+
+def _eq5_minimiser_error(own):
+    """H = I, lambda = 0, gamma_n = 1: the minimiser of Eq. 5 is, per DFT
+    frequency, (G_own^2 D + G_other R) / (G_own^2 + G_other^2); FISTA's
+    image W alpha after 300 iterations against it (relative L2)."""
+    n = 32
+    rng = np.random.default_rng(42)
+    dirty = rng.standard_normal((n, n))
+    rho = rng.standard_normal((n, n))
+    psf = np.zeros((2 * n, 2 * n))
+    psf[n, n] = 1.0
+    ell, delta = 6.3, 1.0
+    g_own, g_other = decentral.filters(n, ell, delta, own)
+    spec = ((g_own ** 2) * np.fft.fft2(dirty) + g_other * np.fft.fft2(rho)) / (g_own ** 2 + g_other ** 2)
+    expect = np.fft.ifft2(spec).real
+    prob = fista.NodeProblem(dirty, psf, rho, 1.0, ell, delta, own, wavelets.daubechies(4), 2)
+    L_hat = fista.power_iteration(prob, rng.standard_normal((n, n)), 30)
+    alpha, _ = fista.fista(prob, 0.0, 300, L_hat)
+    got = prob.W(alpha)
+    return np.linalg.norm(got - expect) / np.linalg.norm(expect)
+
+
+@pytest.mark.parametrize("own", ["L", "H"])
+def test_fista_reaches_eq5_minimiser_in_closed_form(own):
+    assert _eq5_minimiser_error(own) < 1e-9
+
+
+@pytest.mark.parametrize("planted", [_grad_rho_sign, _grad_rho_own_filter])
+def test_eq5_minimiser_pin_catches_planted_mistakes(monkeypatch, planted):
+    monkeypatch.setattr(fista.NodeProblem, "grad", planted)
+    with np.errstate(over="ignore", invalid="ignore"):
+        err = _eq5_minimiser_error("L")
+    assert not (err < 1e-3), err
+
+
+# ------------------------------------------------------------------ composition (Eq. 7)
+
+N_C, CELL, ELL, DELTA = 32, 1.0e-3, 4.3, 1.0
+
+
+def _lattice():
+    """Samples on the N x N image's Fourier lattice (integer Fourier pixels
+    a, b), both partitions well populated and several in the overlap ramp."""
+    rng = np.random.default_rng(50)
+    ab = rng.integers(-7, 8, (2, 160)).astype(np.float64)
+    u, v = ab / (N_C * CELL)
+    w = rng.uniform(0.5, 2.0, 160)
+    vis = rng.standard_normal(160) + 1j * rng.standard_normal(160)
+    low, high, _ = imaging.partition(u, v, N_C, CELL, ell=ELL, delta=DELTA)
+    rho_k = np.hypot(ab[0], ab[1])
+    assert np.sum((rho_k > ELL - DELTA) & (rho_k < ELL + DELTA)) > 10
+    return u, v, w, vis, {"L": low, "H": high}, rho_k
+
+
+def _ramp(rho_k, node):
+    lo = np.clip((ELL + DELTA - rho_k) / (2 * DELTA), 0.0, 1.0)
+    return lo if node == "L" else 1.0 - lo
+
+
+def _psf_dft(u, v, w):
+    return dft.adjoint(w, u, v, CELL, 2 * N_C).real / w.sum()
+
+
+def _cos_sum(u, v, amp, n):
+    """Re sum_k amp_k exp(+2 pi i (u_k l + v_k m)) on an n x n image."""
+    return dft.adjoint(amp, u, v, CELL, n).real
+
+
+def _composition_errors(gamma=0.35, mu=0.65):
+    u, v, w, vis, mask, rho_k = _lattice()
+    other = {"L": "H", "H": "L"}
+    rng = np.random.default_rng(51)
+    rho_img = rng.standard_normal((N_C, N_C))
+    errs = {}
+    for own in ("L", "H"):
+        mo, mt = mask[own], mask[other[own]]
+        wo, wt = w[mo].sum(), w[mt].sum()
+        psf_own, psf_other = _psf_dft(u[mo], v[mo], w[mo]), _psf_dft(u[mt], v[mt], w[mt])
+        got_p = decentral.compose_psf(psf_own, psf_other, ELL, DELTA, own, gamma, mu)
+        exp_p = (gamma * _cos_sum(u[mo], v[mo], w[mo] * _ramp(rho_k[mo], own), 2 * N_C) / wo
+                 + mu * _cos_sum(u[mt], v[mt], w[mt] * _ramp(rho_k[mt], other[own]), 2 * N_C) / wt)
+        resid = _cos_sum(u[mo], v[mo], w[mo] * vis[mo], N_C) / wo
+        got_d = decentral.compose_dirty(resid, rho_img, psf_other, ELL, DELTA, own, gamma, mu)
+        a_rho = dft.forward(rho_img, u[mt], v[mt], CELL)
+        exp_d = (gamma * _cos_sum(u[mo], v[mo], w[mo] * _ramp(rho_k[mo], own) * vis[mo], N_C) / wo
+                 + mu * dft.adjoint(w[mt] * a_rho, u[mt], v[mt], CELL, N_C).real / wt)
+        errs[own] = (np.abs(got_p - exp_p).max() / np.abs(exp_p).max(),
+                     np.abs(got_d - exp_d).max() / np.abs(exp_d).max())
+    return errs
+
+
+def test_composition_closed_forms_with_mu():
+    errs = _composition_errors()
+    assert max(max(e) for e in errs.values()) < 1e-12, errs
+
+
+_ORIG_FILTERS, _ORIG_PSF_FILTERS = decentral.filters, decentral.psf_filters
+
+
+def _filters_swapped(n_img, ell, delta, own):
+    a, b = _ORIG_FILTERS(n_img, ell, delta, own)
+    return b, a
+
+
+def _psf_filters_swapped(n_img, ell, delta, own):
+    a, b = _ORIG_PSF_FILTERS(n_img, ell, delta, own)
+    return b, a
+
+
+def _psf_filters_unscaled(n_img, ell, delta, own):
+    lo = decentral.gamma_low(2 * n_img, ell, delta)  # index, not physical frequency
+    return (lo, 1.0 - lo) if own == "L" else (1.0 - lo, lo)
+
+
+def _psf_filters_same(n_img, ell, delta, own):
+    a, _ = _ORIG_PSF_FILTERS(n_img, ell, delta, own)
+    return a, a
+
+
+@pytest.mark.parametrize("name,planted", [("filters", _filters_swapped),
+                                          ("psf_filters", _psf_filters_swapped),
+                                          ("psf_filters", _psf_filters_unscaled),
+                                          ("psf_filters", _psf_filters_same)])
+def test_composition_pin_catches_planted_mistakes(monkeypatch, name, planted):
+    monkeypatch.setattr(decentral, name, planted)
+    errs = _composition_errors()
+    assert max(max(e) for e in errs.values()) > 1e-3, errs
+
+
+def test_composition_pin_catches_swapped_psfs():
+    """compose_* given the own PSF where the other's belongs (or the
+    reverse) misses the closed form."""
+    u, v, w, vis, mask, rho_k = _lattice()
+    rng = np.random.default_rng(51)
+    rho_img = rng.standard_normal((N_C, N_C))
+    mo, mt = mask["L"], mask["H"]
+    psf_own, psf_other = _psf_dft(u[mo], v[mo], w[mo]), _psf_dft(u[mt], v[mt], w[mt])
+    good = decentral.compose_psf(psf_own, psf_other, ELL, DELTA, "L", 0.35, 0.65)
+    bad = decentral.compose_psf(psf_other, psf_own, ELL, DELTA, "L", 0.35, 0.65)
+    assert np.abs(good - bad).max() > 1e-3 * np.abs(good).max()
+    resid = _cos_sum(u[mo], v[mo], w[mo] * vis[mo], N_C) / w[mo].sum()
+    good = decentral.compose_dirty(resid, rho_img, psf_other, ELL, DELTA, "L", 0.35, 0.65)
+    bad = decentral.compose_dirty(resid, rho_img, psf_own, ELL, DELTA, "L", 0.35, 0.65)
+    assert np.abs(good - bad).max() > 1e-3 * np.abs(good).max()
+
+
+def test_loop_composes_with_the_other_partitions_psf_and_rho():
+    """In the decentralized loop, node k's cycle-2 dirty image minus
+    gamma Gamma_own i~_own is mu H_other rho_k, with H_other the other
+    partition's normal operator at the direct-sum level (gridding
+    accuracy) and rho_k = Gamma_other (ibar_other - ibar_own) of cycle 1."""
+    u, v, w, vis, mask, rho_k = _lattice()
+    final, models, hist = decentral.reconstruct_msclean(
+        u, v, vis, w, N_C, CELL, 2, [0, 2], gain=0.2, niter=30, partitions=2, ell=ELL,
+        delta=DELTA)
+    other = {"L": "H", "H": "L"}
+    wsum = {k: w[m].sum() for k, m in mask.items()}
+    for own in ("L", "H"):
+        mo, mt = mask[own], mask[other[own]]
+        ib_own, ib_other = hist[0][own][3], hist[0][other[own]][3]
+        gamma, mu = decentral.weights_schedule(2, wsum[own], wsum[other[own]])
+        resid, _ = imaging.residual_image(u[mo], v[mo], vis[mo], w[mo], ib_own, CELL)
+        g_own, g_other = decentral.filters(N_C, ELL, DELTA, own)
+        mu_term = hist[1][own][0] - gamma * decentral.apply_filter(resid, g_own)
+        rho = decentral.apply_filter(ib_other - ib_own, g_other)
+        expect = mu * dft.adjoint(w[mt] * dft.forward(rho, u[mt], v[mt], CELL), u[mt], v[mt],
+                                  CELL, N_C).real / wsum[other[own]]
+        err = np.linalg.norm(mu_term - expect) / np.linalg.norm(expect)
+        assert err < 1e-5, (own, err)
