@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the major-cycle measurement operator on one MI355X.
 
-A step is one decentralized major cycle of the two-partition workload:
-for each node (V_L, then V_H) the model is transformed to the grid, every
-visibility is degridded, its weighted residual gridded, the grid flushed and
-transformed back to the residual image (Eq. 2), and the residual is composed
-with the other node's aggregate through the other node's PSF (Eq. 7).
-Preparation (weighting, partition, sort) and the PSFs are one-time work of
-imager_create and are timed separately (create_ms).
+A step is one decentralized major cycle of a two-partition workload: for
+each node (V_L and V_H, concurrently) the model is transformed to the
+grid, every visibility is degridded, its weighted residual gridded, the
+grid flushed and transformed back to the residual image (Eq. 2), and the
+residual is composed with the other node's aggregate through the other
+node's PSF (Eq. 7).  Preparation (weighting, partition, sort) and the PSFs
+are one-time work of imager_create and are timed separately (create_ms).
+
+The headline workload is the largest single-GPU one (50,004,480
+visibilities, 2048^2 image); the 15.7M-visibility 1024^2 workload is
+measured the same way as an extra.  Every timed configuration's outputs are
+compared with the FP64 oracle run over the same full partitions, which is
+also timed on the host's cores as the CPU baseline.
 
 Prints one JSON line.  ``value`` is whole-job throughput: unflagged
 visibilities of the data set per second of major cycle (Mvis/s), inputs
@@ -28,21 +34,26 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_MATRIX = 157.3
 
 
-# HBM bytes per launch of the fused de/grid kernel on this workload, from the
+# HBM bytes per launch of the fused de/grid kernel, per workload, from the
 # FETCH_SIZE / WRITE_SIZE counter runs with the copy-kernel calibration
-# (profiles/k_window_decentral_hbm_traffic.md), valid only for the kernel
-# source the counters were taken on.
-KWINDOW_TRAFFIC = {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
-                   "sha256_16": "77d023a885a28790",
-                   "bytes_per_launch": (99263.4 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)}
+# (profiles/k_window_*_hbm_traffic.md), valid only for the kernel source the
+# counters were taken on.
+KWINDOW_TRAFFIC = {
+    "decentral": {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
+                  "sha256_16": "77d023a885a28790",
+                  "bytes_per_launch": (99263.4 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)},
+}
 
 
-def measured_traffic():
+def measured_traffic(name):
     import hashlib
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), KWINDOW_TRAFFIC["src"])
+    t = KWINDOW_TRAFFIC.get(name)
+    if t is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["src"])
     with open(path, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return KWINDOW_TRAFFIC["bytes_per_launch"] if sha == KWINDOW_TRAFFIC["sha256_16"] else None
+    return t["bytes_per_launch"] if sha == t["sha256_16"] else None
 
 
 def log(msg):
@@ -57,63 +68,75 @@ def flops_per_vis(w):
     return 8 * w * w + 18 * w + 4
 
 
-def cpu_baseline(args, gpu_gamma_mu):
-    """The FP64 oracle, as it stands, on a sample of the same workload (the
-    first n_time time steps); the GPU runs the same sample to report the
-    error of the benchmarked path against it."""
+def oracle_cycle(d, outs, locs, workers):
+    """The FP64 oracle, as it stands, on the full timed partitions: weights,
+    partition and both PSFs (one-time work, untimed, as the library's
+    create), then one decentralized major cycle of both nodes (Eq. 2 for
+    each node's visibilities, then Eq. 7) with the same model and aggregate
+    images as the timed steps, timed.  Gridding and degridding run over
+    visibility chunks on ``workers`` host processes (oracle.pool); the FFTs
+    are NumPy's.  Returns the cpu_baseline object and the errors of the
+    timed GPU outputs against the oracle's."""
     import numpy as np
-    import torch
-    from oracle import decentral, geometry, imaging
-    from paper_2507_22128_amd import imager, synth
-
-    d = synth.make(args.workload, n_time=args.cpu_sample_times)
+    from oracle import decentral, geometry, imaging, pool
     n = d["n_img"]
+    cell = d["cell"]
+    t0 = time.perf_counter()
     u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
-    w = imaging.uniform_weights(u, v, n, d["cell"])
-    low, high, ell = imaging.partition(u, v, n, d["cell"])
+    w = imaging.uniform_weights(u, v, n, cell)
+    low, high, ell = imaging.partition(u, v, n, cell)
     masks = (low, high)
-    model = 0.5 * d["truth"]
-    rho = 0.01 * d["truth"]
-    psfs = [imaging.psf2(u[m], v[m], w[m], n, d["cell"]) for m in masks]
+    psfs = [pool.psf2(u[m], v[m], w[m], n, cell, workers=workers) for m in masks]
+    t_setup = time.perf_counter() - t0
     wsum = [w[m].sum() for m in masks]
     gm = [decentral.weights_schedule(2, wsum[p], wsum[1 - p]) for p in (0, 1)]
+    model = [0.5 * d["truth"]] * 2
+    rho = [0.01 * d["truth"]] * 2
     t0 = time.perf_counter()
-    outs = []
-    for p, own in ((0, "L"), (1, "H")):
-        m = masks[p]
-        loc, _ = imaging.residual_image(u[m], v[m], d["vis"][m], w[m], model, d["cell"])
-        outs.append(decentral.compose_dirty(loc, rho, psfs[1 - p], ell, 1.0, own, *gm[p]))
+    ref_outs, ref_locs = pool.decentral_cycle(u, v, d["vis"], w, masks, model, rho, psfs,
+                                              [g[0] for g in gm], [g[1] for g in gm], ell, 1.0,
+                                              cell, workers=workers)
     t_cpu = time.perf_counter() - t0
-    n_valid = len(u)
-    # the GPU on the same sample
-    h = imager.Imager.create(d, n_partitions=2, weighting="uniform")
-    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
-    errs = []
-    for p in (0, 1):
-        got = h.major_cycle(p, dev(model), dev(rho), *gm[p]).cpu().double().numpy()
-        errs.append(float(np.linalg.norm(got - outs[p]) / np.linalg.norm(outs[p])))
-    h.destroy()
-    return {
-        "value": n_valid / t_cpu / 1e6,
+    relerr = lambda a, b: float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+    err = {"composed_rel_l2": [relerr(outs[p], ref_outs[p]) for p in (0, 1)],
+           "local_rel_l2": [relerr(locs[p], ref_locs[p]) for p in (0, 1)]}
+    err["max_rel_l2"] = max(err["composed_rel_l2"] + err["local_rel_l2"])
+    err["tolerance"] = 1e-5
+    err["pass"] = bool(err["max_rel_l2"] <= 1e-5)
+    try:
+        cpu_model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                     if ln.startswith("model name")][0]
+    except (OSError, IndexError):
+        cpu_model = "unknown"
+    base = {
+        "value": round(len(u) / t_cpu / 1e6, 4),
         "unit": "Mvis/s",
-        "cores": 1,
+        "cores": int(workers),
         "kind": "oracle",
-        "sample": "one decentralized major cycle (both partitions, Eq. 2 + Eq. 7) of the first %d "
-                  "time steps of the same array, sky and image (%d visibilities), FP64 "
-                  "NumPy/SciPy, single thread, %.1f s" % (args.cpu_sample_times, n_valid, t_cpu),
-        "gpu_rel_err_on_sample": max(errs),
+        "sample": "the whole timed workload: one decentralized major cycle of both partitions "
+                  "(%d visibilities; Eq. 2 per node, then Eq. 7) with the timed step's model "
+                  "and aggregate images, FP64 NumPy/SciPy oracle, de/gridding over visibility "
+                  "chunks on %d processes, NumPy FFTs; %.1f s (weights, partition and PSFs, "
+                  "one-time like the library's create, %.1f s more, untimed)"
+                  % (len(u), workers, t_cpu, t_setup),
+        "cpu_model": cpu_model,
+        "seconds": round(t_cpu, 2),
     }
+    return base, err
 
 
-def minor_cycles(h, info, model, rho, gammas, mus, n):
-    """Device time of the two minor cycles on node V_L's cycle-2 problem of
-    the benchmark workload: multi-scale CLEAN (S = {0, 4, 12} px, gain 0.1,
-    K = 2000, FP64) on the composed dirty image and PSF of Eq. 7, and FISTA
-    (db8, 3 levels, 200 iterations, 30 power iterations, lambda = 1e-3 max |i~|,
-    FP64 transforms) on the node's residual and aggregate (Eq. 5)."""
+def minor_cycles(h, info, model, rho, gammas, mus, n, msclean=True):
+    """Device time of the minor cycles on node V_L's cycle-2 problem of the
+    workload: multi-scale CLEAN (S = {0, 4, 12} px, gain 0.1, K = 2000,
+    FP64) on the composed dirty image and PSF of Eq. 7 (with ``msclean``),
+    and FISTA (db8, 3 levels, 200 iterations, 30 power iterations, lambda =
+    1e-3 max |i~|, FP64 transforms) on the node's residual and aggregate
+    (Eq. 5), plus FISTA over the 8-basis dictionary (50 iterations)."""
     import numpy as np
     import torch
     out = {}
+    if not msclean:
+        return _fista_cycles(h, model, rho, gammas, mus, n, out)
     dirty = h.major_cycle(0, model[0], rho[0], gammas[0], mus[0])
     psf = h.composed_psf(0, gammas[0], mus[0])
     h.minor_cycle_msclean(0, dirty, psf, [0, 4, 12], niter=10)  # work area, warm
@@ -130,6 +153,12 @@ def minor_cycles(h, info, model, rho, gammas, mus, n):
         "update_hbm_frac": round(bytes_iter * len(comps) / t_msc / 1e9 / HBM_PEAK_GBS, 4),
         "config": "node V_L, cycle-2 composed dirty / PSF (Eq. 7), %d^2, S = {0, 4, 12} px, "
                   "gain 0.1, K = 2000, FP64" % n}
+    return _fista_cycles(h, model, rho, gammas, mus, n, out)
+
+
+def _fista_cycles(h, model, rho, gammas, mus, n, out):
+    import numpy as np
+    import torch
     local = torch.empty((n, n), device="cuda")
     h.major_cycle(0, model[0], rho[0], gammas[0], mus[0], local_out=local)
     start = torch.tensor(np.random.default_rng(7).standard_normal((n, n)), dtype=torch.float32,
@@ -157,73 +186,12 @@ def minor_cycles(h, info, model, rho, gammas, mus, n):
         "ms": round(1e3 * t_fd, 2), "iterations": 50, "power_iterations": 30,
         "config": "node V_L, Eq. 5 with gamma_n = 1, %d^2, W = the concatenation of db1 .. db8 "
                   "(8 N^2 coefficients), 3 levels, lambda = 1e-3 max |i~|, FP64 transforms" % n}
-    log("minor cycles: msCLEAN %.1f ms (%d iterations), FISTA %.1f ms (200 + 30 power), "
-        "FISTA with the 8-basis dictionary %.1f ms (50 + 30 power)"
-        % (1e3 * t_msc, len(comps), 1e3 * t_fista, 1e3 * t_fd))
+    log("minor cycles at N = %d: %s, FISTA %.1f ms (200 + 30 power), FISTA with the 8-basis "
+        "dictionary %.1f ms (50 + 30 power)"
+        % (n, ("msCLEAN %.1f ms (%d iterations)" % (out["msclean"]["ms"],
+                                                    out["msclean"]["iterations"]))
+           if "msclean" in out else "no msCLEAN", 1e3 * t_fista, 1e3 * t_fd))
     return out
-
-
-def convex(args):
-    """The sparsity-regularised workload's shapes: 256 antennas x 1532 times
-    = 50,004,480 visibilities at 1.4 GHz, N = 2048, 2 partitions (median
-    split), support 8; point-source sky (500 sources) from the GPU
-    generator.  Times the two-node major cycle and node V_L's FISTA minor
-    cycle (db8, 3 levels, 200 iterations, 30 power iterations, lambda =
-    1e-3 max |i~|, gamma_n = 1)."""
-    import numpy as np
-    import torch
-    from paper_2507_22128_amd import imager, synth
-    t0 = time.perf_counter()
-    d = synth.make_channels(n_chan=1, n_time=1532, f_lo=1.4e9, f_hi=1.4e9, flag_max=0.0,
-                            sizes=(2048,), n_points=500, seed=3, device="cuda")
-    c = d["channels"][0]
-    h = imager.Imager.create(uvw=d["uvw"], vis=c["vis"], freq_hz=c["freq_hz"], cell=c["cell"],
-                             n_pix=2048, n_partitions=2, weighting="uniform")
-    info = h.info
-    del d, c
-    torch.cuda.empty_cache()
-    log("convex: %d visibilities, N = 2048, handle built in %.1f s (create %.0f ms)"
-        % (info.n_valid, time.perf_counter() - t0, info.create_ms))
-    n = 2048
-    g = torch.Generator(device="cuda")
-    g.manual_seed(5)
-    model = [torch.zeros((n, n), device="cuda") for _ in range(2)]
-    rho = [1e-3 * torch.randn((n, n), generator=g, device="cuda") for _ in range(2)]
-    outs = [torch.empty((n, n), device="cuda") for _ in range(2)]
-    locs = [torch.empty((n, n), device="cuda") for _ in range(2)]
-    wsum = info.sum_w[0] + info.sum_w[1]
-    gm = [info.sum_w[0] / wsum, info.sum_w[1] / wsum]
-    mu = [gm[1], gm[0]]
-    for _ in range(2):
-        h.major_cycle_nodes(model, rho, gm, mu, outs=outs, local_outs=locs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps = 10
-    for _ in range(steps):
-        h.major_cycle_nodes(model, rho, gm, mu, outs=outs, local_outs=locs)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
-    start = torch.tensor(np.random.default_rng(7).standard_normal((n, n)), dtype=torch.float32,
-                         device="cuda")
-    h.minor_cycle_fista(0, locs[0], start, rho_other=rho[0], n_iter=2, power_iters=2, gamma_n=1.0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, L, lam = h.minor_cycle_fista(0, locs[0], start, rho_other=rho[0], n_iter=200,
-                                       power_iters=30, gamma_n=1.0)
-    t_f = time.perf_counter() - t0
-    h.destroy()
-    torch.cuda.empty_cache()
-    log("convex: major cycle %.3f ms (%.0f Mvis/s), FISTA %.1f ms" % (
-        ms, info.n_valid / (ms / 1e3) / 1e6, 1e3 * t_f))
-    return {"workload": "256 antennas x 1532 times = %d visibilities (complex64), 1.40 GHz, "
-                        "2048^2 image, 2 partitions split at the median |uv|, uniform weighting, "
-                        "ES support 8; 500 point sources" % info.n_valid,
-            "n_vis_partitions": [int(info.n_vis[0]), int(info.n_vis[1])],
-            "major_cycle_ms": round(ms, 3),
-            "major_cycle_mvis_per_s": round(info.n_valid / (ms / 1e3) / 1e6, 1),
-            "fista_ms": round(1e3 * t_f, 1), "fista_ms_per_iteration": round(1e3 * t_f / 230, 3),
-            "fista_config": "node V_L, Eq. 5 with gamma_n = 1, db8 3 levels, 200 iterations + "
-                            "30 power iterations, lambda = 1e-3 max |i~|, FP64 transforms"}
 
 
 def batched_channels(args, small=False):
@@ -420,17 +388,184 @@ def serving(args):
     return out
 
 
+CONFIG_TEXT = {
+    "decentral": "256 antennas in an 8 km disk, 32640 baselines x 480 times = %d visibilities "
+                 "(complex64), 1 channel at 1.40 GHz, uniform weighting, 2 partitions split at "
+                 "the median |uv| (delta 1 px), 1024^2 image, 2x padded grid, ES support 8; sky "
+                 "200 points + 30 Gaussians (sigma 2-8 px)",
+    "convex": "256 antennas in an 8 km disk, 32640 baselines x 1532 times = %d visibilities "
+              "(complex64), 1 channel at 1.40 GHz, uniform weighting, 2 partitions split at the "
+              "median |uv| (delta 1 px), 2048^2 image, 2x padded grid, ES support 8; sky 500 "
+              "points + 50 Gaussians (sigma 4-40 px)",
+}
+
+
+def measure_cycle(name, args, workers, with_oracle=True, minor=True):
+    """Times the decentralized major cycle of workload ``name``: both nodes'
+    cycles (Eq. 2 then Eq. 7) with the model 0.5 x the true sky and the
+    aggregate 0.01 x the true sky, gamma / mu from the partitions' summed
+    weights.  Returns the measurement dict (value, p50 / p99, stages,
+    roofline of the window kernel, errors against the oracle, minor
+    cycles)."""
+    import numpy as np
+    import torch
+    from paper_2507_22128_amd import imager, synth
+
+    t0 = time.perf_counter()
+    d = synth.make(name, device="cuda")
+    n = d["n_img"]
+    log("workload %s: %d visibilities, N=%d (generated in %.1f s)"
+        % (name, len(d["vis"]), n, time.perf_counter() - t0))
+    h = imager.Imager.create(d, n_partitions=2, weighting="uniform")
+    info = h.info
+    log("create: %.1f ms, partitions %d / %d visibilities, %d / %d chunks, ell %.3f px"
+        % (info.create_ms, info.n_vis[0], info.n_vis[1], info.n_chunks[0], info.n_chunks[1],
+           info.ell_pix))
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+    model = [dev(0.5 * d["truth"]), dev(0.5 * d["truth"])]
+    rho = [dev(0.01 * d["truth"]), dev(0.01 * d["truth"])]
+    out = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    local = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    wsum = [info.sum_w[0], info.sum_w[1]]
+    gammas = [wsum[p] / (wsum[0] + wsum[1]) for p in (0, 1)]
+    mus = [wsum[1 - p] / (wsum[0] + wsum[1]) for p in (0, 1)]
+
+    def step():
+        # both nodes' major cycles, concurrent on the device
+        h.major_cycle_nodes(model, rho, gammas, mus, outs=out, local_outs=local)
+
+    for _ in range(args.warmup):
+        step()
+    # the timed steps: nothing but the steps between the two synchronizations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    outs_np = [o.cpu().numpy() for o in out]
+    locs_np = [o.cpu().numpy() for o in local]
+    # the same number of steps again with an event pair around each (p50 / p99
+    # of the per-step device time), then with the handle's stage events (per
+    # stage); both add event packets to the streams, so neither is part of the
+    # timed steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for k in range(args.steps):
+        ev[k][0].record()
+        step()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(a.elapsed_time(b) for a, b in ev)
+    h.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    cycles, stage_ms = h.get_timing()
+    stage_conc = {k: v / cycles for k, v in stage_ms.items()}
+    # the same cycles one node at a time on the handle's stream: each kernel's
+    # own launch duration (what a kernel trace reports), for the roofline
+    for _ in range(args.steps):
+        for p in (0, 1):
+            h.major_cycle(p, model[p], rho[p], gammas[p], mus[p], out=out[p], local_out=local[p])
+    cycles_s, stage_ms_s = h.get_timing()
+    h.set_timing(False)
+    stage_avg = {k: v / cycles_s for k, v in stage_ms_s.items()}
+    ms_per_step = 1e3 * wall / args.steps
+    value = info.n_valid / (ms_per_step / 1e3) / 1e6
+    log("%s: %d steps: %.4f ms/step, %.0f Mvis/s (p50 %.4f ms, p99 %.4f ms)"
+        % (name, args.steps, ms_per_step, value, per_step[len(per_step) // 2],
+           per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))]))
+    log("%s: per node-cycle stage ms, nodes concurrent: %s" % (name, json.dumps(
+        {k: round(v, 4) for k, v in stage_conc.items()})))
+    log("%s: per node-cycle stage ms, one node at a time: %s" % (name, json.dumps(
+        {k: round(v, 4) for k, v in stage_avg.items()})))
+
+    # roofline of the dominant kernel, the fused de/grid window kernel: one
+    # launch per node-cycle, timed by the handle's stage events on its stream
+    # in the one-node-at-a-time pass; units averaged over the two launches
+    ng = info.n_grid
+    wt = info.support
+    m_avg = 0.5 * (info.n_vis[0] + info.n_vis[1])
+    t_launch = stage_avg["degrid_grid"] / 1e3
+    flops = flops_per_vis(wt) * m_avg
+    bytes_alg = 20.0 * m_avg
+    achieved_tf = flops / t_launch / 1e12
+    achieved_gbs = bytes_alg / t_launch / 1e9
+    roofline = {
+        "bound": "mfma",
+        "achieved": round(achieved_tf, 3),
+        "peak": FP32_PEAK_MATRIX,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tf / FP32_PEAK_MATRIX, 4),
+        "traffic": measured_traffic(name),
+        "kernel": "k_window<%d,%d,MODE_DEGRID_GRID> (fused degrid / residual / grid)"
+                  % (wt, info.tile),
+        "avg_launch_ms": round(stage_avg["degrid_grid"], 4),
+        "flop_per_vis": flops_per_vis(wt),
+        "vis_per_launch": m_avg,
+        "hbm_achieved_gbs": round(achieved_gbs, 1),
+        "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "bytes_alg_per_launch": bytes_alg,
+    }
+    # whole-cycle algorithmic bytes: visibility stream, ~8 grid passes, images
+    cycle_bytes = sum(20.0 * info.n_vis[p] + 64.0 * ng * ng + 8.0 * n * n for p in (0, 1))
+    res = {
+        "value": round(value, 1),
+        "ms_per_step": round(ms_per_step, 4),
+        "config": {
+            "workload": name + ": " + CONFIG_TEXT[name] % len(d["vis"]),
+            "n_vis": int(info.n_valid),
+            "n_vis_partitions": [int(info.n_vis[0]), int(info.n_vis[1])],
+            "n_pix": n,
+            "n_grid": ng,
+            "parallelism": "single GPU, both partitions on one device",
+        },
+        "p50_ms": round(per_step[len(per_step) // 2], 4),
+        "p99_ms": round(per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))], 4),
+        "event_timed_steps": len(per_step),
+        "create_ms": round(info.create_ms, 1),
+        "stage_ms_per_node_cycle": {k: round(v, 4) for k, v in stage_avg.items()},
+        "stage_ms_per_node_cycle_concurrent": {k: round(v, 4) for k, v in stage_conc.items()},
+        "cycle_hbm_frac": round(cycle_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the partitions' members summed (visibilities of the overlap ring counted in both)
+        "mvis_per_s_partition_sum": round((info.n_vis[0] + info.n_vis[1]) /
+                                          (ms_per_step / 1e3) / 1e6, 1),
+        # the fused degrid / residual / grid kernel alone, one launch per partition
+        "degrid_grid_kernel_mvis_per_s": round(m_avg / t_launch / 1e6, 1),
+        "roofline": roofline,
+    }
+    if minor:
+        res["minor_cycles"] = minor_cycles(h, info, model, rho, gammas, mus, n,
+                                           msclean=(name == "decentral"))
+    h.destroy()
+    del model, rho, out, local
+    torch.cuda.empty_cache()
+    if with_oracle:
+        log("%s: oracle on the full partitions (%d processes) ..." % (name, workers))
+        base, err = oracle_cycle(d, outs_np, locs_np, workers)
+        res["err_vs_oracle"] = err
+        res["cpu_baseline"] = base
+        log("%s: oracle %.1f s (%.3f Mvis/s); GPU error vs oracle: composed %s, local %s"
+            % (name, base["seconds"], base["value"],
+               ["%.2e" % e for e in err["composed_rel_l2"]],
+               ["%.2e" % e for e in err["local_rel_l2"]]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="decentral")
-    ap.add_argument("--cpu-sample-times", type=int, default=128)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="convex")
+    ap.add_argument("--oracle-workers", type=int, default=0,
+                    help="host processes of the oracle run (0: every core this process may use)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle run (no cpu_baseline, no error against the oracle)")
     ap.add_argument("--no-minor-cycles", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-convex", action="store_true")
+    ap.add_argument("--no-decentral", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=64)
     ap.add_argument("--batch-small-channels", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -449,35 +584,9 @@ def main():
               "(the two partitions run on one device)" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2507_22128_amd import imager, synth
-
-    t0 = time.perf_counter()
-    d = synth.make(args.workload)
-    wl = d["workload"]
-    n = d["n_img"]
-    log("workload %s: %d visibilities, N=%d (generated in %.1f s)"
-        % (args.workload, len(d["vis"]), n, time.perf_counter() - t0))
-    h = imager.Imager.create(d, n_partitions=2, weighting="uniform")
-    info = h.info
-    log("create: %.1f ms, partitions %d / %d visibilities, %d / %d chunks, ell %.3f px"
-        % (info.create_ms, info.n_vis[0], info.n_vis[1], info.n_chunks[0], info.n_chunks[1],
-           info.ell_pix))
-
-    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
-    model = [dev(0.5 * d["truth"]), dev(0.5 * d["truth"])]
-    rho = [dev(0.01 * d["truth"]), dev(0.01 * d["truth"])]
-    out = [torch.empty((n, n), device="cuda") for _ in range(2)]
-    local = [torch.empty((n, n), device="cuda") for _ in range(2)]
-    wsum = [info.sum_w[0], info.sum_w[1]]
-    gm = [(wsum[p] / (wsum[0] + wsum[1]), wsum[1 - p] / (wsum[0] + wsum[1])) for p in (0, 1)]
-
-    gammas, mus = [gm[0][0], gm[1][0]], [gm[0][1], gm[1][1]]
-
-    def step():
-        # both nodes' major cycles, concurrent on the device
-        h.major_cycle_nodes(model, rho, gammas, mus, outs=out, local_outs=local)
+    from oracle import pool
+    workers = args.oracle_workers or pool.default_workers()
 
     if args.calibrate_copy_mb:
         nb = args.calibrate_copy_mb << 20
@@ -489,133 +598,33 @@ def main():
         log("calibration copy: 3 x %d MiB device to device" % args.calibrate_copy_mb)
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    # the timed steps: nothing but the steps between the two synchronizations
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # the same number of steps again with an event pair around each (p50 / p99 of
-    # the per-step device time), then again with the handle's stage events
-    # (per-stage breakdown); both add event packets to the streams, so neither
-    # is part of the timed steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    for k in range(args.steps):
-        ev[k][0].record()
-        step()
-        ev[k][1].record()
-    torch.cuda.synchronize()
-    per_step = sorted(a.elapsed_time(b) for a, b in ev)
-    h.set_timing(True)
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    cycles, stage_ms = h.get_timing()
-    ms_per_step = 1e3 * wall / args.steps
-    n_valid = info.n_valid
-    value = n_valid / (ms_per_step / 1e3) / 1e6
-    log("%d steps: %.3f ms/step, %.0f Mvis/s" % (args.steps, ms_per_step, value))
-    stage_conc = {k: v / cycles for k, v in stage_ms.items()}
-    log("per node-cycle stage ms (nodes concurrent): %s"
-        % json.dumps({k: round(v, 4) for k, v in stage_conc.items()}))
-    # the same cycles one node at a time on one stream: each kernel's own
-    # launch duration (what a kernel trace reports), for the roofline
-    for _ in range(args.steps):
-        for p in (0, 1):
-            h.major_cycle(p, model[p], rho[p], gammas[p], mus[p], out=out[p], local_out=local[p])
-    cycles_s, stage_ms_s = h.get_timing()
-    h.set_timing(False)
-    stage_avg = {k: v / cycles_s for k, v in stage_ms_s.items()}
-    log("per node-cycle stage ms (one node at a time): %s"
-        % json.dumps({k: round(v, 4) for k, v in stage_avg.items()}))
-
-    # roofline of the dominant kernel: the fused de/grid window kernel (one
-    # launch per node-cycle, timed by the handle's stage events on its
-    # stream in the one-node-at-a-time pass); units averaged over the two
-    # partitions' launches
-    ng = info.n_grid
-    wt = info.support
-    m_avg = 0.5 * (info.n_vis[0] + info.n_vis[1])
-    t_launch = stage_avg["degrid_grid"] / 1e3
-    flops = flops_per_vis(wt) * m_avg
-    bytes_alg = 20.0 * m_avg
-    achieved_tf = flops / t_launch / 1e12
-    achieved_gbs = bytes_alg / t_launch / 1e9
-    roofline = {
-        "bound": "mfma",
-        "achieved": round(achieved_tf, 3),
-        "peak": FP32_PEAK_MATRIX,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_tf / FP32_PEAK_MATRIX, 4),
-        "traffic": measured_traffic(),
-        "kernel": "k_window<%d,%d,MODE_DEGRID_GRID> (fused degrid / residual / grid)"
-                  % (wt, info.tile),
-        "avg_launch_ms": round(stage_avg["degrid_grid"], 4),
-        "flop_per_vis": flops_per_vis(wt),
-        "hbm_achieved_gbs": round(achieved_gbs, 1),
-        "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-        "bytes_alg_per_launch": bytes_alg,
-    }
-    # whole-cycle algorithmic bytes: visibility stream, ~8 grid passes, images
-    cycle_bytes = sum(20.0 * info.n_vis[p] + 64.0 * ng * ng + 8.0 * n * n for p in (0, 1))
+    head = measure_cycle(args.workload, args, workers, with_oracle=not args.no_cpu_baseline,
+                         minor=not args.no_minor_cycles)
     res = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": head.pop("value"),
         "unit": "Mvis/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "%s: %d antennas in an %.0f km disk, %d baselines x %d times = %d "
-                        "visibilities (complex64), 1 channel at %.2f GHz, uniform weighting, "
-                        "2 partitions split at the median |uv| (delta 1 px), %d^2 image, "
-                        "2x padded grid, ES support %d"
-                        % (args.workload, wl.n_ant, 2 * wl.radius_m / 1e3,
-                           wl.n_ant * (wl.n_ant - 1) // 2, wl.n_time, len(d["vis"]),
-                           wl.freq_hz / 1e9, n, wt),
-            "n_vis": int(n_valid),
-            "n_vis_partitions": [int(info.n_vis[0]), int(info.n_vis[1])],
-            "n_pix": n,
-            "n_grid": ng,
-            "parallelism": "single GPU, both partitions on one device",
-        },
-        "p50_ms": round(per_step[len(per_step) // 2], 4),
-        "p99_ms": round(per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))], 4),
-        "create_ms": round(info.create_ms, 1),
-        "stage_ms_per_node_cycle": {k: round(v, 4) for k, v in stage_avg.items()},
-        "stage_ms_per_node_cycle_concurrent": {k: round(v, 4) for k, v in stage_conc.items()},
-        "cycle_hbm_frac": round(cycle_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        # the partitions' members summed (visibilities of the overlap ring counted in both)
-        "mvis_per_s_partition_sum": round((info.n_vis[0] + info.n_vis[1]) /
-                                          (ms_per_step / 1e3) / 1e6, 1),
-        # the fused degrid / residual / grid kernel alone, one launch per partition
-        "degrid_grid_kernel_mvis_per_s": round(m_avg / t_launch / 1e6, 1),
-        "roofline": roofline,
+        "config": head.pop("config"),
     }
-    if not args.no_minor_cycles:
-        res["minor_cycles"] = minor_cycles(h, info, model, rho, gammas, mus, n)
-    h.destroy()
-    if not args.no_convex:
-        res["convex"] = convex(args)
+    res.update(head)
+    if args.workload != "decentral" and not args.no_decentral:
+        res["decentral"] = measure_cycle("decentral", args, workers,
+                                         with_oracle=not args.no_cpu_baseline,
+                                         minor=not args.no_minor_cycles)
     if not args.no_batch:
         res["batched_channels"] = batched_channels(args)
         res["batched_small_channels"] = batched_channels(args, small=True)
     if not args.no_serve:
         res["serving"] = serving(args)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a sample) ...")
-        res["cpu_baseline"] = cpu_baseline(args, gm)
-        log("cpu baseline: %.3f Mvis/s" % res["cpu_baseline"]["value"])
     print(json.dumps(res))
 
 

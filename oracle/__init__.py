@@ -23,9 +23,11 @@ checks it against the paper by eye:
 * ``msclean``    - multi-scale CLEAN minor cycle (Eq. 6)
 * ``wavelets``   - orthonormal Daubechies filters and periodized transforms
 * ``fista``      - FISTA for the wavelet-l1 problems of Eqs. 4 and 5
+* ``pool``       - runs ``gridding``'s degrid / grid unchanged over chunks
+                   of large visibility sets on several host processes
 
 Parity status of each function is stated in its docstring; items whose
 definition is a reading of a silent or ambiguous passage say so.
 """
 
-from . import geometry, es_kernel, dft, gridding, imaging, decentral, msclean, wavelets, fista  # noqa: F401,E501
+from . import geometry, es_kernel, dft, gridding, imaging, decentral, msclean, wavelets, fista, pool  # noqa: F401,E501

@@ -65,21 +65,28 @@ def degrid(grid, gx, gy, support, beta):
     return out
 
 
-def grid_vis(vis, gx, gy, n_grid, support, beta):
-    """K^T: accumulate visibilities onto an Ng x Ng grid."""
+def grid_vis(vis, gx, gy, n_grid, support, beta, block=1 << 18):
+    """K^T: accumulate visibilities onto an Ng x Ng grid.
+
+    Every (visibility, tap) pair adds vis_k * wy_k[j] * wx_k[i] to cell
+    ((fy_k + j) mod Ng, (fx_k + i) mod Ng); the pairs of ``block``
+    visibilities at a time are summed by one bincount (FP64)."""
     fx, wx = taps(gx, support, beta)
     fy, wy = taps(gy, support, beta)
     vis = np.asarray(vis, dtype=np.complex128)
     acc_re = np.zeros(n_grid * n_grid)
     acc_im = np.zeros(n_grid * n_grid)
-    for j in range(support):
-        row = (fy + j) % n_grid
-        for i in range(support):
-            col = (fx + i) % n_grid
-            flat = row * n_grid + col
-            w = wy[:, j] * wx[:, i]
-            acc_re += np.bincount(flat, weights=w * vis.real, minlength=n_grid * n_grid)
-            acc_im += np.bincount(flat, weights=w * vis.imag, minlength=n_grid * n_grid)
+    t = np.arange(support)
+    for a in range(0, len(vis), block):
+        e = slice(a, a + block)
+        rows = (fy[e, None] + t) % n_grid                          # [m, W]
+        cols = (fx[e, None] + t) % n_grid                          # [m, W]
+        flat = (rows[:, :, None] * n_grid + cols[:, None, :]).ravel()  # [m, W, W]
+        w = wy[e, :, None] * wx[e, None, :]                        # [m, W, W]
+        acc_re += np.bincount(flat, weights=(w * vis[e].real[:, None, None]).ravel(),
+                              minlength=n_grid * n_grid)
+        acc_im += np.bincount(flat, weights=(w * vis[e].imag[:, None, None]).ravel(),
+                              minlength=n_grid * n_grid)
     return (acc_re + 1j * acc_im).reshape(n_grid, n_grid)
 
 

@@ -89,11 +89,17 @@ def baselines(n_ant):
     return i.astype(np.int64), j.astype(np.int64)
 
 
-def make(name="tiny", seed=None, n_time=None, with_noise=True, sky_scale=1.0):
+def make(name="tiny", seed=None, n_time=None, with_noise=True, sky_scale=1.0, device=None):
     """Generate a workload.  Returns a dict with
 
-    uvw [M, 3] float64 metres, vis [M] complex128, weight [M] float32 (ones),
-    freq_hz, cell (rad), n_img, truth [N, N] float64 (Jy/pixel), sources.
+    uvw [M, 3] float64 metres, vis [M] complex128 (complex64 for the c64
+    workloads), weight [M] float32 (ones), freq_hz, cell (rad), n_img,
+    truth [N, N] float64 (Jy/pixel), sources.
+
+    With ``device`` (a torch device) the source sums of each time step are
+    evaluated there in FP64 (batches of time steps), for the large
+    workloads; the arrays returned are numpy arrays either way and the
+    two evaluations differ only in FP64 rounding.
     """
     wl = WORKLOADS[name]
     rng = np.random.default_rng(wl.seed if seed is None else seed)
@@ -125,7 +131,9 @@ def make(name="tiny", seed=None, n_time=None, with_noise=True, sky_scale=1.0):
     vis = np.empty(n_time * n_bl, np.complex128)
     pts = slice(0, wl.n_points)
     gss = slice(wl.n_points, n_src)
-    for t in range(n_time):
+    if device is not None:
+        _vis_device(vis, auvw / lam, bi, bj, l0, m0, flux, sig * cell, wl.n_points, device)
+    for t in range(n_time if device is None else 0):
         ua = auvw[t, :, 0] / lam
         va = auvw[t, :, 1] / lam
         ph = np.exp(-2j * np.pi * (np.outer(ua, l0) + np.outer(va, m0)))  # [A, S]
@@ -155,6 +163,38 @@ def make(name="tiny", seed=None, n_time=None, with_noise=True, sky_scale=1.0):
     return dict(name=name, uvw=uvw, vis=vis, weight=np.ones(len(vis), np.float32),
                 freq_hz=wl.freq_hz, cell=cell, n_img=n, truth=truth,
                 sources=dict(ix=ix, iy=iy, flux=flux, sigma_px=sig), workload=wl)
+
+
+def _vis_device(out, auv, bi, bj, l0, m0, flux, sig_rad, n_points, device, batch=16):
+    """The per-time source sums of ``make`` with torch on ``device`` (FP64):
+    points through the antenna phasors, Gaussians with their envelopes."""
+    import torch
+    n_time, n_ant = auv.shape[0], auv.shape[1]
+    n_bl = len(bi)
+    t_l0 = torch.tensor(l0, dtype=torch.float64, device=device)
+    t_m0 = torch.tensor(m0, dtype=torch.float64, device=device)
+    t_flux = torch.tensor(flux, dtype=torch.float64, device=device)
+    t_sig = torch.tensor(sig_rad, dtype=torch.float64, device=device)
+    t_bi = torch.tensor(bi, device=device)
+    t_bj = torch.tensor(bj, device=device)
+    pts, gss = slice(0, n_points), slice(n_points, len(flux))
+    for t0 in range(0, n_time, batch):
+        t1 = min(n_time, t0 + batch)
+        a = torch.tensor(auv[t0:t1], dtype=torch.float64, device=device)   # [T, A, 3]
+        phase = -2.0 * np.pi * (a[:, :, 0:1] * t_l0 + a[:, :, 1:2] * t_m0)  # [T, A, S]
+        ph = torch.polar(torch.ones_like(phase), phase)                     # complex128
+        left = (ph[:, :, pts] * t_flux[pts]).contiguous()
+        right = ph[:, :, pts].conj().transpose(1, 2).contiguous()           # [T, S, A]
+        vt = torch.bmm(left, right)[:, t_bj, t_bi]                          # [T, B]
+        if len(flux) > n_points:
+            ub = a[:, t_bj, 0] - a[:, t_bi, 0]
+            vb = a[:, t_bj, 1] - a[:, t_bi, 1]
+            q = ub * ub + vb * vb                                           # [T, B]
+            env = torch.exp(-2.0 * np.pi ** 2 * q[:, :, None] * (t_sig[gss] ** 2))  # [T, B, G]
+            pg = ph[:, t_bj, gss] * ph[:, t_bi, gss].conj()
+            vt = vt + ((env * pg) * t_flux[gss]).sum(dim=2)
+        out[t0 * n_bl:t1 * n_bl] = vt.reshape(-1).cpu().numpy()
+        del a, phase, ph, left, right, vt
 
 
 def random_uv_cells(m, n_grid, rng, frac=1.0 / 3.0):

@@ -3,13 +3,14 @@
 The decentral workload as the benchmark runs it: 15,667,200 visibilities,
 N = 1024, 2 partitions split at the median |uv|, uniform weighting, support
 8, the default block side and chunk cap, both nodes' cycles through
-imager_major_cycle_nodes.  The oracle cannot form whole images at this size,
-so integer results (weights' cells, ell, membership) are compared in full
-and floating-point results at sampled outputs, each computed by the oracle
-as the plain direct Fourier sum over all of the partition's visibilities
-(oracle.dft.adjoint_at / forward_points).  The GPU's gridded operator
-differs from the direct sum by the kernel's error (about 1e-7 relative at
-W = 8) plus FP32 rounding; the bound is 1e-5 of the largest sampled value.
+imager_major_cycle_nodes.  Integer results (weights' cells, ell,
+membership) are compared in full.  Floating-point results are compared two
+ways: whole images element by element against the FP64 gridded oracle run
+over every visibility of each partition (oracle.pool: the oracle's own
+de/gridding over chunks on the host's cores), and sampled outputs against
+the plain direct Fourier sum (oracle.dft.adjoint_at / forward_points),
+which also bounds the kernel's error.  Bound: relative L2 1e-5 for whole
+images; 1e-5 of the largest sampled value for the direct sums.
 """
 
 import numpy as np
@@ -35,7 +36,8 @@ def _dft():
 def full():
     say("case: decentral workload at full size (15,667,200 visibilities, N = 1024, "
         "2 partitions, W = 8, default tile and chunk)")
-    d = workload("decentral")
+    from paper_2507_22128_amd import synth
+    d = synth.make("decentral", device="cuda")
     h = _imager().Imager.create(d, n_partitions=2, weighting="uniform")
     n = d["n_img"]
     u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
@@ -149,3 +151,48 @@ def test_full_residual_point_source_sampled(full):
         say("partition %d residual of a point model, %d sampled pixels: max err %.3e" %
             (p, len(iy), err))
         assert err < TOL
+
+
+@pytest.mark.timeout(900)
+def test_full_bench_step_elementwise(full):
+    """The benchmark's step exactly (model 0.5 x truth, aggregate 0.01 x
+    truth, gamma / mu the partitions' weight shares): both nodes' local
+    residuals (Eq. 2) and composed images (Eq. 7), and both PSFs, element by
+    element against the FP64 gridded oracle over the full partitions.  The
+    residual error is also reported relative to the dirty image's norm (the
+    operator-relative norm of the residual; the gate is on the plain
+    relative L2)."""
+    import torch
+    from oracle import decentral, pool
+    d, h, n = full["d"], full["h"], full["n"]
+    u, v, w, parts, ell = full["u"], full["v"], full["w"], full["parts"], full["ell"]
+    model = [to_dev(0.5 * d["truth"])] * 2
+    rho = [to_dev(0.01 * d["truth"])] * 2
+    ws = [h.sum_w(0), h.sum_w(1)]
+    gam = [ws[p] / (ws[0] + ws[1]) for p in (0, 1)]
+    mu = [ws[1 - p] / (ws[0] + ws[1]) for p in (0, 1)]
+    outs = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    locs = [torch.empty((n, n), device="cuda") for _ in range(2)]
+    for _ in range(3):  # the benchmark's repeated steps, last outputs kept
+        h.major_cycle_nodes(model, rho, gam, mu, outs=outs, local_outs=locs)
+    got_o, got_l = [to_np(o) for o in outs], [to_np(o) for o in locs]
+    got_psf = [to_np(h.psf(p)) for p in (0, 1)]
+    workers = pool.default_workers()
+    say("oracle on the full partitions, %d processes" % workers)
+    psfs = [pool.psf2(u[m], v[m], w[m], n, d["cell"], workers=workers) for m in parts]
+    wsum = [w[m].sum() for m in parts]
+    gm = [decentral.weights_schedule(2, wsum[p], wsum[1 - p]) for p in (0, 1)]
+    ref_o, ref_l = pool.decentral_cycle(
+        u, v, d["vis"], w, parts, [0.5 * d["truth"]] * 2, [0.01 * d["truth"]] * 2, psfs,
+        [g[0] for g in gm], [g[1] for g in gm], ell, 1.0, d["cell"], workers=workers)
+    for p in (0, 1):
+        m = parts[p]
+        dirty0, _ = pool.residual_image(u[m], v[m], d["vis"][m], w[m], np.zeros((n, n)),
+                                        d["cell"], workers=workers)
+        e_psf = rel(got_psf[p], psfs[p])
+        e_loc = rel(got_l[p], ref_l[p])
+        e_out = rel(got_o[p], ref_o[p])
+        e_op = float(np.linalg.norm(got_l[p] - ref_l[p]) / np.linalg.norm(dirty0))
+        say("partition %d: PSF rel L2 %.3e, local residual %.3e (%.3e of the dirty image's "
+            "norm), composed (Eq. 7, mu = %.3f) %.3e" % (p, e_psf, e_loc, e_op, mu[p], e_out))
+        assert e_psf < TOL and e_loc < TOL and e_out < TOL

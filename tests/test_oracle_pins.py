@@ -362,3 +362,26 @@ def test_loop_composes_with_the_other_partitions_psf_and_rho():
                                   CELL, N_C).real / wsum[other[own]]
         err = np.linalg.norm(mu_term - expect) / np.linalg.norm(expect)
         assert err < 1e-5, (own, err)
+
+
+# ------------------------------------------------------------------ parallel runner
+
+def test_pool_runner_equals_serial_oracle(monkeypatch):
+    """oracle.pool only splits the visibilities over processes: residual
+    images, predictions and PSFs equal the serial calls to FP64 rounding."""
+    from oracle import pool
+    monkeypatch.setattr(pool, "MIN_CHUNK", 2000)
+    from paper_2507_22128_amd import synth
+    from oracle import geometry
+    d = synth.make("tiny", n_time=6)
+    n = d["n_img"]
+    u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
+    w = imaging.uniform_weights(u, v, n, d["cell"])
+    model = 0.5 * d["truth"]
+    ref, ref_pred = imaging.residual_image(u, v, d["vis"], w, model, d["cell"])
+    got, got_pred = pool.residual_image(u, v, d["vis"], w, model, d["cell"], workers=3)
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+    assert np.abs(got_pred - ref_pred).max() < 1e-13 * np.abs(ref_pred).max()
+    p_ref = imaging.psf2(u, v, w, n, d["cell"])
+    p_got = pool.psf2(u, v, w, n, d["cell"], workers=3)
+    assert np.abs(p_got - p_ref).max() < 1e-13
