@@ -273,6 +273,30 @@ imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t part, const imgr_msclea
                                        float *model_accum, float *residual_out,
                                        imgr_component *comps, int32_t *n_comps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * minor cycle of imager_minor_cycle_msclean, same arguments and same
+ * results bit for bit, with its FP64 work area (smoothed residuals, cross
+ * PSFs, model, kernels, peak candidates, loop state) taken from a fixed
+ * device array of IMGR_MSCLEAN_STATIC_BYTES that the library holds on
+ * every device it runs on until the process ends, instead of the handle's
+ * work area grown on first use.  The call allocates nothing (no hipMalloc,
+ * no hipFree).  It needs 8 (N^2 (n_int + 1) + 4 N^2 n_int (n_int + 1) / 2)
+ * bytes plus about 80 KB, n_int = |S| (+ 1 if 0 is not in S): N = 512 with
+ * 3 scales, or N = 256 with up to 5, fits; larger needs are refused with
+ * EINVAL and nothing enqueued.  The handle's device must be current.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (each call clears what it needs): calls that overlap on
+ * one device, from different threads or streams, race.  Synchronises the
+ * handle's stream before returning. */
+#define IMGR_MSCLEAN_STATIC_BYTES (64u << 20)
+imgr_status imager_minor_cycle_msclean_static(imgr_t h, int32_t part,
+                                              const imgr_msclean_params *params,
+                                              const float *dirty, const float *psf,
+                                              float *model_delta, float *model_accum,
+                                              float *residual_out, imgr_component *comps,
+                                              int32_t *n_comps);
+
 /* The whole major/minor loop with multi-scale CLEAN (Section 4.2): for
  * cycle n = 1 .. n_cycles and every node k, concurrently,
  *   i~ = residual of model[k] on the node's visibilities            (Eq. 2)

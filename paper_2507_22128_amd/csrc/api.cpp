@@ -320,6 +320,7 @@ imgr_status imager_create(const imgr_config *cfg, const imgr_vis *vis, imgr_t *o
                "n_pix must be a power of two in [64, 2048]");
     h->N = cfg->n_pix;
     h->Ng = 2 * h->N;
+    IMGR_HIP(hipGetDevice(&h->device));
     if (cfg->support == 0 && cfg->tolerance > 0) {
       h->W = support_for_tolerance(cfg->tolerance);
       IMGR_CHECK(h->W > 0, "no built support reaches the requested tolerance");
@@ -560,6 +561,24 @@ static void check_part(imgr_s *h, int part) {
   IMGR_CHECK(part >= 0 && part < h->n_parts, "partition index out of range");
 }
 
+// the minor cycle's parameters checked, with psi^1's scale subset applied
+static imgr_msclean_params checked_msclean_params(imgr_s *h, int part,
+                                                  const imgr_msclean_params &p) {
+  IMGR_CHECK(p.n_scales >= 1 && p.n_scales <= IMGR_MAX_SCALES, "n_scales must be in [1, 8]");
+  for (int i = 0; i < p.n_scales; ++i)
+    IMGR_CHECK(p.scales[i] >= 0.0 && p.scales[i] <= 64.0 && std::isfinite(p.scales[i]),
+               "scales must be in [0, 64] pixels");
+  IMGR_CHECK(p.gain > 0.0 && p.gain <= 1.0, "gain must be in (0, 1]");
+  IMGR_CHECK(p.max_iter >= 0, "max_iter must be >= 0");
+  IMGR_CHECK(std::isfinite(p.threshold) && std::isfinite(p.bias_slope), "threshold / bias");
+  IMGR_CHECK(p.active_mask == 0u || (p.active_mask & ((1u << p.n_scales) - 1u)) != 0u,
+             "active_mask selects no scale");
+  imgr_msclean_params q = p;
+  if (p.own_scales_only) q.active_mask = (p.active_mask ? p.active_mask : ~0u) &
+                                         msclean_own_scales(h, part, p);
+  return q;
+}
+
 imgr_status imager_vis_index(imgr_t h, int32_t part, int64_t *idx) {
   API_BEGIN(h)
   check_part(h, part);
@@ -711,23 +730,26 @@ imgr_status imager_minor_cycle_msclean(imgr_t h, int32_t part, const imgr_msclea
   API_BEGIN(h)
   check_part(h, part);
   IMGR_CHECK(params && dirty && psf && n_comps, "null pointer");
-  const imgr_msclean_params &p = *params;
-  IMGR_CHECK(p.n_scales >= 1 && p.n_scales <= IMGR_MAX_SCALES, "n_scales must be in [1, 8]");
-  for (int i = 0; i < p.n_scales; ++i)
-    IMGR_CHECK(p.scales[i] >= 0.0 && p.scales[i] <= 64.0 && std::isfinite(p.scales[i]),
-               "scales must be in [0, 64] pixels");
-  IMGR_CHECK(p.gain > 0.0 && p.gain <= 1.0, "gain must be in (0, 1]");
-  IMGR_CHECK(p.max_iter >= 0, "max_iter must be >= 0");
-  IMGR_CHECK(std::isfinite(p.threshold) && std::isfinite(p.bias_slope), "threshold / bias");
-  IMGR_CHECK(p.active_mask == 0u || (p.active_mask & ((1u << p.n_scales) - 1u)) != 0u,
-             "active_mask selects no scale");
-  imgr_msclean_params q = p;
-  if (p.own_scales_only) q.active_mask = (p.active_mask ? p.active_mask : ~0u) &
-                                         msclean_own_scales(h, part, p);
+  const imgr_msclean_params q = checked_msclean_params(h, part, *params);
   msclean_enqueue(h, part, q, dirty, psf, model_delta, model_accum, residual_out, comps,
                   h->stream);
   IMGR_HIP(hipStreamSynchronize(h->stream));
   *n_comps = msclean_count(h, part);
+  API_END(h)
+}
+
+imgr_status imager_minor_cycle_msclean_static(imgr_t h, int32_t part,
+                                              const imgr_msclean_params *params,
+                                              const float *dirty, const float *psf,
+                                              float *model_delta, float *model_accum,
+                                              float *residual_out, imgr_component *comps,
+                                              int32_t *n_comps) {
+  API_BEGIN(h)
+  check_part(h, part);
+  IMGR_CHECK(params && dirty && psf && n_comps, "null pointer");
+  const imgr_msclean_params q = checked_msclean_params(h, part, *params);
+  *n_comps = msclean_enqueue_static(h, q, dirty, psf, model_delta, model_accum, residual_out,
+                                    comps, h->stream);
   API_END(h)
 }
 

@@ -126,6 +126,7 @@ struct Partition {
 struct imgr_s {
   // geometry
   int N = 0, Ng = 0, W = 8, blk = 8, n_parts = 1, C = 1024;
+  int device = 0;  // the device current at imager_create
   double cell = 0, beta = 0, ell = 0, delta = 1;
   int weighting = 0;
   int64_t n_valid = 0;
@@ -397,6 +398,13 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
                      const float *psf, float *model_delta, float *model_accum, float *resid_out,
                      imgr_component *comps, hipStream_t s);
 int msclean_count(imgr_s *h, int part);
+// bytes of the static work area a call with these parameters needs
+size_t msclean_static_bytes(const imgr_s *h, const imgr_msclean_params &prm);
+// the same minor cycle on the device's static work area (nothing is
+// allocated); synchronises s and returns the number of components
+int msclean_enqueue_static(imgr_s *h, const imgr_msclean_params &prm, const float *dirty,
+                           const float *psf, float *model_delta, float *model_accum,
+                           float *resid_out, imgr_component *comps, hipStream_t s);
 uint32_t msclean_own_scales(const imgr_s *h, int part, const imgr_msclean_params &prm);
 void msclean_release(imgr_s *h, int part);
 

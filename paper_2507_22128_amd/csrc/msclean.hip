@@ -19,9 +19,19 @@
 // returns at once.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.h"
+
+// The work area of imager_minor_cycle_msclean_static: one array per device
+// (each GPU the library runs on holds its own copy until the process ends),
+// shared by every call on that device.  Host code never passes `scratch`
+// itself to a kernel or copy: in host code that name is a stand-in, not a
+// device address.  The address comes from hipGetSymbolAddress
+// (imgr::static_area) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[IMGR_MSCLEAN_STATIC_BYTES];
 
 namespace imgr {
 namespace {
@@ -434,10 +444,21 @@ int msclean_count(imgr_s *h, int part) {
   return hs.n_comps;
 }
 
-void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const float *dirty,
-                     const float *psf, float *model_delta, float *model_accum, float *resid_out,
-                     imgr_component *comps, hipStream_t s) {
-  const int n = h->N, nn = n * n, n2 = 2 * n;
+namespace {
+
+// Everything the host derives from the parameters before any device work:
+// internal scales, the scale kernels and their pairwise convolutions
+// (concatenated in kall), and the device work area's size.
+struct CleanPlan {
+  int n_int = 0, n_pairs = 0, r0 = 0;
+  double smax = 0.0;
+  std::vector<double> sc, kall;
+  std::vector<int> user, selectable, rad, koff, poff, prad;
+  int pair[kMaxInt][kMaxInt];
+};
+
+CleanPlan make_plan(const imgr_msclean_params &prm) {
+  CleanPlan P;
   const int ns = prm.n_scales;
   // internal scales: scale 0 first when S lacks it (tracked, not selectable)
   int r0_user = -1;
@@ -447,64 +468,53 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
       break;
     }
   const int shift = (r0_user < 0) ? 1 : 0;
-  const int n_int = ns + shift;
-  std::vector<double> sc(n_int);
-  std::vector<int> user(n_int, -1), selectable(n_int, 0);
-  if (shift) sc[0] = 0.0;
-  double smax = 0.0;
-  for (int i = 0; i < ns; ++i) smax = std::max(smax, prm.scales[i]);
+  P.n_int = ns + shift;
+  P.sc.assign(P.n_int, 0.0);
+  P.user.assign(P.n_int, -1);
+  P.selectable.assign(P.n_int, 0);
+  for (int i = 0; i < ns; ++i) P.smax = std::max(P.smax, prm.scales[i]);
   for (int i = 0; i < ns; ++i) {
-    sc[i + shift] = prm.scales[i];
-    user[i + shift] = i;
-    selectable[i + shift] = (prm.active_mask == 0u || ((prm.active_mask >> i) & 1u)) ? 1 : 0;
+    P.sc[i + shift] = prm.scales[i];
+    P.user[i + shift] = i;
+    P.selectable[i + shift] = (prm.active_mask == 0u || ((prm.active_mask >> i) & 1u)) ? 1 : 0;
   }
-  const int r0 = shift ? 0 : r0_user;
+  P.r0 = shift ? 0 : r0_user;
   // kernels phi_s and phi_a * phi_b
-  std::vector<std::vector<double>> ph(n_int);
-  std::vector<int> rad(n_int);
-  for (int i = 0; i < n_int; ++i) ph[i] = scale_kernel(sc[i], rad[i]);
-  std::vector<double> kall;
-  std::vector<int> koff(n_int);
-  for (int i = 0; i < n_int; ++i) {
-    koff[i] = (int)kall.size();
-    kall.insert(kall.end(), ph[i].begin(), ph[i].end());
+  std::vector<std::vector<double>> ph(P.n_int);
+  P.rad.assign(P.n_int, 0);
+  for (int i = 0; i < P.n_int; ++i) ph[i] = scale_kernel(P.sc[i], P.rad[i]);
+  P.koff.assign(P.n_int, 0);
+  for (int i = 0; i < P.n_int; ++i) {
+    P.koff[i] = (int)P.kall.size();
+    P.kall.insert(P.kall.end(), ph[i].begin(), ph[i].end());
   }
-  int pair[kMaxInt][kMaxInt];
-  std::vector<int> poff, prad;
-  int n_pairs = 0;
-  for (int a = 0; a < n_int; ++a)
-    for (int b = a; b < n_int; ++b) {
+  for (int a = 0; a < P.n_int; ++a)
+    for (int b = a; b < P.n_int; ++b) {
       int r;
-      std::vector<double> c = conv_full(ph[a], rad[a], ph[b], rad[b], r);
-      poff.push_back((int)kall.size());
-      prad.push_back(r);
-      kall.insert(kall.end(), c.begin(), c.end());
-      pair[a][b] = pair[b][a] = n_pairs++;
+      std::vector<double> c = conv_full(ph[a], P.rad[a], ph[b], P.rad[b], r);
+      P.poff.push_back((int)P.kall.size());
+      P.prad.push_back(r);
+      P.kall.insert(P.kall.end(), c.begin(), c.end());
+      P.pair[a][b] = P.pair[b][a] = P.n_pairs++;
     }
-  // device work area of this node (grown on demand, kept for later calls)
-  CleanWork &cw = h->clean[part];
-  const size_t need_R = (size_t)n_int * nn, need_B = (size_t)n_pairs * n2 * n2;
-  if (cw.R_elems < need_R || cw.B_elems < need_B || cw.k_elems < kall.size()) {
-    msclean_release(h, part);
-    cw.R = (double *)dev_alloc(h, need_R * sizeof(double));
-    cw.B = (double *)dev_alloc(h, need_B * sizeof(double));
-    cw.kern = (double *)dev_alloc(h, kall.size() * sizeof(double));
-    cw.model = (double *)dev_alloc(h, (size_t)nn * sizeof(double));
-    cw.state = dev_alloc(h, sizeof(CleanState));
-    cw.slots = dev_alloc(h, (size_t)2 * kStepBlocks * sizeof(Cand));
-    cw.R_elems = need_R;
-    cw.B_elems = need_B;
-    cw.k_elems = kall.size();
-  }
-  IMGR_HIP(hipMemcpyAsync(cw.kern, kall.data(), kall.size() * sizeof(double),
+  return P;
+}
+
+// the minor cycle on a given work area (nothing is allocated here)
+void enqueue_plan(imgr_s *h, const CleanPlan &P, const imgr_msclean_params &prm,
+                  const float *dirty, const float *psf, float *model_delta, float *model_accum,
+                  float *resid_out, imgr_component *comps, const CleanWork &cw, hipStream_t s) {
+  const int n = h->N, nn = n * n, n2 = 2 * n;
+  const int n_int = P.n_int, n_pairs = P.n_pairs;
+  IMGR_HIP(hipMemcpyAsync(cw.kern, P.kall.data(), P.kall.size() * sizeof(double),
                           hipMemcpyHostToDevice, s));
   IMGR_HIP(hipMemsetAsync(cw.model, 0, (size_t)nn * sizeof(double), s));
   IMGR_HIP(hipMemsetAsync(cw.state, 0, sizeof(CleanState), s));
   // R_s = phi_s * D, B_ab = phi_a phi_b * P
   for (int i = 0; i < n_int; ++i)
-    conv_same(dirty, n, cw.kern + koff[i], rad[i], cw.R + (size_t)i * nn, s);
+    conv_same(dirty, n, cw.kern + P.koff[i], P.rad[i], cw.R + (size_t)i * nn, s);
   for (int q = 0; q < n_pairs; ++q)
-    conv_same(psf, n2, cw.kern + poff[q], prad[q], cw.B + (size_t)q * n2 * n2, s);
+    conv_same(psf, n2, cw.kern + P.poff[q], P.prad[q], cw.B + (size_t)q * n2 * n2, s);
   IMGR_HIP(hipGetLastError());
 
   StepArgs sa;
@@ -515,22 +525,22 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
   se.kern = cw.kern;
   for (int a = 0; a < kMaxInt; ++a) {
     for (int b = 0; b < kMaxInt; ++b)
-      sa.pair[a][b] = se.pair[a][b] = (a < n_int && b < n_int) ? pair[a][b] : 0;
+      sa.pair[a][b] = se.pair[a][b] = (a < n_int && b < n_int) ? P.pair[a][b] : 0;
     sa.bias[a] = 0.0;
     sa.selectable[a] = 0;
     se.koff[a] = se.krad[a] = 0;
     se.user[a] = -1;
   }
   for (int i = 0; i < n_int; ++i) {
-    sa.bias[i] = (smax == 0.0) ? 1.0 : 1.0 - prm.bias_slope * sc[i] / smax;
-    sa.selectable[i] = selectable[i];
-    se.koff[i] = koff[i];
-    se.krad[i] = rad[i];
-    se.user[i] = user[i];
+    sa.bias[i] = (P.smax == 0.0) ? 1.0 : 1.0 - prm.bias_slope * P.sc[i] / P.smax;
+    sa.selectable[i] = P.selectable[i];
+    se.koff[i] = P.koff[i];
+    se.krad[i] = P.rad[i];
+    se.user[i] = P.user[i];
   }
   sa.n_int = se.n_int = n_int;
   sa.n = se.n = n;
-  sa.r0 = r0;
+  sa.r0 = P.r0;
   se.gain = prm.gain;
   se.threshold = prm.threshold;
   const int nblk = std::min(kStepBlocks, (int)cdiv(nn, kStepThreads));
@@ -561,10 +571,100 @@ void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const 
                        slots + ((k + 1) % 2) * kStepBlocks, 0, comps, cw.model);
   IMGR_HIP(hipGetLastError());
   FinishArgs fa;
-  for (int t = 0; t < kMaxInt; ++t) fa.pair_r0[t] = (t < n_int) ? pair[t][r0] : 0;
-  hipLaunchKernelGGL(k_clean_finish, dim3(cdiv(nn, 256)), dim3(256), 0, s, cw.R + (size_t)r0 * nn,
-                     cw.B, fa, st, n, cw.model, model_delta, model_accum, resid_out);
+  for (int t = 0; t < kMaxInt; ++t) fa.pair_r0[t] = (t < n_int) ? P.pair[t][P.r0] : 0;
+  hipLaunchKernelGGL(k_clean_finish, dim3(cdiv(nn, 256)), dim3(256), 0, s,
+                     cw.R + (size_t)P.r0 * nn, cw.B, fa, st, n, cw.model, model_delta,
+                     model_accum, resid_out);
   IMGR_HIP(hipGetLastError());
+}
+
+// Device addresses of `scratch` (below), one per device, taken once per
+// device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+void *static_area(int device) {
+  IMGR_CHECK(device >= 0 && device < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[device]) {
+    void *p = nullptr;
+    IMGR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    IMGR_CHECK(p != nullptr, "hipGetSymbolAddress returned no address for the work area");
+    g_static_ptr[device] = p;
+  }
+  return g_static_ptr[device];
+}
+
+inline size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+void msclean_enqueue(imgr_s *h, int part, const imgr_msclean_params &prm, const float *dirty,
+                     const float *psf, float *model_delta, float *model_accum, float *resid_out,
+                     imgr_component *comps, hipStream_t s) {
+  const int n = h->N, nn = n * n, n2 = 2 * n;
+  const CleanPlan P = make_plan(prm);
+  // device work area of this node (grown on demand, kept for later calls)
+  CleanWork &cw = h->clean[part];
+  const size_t need_R = (size_t)P.n_int * nn, need_B = (size_t)P.n_pairs * n2 * n2;
+  if (cw.R_elems < need_R || cw.B_elems < need_B || cw.k_elems < P.kall.size()) {
+    msclean_release(h, part);
+    cw.R = (double *)dev_alloc(h, need_R * sizeof(double));
+    cw.B = (double *)dev_alloc(h, need_B * sizeof(double));
+    cw.kern = (double *)dev_alloc(h, P.kall.size() * sizeof(double));
+    cw.model = (double *)dev_alloc(h, (size_t)nn * sizeof(double));
+    cw.state = dev_alloc(h, sizeof(CleanState));
+    cw.slots = dev_alloc(h, (size_t)2 * kStepBlocks * sizeof(Cand));
+    cw.R_elems = need_R;
+    cw.B_elems = need_B;
+    cw.k_elems = P.kall.size();
+  }
+  enqueue_plan(h, P, prm, dirty, psf, model_delta, model_accum, resid_out, comps, cw, s);
+}
+
+size_t msclean_static_bytes(const imgr_s *h, const imgr_msclean_params &prm) {
+  const CleanPlan P = make_plan(prm);
+  const size_t nn = (size_t)h->N * h->N;
+  return up256(sizeof(CleanState)) + up256((size_t)2 * kStepBlocks * sizeof(Cand)) +
+         up256(nn * sizeof(double)) + up256(P.kall.size() * sizeof(double)) +
+         up256((size_t)P.n_int * nn * sizeof(double)) +
+         up256((size_t)P.n_pairs * 4 * nn * sizeof(double));
+}
+
+int msclean_enqueue_static(imgr_s *h, const imgr_msclean_params &prm, const float *dirty,
+                           const float *psf, float *model_delta, float *model_accum,
+                           float *resid_out, imgr_component *comps, hipStream_t s) {
+  const CleanPlan P = make_plan(prm);
+  const size_t need = msclean_static_bytes(h, prm);
+  if (need > (size_t)IMGR_MSCLEAN_STATIC_BYTES)
+    throw Error{IMGR_EINVAL, "the static msCLEAN work area holds " +
+                                 std::to_string((size_t)IMGR_MSCLEAN_STATIC_BYTES) +
+                                 " bytes; this image size and scale set need " +
+                                 std::to_string(need)};
+  int dev = -1;
+  IMGR_HIP(hipGetDevice(&dev));
+  IMGR_CHECK(dev == h->device, "the handle's device must be current");
+  unsigned char *base = (unsigned char *)static_area(dev);
+  const size_t nn = (size_t)h->N * h->N;
+  CleanWork cw;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void *p = base + off;
+    off += up256(bytes);
+    return p;
+  };
+  cw.state = take(sizeof(CleanState));
+  cw.slots = take((size_t)2 * kStepBlocks * sizeof(Cand));
+  cw.model = (double *)take(nn * sizeof(double));
+  cw.kern = (double *)take(P.kall.size() * sizeof(double));
+  cw.R = (double *)take((size_t)P.n_int * nn * sizeof(double));
+  cw.B = (double *)take((size_t)P.n_pairs * 4 * nn * sizeof(double));
+  enqueue_plan(h, P, prm, dirty, psf, model_delta, model_accum, resid_out, comps, cw, s);
+  IMGR_HIP(hipStreamSynchronize(s));
+  CleanState hs;
+  IMGR_HIP(hipMemcpy(&hs, cw.state, sizeof(CleanState), hipMemcpyDeviceToHost));
+  return hs.n_comps;
 }
 
 }  // namespace imgr

@@ -87,6 +87,7 @@ _SIGS = {
     "imager_major_cycle_nodes": [_P, _P, _P, _P, _P, _P, _P, _I],
     "imager_composed_psf": [_P, _I, _D, _D, _P],
     "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
+    "imager_minor_cycle_msclean_static": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "imager_reconstruct_msclean": [_P, _I, _P, _P, _P, _P, _P],
     "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "imager_reconstruct_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P],
@@ -424,9 +425,11 @@ class Imager:
 
     def minor_cycle_msclean(self, part, dirty, psf, scales, gain=0.1, niter=2000, threshold=0.0,
                             bias_slope=0.6, active=None, own_scales_only=False, model_accum=None,
-                            want_residual=True):
+                            want_residual=True, static=False):
         """Multi-scale CLEAN of one node (synchronous).  Returns (model_delta,
-        components (numpy structured array), residual or None)."""
+        components (numpy structured array), residual or None).  With
+        ``static`` the library's non-allocating entry point is called
+        (imager_minor_cycle_msclean_static)."""
         import torch
         n = self.n_pix
         _dev_f32(dirty, (n, n), torch)
@@ -437,9 +440,10 @@ class Imager:
         comps = torch.empty(max(int(niter), 1) * COMPONENT_DTYPE.itemsize, dtype=torch.uint8,
                             device="cuda")
         cnt = ctypes.c_int32(0)
-        self._check(lib().imager_minor_cycle_msclean(
-            self._h, part, ctypes.byref(prm), _ptr(dirty), _ptr(psf), _ptr(delta),
-            _ptr(model_accum), _ptr(resid), _ptr(comps), ctypes.byref(cnt)))
+        fn = (lib().imager_minor_cycle_msclean_static if static
+              else lib().imager_minor_cycle_msclean)
+        self._check(fn(self._h, part, ctypes.byref(prm), _ptr(dirty), _ptr(psf), _ptr(delta),
+                       _ptr(model_accum), _ptr(resid), _ptr(comps), ctypes.byref(cnt)))
         raw = comps[:cnt.value * COMPONENT_DTYPE.itemsize].cpu().numpy()
         return delta, np.frombuffer(raw.tobytes(), dtype=COMPONENT_DTYPE), resid
 
