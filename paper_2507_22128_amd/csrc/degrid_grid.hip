@@ -87,9 +87,12 @@ __device__ __forceinline__ void st2(float2 *p, size_t i, float2 v) {
 // orders the LDS traffic of one wave around a point where its lanes
 // exchange data (no other wave shares the data)
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  // A wave's LDS instructions are executed in the order it issues them, so
+  // a lane reads what another lane of the same wave wrote by an earlier
+  // instruction without waiting for the write to complete; only the
+  // compiler must not move LDS accesses across this point.
+  __asm__ volatile("" ::: "memory");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // sums over the four lanes c16 + 16 g (g = 0..3) of a wave: lanes with
@@ -257,14 +260,21 @@ __device__ __forceinline__ void window_chunk(const WinArgs &a, int chunk, float 
   }
 }
 
-// LDS of one wave in the row-group form
-// row strides of the tap tables: 20 and 12 floats keep the 16-byte reads
-// of eight consecutive lanes on distinct banks
-constexpr int kKx = 20, kKy = 12;
+// LDS of one wave in the row-group form.  Per batch of 16 visibilities:
+//   kxT[x][k]      column weight of visibility k at window column x,
+//   ky[k][t]       row weight of visibility k at footprint row t,
+//   pT[m][k]       part_c(r_k) ky_k[y] for m = 8 c + y (the gridding product's
+//                  left operand), written over ky once ky has been read.
+// Row strides: 20 floats for the transposed tables (the 16-byte reads of
+// eight consecutive lanes, rows m .. m + 7, land on distinct banks) and 12
+// for ky (the same for its 16-byte reads).
+constexpr int kS = 20, kKy = 12;
 struct RowsLds {
-  float kx[16 * kKx];    // [visibility][window column] tap weights
-  float ky[16 * kKy];    // [visibility][footprint row] tap weights
-  float r[16 * 2];       // weighted residual (re, im) per visibility
+  float kxT[16 * kS];
+  union {
+    float ky[16 * kKy];
+    float pT[16 * kS];
+  };
   float g[2][16 * 16];   // model window: real, imaginary planes [row][column]
   float acc[2][16 * 16]; // residual window: real, imaginary planes
 };
@@ -273,7 +283,6 @@ template <int W, int BLK, int MODE>
 __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, RowsLds &s) {
   static_assert(W <= 8 && BLK + 7 <= kWin, "the row groups must fit the window");
   constexpr int H = W / 2 - 1;
-  constexpr int TPL = (W + 3) / 4;  // taps per lane and axis
   constexpr float kC = 2.0f / W;    // z = (t - H - f) * kC for tap t at fraction f
   constexpr bool kDegrid = (MODE == MODE_DEGRID_GRID || MODE == MODE_DEGRID);
   constexpr bool kGrid = (MODE != MODE_DEGRID);
@@ -289,17 +298,19 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
   const int b = cst(a.chunk_begin)[chunk];
   const AS_CONST int32_t *__restrict__ rows = cst(a.chunk_rows) + 8 * chunk;
 
-  float qa[TPL], qb[TPL];
+  // this lane's taps t = 2 g, 2 g + 1 of each axis (those >= W have zero
+  // weight); 1 - z^2 = qa + qb f + qc f^2 with t0 = t - H
+  float qa[2], qb[2];
 #pragma unroll
-  for (int q = 0; q < TPL; ++q) {
-    const float t0 = (float)(g * TPL + q - H);
+  for (int q = 0; q < 2; ++q) {
+    const float t0 = (float)(2 * g + q - H);
     qa[q] = 1.0f - kC * kC * t0 * t0;
     qb[q] = 2.0f * kC * kC * t0;
   }
   constexpr float qc = -kC * kC;
 
-  // chunk set-up: the model window in LDS (two planes), a zero residual
-  // window, and zero footprint rows (taps W .. 7 are never written)
+  // chunk set-up: the model window in LDS (two planes) and a zero residual
+  // window
   wave_sync();
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -314,15 +325,14 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       s.acc[1][y * 16 + c16] = 0.f;
     }
   }
-  *(float2 *)&s.ky[c16 * kKy + 2 * g] = make_float2(0.f, 0.f);
   wave_sync();
 
   // row groups: group j holds the chunk's visibilities [b + rows[j-1], b + rows[j])
   int oy = 0, ge = b + rows[0];
   while (ge == b && oy < BLK - 1) ge = b + rows[++oy];
   float foy = (float)oy;
-  // A operand of the group: in K-step q lane (c16, g) holds G_c[oy + y][4 q + g],
-  // c16 = 8 c + y
+  // A operand of the degridding: in K-step q lane (c16, g) holds
+  // G_c[oy + y][4 q + g], c16 = 8 c + y
   floatx4 ga = {0.f, 0.f, 0.f, 0.f};
   auto load_ga = [&]() {
     const float *row = &s.g[c16 >> 3][(oy + (c16 & 7)) * 16 + g];
@@ -333,13 +343,11 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 
   // lane (c16, g) works on visibility c16 of each batch; the record of the
-  // next batch is loaded while the current one is processed (indices past
-  // the group are clamped to its last visibility and masked by `valid`)
-  // (chunks are never empty; the guard keeps every read inside the chunk).
-  // The stream is read through buffer descriptors with 32-bit offsets.  The
-  // record index of a lane past the batch's group is clamped to the group's
-  // last visibility; its weight is read through a descriptor that ends at
-  // the group, so the hardware returns 0 for it and masks its residual
+  // next batch is loaded while the current one is processed.  The stream is
+  // read through buffer descriptors with 32-bit offsets.  The record index
+  // of a lane past the batch's group is clamped to the group's last
+  // visibility; its weight is read through a descriptor that ends at the
+  // group, so the hardware returns 0 for it and masks its residual
   const __amdgpu_buffer_rsrc_t pv_rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)posvis, (short)0, a.n * 16, kBufferWord3);
   auto load_pv = [&](int first, int end) {  // record first + c16 (clamped to end - 1)
@@ -354,17 +362,21 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
     return __uint_as_float(
         __builtin_amdgcn_raw_buffer_load_b32(rs, (unsigned)(first + c16) * 4u, 0, 0));
   };
-  float4 pv_next = make_float4(0.f, 0.f, 0.f, 0.f);
-  float w_next = 0.f;
+  // two record sets in turn (ping-pong): a batch loads the next batch's
+  // records into the other set, so no register copy (which would wait for
+  // the load) closes an iteration
+  float4 pvA = make_float4(0.f, 0.f, 0.f, 0.f), pvB = pvA;
+  float wA = 0.f, wB = 0.f;
   if (ge > b) {
-    pv_next = load_pv(b, ge);
-    if constexpr (kGrid) w_next = load_w(b, ge);
+    pvA = load_pv(b, ge);
+    if constexpr (kGrid) wA = load_w(b, ge);
   }
-  for (int base = b; ge > b;) {
+  int base = b;
+  // one batch on records (pv, w); loads the next batch's into (pvn, wn);
+  // false once the chunk is done
+  auto batch = [&](const float4 pv, const float w, float4 &pvn, float &wn) -> bool {
     const int v = base + c16;
     const bool valid = c16 < ge - base;
-    const float4 pv = pv_next;
-    const float w = w_next;  // 0 for lanes past the group
     // the next batch: the rest of this group, else the next nonempty group
     int nbase = base + 16, nge = ge, noy = oy;
     const bool group_end = nbase >= ge;
@@ -375,32 +387,35 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
     // (without a next batch, nbase == nge: the loads re-read the last record
     // and return zero weights, which keeps them unconditional)
     const bool more = nbase < nge;
-    pv_next = load_pv(nbase, nge);
-    if constexpr (kGrid) w_next = load_w(nbase, nge);
+    pvn = load_pv(nbase, nge);
+    if constexpr (kGrid) wn = load_w(nbase, nge);
     // offsets are >= 0, so truncation is the floor; the row is the group's
     const int ox = min(max((int)pv.x, 0), BLK - 1);
     const float fx = pv.x - (float)ox, fy = pv.y - foy;
 
-    // tap weights: clear this lane's quarter of the column table row of its
-    // visibility, then write taps g*TPL .. g*TPL + TPL - 1 of each axis:
-    // phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1))
-    *(floatx4 *)&s.kx[c16 * kKx + 4 * g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // tap weights phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1)); the column
+    // table is cleared by the whole wave first (lane l: row l / 4, columns
+    // 4 (l % 4) ..), then every lane writes its column taps at window
+    // columns ox + t and its row taps t (zero for t >= W)
+    *(floatx4 *)&s.kxT[(l >> 2) * kS + 4 * (l & 3)] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float wy2[2];
 #pragma unroll
-    for (int q = 0; q < TPL; ++q) {
-      const int t = g * TPL + q;
-      if (t < W) {
-        // 1 - z^2 >= 0 on the support; rounding can leave -1e-8 at |z| = 1,
-        // so the root takes the magnitude (a free source modifier)
-        const float sx = fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]);
-        const float sy = fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]);
-        s.kx[c16 * kKx + ox + t] =
-            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(fabsf(sx)), -bl2e));
-        s.ky[c16 * kKy + t] =
-            __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(fabsf(sy)), -bl2e));
-      }
+    for (int q = 0; q < 2; ++q) {
+      const int t = 2 * g + q;
+      // 1 - z^2 >= 0 on the support; rounding can leave -1e-8 at |z| = 1,
+      // so the root takes the magnitude (a free source modifier)
+      const float sx = fmaf(fmaf(qc, fx, qb[q]), fx, qa[q]);
+      const float sy = fmaf(fmaf(qc, fy, qb[q]), fy, qa[q]);
+      const float wx = __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(fabsf(sx)), -bl2e));
+      const float wyv = __builtin_amdgcn_exp2f(fmaf(bl2e, __builtin_amdgcn_sqrtf(fabsf(sy)), -bl2e));
+      if (W == 8 || t < W) s.kxT[(ox + t) * kS + c16] = wx;
+      wy2[q] = (W == 8 || t < W) ? wyv : 0.f;
     }
+    *(float2 *)&s.ky[c16 * kKy + 2 * g] = make_float2(wy2[0], wy2[1]);
     wave_sync();
 
+    // row weights of this lane's footprint rows 4 (g & 1) .. + 3
+    const floatx4 by = *(const floatx4 *)&s.ky[c16 * kKy + 4 * (g & 1)];
     float val = 0.f;  // predicted visibility: real part in lanes g = 0, 1, imaginary in g = 2, 3
     if constexpr (kDegrid) {
       // T[m][k] = sum_x Gs[m][x] kx_k[x]: K-step q takes window columns
@@ -411,8 +426,8 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       // are skipped, which leaves the sums unchanged
       const int s_lo = __builtin_amdgcn_readfirstlane(ox) >> 2;
       const int s_hi = (__builtin_amdgcn_readlane(ox, 15) + W - 1) >> 2;
-      const float *kxr = &s.kx[c16 * kKx + g];
-      const floatx4 kq = {kxr[0], kxr[4], kxr[8], kxr[12]};
+      const float *kxr = &s.kxT[g * kS + c16];
+      const floatx4 kq = {kxr[0], kxr[4 * kS], kxr[8 * kS], kxr[12 * kS]};
       floatx4 t = {0.f, 0.f, 0.f, 0.f};
 #define MF_(q) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[q], kq[q], t, 0, 0, 0)
       switch (s_lo * 4 + s_hi) {  // (first, last) K-step
@@ -429,7 +444,6 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       }
 #undef MF_
       // lane (c16, g) holds T[4 g + r][c16]: part g >> 1, rows 4 (g & 1) + r
-      const floatx4 by = *(const floatx4 *)&s.ky[c16 * kKy + 4 * (g & 1)];
       float p = by[0] * t[0];
 #pragma unroll
       for (int r = 1; r < 4; ++r) p = fmaf(by[r], t[r], p);
@@ -443,31 +457,28 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
         glb(reinterpret_cast<float *>(a.vis_out))[2 * (size_t)glb(a.outpos)[v] + (g >> 1)] = val;
     }
     if constexpr (kGrid) {
+      // part c = g >> 1 of the weighted residual (or visibility) r_k of this
+      // lane's visibility k = c16
+      float rc;
       if constexpr (MODE == MODE_DEGRID_GRID) {
-        // lane g = 0 forms the real part of w (v - v_hat), lane g = 2 the imaginary
-        if (!(g & 1)) s.r[2 * c16 + (g >> 1)] = w * ((g ? pv.w : pv.z) - val);
-      } else if (g == 0) {
-        float2 r;
-        if constexpr (MODE == MODE_GRID) {
-          float2 x = make_float2(0.f, 0.f);
-          if (valid) x = ld2(a.vis_in, glb(a.outpos)[v]);
-          r = make_float2(w * x.x, w * x.y);
-        } else {  // MODE_PSF: unit visibilities
-          r = make_float2(w, 0.f);
-        }
-        *(float2 *)&s.r[2 * c16] = r;
+        rc = w * ((g >> 1 ? pv.w : pv.z) - val);
+      } else if constexpr (MODE == MODE_GRID) {
+        float2 x = make_float2(0.f, 0.f);
+        if (valid) x = ld2(a.vis_in, glb(a.outpos)[v]);
+        rc = w * (g >> 1 ? x.y : x.x);
+      } else {  // MODE_PSF: unit visibilities
+        rc = (g >> 1) ? 0.f : w;
       }
-      wave_sync();
-      // A_oy[m][x] += sum_k part_c(r_k) ky_k[y] kx_k[x], m = c16 = 8 c + y;
-      // K-step q covers k = 4 q + g
+      // pT[m][k] = part_c(r_k) ky_k[y] for m = 8 c + y = 4 g + r (over ky:
+      // this wave has read it)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = 4 * q + g;
-        const float kyv = s.ky[k * kKy + (c16 & 7)];
-        const float kxv = s.kx[k * kKx + c16];
-        const float rc = s.r[2 * k + (c16 >> 3)];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(rc * kyv, kxv, acc, 0, 0, 0);
-      }
+      for (int r = 0; r < 4; ++r) s.pT[(4 * g + r) * kS + c16] = rc * by[r];
+      wave_sync();
+      // A_oy[m][x] += sum_k pT[m][k] kxT[x][k]; K-step q covers k = 4 g + q
+      const floatx4 pa = *(const floatx4 *)&s.pT[c16 * kS + 4 * g];
+      const floatx4 kb = *(const floatx4 *)&s.kxT[c16 * kS + 4 * g];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[q], kb[q], acc, 0, 0, 0);
     }
     wave_sync();  // the tables are rewritten by the next batch
 
@@ -479,13 +490,20 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
         acc = floatx4{0.f, 0.f, 0.f, 0.f};
         wave_sync();
       }
-      if (!more) break;
+      if (!more) return false;
       oy = noy;
       foy = (float)oy;
       if constexpr (kDegrid) load_ga();
     }
     base = nbase;
     ge = nge;
+    return true;
+  };
+  if (ge > b) {
+    for (;;) {
+      if (!batch(pvA, wA, pvB, wB)) break;
+      if (!batch(pvB, wB, pvA, wA)) break;
+    }
   }
 
   if constexpr (kGrid) {
