@@ -36,12 +36,12 @@ FP32_PEAK_MATRIX = 157.3
 
 # HBM bytes per launch of the fused de/grid kernel, per workload, from the
 # FETCH_SIZE / WRITE_SIZE counter runs with the copy-kernel calibration
-# (profiles/k_window_*_hbm_traffic.md), valid only for the kernel source the
+# (profiles/convex_hbm_traffic.md), valid only for the kernel source the
 # counters were taken on.
 KWINDOW_TRAFFIC = {
-    "decentral": {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
-                  "sha256_16": "77d023a885a28790",
-                  "bytes_per_launch": (99263.4 * 1024 * 2.0 + 29744.0 * 1024 * 1.0)},
+    "convex": {"src": "paper_2507_22128_amd/csrc/degrid_grid.hip",
+               "sha256_16": "82c20d456774f7c4",
+               "bytes_per_launch": (340043.8 * 1024 * 2.0 + 101240.0 * 1024 * 1.0)},
 }
 
 
@@ -210,7 +210,7 @@ def batched_channels(args, small=False):
     t0 = time.perf_counter()
     cfg = dict(synth.CHANNELS)
     if small:
-        cfg.update(n_chan=args.batch_small_channels, n_time=16, sizes=(256, 512))
+        cfg.update(n_chan=args.batch_small_channels, n_time=16, t_min=8, sizes=(256, 512))
     else:
         cfg["n_chan"] = args.batch_channels
     d = synth.make_channels(device="cuda", **cfg)
@@ -272,23 +272,52 @@ def batched_channels(args, small=False):
         last[name] = [r.clone() for r in res]
         log("%s %s: %.3f ms per cycle of all channels, %.0f Mvis/s"
             % (tag, name, ms, info.n_vis / (ms / 1e3) / 1e6))
+    # the same fused cycle in member sets of 128 MB (half of the last-level
+    # cache), each set's stages back to back (default: one set, one
+    # de/gridding launch and one flush for all channels)
+    n_sets = int(b.info().n_sets)
+    b.set_bytes(128 << 20)
+    n_sets_cache = int(b.info().n_sets)
+    for name, mode in (("fused_sets_128mb_graph", dict(graph=True)),
+                       ("fused_sets_128mb_eager", {})):
+        for _ in range(args.warmup):
+            b.major_cycle(models, res, **mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            b.major_cycle(models, res, **mode)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.batch_steps
+        out[name] = {"ms_per_cycle": round(ms, 3),
+                     "mvis_per_s": round(info.n_vis / (ms / 1e3) / 1e6, 1)}
+        last[name] = [r.clone() for r in res]
+        log("%s %s: %.3f ms per cycle of all channels, %.0f Mvis/s"
+            % (tag, name, ms, info.n_vis / (ms / 1e3) / 1e6))
+    b.set_bytes(0)
     same = all(torch.equal(a, c) for a, c in zip(last["fused_graph"], last["per_channel_loop"]))
+    same = same and all(torch.equal(a, c) for a, c in zip(last["fused_graph"],
+                                                          last["fused_sets_128mb_graph"]))
     sizes = [m.n_pix for m in members]
     t_win = cap_ms[chosen] / 1e3
     flops = flops_per_vis(i0.support) * info.n_vis
     out.update({
-        "workload": "%d channels %.2f - %.2f GHz, %d antennas x %d times (%d visibilities per "
-                    "channel before flags), flags uniform 0 - %.0f %% per channel, images %s, "
-                    "complex64, uniform weighting, 1 partition per channel"
+        "workload": "%d channels %.2f - %.2f GHz, %d antennas, %d baselines x T_c times with "
+                    "T_c uniform in %d .. %d per channel, flags uniform 0 - %.0f %% per channel, "
+                    "images %s, complex64, uniform weighting, 1 partition per channel"
                     % (len(chans), cfg["f_lo"] / 1e9, cfg["f_hi"] / 1e9, cfg["n_ant"],
-                       cfg["n_time"], d["n_vis"], 100 * cfg["flag_max"],
+                       cfg["n_ant"] * (cfg["n_ant"] - 1) // 2,
+                       cfg.get("t_min") or cfg["n_time"], cfg["n_time"], 100 * cfg["flag_max"],
                        "/".join(str(x) for x in cfg["sizes"])),
         "n_channels": len(members),
         "n_vis": int(info.n_vis),
         "image_sizes": {str(x): sizes.count(x) for x in sorted(set(sizes))},
         "support": i0.support, "tile": i0.tile, "chunk": chosen,
         "n_chunks_fused": int(info.n_chunks),
-        "n_sets": int(b.info().n_sets),
+        "n_sets": n_sets,
+        "n_sets_128mb": n_sets_cache,
+        "time_samples_per_channel": [int(min(c["n_time"] for c in chans)),
+                                     int(max(c["n_time"] for c in chans))],
+        "n_vis_per_channel": [int(min(n_ok)), int(max(n_ok))],
         "create_tuner": [{"tile": t, "chunk": c, "ms": round(x, 4)} for t, c, x in tune_log],
         "batch_tuner_ms": {str(k): round(v, 4) for k, v in cap_ms.items()},
         "fused_window_flush_ms": round(cap_ms[chosen], 4),
@@ -308,38 +337,51 @@ def batched_channels(args, small=False):
 
 def serving(args):
     """Serving workload: a Poisson stream of imaging requests shaped like the
-    single-channel workloads (images 512 / 1024, 2.2 - 7.8M unflagged
-    visibilities from the 256-antenna array at 240 times with 0-60 % flags,
-    msCLEAN (S = {0, 4, 12}, K = 500 per cycle) or FISTA (db8, 50 iterations,
-    30 power iterations), 1 or 2 partitions, 5-10 major cycles), served with
+    single-channel workloads (the 256-antenna array, 1 - 50M visibilities
+    log-uniform, images 512 / 1024 / 2048, msCLEAN (S = {0, 4, 12}) or
+    FISTA (db8), 1 or 2 partitions, 5 - 10 major cycles), served with
     admission by device-memory footprint and continuous batching at cycle
-    boundaries; compared with plain serial execution of the same requests."""
+    boundaries, at each arrival rate; compared with plain serial execution
+    of the same requests."""
     import numpy as np
     import torch
     from paper_2507_22128_amd import serve, synth
     n_req = args.serve_requests
-    d = synth.make_channels(n_chan=n_req, n_time=240, sizes=(512, 1024), seed=6, device="cuda")
+    t0 = time.perf_counter()
+    d = synth.make_requests(n_req, seed=6, device="cuda")
+    torch.cuda.synchronize()
+    log("serving: %d requests generated in %.1f s (%.1f - %.1f M visibilities, images %s)"
+        % (n_req, time.perf_counter() - t0, min(r["n_vis"] for r in d) / 1e6,
+           max(r["n_vis"] for r in d) / 1e6, sorted(set(r["n_img"] for r in d))))
     rng = np.random.default_rng(8)
     reqs = []
-    for k, c in enumerate(d["channels"]):
+    for k, r in enumerate(d):
         reqs.append(serve.Request(
-            uvw=d["uvw"], vis=c["vis"], freq_hz=c["freq_hz"], cell=c["cell"], n_pix=c["n_img"],
-            flag=c["flag"], method="msclean" if rng.random() < 0.5 else "fista",
-            n_cycles=int(rng.integers(5, 11)), n_partitions=int(rng.integers(1, 3)), niter=500,
-            fista_iter=50, power_iters=30, name="req%d" % k, power_seed=k))
+            uvw=r["uvw"], vis=r["vis"], freq_hz=r["freq_hz"], cell=r["cell"], n_pix=r["n_img"],
+            method="msclean" if rng.random() < 0.5 else "fista",
+            n_cycles=int(rng.integers(5, 11)), n_partitions=int(rng.integers(1, 3)),
+            niter=args.serve_clean_iter, fista_iter=args.serve_fista_iter,
+            power_iters=args.serve_power_iter, name="req%d" % k, power_seed=k))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     serial = serve.run_serial(reqs)
     t_serial = time.perf_counter() - t0
     ref = [f for f, _ in serial]
+    service = [t for _, t in serial]
     log("serving: %d requests, plain serial execution %.2f s" % (n_req, t_serial))
     out = {"requests": n_req,
            "mix": {"msclean": sum(r.method == "msclean" for r in reqs),
                    "fista": sum(r.method == "fista" for r in reqs),
                    "two_partitions": sum(r.n_partitions == 2 for r in reqs),
-                   "image_sizes": sorted(set(r.n_pix for r in reqs)),
+                   "image_sizes": {str(x): sum(r.n_pix == x for r in reqs)
+                                   for x in sorted(set(r.n_pix for r in reqs))},
+                   "n_vis_millions": [round(min(r.n_vis for r in reqs) / 1e6, 2),
+                                      round(max(r.n_vis for r in reqs) / 1e6, 2)],
                    "cycles": [int(min(r.n_cycles for r in reqs)),
-                              int(max(r.n_cycles for r in reqs))]},
+                              int(max(r.n_cycles for r in reqs))],
+                   "per_cycle": "msCLEAN K = %d per node, FISTA %d iterations + %d power "
+                                "iterations" % (args.serve_clean_iter, args.serve_fista_iter,
+                                                args.serve_power_iter)},
            "hbm_budget_gib": args.serve_budget_gib, "workers": args.serve_workers,
            "rates": {}}
     vis_cycles = None
@@ -363,9 +405,19 @@ def serving(args):
         for r, f in zip(res, ref):
             same = same and bool(torch.equal(r.final, f))
             errs.append(float(torch.linalg.norm(r.final - f) / torch.linalg.norm(f)))
+        # the plain path at the same arrivals: one request after another in
+        # arrival order, each taking its measured serial service time
+        done, ser_lat = 0.0, []
+        for at, sv in zip(arr, service):
+            done = max(done, at) + sv
+            ser_lat.append(done - at)
+        ser_lat = np.array(sorted(ser_lat)) * 1e3
         out["rates"][str(rate)] = {
             "p50_ms": round(float(np.percentile(lat, 50)), 1),
             "p99_ms": round(float(np.percentile(lat, 99)), 1),
+            "serial_p50_ms": round(float(np.percentile(ser_lat, 50)), 1),
+            "serial_p99_ms": round(float(np.percentile(ser_lat, 99)), 1),
+            "serial_makespan_s": round(float(done), 3),
             "makespan_s": round(makespan, 3),
             "aggregate_mvis_per_s": round(vis_cycles / makespan / 1e6, 1),
             "max_resident_requests": srv.max_resident_jobs,
@@ -375,11 +427,11 @@ def serving(args):
             "max_rel_err_vs_serial": max(errs),
             "identical_to_serial": same,
         }
-        log("serving at %.0f req/s: p50 %.0f ms, p99 %.0f ms, makespan %.2f s, %.0f Mvis/s "
-            "(serial %.0f Mvis/s), identical %s" % (rate, np.percentile(lat, 50),
-                                                    np.percentile(lat, 99), makespan,
-                                                    vis_cycles / makespan / 1e6,
-                                                    vis_cycles / t_serial / 1e6, same))
+        log("serving at %.0f req/s: p50 %.0f ms, p99 %.0f ms (serial at these arrivals: %.0f / "
+            "%.0f ms), makespan %.2f s, %.0f Mvis/s (serial %.0f Mvis/s), identical %s"
+            % (rate, np.percentile(lat, 50), np.percentile(lat, 99), np.percentile(ser_lat, 50),
+               np.percentile(ser_lat, 99), makespan, vis_cycles / makespan / 1e6,
+               vis_cycles / t_serial / 1e6, same))
     out["serial"] = {"seconds": round(t_serial, 3),
                      "aggregate_mvis_per_s": round(vis_cycles / t_serial / 1e6, 1)}
     out["vis_cycles"] = int(vis_cycles)
@@ -570,10 +622,13 @@ def main():
     ap.add_argument("--batch-small-channels", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[2.0, 10.0, 50.0])
+    ap.add_argument("--serve-requests", type=int, default=50)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[2.0, 5.0, 10.0, 20.0, 50.0])
     ap.add_argument("--serve-workers", type=int, default=4)
-    ap.add_argument("--serve-budget-gib", type=float, default=12.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-clean-iter", type=int, default=200)
+    ap.add_argument("--serve-fista-iter", type=int, default=20)
+    ap.add_argument("--serve-power-iter", type=int, default=10)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the steps, run a plain device copy of this many MiB three "
                          "times (a known-size kernel to scale hardware byte counters by)")

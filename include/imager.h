@@ -433,8 +433,8 @@ imgr_status imager_set_chunk(imgr_t h, int32_t chunk);
  * cell and flags, with the de/gridding of many of them as one fused launch
  * over their chunks (largest chunks first across channels), one fused
  * flush, and the model / residual transforms of the members with one image
- * size as one launch per pass.  Members are taken in consecutive sets sized
- * to the last-level cache, one fused launch each (imgr_batch_info.n_sets).  Members must have one partition, equal support and tile, and
+ * size as one launch per pass (imager_batch_set_bytes can split the members
+ * into cache-sized sets, one fused launch each; imgr_batch_info.n_sets).  Members must have one partition, equal support and tile, and
  * one stream, on which the batch enqueues its work.  The caller owns the
  * members; they must outlive the batch.  The batch uses the members' work
  * buffers, so a member's own calls and batch calls must be ordered (they
@@ -454,8 +454,8 @@ typedef struct {
   int64_t n_vis;        /* member visibilities over all members */
   int64_t n_chunks;     /* chunks of the fused launches */
   int32_t graph_ready;  /* 1 if a captured graph is held */
-  int32_t n_sets;       /* consecutive member sets, one fused launch each (their grids and
-                           chunk windows stay within half of the last-level cache) */
+  int32_t n_sets;       /* consecutive member sets, one fused launch each (1 unless
+                           imager_batch_set_bytes set a cache budget) */
 } imgr_batch_info;
 
 /* members: host array of n >= 1 handles.  Synchronous. */
@@ -478,6 +478,14 @@ imgr_status imager_batch_major_cycle(imgr_batch_t b, const float *const *model,
  * applied to all members and returned in *chosen.  Synchronous. */
 imgr_status imager_batch_autotune(imgr_batch_t b, const int32_t *caps, int32_t n_caps,
                                   int32_t reps, float *ms, int32_t *chosen);
+
+/* Cache budget of a member set (imgr_batch_info.n_sets).  By default (and
+ * with bytes = 0) all members form one set: one fused de/gridding launch and
+ * one flush per major cycle for all of them.  With bytes > 0 members are
+ * taken in consecutive sets whose model grids and chunk windows stay within
+ * `bytes`, each set's stages running back to back.  Results are unchanged
+ * bit for bit.  Rebuilds the batch's tables; synchronous. */
+imgr_status imager_batch_set_bytes(imgr_batch_t b, uint64_t bytes);
 
 /* Message for the last failure on b.  Never NULL. */
 const char *imager_batch_last_error(imgr_batch_t b);

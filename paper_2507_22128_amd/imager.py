@@ -103,6 +103,7 @@ _SIGS = {
     "imager_batch_info": [_P, ctypes.POINTER(BatchInfo)],
     "imager_batch_major_cycle": [_P, _P, _P, _I],
     "imager_batch_autotune": [_P, _P, _I, _I, _P, _P],
+    "imager_batch_set_bytes": [_P, ctypes.c_uint64],
 }
 
 MAX_SCALES = 8
@@ -590,6 +591,11 @@ class Batch:
         self._check(lib().imager_batch_major_cycle(self._b, _ptr_array(models),
                                                    _ptr_array(residuals), flags))
         return residuals
+
+    def set_bytes(self, nbytes):
+        """Cache budget of a member set (0: default; at least the members'
+        total: one set)."""
+        self._check(lib().imager_batch_set_bytes(self._b, int(nbytes)))
 
     def autotune(self, caps=(256, 512, 1024, 2048, 4096), reps=3):
         """Times the fused launch for every chunk cap, applies the fastest;

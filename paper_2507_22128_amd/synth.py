@@ -207,17 +207,21 @@ def random_uv_cells(m, n_grid, rng, frac=1.0 / 3.0):
 # uniformly at random with its own fraction in [0, 0.6], image sizes drawn
 # from 512 / 1024 / 2048 (the batched-channel workload).
 CHANNELS = dict(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9, f_hi=1.75e9,
-                flag_max=0.6, sizes=(512, 1024, 2048), n_points=200, seed=5)
+                flag_max=0.6, sizes=(512, 1024, 2048), n_points=200, seed=5, t_min=240)
 
 
 def make_channels(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9, f_hi=1.75e9,
-                  flag_max=0.6, sizes=(512, 1024, 2048), n_points=200, seed=5, device=None):
+                  flag_max=0.6, sizes=(512, 1024, 2048), n_points=200, seed=5, device=None,
+                  t_min=None):
     """Multi-channel workload over one array and one time range.
 
     Returns dict(uvw [M, 3] float64 metres shared by all channels, channels =
     list of dict(freq_hz, cell, n_img, flag uint8 [M], vis complex64 [M],
-    flag_frac)).  Channel c is at f_lo + (f_hi - f_lo) c / (n_chan - 1); its
-    cell is 1 / (3 max |u|) at that frequency.  The sky is n_points point
+    flag_frac, n_time)).  Channel c is at f_lo + (f_hi - f_lo) c / (n_chan - 1); its
+    cell is 1 / (3 max |u|) at that frequency.  With ``t_min`` each channel
+    keeps its own number of time samples T_c, uniform in {t_min .. n_time}:
+    its samples past the first T_c time steps are flagged (an uneven
+    observation length per channel).  The sky is n_points point
     sources with log-uniform fluxes in [1 mJy, 1 Jy] and spectral index -0.7
     (reference 1.4 GHz), placed in the central 80 % of the smallest field of
     view of the band; noise sigma 1 mJy.  With ``device`` (a torch cuda
@@ -242,6 +246,8 @@ def make_channels(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9
     m0 = rng.uniform(-0.4, 0.4, n_points) * fov
     flux0 = 10.0 ** rng.uniform(-3.0, 0.0, n_points)
     seeds = rng.integers(0, 2 ** 31 - 1, n_chan)
+    t_keep = (rng.integers(t_min, n_time + 1, n_chan) if t_min is not None
+              else np.full(n_chan, n_time))
     chans = []
     if device is not None:
         import torch
@@ -266,6 +272,7 @@ def make_channels(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9
                 vis[t * n_bl:(t + 1) * n_bl] = vmat[bj, bi]
             vis += 1e-3 * (crng.standard_normal(m_vis) + 1j * crng.standard_normal(m_vis))
             flag = (crng.random(m_vis) < flag_frac[c]).astype(np.uint8)
+            flag[int(t_keep[c]) * len(bi):] = 1
             vis = vis.astype(np.complex64)
         else:
             import torch
@@ -280,8 +287,80 @@ def make_channels(n_chan=64, n_ant=256, radius_m=4000.0, n_time=480, f_lo=0.95e9
             noise = torch.randn(2, m_vis, generator=g, device=device, dtype=torch.float32)
             vis = vis + 1e-3 * torch.complex(noise[0], noise[1])
             flag = (torch.rand(m_vis, generator=g, device=device) < flag_frac[c]).to(torch.uint8)
+            flag[int(t_keep[c]) * len(bi):] = 1
             del phase, ph, right, vmat, noise
         chans.append(dict(freq_hz=float(f), cell=float(cells[c]), n_img=n_img[c], flag=flag,
-                          vis=vis, flag_frac=float(flag_frac[c])))
+                          vis=vis, flag_frac=float(flag_frac[c]), n_time=int(t_keep[c])))
     return dict(uvw=uvw if device is None else uvw_out, channels=chans, n_vis=m_vis,
                 n_ant=n_ant, n_time=n_time)
+
+
+def make_requests(n_req, seed=6, n_ant=256, radius_m=4000.0, vis_range=(1.0e6, 5.0e7),
+                  sizes=(512, 1024, 2048), freq_hz=1.4e9, n_points=100, n_gauss=10,
+                  gauss_sigma_px=(2.0, 8.0), device="cuda"):
+    """Imaging requests of mixed shape for the serving workload.
+
+    Request r observes with the n_ant-antenna array for T_r time samples
+    over [-2 h, +2 h] (its own hour-angle grid), T_r = M_r / n_baselines
+    rounded, with M_r log-uniform in ``vis_range``; its image side is drawn
+    from ``sizes`` and its cell is 1 / (3 max |u|) of its own samples.  Its
+    sky has n_points points and n_gauss circular Gaussians (sigma in pixels
+    uniform in gauss_sigma_px), pixel-centred in the central 80 % of its
+    image, fluxes log-uniform in [1 mJy, 1 Jy]; noise sigma 1 mJy.  The
+    source sums are evaluated with torch on ``device`` in complex64.
+    Returns a list of dict(uvw [M_r, 3] float64, vis [M_r] complex64 (both
+    device tensors), freq_hz, cell, n_img, n_time, n_vis)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    xyz = antenna_xyz(n_ant, radius_m, rng)
+    bi, bj = baselines(n_ant)
+    t_bi = torch.tensor(bi, device=device)
+    t_bj = torch.tensor(bj, device=device)
+    n_bl = len(bi)
+    lam = C_LIGHT / freq_hz
+    out = []
+    for _ in range(n_req):
+        m_r = float(np.exp(rng.uniform(np.log(vis_range[0]), np.log(vis_range[1]))))
+        n_time = max(1, int(round(m_r / n_bl)))
+        n = int(sizes[rng.integers(0, len(sizes))])
+        auvw = antenna_uvw(xyz, hour_angles(n_time))                  # [T, A, 3] metres
+        t_auvw = torch.tensor(auvw, dtype=torch.float64, device=device)
+        uvw = (t_auvw[:, t_bj, :] - t_auvw[:, t_bi, :]).reshape(-1, 3)
+        umax = float(torch.max(torch.abs(uvw[:, :2])).item()) / lam
+        cell = 1.0 / (3.0 * umax)
+        lo, hi = int(0.1 * n), int(0.9 * n)
+        n_src = n_points + n_gauss
+        ix = rng.integers(lo, hi, n_src)
+        iy = rng.integers(lo, hi, n_src)
+        flux = 10.0 ** rng.uniform(-3.0, 0.0, n_src)
+        sig = rng.uniform(gauss_sigma_px[0], gauss_sigma_px[1], n_gauss) * cell
+        l0 = torch.tensor((ix - n // 2) * cell, device=device)
+        m0 = torch.tensor((iy - n // 2) * cell, device=device)
+        t_flux = torch.tensor(flux, dtype=torch.float32, device=device)
+        t_sig = torch.tensor(sig, device=device)
+        vis = torch.empty(n_time * n_bl, dtype=torch.complex64, device=device)
+        pts, gss = slice(0, n_points), slice(n_points, n_src)
+        for t0 in range(0, n_time, 32):
+            t1 = min(n_time, t0 + 32)
+            a = t_auvw[t0:t1] / lam                                         # [T, A, 3]
+            phase = -2.0 * np.pi * (a[:, :, 0:1] * l0 + a[:, :, 1:2] * m0)  # [T, A, S]
+            ph = torch.polar(torch.ones_like(phase), phase).to(torch.complex64)
+            left = (ph[:, :, pts] * t_flux[pts]).contiguous()
+            right = ph[:, :, pts].conj().transpose(1, 2).contiguous()
+            vt = torch.bmm(left, right)[:, t_bj, t_bi]
+            ub = a[:, t_bj, 0] - a[:, t_bi, 0]
+            vb = a[:, t_bj, 1] - a[:, t_bi, 1]
+            q = (ub * ub + vb * vb)
+            env = torch.exp(-2.0 * np.pi ** 2 * q[:, :, None] * (t_sig ** 2)).to(torch.float32)
+            pg = ph[:, t_bj, gss] * ph[:, t_bi, gss].conj()
+            vt = vt + ((env * pg) * t_flux[gss]).sum(dim=2)
+            vis[t0 * n_bl:t1 * n_bl] = vt.reshape(-1)
+            del a, phase, ph, left, right, vt, ub, vb, q, env, pg
+        g = torch.Generator(device=device)
+        g.manual_seed(int(rng.integers(0, 2 ** 31 - 1)))
+        noise = torch.randn(2, vis.shape[0], generator=g, device=device, dtype=torch.float32)
+        vis += 1e-3 * torch.complex(noise[0], noise[1])
+        del noise, t_auvw
+        out.append(dict(uvw=uvw, vis=vis, freq_hz=freq_hz, cell=cell, n_img=n, n_time=n_time,
+                        n_vis=int(vis.shape[0])))
+    return out

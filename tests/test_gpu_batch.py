@@ -120,11 +120,12 @@ def test_batch_members_against_oracle(chans):
 
 
 def test_batch_member_sets_bitwise():
-    """Members whose grids and chunk windows together exceed the cache budget
-    of one fused launch run in several consecutive sets; every mode still
-    equals each member's own cycle bit for bit."""
+    """With a cache budget, members whose grids and chunk windows together
+    exceed it run in several consecutive sets; every mode, with sets and
+    with the default single set, still equals each member's own cycle bit
+    for bit."""
     from paper_2507_22128_amd import synth
-    say("case: 3 channels of N = 2048 (4096^2 grids of 134 MB each: one set per member)")
+    say("case: 3 channels of N = 2048 (4096^2 grids of 134 MB each), sets of 128 MB and one set")
     d = synth.make_channels(n_chan=3, n_ant=24, n_time=8, sizes=(2048,), seed=9)
     members = [_create(d, c, chunk=256) for c in d["channels"]]
     try:
@@ -134,7 +135,15 @@ def test_batch_member_sets_bitwise():
         ref = _singles(members, models)
         b = _imager().Batch(members)
         try:
+            b.set_bytes(128 << 20)  # half of the last-level cache: one set per member
             assert b.info().n_sets == 3
+            for mode in (dict(), dict(graph=True)):
+                got = [to_np(r) for r in b.major_cycle(models, **mode)]
+                for g, r in zip(got, ref):
+                    assert np.array_equal(g, r)
+            # the default: one fused launch for all
+            b.set_bytes(0)
+            assert b.info().n_sets == 1
             for mode in (dict(), dict(graph=True)):
                 got = [to_np(r) for r in b.major_cycle(models, **mode)]
                 for g, r in zip(got, ref):
@@ -238,3 +247,42 @@ def test_batch_rejects_mismatched_members(chans):
             im.Batch([members[0], members[0]])
     finally:
         other.destroy()
+
+
+def test_batch_nine_channels_against_oracle():
+    """Nine channels with uneven observation lengths (T_c uniform in 6 .. 12
+    time steps) and flags, images 128 - 512 plus one of 2048^2: every
+    member's residual from the fused batch (graph replay) against the FP64
+    oracle."""
+    from paper_2507_22128_amd import synth
+    say("case: 8 channels (40 antennas, T_c in 6..12, sizes 128/256/512) + 1 channel at 2048^2")
+    sets = [synth.make_channels(n_chan=8, n_ant=40, n_time=12, t_min=6, sizes=(128, 256, 512),
+                                seed=31),
+            synth.make_channels(n_chan=1, n_ant=40, n_time=12, t_min=6, sizes=(2048,), seed=32,
+                                f_lo=1.4e9, f_hi=1.4e9)]
+    pairs = [(d, c) for d in sets for c in d["channels"]]
+    assert len(pairs) == 9 and any(c["n_img"] == 2048 for _, c in pairs)
+    assert len({c["n_time"] for _, c in pairs}) > 1
+    members = [_create(d, c, chunk=256) for d, c in pairs]
+    rng = np.random.default_rng(23)
+    models = [to_dev(random_model(c["n_img"], rng, n_points=10, smooth=False)) for _, c in pairs]
+    b = _imager().Batch(members)
+    try:
+        got = [to_np(r) for r in b.major_cycle(models, graph=True)]
+        again = [to_np(r) for r in b.major_cycle(models, graph=True)]
+    finally:
+        b.destroy()
+        for m in members:
+            m.destroy()
+    for k, ((d, c), g) in enumerate(zip(pairs, got)):
+        assert np.array_equal(g, again[k])
+        n = c["n_img"]
+        u, v = geometry.uv_lambda(d["uvw"], c["freq_hz"])
+        valid = c["flag"] == 0
+        w = imaging.uniform_weights(u, v, n, c["cell"], valid=valid)
+        ref, _ = imaging.residual_image(u[valid], v[valid], c["vis"][valid], w[valid],
+                                        to_np(models[k]).astype(np.float64), c["cell"])
+        err = rel(g, ref)
+        say("channel %d (N=%d, T_c=%d, %d unflagged): rel err %.3e"
+            % (k, n, c["n_time"], int(valid.sum()), err))
+        assert err < TOL

@@ -168,3 +168,111 @@ def test_reconstruct_msclean_serial_end_to_end(tiny1):
     say("serial end-to-end final rel err %.3e" % err)
     assert counts.tolist() == [[len(hc["L"][2])] for hc in hist]
     assert err < 1e-5
+
+
+def _compare_with_ties(comps, ref_comps, gaps, peak, tol=1e-9):
+    """Component sequences equal up to the first near-tie: at the first
+    difference the oracle's margin between its chosen candidate and the
+    runner-up must be within ``tol`` of the residual peak (rounding can then
+    order the two either way; the rest of the sequence is not compared).
+    Returns (number of equal leading components, near-tie index or None)."""
+    got = [(int(c["scale"]), int(c["iy"]), int(c["ix"])) for c in comps]
+    exp = [tuple(int(v) for v in c[:3]) for c in ref_comps]
+    k = next((i for i, (a, b) in enumerate(zip(got, exp)) if a != b), None)
+    if k is None:
+        assert len(got) == len(exp), (len(got), len(exp))
+        return len(got), None
+    assert gaps[k] <= tol * peak, "sequences differ at %d with an oracle margin of %.3e" % (
+        k, gaps[k])
+    return k, k
+
+
+@pytest.mark.timeout(900)
+def test_msclean_c1_as_configured():
+    """The tiny workload as configured: 5 major cycles of multi-scale CLEAN
+    (S = {0, 4, 12} px, gain 0.1, K = 2000, threshold 1e-4).
+
+    Teacher forcing: each cycle's dirty image and PSF from the oracle's loop,
+    rounded to FP32, go to the GPU minor cycle and to the oracle's; their
+    (scale, iy, ix) sequences must be identical (a difference is allowed
+    only at a near-tie: an oracle margin within rounding of the peak).
+
+    End to end: the library's loop (FP32 major cycles, GPU minor cycles) run
+    one cycle at a time gives the GPU's components per cycle; it must equal
+    the library's one-call loop bit for bit, and its sequences must equal
+    the oracle loop's up to the first step whose oracle margin lies below
+    the major cycle's error bound (1e-5 of the dirty peak), after which the
+    two runs may take different components (the near-tie rule of the error
+    norm).  Both final models must fit the data alike: residual norms
+    within 1 %."""
+    import torch
+    from oracle import decentral
+    msc = _oracle_msclean()
+    d = workload("tiny")
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    scales, K, thr, cycles = [0, 4, 12], 2000, 1e-4, 5
+    say("case: tiny as configured, 5 cycles, S = %s, K = %d, threshold %g" % (scales, K, thr))
+    ref_final, _, hist = decentral.reconstruct_msclean(
+        u, v, d["vis"], w, n, d["cell"], cycles, scales, gain=0.1, niter=K, threshold=thr,
+        partitions=1, record_gaps=True)
+    h = _imager().Imager.create(d, n_partitions=1, weighting="uniform")
+    try:
+        ties = 0
+        for c, step in enumerate(hist):
+            dirty32, psf32 = step["L"][0].astype(np.float32), step["L"][1].astype(np.float32)
+            _, comps, _ = h.minor_cycle_msclean(0, to_dev(dirty32), to_dev(psf32), scales,
+                                                gain=0.1, niter=K, threshold=thr)
+            st = {}
+            _, _, ref = msc.msclean(dirty32.astype(np.float64), psf32.astype(np.float64), scales,
+                                    gain=0.1, niter=K, threshold=thr, state=st)
+            same, tie = _compare_with_ties(comps, ref, st["gaps"],
+                                           float(np.abs(dirty32).max()))
+            ties += tie is not None
+            say("teacher-forced cycle %d: %d components (oracle %d), %d equal%s, smallest "
+                "oracle margin %.3e" % (c + 1, len(comps), len(ref), same,
+                                        "" if tie is None else " then a near-tie",
+                                        min(st["gaps"] or [0.0])))
+        assert ties <= 1
+        # the library's loop one cycle at a time
+        model = torch.zeros((n, n), device="cuda")
+        psf = h.psf(0)
+        diverged = False
+        for c in range(cycles):
+            dirty = h.major_cycle(0, model)
+            _, comps, _ = h.minor_cycle_msclean(0, dirty, psf, scales, gain=0.1, niter=K,
+                                                threshold=thr, model_accum=model)
+            if diverged:
+                say("end-to-end cycle %d: %d components (oracle %d), not compared after the "
+                    "near-tie" % (c + 1, len(comps), len(hist[c]["L"][2])))
+                continue
+            got = [(int(x["scale"]), int(x["iy"]), int(x["ix"])) for x in comps]
+            exp = [tuple(int(t) for t in x[:3]) for x in hist[c]["L"][2]]
+            k = next((i for i, (a, b) in enumerate(zip(got, exp)) if a != b), None)
+            gaps = hist[c]["L"][4]
+            peak = float(np.abs(hist[c]["L"][0]).max())
+            if k is None:
+                # equal sequences; a count difference only at the threshold
+                assert len(got) == len(exp) or (len(got) < K and len(exp) < K)
+                say("end-to-end cycle %d: %d components (oracle %d), all equal"
+                    % (c + 1, len(got), len(exp)))
+                diverged = len(got) != len(exp)
+            else:
+                assert gaps[k] <= 1e-5 * peak, (c, k, gaps[k])
+                say("end-to-end cycle %d: first %d of %d components equal, then a near-tie "
+                    "(oracle margin %.2e of the peak)" % (c + 1, k, len(got), gaps[k] / peak))
+                diverged = True
+        final, _, _, counts = h.reconstruct_msclean(cycles, scales, gain=0.1, niter=K,
+                                                    threshold=thr)
+        assert torch.equal(final.float(), model) or np.array_equal(
+            to_np(final).astype(np.float32), to_np(model))
+        r_got, _ = imaging.residual_image(u, v, d["vis"], w, to_np(final).astype(np.float64),
+                                          d["cell"])
+        r_ref, _ = imaging.residual_image(u, v, d["vis"], w, ref_final, d["cell"])
+        a, b = float(np.linalg.norm(r_got)), float(np.linalg.norm(r_ref))
+        say("library loop: counts %s (oracle %s); residual norm %.6e (oracle %.6e)"
+            % (counts[:, 0].tolist(), [len(hc["L"][2]) for hc in hist], a, b))
+        assert abs(a - b) <= 0.01 * b
+    finally:
+        h.destroy()
