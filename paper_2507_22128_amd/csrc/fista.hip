@@ -7,8 +7,8 @@
 //
 // H (the node's 2N x 2N PSF) and Gamma are applied with the fused transform
 // pipelines of fft.hip (H and Gamma are self-adjoint: the PSF is even, the
-// filters real and radial).  The wavelet transforms are level-by-level
-// gather kernels over the Mallat layout.  Everything runs in FP64 (the
+// filters real and radial).  The wavelet transforms run one fused
+// launch per level (both axes through LDS).  Everything runs in FP64 (the
 // transforms with the FP64 twiddle table and PSF spectrum): FISTA's
 // momentum amplifies operator rounding by about ten per fifty iterations
 // on these deconvolution problems, which FP32 transforms cannot absorb over
@@ -116,80 +116,150 @@ std::vector<double> daubechies(int p) {
 
 // ------------------------------------------------------------------ wavelet kernels
 // hg: taps low-pass h then taps high-pass g, g_j = (-1)^j h_{L-1-j}
+//
+// One launch per level and transform, both axes fused through LDS: a
+// workgroup stages the input patch its outputs need (periodic wrap), filters
+// it along the rows into LDS, then along the columns.  Every sum runs over
+// the taps in increasing order with one FMA per tap, as a plain loop would.
+// Block sizes are powers of two (N is one), so the wrap is a mask.
 
-// analysis of the top-left n x n block along the rows (AXIS 1) or the
-// columns (AXIS 0): a[k] = sum_j h_j x[(2k + j) mod n], d[k] likewise with g;
-// the input is a - b (b may be NULL)
 constexpr int kMaxBases = 10;  // dictionary bases: db1 .. db10 at most
+constexpr int kMaxTaps = 20;   // db10
 
-// filters of the dictionary's bases (blockIdx.y = basis)
+// filters of the dictionary's bases (blockIdx.z = basis)
 struct Bases {
   int hoff[kMaxBases], taps[kMaxBases];
 };
 
-// The tap count T is a template argument (each basis' launch dispatches on
-// it), so every tap's load is issued before the first product: the sums
-// themselves run in the same order as a plain loop over the taps.
-__device__ __forceinline__ int wrap_hi(int m, int n) {  // m mod n for m >= 0
-  while (m >= n) m -= n;
-  return m;
+// analysis: a workgroup makes kAnaK x kAnaK outputs of each of the four
+// subbands from an input patch of (2 kAnaK + T - 2)^2 samples
+constexpr int kAnaK = 16;
+constexpr int kAnaS = 2 * kAnaK + kMaxTaps - 2;  // patch side, 50 at most
+// synthesis: a workgroup makes kSynM x kSynM outputs from patches of
+// (kSynM / 2 + T / 2 - 1)^2 coefficients of each subband
+constexpr int kSynM = 32;
+constexpr int kSynC = kSynM / 2 + kMaxTaps / 2 - 1;  // patch side, 25 at most
+constexpr int kAnaLds = kAnaS * kAnaS + kAnaS * 2 * kAnaK;
+constexpr int kSynLds = 4 * kSynC * kSynC + kSynM * 2 * kSynC;
+constexpr int kWavLds = kAnaLds > kSynLds ? kAnaLds : kSynLds;  // doubles
+// one work item per thread in the single-pass stages
+static_assert(kAnaS * (kAnaK / 4) <= 256 && (kAnaK / 2) * 2 * kAnaK == 256, "analysis tiling");
+static_assert(kSynM * (kSynM / 4) == 256, "synthesis tiling");
+
+// W^T, one level: the top-left n x n block of src (minus b, times sc) ->
+// the detail subbands at their Mallat places in out (row stride out_ld)
+// and the approximation into ll (row stride ll_ld):
+//   a[k] = sum_j h_j x[(2k + j) mod n],  d[k] = sum_j g_j x[(2k + j) mod n]
+// along the rows first, then along the columns.
+template <int T>
+__device__ __forceinline__ void dwt_level_body(const double *__restrict__ src, int src_ld,
+                                               const double *__restrict__ b, double sc,
+                                               double *__restrict__ out, int out_ld,
+                                               double *__restrict__ ll, int ll_ld, int n,
+                                               const double *__restrict__ hg, double *lds) {
+  constexpr int S = 2 * kAnaK + T - 2;
+  double *x = lds;                    // [S][kAnaS] input patch
+  double *mid = lds + kAnaS * kAnaS;  // [S][2 kAnaK] row-filtered: a | d
+  const int tid = threadIdx.x;
+  const int half = n >> 1, mask = n - 1;
+  const int ky0 = blockIdx.y * kAnaK, kx0 = blockIdx.x * kAnaK;
+  {
+    // every load of the patch is issued before the first LDS store
+    constexpr int R = (S + 3) / 4;
+    const int c = tid & 63;
+    const int gx = (2 * kx0 + c) & mask;
+    double v[R], w[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = (tid >> 6) + 4 * i;
+      const size_t off = (size_t)((2 * ky0 + r) & mask) * src_ld + gx;
+      if (c < S && r < S) {
+        v[i] = src[off];
+        if (b) w[i] = b[off];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = (tid >> 6) + 4 * i;
+      if (c < S && r < S) {
+        double y = v[i];
+        if (b) y -= w[i];
+        if (sc != 1.0) y *= sc;
+        x[r * kAnaS + c] = y;
+      }
+    }
+  }
+  __syncthreads();
+  // along the rows: a thread makes 4 adjacent outputs of one patch row from
+  // the T + 6 samples they span (read once from LDS)
+  if (tid < S * (kAnaK / 4)) {
+    const int r = tid >> 2, kg = tid & 3;
+    const double *xr = x + r * kAnaS + 8 * kg;
+    double v[T + 6];
+#pragma unroll
+    for (int m = 0; m < T + 6; ++m) v[m] = xr[m];
+    double lo[4], hi[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      lo[e] = 0.0;
+      hi[e] = 0.0;
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        lo[e] = fma(hg[j], v[2 * e + j], lo[e]);
+        hi[e] = fma(hg[T + j], v[2 * e + j], hi[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      mid[r * 2 * kAnaK + 4 * kg + e] = lo[e];
+      mid[r * 2 * kAnaK + kAnaK + 4 * kg + e] = hi[e];
+    }
+  }
+  __syncthreads();
+  // along the columns: a thread makes 2 adjacent outputs of one column
+  {
+    const int k = tid & (kAnaK - 1), hx = (tid / kAnaK) & 1, kyp = tid / (2 * kAnaK);
+    const double *mc = mid + 4 * kyp * 2 * kAnaK + hx * kAnaK + k;
+    double v[T + 2];
+#pragma unroll
+    for (int m = 0; m < T + 2; ++m) v[m] = mc[m * 2 * kAnaK];
+    const int gx = kx0 + k;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      double lo = 0.0, hi = 0.0;
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        lo = fma(hg[j], v[2 * e + j], lo);
+        hi = fma(hg[T + j], v[2 * e + j], hi);
+      }
+      const int gy = ky0 + 2 * kyp + e;
+      if (gy < half && gx < half) {
+        if (hx == 0)
+          ll[(size_t)gy * ll_ld + gx] = lo;
+        else
+          out[(size_t)gy * out_ld + half + gx] = lo;
+        out[(size_t)(half + gy) * out_ld + hx * half + gx] = hi;
+      }
+    }
+  }
 }
 
-template <int AXIS, int T>
-__device__ __forceinline__ void dwt_body(const double *__restrict__ a,
-                                         const double *__restrict__ b, int in_stride,
-                                         double *__restrict__ out, int out_stride, int n,
-                                         const double *__restrict__ hg, double sc, int line,
-                                         int k) {
-  const int half = n / 2;
-  double v[T];
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    const int m = wrap_hi(2 * k + j, n);
-    const size_t off = (AXIS == 1) ? (size_t)line * in_stride + m : (size_t)m * in_stride + line;
-    v[j] = a[off];
-    if (b) v[j] -= b[off];
-  }
-  double lo = 0.0, hi = 0.0;
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
-    double x = v[j];
-    if (sc != 1.0) x *= sc;
-    lo = fma(hg[j], x, lo);
-    hi = fma(hg[T + j], x, hi);
-  }
-  if (AXIS == 1) {
-    out[(size_t)line * out_stride + k] = lo;
-    out[(size_t)line * out_stride + half + k] = hi;
-  } else {
-    out[(size_t)k * out_stride + line] = lo;
-    out[(size_t)(half + k) * out_stride + line] = hi;
-  }
-}
-
-template <int AXIS>
-__global__ void k_dwt(const double *__restrict__ a, size_t a_bstride, const double *__restrict__ b,
-                      int in_stride, double *__restrict__ out, size_t out_bstride, int out_stride,
-                      int n, const double *__restrict__ hlo, Bases bs, double sc) {
-  const int p = blockIdx.y;
+// src, ll, out: basis p at + p * bstride (src_bs 0: one input for all bases)
+__global__ __launch_bounds__(256) void k_dwt_level(const double *__restrict__ src, size_t src_bs,
+                                                   int src_ld, const double *__restrict__ b,
+                                                   double sc, double *__restrict__ out,
+                                                   int out_ld, double *__restrict__ ll,
+                                                   int ll_ld, size_t bstride, int n,
+                                                   const double *__restrict__ hlo, Bases bs) {
+  __shared__ double lds[kWavLds];
+  const int p = blockIdx.z;
   const double *__restrict__ hg = hlo + bs.hoff[p];
-  const int taps = bs.taps[p];
-  a += p * a_bstride;
-  out += p * out_bstride;
-  const int half = n / 2;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * half) return;
-  int line, k;
-  if (AXIS == 1) {
-    line = (int)(idx / half);
-    k = (int)(idx % half);
-  } else {
-    line = (int)(idx % n);
-    k = (int)(idx / n);
-  }
-  switch (taps) {
+  src += p * src_bs;
+  out += p * bstride;
+  ll += p * bstride;
+  switch (bs.taps[p]) {
 #define TAPS_(T) \
-  case T: dwt_body<AXIS, T>(a, b, in_stride, out, out_stride, n, hg, sc, line, k); break;
+  case T: dwt_level_body<T>(src, src_ld, b, sc, out, out_ld, ll, ll_ld, n, hg, lds); break;
     TAPS_(2) TAPS_(4) TAPS_(6) TAPS_(8) TAPS_(10) TAPS_(12) TAPS_(14) TAPS_(16) TAPS_(18)
     TAPS_(20)
 #undef TAPS_
@@ -197,74 +267,129 @@ __global__ void k_dwt(const double *__restrict__ a, size_t a_bstride, const doub
   }
 }
 
-// synthesis (the transpose): x[m] = sum over j with m - j even of
-// h_j a[k] + g_j d[k], k = ((m - j) mod n) / 2
-template <int AXIS, int T>
-__device__ __forceinline__ void idwt_body(const double *__restrict__ in,
-                                          const double *__restrict__ ll, int in_stride,
-                                          double *__restrict__ out, int out_stride, int n,
-                                          const double *__restrict__ hg, int line, int m) {
-  const int half = n / 2;
-  // the approximation quadrant (rows and columns below half) comes from ll
-  // when given; the detail quadrants always come from in
-  const double *__restrict__ lo_src = (ll && line < half) ? ll : in;
-  const int j0 = m & 1;
-  double va[T / 2], vd[T / 2];
+// W, one level (the transpose of the analysis level): the n x n block of
+// out from the n/2 x n/2 approximation ll (row stride ll_ld) and the three
+// detail subbands of the coefficient array c (row stride c_ld):
+//   x[m] = sum over j with m - j even of h_j a[k] + g_j d[k],  k = ((m - j) mod n) / 2
+// along the columns first, then along the rows.
+template <int T>
+__device__ __forceinline__ void idwt_level_body(const double *__restrict__ c, int c_ld,
+                                                const double *__restrict__ ll, int ll_ld,
+                                                double *__restrict__ out, int out_ld, int n,
+                                                const double *__restrict__ hg, double *lds) {
+  constexpr int C = kSynM / 2 + T / 2 - 1;
+  double *q = lds;                        // [2 (a|d along y)][2 (a|d along x)][C][kSynC]
+  double *t = lds + 4 * kSynC * kSynC;    // [kSynM][2][kSynC] column-synthesised
+  const int tid = threadIdx.x;
+  const int half = n >> 1, hmask = half - 1;
+  const int my0 = blockIdx.y * kSynM, mx0 = blockIdx.x * kSynM;
+  // coefficient k' = (m - j) / 2 spans my0 / 2 - T / 2 + 1 ... my0 / 2 + kSynM / 2 - 1
+  const int kyb = my0 / 2 - T / 2 + 1, kxb = mx0 / 2 - T / 2 + 1;
+  {
+    // every load of the four patches is issued before the first LDS store
+    constexpr int R = (4 * C + 7) / 8;
+    const int ix = tid & 31;
+    const int kx = (kxb + ix) & hmask;
+    double v[R];
 #pragma unroll
-  for (int i = 0; i < T / 2; ++i) {
-    const int j = j0 + 2 * i;
-    int t = m - j;
-    while (t < 0) t += n;
-    const int k = t / 2;
-    size_t oa, od;
-    if (AXIS == 1) {
-      oa = (size_t)line * in_stride + k;
-      od = oa + half;
-    } else {
-      oa = (size_t)k * in_stride + line;
-      od = (size_t)(half + k) * in_stride + line;
+    for (int i = 0; i < R; ++i) {
+      const int row = (tid >> 5) + 8 * i;
+      const int quad = row / C, iy = row % C;
+      const int hy = quad >> 1, hx = quad & 1;
+      const int ky = (kyb + iy) & hmask;
+      if (ix < C && row < 4 * C)
+        v[i] = (hy == 0 && hx == 0) ? ll[(size_t)ky * ll_ld + kx]
+                                    : c[(size_t)(hy * half + ky) * c_ld + hx * half + kx];
     }
-    va[i] = lo_src[oa];
-    vd[i] = in[od];
-  }
-  double acc = 0.0;
 #pragma unroll
-  for (int i = 0; i < T / 2; ++i) {
-    const int j = j0 + 2 * i;
-    acc = fma(hg[j], va[i], acc);
-    acc = fma(hg[T + j], vd[i], acc);
+    for (int i = 0; i < R; ++i) {
+      const int row = (tid >> 5) + 8 * i;
+      if (ix < C && row < 4 * C) q[((row / C) * kSynC + row % C) * kSynC + ix] = v[i];
+    }
   }
-  if (AXIS == 1)
-    out[(size_t)line * out_stride + m] = acc;
-  else
-    out[(size_t)m * out_stride + line] = acc;
+  __syncthreads();
+  // Output rows (columns) 2p and 2p + 1 take the same coefficients k = p - i
+  // (i < T / 2), with the even and the odd taps.  A thread makes two such
+  // pairs, from the T / 2 + 1 coefficients of each half that they span.
+  // along y: 16 row pairs x 2 halves along x x 32 patch columns (25 used)
+  for (int it = tid; it < (kSynM / 4) * 2 * 32; it += 256) {
+    const int ix = it & 31, hx = (it >> 5) & 1, pg = it >> 6;
+    if (ix < C) {
+      const double *qa = q + (hx * kSynC + 2 * pg) * kSynC + ix;        // a along y
+      const double *qd = q + ((2 + hx) * kSynC + 2 * pg) * kSynC + ix;  // d along y
+      double va[T / 2 + 1], vd[T / 2 + 1];
+#pragma unroll
+      for (int m = 0; m <= T / 2; ++m) {
+        va[m] = qa[m * kSynC];
+        vd[m] = qd[m * kSynC];
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        double ev = 0.0, od = 0.0;
+#pragma unroll
+        for (int i = 0; i < T / 2; ++i) {
+          const int m = e + T / 2 - 1 - i;
+          ev = fma(hg[2 * i], va[m], ev);
+          ev = fma(hg[T + 2 * i], vd[m], ev);
+          od = fma(hg[2 * i + 1], va[m], od);
+          od = fma(hg[T + 2 * i + 1], vd[m], od);
+        }
+        const int my = 2 * (2 * pg + e);
+        t[(my * 2 + hx) * kSynC + ix] = ev;
+        t[((my + 1) * 2 + hx) * kSynC + ix] = od;
+      }
+    }
+  }
+  __syncthreads();
+  // along x: 32 rows x 8 groups of 4 adjacent outputs
+  {
+    const int g = tid & 7, my = tid >> 3;
+    const double *ta = t + (my * 2) * kSynC + 2 * g, *td = ta + kSynC;
+    double ua[T / 2 + 1], ud[T / 2 + 1];
+#pragma unroll
+    for (int m = 0; m <= T / 2; ++m) {
+      ua[m] = ta[m];
+      ud[m] = td[m];
+    }
+    double r[4];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      double ev = 0.0, od = 0.0;
+#pragma unroll
+      for (int i = 0; i < T / 2; ++i) {
+        const int m = e + T / 2 - 1 - i;
+        ev = fma(hg[2 * i], ua[m], ev);
+        ev = fma(hg[T + 2 * i], ud[m], ev);
+        od = fma(hg[2 * i + 1], ua[m], od);
+        od = fma(hg[T + 2 * i + 1], ud[m], od);
+      }
+      r[2 * e] = ev;
+      r[2 * e + 1] = od;
+    }
+    if (my0 + my < n) {
+      double *o = out + (size_t)(my0 + my) * out_ld + mx0 + 4 * g;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (mx0 + 4 * g + e < n) o[e] = r[e];
+    }
+  }
 }
 
-// (AXIS 0 only: ll, when given, holds the approximation quadrant in place of
-// in, with in's layout)
-template <int AXIS>
-__global__ void k_idwt(const double *__restrict__ in, const double *__restrict__ ll,
-                       int in_stride, double *__restrict__ out, int out_stride, size_t bstride,
-                       int n, const double *__restrict__ hlo, Bases bs) {
-  const int p = blockIdx.y;
+// c, ll, out: basis p at + p * bstride
+__global__ __launch_bounds__(256) void k_idwt_level(const double *__restrict__ c, int c_ld,
+                                                    const double *__restrict__ ll, int ll_ld,
+                                                    double *__restrict__ out, int out_ld,
+                                                    size_t bstride, int n,
+                                                    const double *__restrict__ hlo, Bases bs) {
+  __shared__ double lds[kWavLds];
+  const int p = blockIdx.z;
   const double *__restrict__ hg = hlo + bs.hoff[p];
-  const int taps = bs.taps[p];
-  in += p * bstride;
-  if (ll) ll += p * bstride;
+  c += p * bstride;
+  ll += p * bstride;
   out += p * bstride;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  int line, m;
-  if (AXIS == 1) {
-    line = (int)(idx / n);
-    m = (int)(idx % n);
-  } else {
-    line = (int)(idx % n);
-    m = (int)(idx / n);
-  }
-  switch (taps) {
+  switch (bs.taps[p]) {
 #define TAPS_(T) \
-  case T: idwt_body<AXIS, T>(in, ll, in_stride, out, out_stride, n, hg, line, m); break;
+  case T: idwt_level_body<T>(c, c_ld, ll, ll_ld, out, out_ld, n, hg, lds); break;
     TAPS_(2) TAPS_(4) TAPS_(6) TAPS_(8) TAPS_(10) TAPS_(12) TAPS_(14) TAPS_(16) TAPS_(18)
     TAPS_(20)
 #undef TAPS_
@@ -402,42 +527,51 @@ struct Ctx {
   double gamma_n;
 };
 
-// W^T (a - b) -> out (coefficients, nb stacked N^2 blocks), via fw->tmp (nb
-// blocks); all bases in one launch per pass, each seeing the input scaled
-// by 1 / sqrt(nb) for a dictionary
+// W^T (a - b) -> out (coefficients, nb stacked N^2 blocks): one launch per
+// level for all bases, each seeing the input scaled by 1 / sqrt(nb) for a
+// dictionary.  The approximation of every level but the last goes to
+// fw->tmp (halves 0 and N^2 / 2 of each basis' block, alternately, so a
+// level never overwrites its own input); the details go to out.
 void dwt2(Ctx &c, const double *a, const double *b, double *out) {
   const int N = c.n;
   const double sc = c.nb > 1 ? 1.0 / std::sqrt((double)c.nb) : 1.0;
-  int n = N;
+  const double *src = a;
+  size_t src_bs = 0;  // one image for every basis
+  int src_ld = N, n = N;
   for (int lev = 0; lev < c.levels; ++lev) {
-    const double *src = lev == 0 ? a : out;
-    const size_t sstride = lev == 0 ? 0 : c.nn;
-    const double *sb = lev == 0 ? b : nullptr;
-    const dim3 grid(cdiv((int64_t)n * (n / 2), 256), c.nb);
-    hipLaunchKernelGGL(k_dwt<1>, grid, dim3(256), 0, c.s, src, sstride, sb, N, c.fw->tmp, c.nn,
-                       N, n, c.fw->hlo, c.bases, lev == 0 ? sc : 1.0);
-    hipLaunchKernelGGL(k_dwt<0>, grid, dim3(256), 0, c.s, (const double *)c.fw->tmp, c.nn,
-                       (const double *)nullptr, N, out, c.nn, N, n, c.fw->hlo, c.bases, 1.0);
+    const bool last = lev == c.levels - 1;
+    double *ll = last ? out : c.fw->tmp + ((lev & 1) ? c.nn / 2 : 0);
+    const int ll_ld = last ? N : n / 2;
+    const int tiles = (int)cdiv(n / 2, kAnaK);
+    hipLaunchKernelGGL(k_dwt_level, dim3(tiles, tiles, c.nb), dim3(256), 0, c.s, src, src_bs,
+                       src_ld, lev == 0 ? b : (const double *)nullptr, lev == 0 ? sc : 1.0, out,
+                       N, ll, ll_ld, c.nn, n, (const double *)c.fw->hlo, c.bases);
+    src = ll;
+    src_bs = c.nn;
+    src_ld = ll_ld;
     n /= 2;
   }
 }
 
-// W alpha -> out image: each basis' synthesis (all in one launch per pass),
-// then for a dictionary the sum over the bases times 1 / sqrt(nb)
+// W alpha -> out image: each basis' synthesis (all in one launch per level),
+// then for a dictionary the sum over the bases times 1 / sqrt(nb).  The
+// coarsest level takes its approximation from alpha; each finer level takes
+// the previous level's output, kept in fw->tmp (alternate halves).
 void idwt2(Ctx &c, const double *alpha, double *out) {
   const int N = c.n;
   double *xs = c.nb > 1 ? c.fw->xb : out;
-  // the detail quadrants are read from alpha itself; the approximation of
-  // each finer level is the previous level's synthesis in xs (the coarsest
-  // level's is alpha's own)
+  const double *ll = alpha;
+  int ll_ld = N;
   int n = N >> (c.levels - 1);
   for (int lev = 0; lev < c.levels; ++lev) {
-    const dim3 grid(cdiv((int64_t)n * n, 256), c.nb);
-    hipLaunchKernelGGL(k_idwt<0>, grid, dim3(256), 0, c.s, alpha,
-                       lev == 0 ? (const double *)nullptr : (const double *)xs, N, c.fw->tmp, N,
-                       c.nn, n, c.fw->hlo, c.bases);
-    hipLaunchKernelGGL(k_idwt<1>, grid, dim3(256), 0, c.s, (const double *)c.fw->tmp,
-                       (const double *)nullptr, N, xs, N, c.nn, n, c.fw->hlo, c.bases);
+    const bool last = lev == c.levels - 1;
+    double *dst = last ? xs : c.fw->tmp + ((lev & 1) ? c.nn / 2 : 0);
+    const int dst_ld = last ? N : n;
+    const int tiles = (int)cdiv(n, kSynM);
+    hipLaunchKernelGGL(k_idwt_level, dim3(tiles, tiles, c.nb), dim3(256), 0, c.s, alpha, N, ll,
+                       ll_ld, dst, dst_ld, c.nn, n, (const double *)c.fw->hlo, c.bases);
+    ll = dst;
+    ll_ld = dst_ld;
     n *= 2;
   }
   if (c.nb > 1)
