@@ -75,11 +75,37 @@ __device__ __forceinline__ void dft(C *x) {
   }
 }
 
+// Row twiddles w_L^m = exp(-2 pi i m / L), m < L, as the product of two
+// short tables staged in LDS: w_L^m = w_L^(B floor(m / B)) w_L^(m mod B),
+// B the power of two nearest sqrt L from above.  Every index of the first
+// passes is a multiple of B and takes w_L^0 = 1 from the second table, an
+// exact product; the tables take B + L / B entries instead of L, which
+// leaves the LDS to the rows (twice the resident rows per CU at L = 4096).
+template <int L>
+struct RowTw {
+  static constexpr int log2l() {
+    int k = 0;
+    while ((1 << k) < L) ++k;
+    return k;
+  }
+  static constexpr int B = 1 << ((log2l() + 1) / 2), H = L / B, SIZE = B + H;
+};
+template <int B, class C>
+struct TwoLevel {
+  const C *lo, *hi;  // lo[m] = w_L^m (m < B), hi[h] = w_L^(B h)
+};
+template <int DIR, int B, class C>
+__device__ __forceinline__ C tw_get(const TwoLevel<B, C> &tw, int idx) {
+  C t = cmul(tw.hi[idx / B], tw.lo[idx & (B - 1)]);
+  if (DIR > 0) t.y = -t.y;
+  return t;
+}
+
 // One sequence of length L in padded LDS, NT threads, Stockham passes from
-// sub-length NS upward (radix 8 while possible, then 4 or 2).  tw holds
-// w_L^m = exp(-2 pi i m / L), m < L (the row kernels stage it in LDS).
-template <int L, int NT, int NS, int DIR, class C>
-__device__ __forceinline__ void stockham_seq(C *s, const C *tw, int t) {
+// sub-length NS upward (radix 8 while possible, then 4 or 2).  tw gives
+// w_L^m, m < L (a table pointer or a TwoLevel view).
+template <int L, int NT, int NS, int DIR, class C, class TW>
+__device__ __forceinline__ void stockham_seq(C *s, const TW &tw, int t) {
   if constexpr (NS < L) {
     constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
     constexpr int NB = L / R;
@@ -111,7 +137,7 @@ __device__ __forceinline__ void stockham_seq(C *s, const C *tw, int t) {
       }
     }
     __syncthreads();
-    stockham_seq<L, NT, NS * R, DIR, C>(s, tw, t);
+    stockham_seq<L, NT, NS * R, DIR, C, TW>(s, tw, t);
   }
 }
 
@@ -159,16 +185,20 @@ __device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, in
   }
 }
 
-// stage w_L^m, m < L, into LDS from the per-length tables (entry L + m of
-// twr holds w_L^m, so one row's twiddles are one contiguous read)
+// stage the two tables of RowTw<L> into twl (lo then hi) from the per-length
+// tables (entry L + m of twr holds w_L^m)
 template <int L, int NT, class C>
 __device__ __forceinline__ void stage_twiddles(C *twl, const C *__restrict__ twr) {
-  constexpr int PER = L / NT;
-  C v[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) v[q] = twr[L + threadIdx.x + q * NT];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) twl[threadIdx.x + q * NT] = v[q];
+  constexpr int B = RowTw<L>::B, H = RowTw<L>::H;
+  static_assert(B + H <= NT, "one entry per thread");
+  const int t = threadIdx.x;
+  if (t < B + H) twl[t] = twr[L + (t < B ? t : (t - B) * B)];
+}
+
+// the view of the staged tables that stockham_seq takes
+template <int L, class C>
+__device__ __forceinline__ TwoLevel<RowTw<L>::B, C> row_tw(const C *twl) {
+  return TwoLevel<RowTw<L>::B, C>{twl, twl + RowTw<L>::B};
 }
 
 template <int L>
@@ -193,7 +223,7 @@ __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
                                                 int c_hi, int pair) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
-  __shared__ float2 twl[L];
+  __shared__ float2 twl[RowTw<L>::SIZE];
   const int o = (L - n) / 2;
   const int ra = 2 * pair, rb = ra + 1;
   const int ya = o + ra;
@@ -232,7 +262,7 @@ __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
     s[padi(x)] = make_float2(wa, wb);
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, -1>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, -1>(s, row_tw<L>(twl), threadIdx.x);
   // only the columns [c_lo, c_hi) are ever read
   for (int x = c_lo + threadIdx.x; x < c_hi; x += NT) {
     const float2 zx = s[padi(x)], zm = s[padi((L - x) & (L - 1))];
@@ -260,7 +290,7 @@ __device__ __forceinline__ void rows_image_body(const float2 *__restrict__ rows,
                                                 int c_hi, int r) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ float2 s[L + L / 32];
-  __shared__ float2 twl[L];
+  __shared__ float2 twl[RowTw<L>::SIZE];
   const int o = (L - n) / 2;
   const int y = o + r;
   {
@@ -276,7 +306,7 @@ __device__ __forceinline__ void rows_image_body(const float2 *__restrict__ rows,
     for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, 1>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, 1>(s, row_tw<L>(twl), threadIdx.x);
   const float cy = cinv[r] * scale;
   for (int ix = threadIdx.x; ix < n; ix += NT) {
     const int x = o + ix;
@@ -299,7 +329,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
                                                                  const C *__restrict__ twr) {
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
-  __shared__ C twl[L];
+  __shared__ C twl[RowTw<L>::SIZE];
   C *row = buf + (size_t)blockIdx.x * L;
   {
     constexpr int PER = L / NT;
@@ -311,7 +341,7 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
     for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, DIR, C>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, DIR, C>(s, row_tw<L>(twl), threadIdx.x);
   for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
 }
 
@@ -496,7 +526,7 @@ __device__ __forceinline__ void rows_real_fwd_body(const typename Real<C>::T *__
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
-  __shared__ C twl[L];
+  __shared__ C twl[RowTw<L>::SIZE];
   // rows 2 pair and 2 pair + 1 as the real and imaginary parts of one
   // complex sequence z = u + i v; their spectra are separated below by the
   // symmetry of real spectra: U[k] = (Z[k] + conj Z[L-k]) / 2,
@@ -526,7 +556,7 @@ __device__ __forceinline__ void rows_real_fwd_body(const typename Real<C>::T *__
     for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = mkc<C>(u[q], v[q]);
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, -1, C>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, -1, C>(s, row_tw<L>(twl), threadIdx.x);
   const RT h = RT(0.5);
   for (int x = threadIdx.x; x < c_hi; x += NT) {
     const C zx = s[padi(x)], zm = s[padi((L - x) & (L - 1))];
@@ -556,7 +586,7 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
   typedef typename Real<C>::T RT;
   constexpr int NT = RowThreads<L>::v;
   __shared__ C s[L + L / 32];
-  __shared__ C twl[L];
+  __shared__ C twl[RowTw<L>::SIZE];
   // rows 2 pair and 2 pair + 1 in one transform: each row is Hermitian (the
   // 2-D spectrum it came from belongs to a real image), columns above L / 2
   // being the conjugates of those below, so the inverse DFT of
@@ -589,7 +619,7 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
     }
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, 1, C>(s, twl, threadIdx.x);
+  stockham_seq<L, NT, 1, 1, C>(s, row_tw<L>(twl), threadIdx.x);
   if (accumulate) {
     constexpr int PO = (L + NT - 1) / NT;  // n_out <= L
     RT pa[PO], pb[PO];
