@@ -334,8 +334,10 @@ imgr_status imager_reconstruct_msclean(imgr_t h, int32_t n_cycles,
  * power_start (any nonzero N x N image; Beck and Teboulle's method as the
  * paper uses it).  lambda = params->lambda if > 0, else lambda_frac *
  * max |dirty|.  dirty: the node's residual i~ of Eq. 2 (device N x N
- * float32), rho_other: the node's aggregate rho of Eq. 5 (device N x N
- * float32, ignored when gamma_n = 0 or serial).  Outputs (device, each may
+ * float32); psf: the 2N x 2N PSF whose convolution is H (device float32,
+ * centre (N, N), the layout imager_psf writes), or NULL for the node's own
+ * PSF from imager_create; rho_other: the node's aggregate rho of Eq. 5
+ * (device N x N float32, ignored when gamma_n = 0 or serial).  Outputs (device, each may
  * be NULL): model_delta (N x N float32) = W alpha, model_accum += it,
  * objective (float64 [n_iter]) = the objective after every iteration.
  * *lipschitz and *lambda_used (host, may be NULL) receive L_hat and lambda.
@@ -358,10 +360,10 @@ typedef struct {
 } imgr_fista_params;
 
 imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,
-                                     const float *dirty, const float *rho_other,
-                                     const float *power_start, float *model_delta,
-                                     float *model_accum, double *objective, double *lipschitz,
-                                     double *lambda_used);
+                                     const float *dirty, const float *psf,
+                                     const float *rho_other, const float *power_start,
+                                     float *model_delta, float *model_accum, double *objective,
+                                     double *lipschitz, double *lambda_used);
 
 /* The whole major/minor loop with the sparsity-regularised minor cycle
  * (Section 4.1): for cycle n = 1 .. n_cycles and every node k,

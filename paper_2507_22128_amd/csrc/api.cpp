@@ -841,18 +841,18 @@ static void check_fista(imgr_s *h, const imgr_fista_params &p) {
 }
 
 imgr_status imager_minor_cycle_fista(imgr_t h, int32_t part, const imgr_fista_params *params,
-                                     const float *dirty, const float *rho_other,
-                                     const float *power_start, float *model_delta,
-                                     float *model_accum, double *objective, double *lipschitz,
-                                     double *lambda_used) {
+                                     const float *dirty, const float *psf,
+                                     const float *rho_other, const float *power_start,
+                                     float *model_delta, float *model_accum, double *objective,
+                                     double *lipschitz, double *lambda_used) {
   API_BEGIN(h)
   check_part(h, part);
   IMGR_CHECK(params && dirty && power_start, "null pointer");
   check_fista(h, *params);
   IMGR_CHECK(params->serial || params->gamma_n == 0.0 || rho_other || h->n_parts == 1,
              "gamma_n != 0 needs rho_other");
-  fista_enqueue(h, part, *params, dirty, rho_other, power_start, model_delta, model_accum,
-                objective, h->stream);
+  fista_enqueue(h, part, *params, dirty, psf, rho_other, power_start, model_delta,
+                model_accum, objective, h->stream);
   IMGR_HIP(hipStreamSynchronize(h->stream));
   fista_scalars(h, part, lipschitz, lambda_used);
   API_END(h)
@@ -886,8 +886,8 @@ imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fist
       q.serial = 1;
       q.gamma_n = 0.0;
       node_cycle(h, 0, model[0], nullptr, 1.0, 0.0, h->loop_dirty[0], nullptr, 0, s);
-      fista_enqueue(h, 0, q, h->loop_dirty[0], nullptr, power_start[0], h->loop_delta[0],
-                    model[0], nullptr, s);
+      fista_enqueue(h, 0, q, h->loop_dirty[0], nullptr, nullptr, power_start[0],
+                    h->loop_delta[0], model[0], nullptr, s);
     } else {
       q.serial = 0;
       q.gamma_n = (cyc == 1) ? 0.0 : 1.0;  // Eq. 5
@@ -904,8 +904,8 @@ imgr_status imager_reconstruct_fista(imgr_t h, int32_t n_cycles, const imgr_fist
         for (int k = 0; k < 2; ++k) node_stage(h, nc[k], stage);
       for (int k = 0; k < 2; ++k) {
         hipStream_t s = h->node_stream[k];
-        fista_enqueue(h, k, q, h->loop_dirty[k], rho[k], power_start[k], h->loop_delta[k],
-                      model[k], nullptr, s);
+        fista_enqueue(h, k, q, h->loop_dirty[k], nullptr, rho[k], power_start[k],
+                      h->loop_delta[k], model[k], nullptr, s);
         IMGR_HIP(hipEventRecord(h->ev_join[k], s));
       }
       for (int k = 0; k < 2; ++k) IMGR_HIP(hipStreamWaitEvent(h->stream, h->ev_join[k], 0));

@@ -104,6 +104,7 @@ struct FistaWork {
   double *cst = nullptr;                                         // N^2
   double *d64 = nullptr, *r64 = nullptr;                         // inputs in FP64
   double2 *work64 = nullptr, *tmp64 = nullptr;                   // transform buffers
+  double2 *psf_ext = nullptr;  // spectrum of a caller's PSF (4 N^2, on first use)
   double *scal = nullptr;    // device scalars (L_hat, lambda, norms)
   double *part = nullptr;    // reduction partials
   double *hlo = nullptr;     // wavelet filters (low, high) of every basis, concatenated
@@ -318,6 +319,8 @@ void image_gamma64_pair(imgr_s *h, const double *a0, int own0, double coef0, dou
 void fft2_plain64(imgr_s *h, double2 *buf, double2 *tmp, int n, int dir, hipStream_t s);
 // the partition's FP64 PSF spectrum (built on first use, kept)
 const double2 *psf_spectrum64(imgr_s *h, int p, hipStream_t s);
+// FP64 spectrum of a caller's 2N x 2N float32 PSF into out (4 N^2), tmp of the same size
+void psf_spectrum64_of(imgr_s *h, const float *psf, double2 *out, double2 *tmp, hipStream_t s);
 // plain 2-D DFT of an n x n complex buffer in place (dir -1 forward, +1 inverse, unnormalised)
 void fft2_plain(imgr_s *h, float2 *buf, float2 *tmp, int n, int dir, hipStream_t s);
 
@@ -409,9 +412,10 @@ uint32_t msclean_own_scales(const imgr_s *h, int part, const imgr_msclean_params
 void msclean_release(imgr_s *h, int part);
 
 // sparsity-regularised minor cycle of node `part` (Eqs. 4, 5), enqueued on s
+// (psf: a caller's 2N x 2N PSF for H, or NULL for the node's own)
 void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const float *dirty,
-                   const float *rho_other, const float *power_start, float *model_delta,
-                   float *model_accum, double *objective, hipStream_t s);
+                   const float *psf, const float *rho_other, const float *power_start,
+                   float *model_delta, float *model_accum, double *objective, hipStream_t s);
 // (after s has completed) the step constant L_hat and lambda of the last run
 void fista_scalars(imgr_s *h, int part, double *lipschitz, double *lambda);
 

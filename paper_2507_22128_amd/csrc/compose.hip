@@ -96,17 +96,23 @@ __global__ void k_pad_real64(const float *__restrict__ a, int n, double2 *__rest
   if (i < (int64_t)n * n) dst[i] = make_double2((double)a[i], 0.0);
 }
 
-// FP64 spectrum of the partition's 2N x 2N PSF (plain DFT), built once
+// FP64 spectrum (plain DFT) of a 2N x 2N float32 PSF
+void psf_spectrum64_of(imgr_s *h, const float *psf, double2 *out, double2 *tmp, hipStream_t s) {
+  const int nd = 2 * h->N;
+  const size_t m = (size_t)nd * nd;
+  hipLaunchKernelGGL(k_pad_real64, g1((int64_t)m), dim3(256), 0, s, psf, nd, out);
+  IMGR_HIP(hipGetLastError());
+  fft2_plain64(h, out, tmp, nd, -1, s);
+}
+
+// FP64 spectrum of the partition's 2N x 2N PSF, built once
 const double2 *psf_spectrum64(imgr_s *h, int p, hipStream_t s) {
   Partition &P = h->part[p];
   if (P.psf_hat64) return P.psf_hat64;
-  const int nd = 2 * h->N;
-  const size_t m = (size_t)nd * nd;
+  const size_t m = (size_t)4 * h->N * h->N;
   P.psf_hat64 = (double2 *)dev_alloc(h, m * sizeof(double2));
   double2 *tmp = (double2 *)dev_alloc(h, m * sizeof(double2));
-  hipLaunchKernelGGL(k_pad_real64, g1((int64_t)m), dim3(256), 0, s, P.psf, nd, P.psf_hat64);
-  IMGR_HIP(hipGetLastError());
-  fft2_plain64(h, P.psf_hat64, tmp, nd, -1, s);
+  psf_spectrum64_of(h, P.psf, P.psf_hat64, tmp, s);
   IMGR_HIP(hipStreamSynchronize(s));
   dev_free(h, tmp);
   return P.psf_hat64;

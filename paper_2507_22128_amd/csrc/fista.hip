@@ -626,8 +626,8 @@ void reduce(Ctx &c, const double *a, const double *b, const double *al, int mode
 }  // namespace
 
 void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const float *dirty,
-                   const float *rho_other, const float *power_start, float *model_delta,
-                   float *model_accum, double *objective, hipStream_t s) {
+                   const float *psf, const float *rho_other, const float *power_start,
+                   float *model_delta, float *model_accum, double *objective, hipStream_t s) {
   const int n = h->N;
   const size_t nn = (size_t)n * n;
   FistaWork &f = h->fista[part];
@@ -637,7 +637,7 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
     for (void *q : {(void *)f.alpha_prev, (void *)f.y, (void *)f.x, (void *)f.u1, (void *)f.u2,
                     (void *)f.u3, (void *)f.cst, (void *)f.tmp, (void *)f.coef, (void *)f.xb,
                     (void *)f.d64, (void *)f.r64, (void *)f.scal, (void *)f.part, (void *)f.hlo,
-                    (void *)f.work64, (void *)f.tmp64})
+                    (void *)f.work64, (void *)f.tmp64, (void *)f.psf_ext})
       dev_free(h, q);
     f = FistaWork();
     for (double **b : {&f.alpha_prev, &f.y, &f.coef, &f.tmp})
@@ -664,7 +664,14 @@ void fista_enqueue(imgr_s *h, int part, const imgr_fista_params &prm, const floa
     f.n_bases = nbases;
     f.n = nn;
   }
-  const double2 *spec = psf_spectrum64(h, part, s);
+  const double2 *spec;
+  if (psf) {
+    if (!f.psf_ext) f.psf_ext = (double2 *)dev_alloc(h, 4 * nn * sizeof(double2));
+    psf_spectrum64_of(h, psf, f.psf_ext, f.tmp64, s);
+    spec = f.psf_ext;
+  } else {
+    spec = psf_spectrum64(h, part, s);
+  }
   Bases bs{};
   for (int b = 0; b < nbases; ++b) {
     bs.hoff[b] = f.hoff[b];

@@ -89,7 +89,7 @@ _SIGS = {
     "imager_minor_cycle_msclean": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "imager_minor_cycle_msclean_static": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "imager_reconstruct_msclean": [_P, _I, _P, _P, _P, _P, _P],
-    "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "imager_minor_cycle_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "imager_reconstruct_fista": [_P, _I, _P, _P, _P, _P, _P, _P, _P],
     "imager_combine_partitions": [_P, _I, _P, _P, _D, _D, _P, _P],
     "imager_set_timing": [_P, _I],
@@ -469,19 +469,23 @@ class Imager:
         return final, models, rhos, counts
 
     def minor_cycle_fista(self, part, dirty, power_start, rho_other=None, model_accum=None,
-                          want_objective=False, **params):
-        """Sparsity-regularised minor cycle of one node (synchronous).  Returns
+                          want_objective=False, psf=None, **params):
+        """Sparsity-regularised minor cycle of one node (synchronous); psf (2N x
+        2N) replaces the node's own PSF in H when given.  Returns
         (model_delta, objective per iteration or None, L_hat, lambda)."""
         import torch
         n = self.n_pix
         _dev_f32(dirty, (n, n), torch)
         _dev_f32(power_start, (n, n), torch)
+        if psf is not None:
+            _dev_f32(psf, (2 * n, 2 * n), torch)
         prm = fista_params(**params)
         delta = self._empty((n, n), "float32")
         obj = self._empty((max(prm.n_iter, 1),), "float64") if want_objective else None
         L, lam = ctypes.c_double(0.0), ctypes.c_double(0.0)
         self._check(lib().imager_minor_cycle_fista(
-            self._h, part, ctypes.byref(prm), _ptr(dirty), _ptr(rho_other), _ptr(power_start),
+            self._h, part, ctypes.byref(prm), _ptr(dirty), _ptr(psf), _ptr(rho_other),
+            _ptr(power_start),
             _ptr(delta), _ptr(model_accum), _ptr(obj), ctypes.byref(L), ctypes.byref(lam)))
         objective = None if obj is None else obj[:prm.n_iter].cpu().numpy()
         return delta, objective, L.value, lam.value

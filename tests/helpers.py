@@ -51,6 +51,37 @@ def oracle_weights(d, n, valid=None, uniform=True):
     return w
 
 
+@functools.lru_cache(maxsize=4)
+def oracle_inputs(name, n_time=None, partitions=1, model_scale=0.0):
+    """Inputs for teacher-forced minor cycles, all from the oracle (FP64):
+    per partition (one: the whole set; two: the median split of the
+    oracle's partition) the residual image of model_scale * truth (Eq. 2)
+    and the 2N x 2N PSF; with the split's ell and the partitions' weight
+    sums."""
+    d = workload(name, n_time=n_time)
+    n = d["n_img"]
+    u, v = uv(d)
+    w = oracle_weights(d, n)
+    if partitions == 1:
+        masks, ell = [np.ones(len(u), bool)], None
+    else:
+        low, high, ell = imaging.partition(u, v, n, d["cell"])
+        masks = [low, high]
+    model = model_scale * d["truth"]
+    out = {"ell": ell, "sum_w": [float(w[m].sum()) for m in masks], "resid": [], "psf": []}
+    for m in masks:
+        r, _ = imaging.residual_image(u[m], v[m], d["vis"][m], w[m], model, d["cell"])
+        out["resid"].append(r)
+        out["psf"].append(imaging.psf2(u[m], v[m], w[m], n, d["cell"]))
+    return out
+
+
+def f32(a):
+    """Round to float32 (the precision both sides of a teacher-forced test
+    receive), kept as float64 for the oracle."""
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
 def to_dev(x, dtype="float32"):
     import torch
     return torch.tensor(np.ascontiguousarray(x), dtype=getattr(torch, dtype), device="cuda")
@@ -60,5 +91,5 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-__all__ = ["rel", "say", "workload", "uv", "random_model", "oracle_weights", "to_dev", "to_np",
-           "decentral", "imaging", "geometry"]
+__all__ = ["rel", "say", "workload", "uv", "random_model", "oracle_weights", "oracle_inputs",
+           "f32", "to_dev", "to_np", "decentral", "imaging", "geometry"]

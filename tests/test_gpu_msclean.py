@@ -1,9 +1,10 @@
 """Multi-scale CLEAN on the GPU against the FP64 oracle (GPU required).
 
 Teacher forcing: the GPU minor cycle and the oracle get the same dirty image
-and PSF (the GPU's float32 arrays, up-cast exactly for the oracle), so every
-decision must coincide: identical (scale, iy, ix) sequences, amplitudes to
-FP64 rounding, model and residual to the float32 rounding of the outputs.
+and PSF, both made by the oracle and rounded to float32 (up-cast exactly for
+the oracle), so every decision must coincide: identical (scale, iy, ix)
+sequences, amplitudes to FP64 rounding, model and residual to the float32
+rounding of the outputs.
 The end-to-end loop compares the library's whole reconstruction with the
 oracle's, where the major cycles differ at the FP32 level.
 """
@@ -11,7 +12,8 @@ oracle's, where the major cycles differ at the FP32 level.
 import numpy as np
 import pytest
 
-from helpers import imaging, oracle_weights, rel, say, to_dev, to_np, uv, workload
+from helpers import (f32, imaging, oracle_inputs, oracle_weights, rel, say, to_dev, to_np,
+                     uv, workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,25 +50,27 @@ def tiny1():
     h.destroy()
 
 
+def _serial_inputs():
+    """The oracle's dirty image and PSF of the tiny workload, float32."""
+    o = oracle_inputs("tiny")
+    return f32(o["resid"][0]), f32(o["psf"][0])
+
+
 def test_msclean_teacher_forced_serial(tiny1):
-    import torch
     d, h = tiny1
-    n = d["n_img"]
-    dirty = h.major_cycle(0, torch.zeros((n, n), device="cuda"))
-    psf = h.psf(0)
+    dirty64, psf64 = _serial_inputs()
+    dirty, psf = to_dev(dirty64), to_dev(psf64)
     scales = [0, 4, 12]
     delta, comps, resid = h.minor_cycle_msclean(0, dirty, psf, scales, gain=0.1, niter=300)
-    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
-        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), scales, gain=0.1,
-        niter=300)
+    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(dirty64, psf64, scales, gain=0.1,
+                                                             niter=300)
     say("serial msclean: %d components, scales used %s" % (len(comps), sorted(set(comps["scale"]))))
     _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
     # extended scales only (scale 0 tracked for the threshold, not selectable)
     delta, comps, resid = h.minor_cycle_msclean(0, dirty, psf, scales, niter=150, active=[1, 2],
                                                 bias_slope=0.3)
     ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
-        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), scales, niter=150,
-        active=[1, 2], bias_slope=0.3)
+        dirty64, psf64, scales, niter=150, active=[1, 2], bias_slope=0.3)
     assert len(comps) == 150 and set(comps["scale"]) <= {1, 2}
     _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
 
@@ -75,15 +79,14 @@ def test_msclean_threshold_count_and_empty(tiny1):
     import torch
     d, h = tiny1
     n = d["n_img"]
-    dirty = h.major_cycle(0, torch.zeros((n, n), device="cuda"))
-    psf = h.psf(0)
-    thr = 0.5 * float(to_np(dirty).__abs__().max())
+    dirty64, psf64 = _serial_inputs()
+    dirty, psf = to_dev(dirty64), to_dev(psf64)
+    thr = 0.5 * float(np.abs(dirty64).max())
     acc = torch.zeros((n, n), device="cuda")
     delta, comps, resid = h.minor_cycle_msclean(0, dirty, psf, [0, 4], niter=500, threshold=thr,
                                                 model_accum=acc)
-    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(
-        to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64), [0, 4], niter=500,
-        threshold=thr)
+    ref_model, ref_r0, ref_comps = _oracle_msclean().msclean(dirty64, psf64, [0, 4], niter=500,
+                                                             threshold=thr)
     assert 0 < len(comps) < 500
     _compare(comps, ref_comps, to_np(delta), ref_model, to_np(resid), ref_r0)
     assert torch.equal(acc, delta)  # model_accum started at zero
@@ -103,32 +106,35 @@ def tiny2():
 def test_msclean_teacher_forced_two_nodes(tiny2):
     """Cycle-2 composed images (Eq. 7) of both nodes, and the first-cycle
     own-scale subsets."""
+    from oracle import decentral
     d, h = tiny2
     n = d["n_img"]
     rng = np.random.default_rng(12)
-    model = to_dev(0.3 * d["truth"])
-    rho = to_dev(0.002 * rng.standard_normal((n, n)))
-    wl, wh = h.sum_w(0), h.sum_w(1)
+    o = oracle_inputs("tiny", n_time=20, partitions=2, model_scale=0.3)
+    assert h.info.ell_pix == o["ell"] and h.info.delta_pix == 1.0
+    rho = 0.002 * rng.standard_normal((n, n))
+    wl, wh = o["sum_w"]
     scales = [0, 4, 12]
     msc = _oracle_msclean()
     for p, own in ((0, "L"), (1, "H")):
         g = (wl, wh)[p] / (wl + wh)
-        dirty = h.major_cycle(p, model, rho, g, 1.0 - g)
-        psf = h.composed_psf(p, g, 1.0 - g)
-        delta, comps, resid = h.minor_cycle_msclean(p, dirty, psf, scales, niter=200)
-        rm, rr, rc = msc.msclean(to_np(dirty).astype(np.float64), to_np(psf).astype(np.float64),
-                                 scales, niter=200)
+        dirty64 = f32(decentral.compose_dirty(o["resid"][p], rho, o["psf"][1 - p], o["ell"], 1.0,
+                                              own, g, 1.0 - g))
+        psf64 = f32(decentral.compose_psf(o["psf"][p], o["psf"][1 - p], o["ell"], 1.0, own, g,
+                                          1.0 - g))
+        delta, comps, resid = h.minor_cycle_msclean(p, to_dev(dirty64), to_dev(psf64), scales,
+                                                    niter=200)
+        rm, rr, rc = msc.msclean(dirty64, psf64, scales, niter=200)
         say("node %s: %d components" % (own, len(comps)))
         _compare(comps, rc, to_np(delta), rm, to_np(resid), rr)
         # first cycle: gamma = 1, mu = 0, the node's own scales only
-        dirty1 = h.major_cycle(p, model)
-        psf1 = h.composed_psf(p, 1.0, 0.0)
-        active = msc.scale_subset(scales, n, h.info.ell_pix, h.info.delta_pix, own)
-        delta1, comps1, resid1 = h.minor_cycle_msclean(p, dirty1, psf1, scales, niter=100,
-                                                       own_scales_only=True)
-        rm1, rr1, rc1 = msc.msclean(to_np(dirty1).astype(np.float64),
-                                    to_np(psf1).astype(np.float64), scales, niter=100,
-                                    active=active)
+        d1 = f32(decentral.compose_dirty(o["resid"][p], None, None, o["ell"], 1.0, own, 1.0, 0.0))
+        p1 = f32(decentral.compose_psf(o["psf"][p], o["psf"][1 - p], o["ell"], 1.0, own, 1.0,
+                                       0.0))
+        active = msc.scale_subset(scales, n, o["ell"], 1.0, own)
+        delta1, comps1, resid1 = h.minor_cycle_msclean(p, to_dev(d1), to_dev(p1), scales,
+                                                       niter=100, own_scales_only=True)
+        rm1, rr1, rc1 = msc.msclean(d1, p1, scales, niter=100, active=active)
         assert set(comps1["scale"]) <= set(active)
         _compare(comps1, rc1, to_np(delta1), rm1, to_np(resid1), rr1)
 
