@@ -113,7 +113,7 @@ def combine(images, weights=None):
 
 def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, niter=2000,
                         threshold=0.0, partitions=2, ell=None, delta=1.0, support=8,
-                        record_gaps=False):
+                        record_gaps=False, workers=None, minor=None):
     """The major/minor loop with multi-scale CLEAN, serial (partitions = 1)
     or decentralized over V_L / V_H (partitions = 2), in FP64.
 
@@ -131,8 +131,17 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
     per-cycle dicts {node: (dirty D, psf P, components, ibar, gaps)}; gaps
     is the per-iteration near-tie margin of ``msclean.msclean`` with
     ``record_gaps``, else None.
+
+    ``workers`` (optional) runs the residuals and PSFs on that many host
+    processes (``pool``: the same operators, with the FP64 additions of the
+    grid cells in chunk order).  ``minor`` (optional) replaces the minor
+    cycle: minor(cycle, node, D, P, active) -> (ibar, components, gaps),
+    for running the loop on another precision's inputs or replaying a
+    recorded run.
     """
     from . import imaging, msclean as msc
+    if workers is not None:
+        from . import pool
     m = len(u)
     if partitions == 1:
         masks = {"L": np.ones(m, bool)}
@@ -142,8 +151,12 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
         masks = {"L": low, "H": high}
         nodes = ("L", "H")
     other = {"L": "H", "H": "L"}
-    psf = {k: imaging.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support)
-           for k, mk in masks.items()}
+    if workers is None:
+        psf = {k: imaging.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support)
+               for k, mk in masks.items()}
+    else:
+        psf = {k: pool.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support, workers=workers)
+               for k, mk in masks.items()}
     wsum = {k: w[mk].sum() for k, mk in masks.items()}
     models = {k: np.zeros((n_img, n_img)) for k in nodes}
     rho = {k: np.zeros((n_img, n_img)) for k in nodes}   # rho_other held by node k
@@ -152,8 +165,12 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
         step, deltas = {}, {}
         for k in nodes:
             mk = masks[k]
-            resid, _ = imaging.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
-                                              support=support)
+            if workers is None:
+                resid, _ = imaging.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
+                                                  support=support)
+            else:
+                resid, _ = pool.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
+                                               support=support, workers=workers)
             if partitions == 1:
                 d_img, p_img, active = resid, psf[k], None
             else:
@@ -161,11 +178,15 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
                 d_img = compose_dirty(resid, rho[k], psf[other[k]], ell, delta, k, gamma, mu)
                 p_img = compose_psf(psf[k], psf[other[k]], ell, delta, k, gamma, mu)
                 active = msc.scale_subset(scales, n_img, ell, delta, k) if cyc == 1 else None
-            st = {} if record_gaps else None
-            ibar, _, comps = msc.msclean(d_img, p_img, scales, gain, niter, threshold, active,
-                                         state=st)
+            if minor is not None:
+                ibar, comps, gaps = minor(cyc, k, d_img, p_img, active)
+            else:
+                st = {} if record_gaps else None
+                ibar, _, comps = msc.msclean(d_img, p_img, scales, gain, niter, threshold,
+                                             active, state=st)
+                gaps = st["gaps"] if record_gaps else None
             deltas[k] = ibar
-            step[k] = (d_img, p_img, comps, ibar, st["gaps"] if record_gaps else None)
+            step[k] = (d_img, p_img, comps, ibar, gaps)
         for k in nodes:
             models[k] = models[k] + deltas[k]
         if partitions == 2:
@@ -181,7 +202,7 @@ def reconstruct_msclean(u, v, vis, w, n_img, cell, n_cycles, scales, gain=0.1, n
 
 def reconstruct_fista(u, v, vis, w, n_img, cell, n_cycles, start_images, lam_frac=1e-3,
                       n_iter=200, power_iters=30, vanishing=8, levels=3, partitions=2, ell=None,
-                      delta=1.0, support=8, dictionary=False):
+                      delta=1.0, support=8, dictionary=False, workers=None):
     """The major/minor loop with the sparsity-regularised minor cycle (Eqs.
     4 and 5), serial (partitions = 1) or decentralized, in FP64.
 
@@ -194,9 +215,12 @@ def reconstruct_fista(u, v, vis, w, n_img, cell, n_cycles, start_images, lam_fra
     model += ibar (Eq. 3).  Then the Phi / rho exchange of Section 4.1 and,
     at the end, the equal-weight combination of Section 5.2.
     Returns (final image, per-node models, history of per-cycle dicts
-    {node: (lambda, L_hat, objective list)}).
+    {node: (lambda, L_hat, objective list)}).  ``workers`` as in
+    ``reconstruct_msclean``.
     """
     from . import fista as fs, imaging, wavelets
+    if workers is not None:
+        from . import pool
     # one Daubechies basis, or the concatenation of the first `vanishing` ones
     h = ([wavelets.daubechies(p) for p in range(1, vanishing + 1)] if dictionary
          else wavelets.daubechies(vanishing))
@@ -209,8 +233,12 @@ def reconstruct_fista(u, v, vis, w, n_img, cell, n_cycles, start_images, lam_fra
         masks = {"L": low, "H": high}
         nodes = ("L", "H")
     other = {"L": "H", "H": "L"}
-    psf = {k: imaging.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support)
-           for k, mk in masks.items()}
+    if workers is None:
+        psf = {k: imaging.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support)
+               for k, mk in masks.items()}
+    else:
+        psf = {k: pool.psf2(u[mk], v[mk], w[mk], n_img, cell, support=support, workers=workers)
+               for k, mk in masks.items()}
     models = {k: np.zeros((n_img, n_img)) for k in nodes}
     rho = {k: np.zeros((n_img, n_img)) for k in nodes}
     history = []
@@ -218,8 +246,12 @@ def reconstruct_fista(u, v, vis, w, n_img, cell, n_cycles, start_images, lam_fra
         step, deltas = {}, {}
         for k in nodes:
             mk = masks[k]
-            resid, _ = imaging.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
-                                              support=support)
+            if workers is None:
+                resid, _ = imaging.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
+                                                  support=support)
+            else:
+                resid, _ = pool.residual_image(u[mk], v[mk], vis[mk], w[mk], models[k], cell,
+                                               support=support, workers=workers)
             gamma_n = 0.0 if (cyc == 1 or partitions == 1) else 1.0
             lam = lam_frac * float(np.abs(resid).max())
             prob = fs.NodeProblem(resid, psf[k], rho[k], gamma_n, ell, delta, k, h, levels,

@@ -76,6 +76,18 @@ def oracle_inputs(name, n_time=None, partitions=1, model_scale=0.0):
     return out
 
 
+def ibar_from_components(comps, scales, n):
+    """The minor cycle's model ibar rebuilt from its components (scale index,
+    iy, ix, amplitude), placed in order as the oracle's minor cycle places
+    them (bit for bit the same FP64 sums)."""
+    from oracle import msclean
+    kern = [msclean.scale_kernel(s) for s in scales]
+    ibar = np.zeros((n, n))
+    for s, iy, ix, a in comps:
+        msclean.add_component(ibar, kern[int(s)], int(iy), int(ix), float(a))
+    return ibar
+
+
 def f32(a):
     """Round to float32 (the precision both sides of a teacher-forced test
     receive), kept as float64 for the oracle."""
@@ -92,4 +104,4 @@ def to_np(t):
 
 
 __all__ = ["rel", "say", "workload", "uv", "random_model", "oracle_weights", "oracle_inputs",
-           "f32", "to_dev", "to_np", "decentral", "imaging", "geometry"]
+           "ibar_from_components", "f32", "to_dev", "to_np", "decentral", "imaging", "geometry"]

@@ -385,3 +385,45 @@ def test_pool_runner_equals_serial_oracle(monkeypatch):
     p_ref = imaging.psf2(u, v, w, n, d["cell"])
     p_got = pool.psf2(u, v, w, n, d["cell"], workers=3)
     assert np.abs(p_got - p_ref).max() < 1e-13
+
+
+def test_loop_on_the_pool_and_replayed_through_the_minor_hook(monkeypatch):
+    """reconstruct_msclean with ``workers`` takes the same decisions as the
+    serial loop (its images equal to FP64 rounding), and a ``minor`` hook
+    that returns the recorded components' ibar replays the loop's inputs bit
+    for bit (the replay the component-sequence fixtures rely on)."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from helpers import ibar_from_components
+    from oracle import geometry, pool
+    from paper_2507_22128_amd import synth
+    monkeypatch.setattr(pool, "MIN_CHUNK", 2000)
+    d = synth.make("tiny", n_time=6)
+    n = d["n_img"]
+    u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
+    w = imaging.uniform_weights(u, v, n, d["cell"])
+    scales = [0, 2, 4]
+    args = (u, v, d["vis"], w, n, d["cell"], 2, scales)
+    kw = dict(gain=0.1, niter=25, partitions=2, record_gaps=True)
+    _, models, hist = decentral.reconstruct_msclean(*args, **kw)
+    _, models_p, hist_p = decentral.reconstruct_msclean(*args, workers=3, **kw)
+    for c in range(2):
+        for k in ("L", "H"):
+            a, b = hist[c][k], hist_p[c][k]
+            assert np.abs(a[0] - b[0]).max() < 1e-12 * np.abs(a[0]).max()
+            assert [x[:3] for x in a[2]] == [x[:3] for x in b[2]]
+
+    def replay(cyc, node, d_img, p_img, active):
+        comps = hist[cyc - 1][node][2]
+        return ibar_from_components(comps, scales, n), comps, None
+
+    _, models_r, hist_r = decentral.reconstruct_msclean(*args, gain=0.1, niter=25, partitions=2,
+                                                        minor=replay)
+    for c in range(2):
+        for k in ("L", "H"):
+            assert np.array_equal(hist[c][k][0], hist_r[c][k][0])
+            assert np.array_equal(hist[c][k][1], hist_r[c][k][1])
+            assert np.array_equal(hist[c][k][3], hist_r[c][k][3])
+    for k in ("L", "H"):
+        assert np.array_equal(models[k], models_r[k])
