@@ -562,10 +562,19 @@ __global__ __launch_bounds__(64 * kWaves) void k_window_batch(const WinArgs *__r
   }
 }
 
-// One thread per grid cell, 16 x 16 cells per workgroup: FP64 sum over the
-// chunk windows of the blocks whose window covers the cell (fixed order:
-// block row offset, block column offset, chunk), times (-1)^(x + y) for the
-// centred inverse DFT that follows.  The workgroup first stages the chunk
+// s + c += x with the rounding error of every FP64 addition kept in c
+// (Knuth's TwoSum, exact in IEEE arithmetic): a compensated sum
+__device__ __forceinline__ void add_compensated(double &s, double &c, double x) {
+  const double t = s + x;
+  const double z = t - s;
+  c += (s - (t - z)) + (x - z);
+  s = t;
+}
+
+// One thread per grid cell, 16 x 16 cells per workgroup: compensated FP64
+// sum over the chunk windows of the blocks whose window covers the cell
+// (fixed order: block row offset, block column offset, chunk), times
+// (-1)^(x + y) for the centred inverse DFT that follows.  The workgroup first stages the chunk
 // ranges of the blocks around its 16 x 16 cells in LDS; each thread then
 // issues the loads of the first chunk of every covering block at once (the
 // common case is one chunk per block) and adds the values, and any further
@@ -606,25 +615,26 @@ __device__ __forceinline__ void flush_group(const FlushArgs &a, int group) {
       first[i * KA + j] = make_float2(0.f, 0.f);
       if (r.x < r.y) first[i * KA + j] = ld2u(a.scratch, (unsigned)(r.x * (kWin * kWin) + off));
     }
-  double re = 0.0, im = 0.0;
+  double re = 0.0, im = 0.0, cre = 0.0, cim = 0.0;
 #pragma unroll
   for (int i = 0; i < KA; ++i)
 #pragma unroll
     for (int j = 0; j < KA; ++j) {
       const int2 r = rng[(sy0 + i) * SB + sx0 + j];
       if (r.x < r.y) {
-        re += (double)first[i * KA + j].x;
-        im += (double)first[i * KA + j].y;
+        add_compensated(re, cre, (double)first[i * KA + j].x);
+        add_compensated(im, cim, (double)first[i * KA + j].y);
         const int off = (wy0 - i * BLK) * kWin + wx0 - j * BLK;
         for (int c = r.x + 1; c < r.y; ++c) {
           const float2 v = ld2u(a.scratch, (unsigned)(c * (kWin * kWin) + off));
-          re += (double)v.x;
-          im += (double)v.y;
+          add_compensated(re, cre, (double)v.x);
+          add_compensated(im, cim, (double)v.y);
         }
       }
     }
   const float sg = ((cx + cy) & 1) ? -1.f : 1.f;
-  st2(a.grid_out, (size_t)cy * ng + cx, make_float2(sg * (float)re, sg * (float)im));
+  st2(a.grid_out, (size_t)cy * ng + cx,
+      make_float2(sg * (float)(re + cre), sg * (float)(im + cim)));
 }
 
 template <int W, int BLK>
