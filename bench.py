@@ -229,6 +229,40 @@ def whole_loop(h, n, name):
     return out
 
 
+def batch_oracle(d, chans, kept, models, got, args, tag):
+    """The FP64 oracle's residual image (Eq. 2) of every 8th channel, over all
+    of its unflagged visibilities (oracle.pool on the host's cores), against
+    the timed fused cycle's outputs; also the oracle's rate on them."""
+    import numpy as np
+    from oracle import geometry, imaging, pool
+    workers = args.oracle_workers or pool.default_workers()
+    uvw = d["uvw"].cpu().numpy() if hasattr(d["uvw"], "cpu") else d["uvw"]
+    errs, n_vis, secs = {}, 0, 0.0
+    for k, (vis, flag) in kept.items():
+        c = chans[k]
+        n = c["n_img"]
+        u, v = geometry.uv_lambda(uvw, c["freq_hz"])
+        valid = flag == 0
+        w = imaging.uniform_weights(u, v, n, c["cell"], valid=valid)
+        model = models[k].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        ref, _ = pool.residual_image(u[valid], v[valid], vis[valid], w[valid], model, c["cell"],
+                                     workers=workers)
+        secs += time.perf_counter() - t0
+        n_vis += int(valid.sum())
+        g = got[k].cpu().numpy().astype(np.float64)
+        errs[str(k)] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    out = {"channels": sorted(int(k) for k in kept), "rel_l2": errs,
+           "max_rel_l2": max(errs.values()), "tolerance": 1e-5,
+           "pass": bool(max(errs.values()) <= 1e-5),
+           "oracle_mvis_per_s": round(n_vis / secs / 1e6, 3), "oracle_seconds": round(secs, 1),
+           "oracle_cores": workers}
+    log("%s: oracle on every 8th channel (%d channels, %d visibilities, %d processes): %.1f s, "
+        "%.3f Mvis/s; GPU error max %.2e" % (tag, len(kept), n_vis, workers, secs,
+                                             out["oracle_mvis_per_s"], out["max_rel_l2"]))
+    return out
+
+
 def batched_channels(args, small=False):
     """Batched-channel workload: the major cycle (Eq. 2) of every channel of
     a 64-channel observation (0.95 - 1.75 GHz, 256 antennas, 480 times,
@@ -271,6 +305,10 @@ def batched_channels(args, small=False):
         if members[k] is None:
             members[k] = mk(c, support=i0.support, tile=i0.tile, chunk=i0.chunk)
     create_s = time.perf_counter() - t0
+    # host copies of every 8th channel, for the oracle check of the timed outputs
+    sample = (list(range(0, len(chans), 8))
+              if (not small and args.batch_oracle and not args.no_cpu_baseline) else [])
+    kept = {k: (chans[k]["vis"].cpu().numpy(), chans[k]["flag"].cpu().numpy()) for k in sample}
     for c in chans:  # the handles hold their own copies
         c["vis"] = c["flag"] = None
     torch.cuda.empty_cache()
@@ -329,6 +367,9 @@ def batched_channels(args, small=False):
         log("%s %s: %.3f ms per cycle of all channels, %.0f Mvis/s"
             % (tag, name, ms, info.n_vis / (ms / 1e3) / 1e6))
     b.set_bytes(0)
+    if sample:
+        out["oracle_every_8th_channel"] = batch_oracle(d, chans, kept, models, last["fused_graph"],
+                                                       args, tag)
     same = all(torch.equal(a, c) for a, c in zip(last["fused_graph"], last["per_channel_loop"]))
     same = same and all(torch.equal(a, c) for a, c in zip(last["fused_graph"],
                                                           last["fused_sets_128mb_graph"]))
@@ -657,6 +698,8 @@ def main():
     ap.add_argument("--batch-channels", type=int, default=64)
     ap.add_argument("--batch-small-channels", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-batch-oracle", dest="batch_oracle", action="store_false",
+                    help="skip the oracle check of every 8th batched channel")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=50)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[2.0, 5.0, 10.0, 20.0, 50.0])
