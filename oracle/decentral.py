@@ -4,6 +4,11 @@ aggregate rho and exchanged Phi of Eqs. 5 and 7, and the final combination.
 
 Node names: ``own`` is the node doing the work (V_L or V_H), ``other`` the
 node whose filtered deconvolved residuals it receives.
+
+Parity unpinned (the paper gives no formula, so only the reading is
+implemented): the shape of the Gamma ramp (``gamma_low``) and the values of
+gamma and mu (``weights_schedule``); the pins fix where they enter Eqs. 5
+and 7.
 """
 
 import numpy as np

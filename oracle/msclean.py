@@ -27,7 +27,8 @@ Parity: pinned by the Hogbom reduction, the single-source closed form, the
 consistency R_0 = dirty - psf * model, flux conservation, and the
 invariant R_t = phi_t * R_0 on pixels at least the kernel radius from the
 edge, which holds only if every cross PSF B_st and every R_t update is
-right (tests).
+right (tests).  ``scale_subset`` (psi^1 of Eq. 7) is a reading of a rule
+the paper states only in words: parity unpinned.
 """
 
 import numpy as np
@@ -153,7 +154,7 @@ def msclean(dirty, psf2, scales, gain=0.1, niter=2000, threshold=0.0, active=Non
 
 def scale_subset(scales, n_img, ell, delta, node):
     """psi^1 of Eq. 7: the scales present in the node's own domain at the
-    first major cycle (reading): V_L keeps s >= N / (2 (ell + delta)),
+    first major cycle (reading; parity unpinned): V_L keeps s >= N / (2 (ell + delta)),
     V_H keeps s <= N / (ell - delta); if none qualifies, the scale of S
     nearest to the bound.  Returns indices into ``scales``."""
     scales = list(scales)
