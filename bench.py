@@ -666,7 +666,8 @@ def measure_cycle(name, args, workers, with_oracle=True, minor=True):
     if minor:
         res["minor_cycles"] = minor_cycles(h, info, model, rho, gammas, mus, n,
                                            msclean=(name == "decentral"))
-        res["reconstruction"] = whole_loop(h, n, name)
+        if not args.no_reconstruction:
+            res["reconstruction"] = whole_loop(h, n, name)
     h.destroy()
     del model, rho, out, local
     torch.cuda.empty_cache()
@@ -693,6 +694,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle run (no cpu_baseline, no error against the oracle)")
     ap.add_argument("--no-minor-cycles", action="store_true")
+    ap.add_argument("--no-reconstruction", action="store_true",
+                    help="skip the whole reconstructions as configured (the one-call loops)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-decentral", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=64)
