@@ -203,3 +203,38 @@ def test_fista_at_the_2048_workload_teacher_forced():
     assert abs(L / r_L - 1) < 1e-10 and abs(lam / r_lam - 1) < 1e-10
     assert e_obj < 1e-10
     assert e_img < 1e-6
+
+
+@pytest.mark.parametrize("vanishing,levels", [(2, 5), (1, 6), (10, 2)])
+def test_fista_smallest_image_deepest_levels(vanishing, levels):
+    """N = 64, the smallest image: the wavelet levels down to 2 x 2 blocks
+    (db2 over 5 levels, db1 over 6) and the 20-tap db10 over 32 x 32 blocks,
+    where the filters wrap around a block more than once; serial FISTA (Eq. 4)
+    on the oracle's dirty image and PSF, against the oracle."""
+    from oracle import fista, wavelets
+    d = workload("tiny", n_time=8)
+    n = 64
+    u, v = uv(d)
+    w = imaging.uniform_weights(u, v, n, d["cell"])
+    dirty = f32(imaging.dirty_image(u, v, d["vis"], w, n, d["cell"]))
+    psf = f32(imaging.psf2(u, v, w, n, d["cell"]))
+    start = f32(np.random.default_rng(35).standard_normal((n, n)))
+    h = _imager().Imager.create(d, n_pix=n, n_partitions=1, weighting="uniform")
+    try:
+        delta, obj, L, lam = h.minor_cycle_fista(0, to_dev(dirty), to_dev(start), psf=to_dev(psf),
+                                                 n_iter=60, power_iters=20, serial=True,
+                                                 vanishing=vanishing, levels=levels,
+                                                 want_objective=True)
+        got = to_np(delta)
+    finally:
+        h.destroy()
+    prob = fista.NodeProblem(dirty, psf, None, 0.0, 0.0, 1.0, "L",
+                             wavelets.daubechies(vanishing), levels, serial=True)
+    r_L = fista.power_iteration(prob, start, 20)
+    r_lam = 1e-3 * np.abs(dirty).max()
+    alpha, r_obj = fista.fista(prob, r_lam, 60, r_L)
+    e_img, e_obj = rel(got, prob.W(alpha)), np.abs(obj / np.array(r_obj) - 1).max()
+    say("N = 64, db%d, %d levels: L %.6g (oracle %.6g), image rel err %.3e, objective rel %.3e"
+        % (vanishing, levels, L, r_L, e_img, e_obj))
+    assert abs(L / r_L - 1) < 1e-10 and abs(lam / r_lam - 1) < 1e-10
+    assert e_obj < 1e-10 and e_img < 1e-6
