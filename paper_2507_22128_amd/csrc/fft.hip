@@ -141,6 +141,90 @@ __device__ __forceinline__ void stockham_seq(C *s, const TW &tw, int t) {
   }
 }
 
+// The last Stockham pass of a length-L sequence: its sub-length NS and radix R.
+template <int L>
+struct LastPass {
+  static constexpr int ns() {
+    int n = 1;
+    while (true) {
+      const int r = (L / n >= 8) ? 8 : L / n;
+      if (n * r >= L) return n;
+      n *= r;
+    }
+  }
+  static constexpr int NS = ns(), R = L / NS;
+};
+
+// Stockham passes from sub-length NS on, with the last pass left in
+// registers instead of LDS: after the call, o[q][r] holds element
+// j + r * LastPass<L>::NS of the transform, j = t + q * NT (for j below
+// LastPass<L>::NS).  The same arithmetic as stockham_seq, one LDS store and
+// load of the whole sequence fewer.
+template <int L, int NT, int NS, int DIR, class C, class TW, int PO, int RO>
+__device__ __forceinline__ void stockham_out(C *s, const TW &tw, int t, C (&o)[PO][RO]) {
+  constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
+  constexpr int NB = L / R;
+  constexpr int PER = (NB + NT - 1) / NT;
+  C x[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = t + q * NT;
+    if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[q][r] = s[padi(j + r * NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = t + q * NT;
+    if ((NB % NT) == 0 || j < NB) {
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+          x[q][r] = cmul(x[q][r], tw_get<DIR>(tw, r * k * (L / (NS * R))));
+      }
+      dft<R, DIR>(x[q]);
+    }
+  }
+  if constexpr (NS * R == L) {
+    static_assert(PER == PO && R == RO, "last pass shape");
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[q][r] = x[q][r];
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = t + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+        const int k = j & (NS - 1);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[padi(base + r * NS)] = x[q][r];
+      }
+    }
+    __syncthreads();
+    stockham_out<L, NT, NS * R, DIR, C, TW, PO, RO>(s, tw, t, o);
+  }
+}
+
+// Rows with L / 8 threads: thread t loads elements t + q L/8, exactly the
+// inputs of its butterfly in the first pass (sub-length 1, radix 8, no
+// twiddles), which then runs on the loaded registers.
+template <int L, int NT>
+constexpr bool first_pass_in_regs() {
+  return NT * 8 == L;
+}
+
+template <int L, int DIR, class C>
+__device__ __forceinline__ void first_pass_regs(C *s, C (&v)[8], int t) {
+  dft<8, DIR>(v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) s[padi(8 * t + r)] = v[r];
+}
+
 // CW sequences of length LEN stored as s[pos][CW] (column c = t % CW), 256
 // threads in G = 256 / CW groups: group g does butterflies j = g, g + G, ...
 // (with CW = 64 a group is a wave, and its row index and twiddles are
@@ -252,6 +336,7 @@ __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
   }
   // the twiddle loads go out behind the row loads: one wait covers both
   stage_twiddles<L, NT, float2>(twl, twr);
+  float2 w[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int x = threadIdx.x + q * NT;
@@ -259,10 +344,18 @@ __device__ __forceinline__ void rows_model_body(const float *__restrict__ model,
     // (-1)^(x + y): rows ra and rb = ra + 1 have opposite signs
     if ((x + ya) & 1) wa = -wa;
     else wb = -wb;
-    s[padi(x)] = make_float2(wa, wb);
+    w[q] = make_float2(wa, wb);
   }
-  __syncthreads();
-  stockham_seq<L, NT, 1, -1>(s, row_tw<L>(twl), threadIdx.x);
+  if constexpr (first_pass_in_regs<L, NT>()) {
+    first_pass_regs<L, -1>(s, w, threadIdx.x);
+    __syncthreads();
+    stockham_seq<L, NT, 8, -1>(s, row_tw<L>(twl), threadIdx.x);
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = w[q];
+    __syncthreads();
+    stockham_seq<L, NT, 1, -1>(s, row_tw<L>(twl), threadIdx.x);
+  }
   // only the columns [c_lo, c_hi) are ever read
   for (int x = c_lo + threadIdx.x; x < c_hi; x += NT) {
     const float2 zx = s[padi(x)], zm = s[padi((L - x) & (L - 1))];
@@ -293,26 +386,47 @@ __device__ __forceinline__ void rows_image_body(const float2 *__restrict__ rows,
   __shared__ float2 twl[RowTw<L>::SIZE];
   const int o = (L - n) / 2;
   const int y = o + r;
-  {
-    constexpr int PER = L / NT;
-    float2 v[PER];
+  constexpr int PER = L / NT;
+  float2 v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int x = threadIdx.x + q * NT;
-      v[q] = (x >= c_lo && x < c_hi) ? rows[(size_t)r * L + x] : make_float2(0.f, 0.f);
+  for (int q = 0; q < PER; ++q) {
+    const int x = threadIdx.x + q * NT;
+    v[q] = (x >= c_lo && x < c_hi) ? rows[(size_t)r * L + x] : make_float2(0.f, 0.f);
+  }
+  stage_twiddles<L, NT, float2>(twl, twr);
+  const float cy = cinv[r] * scale;
+  if constexpr (first_pass_in_regs<L, NT>()) {
+    // first and last passes in registers: the loaded values feed the first
+    // pass, the last pass's outputs go straight to the image
+    constexpr int NS = LastPass<L>::NS, RL = LastPass<L>::R, PL = (NS + NT - 1) / NT;
+    first_pass_regs<L, 1>(s, v, threadIdx.x);
+    __syncthreads();
+    float2 z[PL][RL];
+    stockham_out<L, NT, 8, 1>(s, row_tw<L>(twl), threadIdx.x, z);
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int j = threadIdx.x + q * NT;
+#pragma unroll
+      for (int k = 0; k < RL; ++k) {
+        const int x = j + k * NS, ix = x - o;
+        if (j < NS && ix >= 0 && ix < n) {
+          float w = z[q][k].x;
+          if ((x + y) & 1) w = -w;
+          out[(size_t)r * n + ix] = w * cinv[ix] * cy;
+        }
+      }
     }
-    stage_twiddles<L, NT, float2>(twl, twr);
+  } else {
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
-  }
-  __syncthreads();
-  stockham_seq<L, NT, 1, 1>(s, row_tw<L>(twl), threadIdx.x);
-  const float cy = cinv[r] * scale;
-  for (int ix = threadIdx.x; ix < n; ix += NT) {
-    const int x = o + ix;
-    float v = s[padi(x)].x;
-    if ((x + y) & 1) v = -v;
-    out[(size_t)r * n + ix] = v * cinv[ix] * cy;
+    __syncthreads();
+    stockham_seq<L, NT, 1, 1>(s, row_tw<L>(twl), threadIdx.x);
+    for (int ix = threadIdx.x; ix < n; ix += NT) {
+      const int x = o + ix;
+      float w = s[padi(x)].x;
+      if ((x + y) & 1) w = -w;
+      out[(size_t)r * n + ix] = w * cinv[ix] * cy;
+    }
   }
 }
 
@@ -331,18 +445,31 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
   __shared__ C s[L + L / 32];
   __shared__ C twl[RowTw<L>::SIZE];
   C *row = buf + (size_t)blockIdx.x * L;
-  {
-    constexpr int PER = L / NT;
-    C v[PER];
+  constexpr int PER = L / NT;
+  C v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) v[q] = row[threadIdx.x + q * NT];
-    stage_twiddles<L, NT, C>(twl, twr);
+  for (int q = 0; q < PER; ++q) v[q] = row[threadIdx.x + q * NT];
+  stage_twiddles<L, NT, C>(twl, twr);
+  if constexpr (first_pass_in_regs<L, NT>()) {
+    constexpr int NS = LastPass<L>::NS, RL = LastPass<L>::R, PL = (NS + NT - 1) / NT;
+    first_pass_regs<L, DIR>(s, v, threadIdx.x);
+    __syncthreads();
+    C z[PL][RL];
+    stockham_out<L, NT, 8, DIR>(s, row_tw<L>(twl), threadIdx.x, z);
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int j = threadIdx.x + q * NT;
+#pragma unroll
+      for (int k = 0; k < RL; ++k)
+        if (j < NS) row[j + k * NS] = z[q][k];
+    }
+  } else {
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = v[q];
+    __syncthreads();
+    stockham_seq<L, NT, 1, DIR, C>(s, row_tw<L>(twl), threadIdx.x);
+    for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
   }
-  __syncthreads();
-  stockham_seq<L, NT, 1, DIR, C>(s, row_tw<L>(twl), threadIdx.x);
-  for (int x = threadIdx.x; x < L; x += NT) row[x] = s[padi(x)];
 }
 
 // ---------------------------------------------------------------- column kernels
@@ -552,11 +679,19 @@ __device__ __forceinline__ void rows_real_fwd_body(const typename Real<C>::T *__
       }
     }
     stage_twiddles<L, NT, C>(twl, twr);
+    if constexpr (first_pass_in_regs<L, NT>()) {
+      C w[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = mkc<C>(u[q], v[q]);
+      for (int q = 0; q < PER; ++q) w[q] = mkc<C>(u[q], v[q]);
+      first_pass_regs<L, -1>(s, w, threadIdx.x);
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = mkc<C>(u[q], v[q]);
+    }
   }
   __syncthreads();
-  stockham_seq<L, NT, 1, -1, C>(s, row_tw<L>(twl), threadIdx.x);
+  stockham_seq<L, NT, first_pass_in_regs<L, NT>() ? 8 : 1, -1, C>(s, row_tw<L>(twl),
+                                                                  threadIdx.x);
   const RT h = RT(0.5);
   for (int x = threadIdx.x; x < c_hi; x += NT) {
     const C zx = s[padi(x)], zm = s[padi((L - x) & (L - 1))];
@@ -605,6 +740,7 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
       v[q] = xs < c_hi ? in[(size_t)rb * L + xs] : mkc<C>(0, 0);
     }
     stage_twiddles<L, NT, C>(twl, twr);
+    C w[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int x = threadIdx.x + q * NT;
@@ -615,10 +751,56 @@ __device__ __forceinline__ void rows_inv_real_body(const C *__restrict__ in, int
         u[q].y = 0;
         v[q].y = 0;
       }
-      s[padi(x)] = mkc<C>(u[q].x - v[q].y, u[q].y + v[q].x);
+      w[q] = mkc<C>(u[q].x - v[q].y, u[q].y + v[q].x);
+    }
+    if constexpr (first_pass_in_regs<L, NT>()) {
+      first_pass_regs<L, 1>(s, w, threadIdx.x);
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) s[padi(threadIdx.x + q * NT)] = w[q];
     }
   }
   __syncthreads();
+  if constexpr (first_pass_in_regs<L, NT>()) {
+    // last pass in registers: thread t holds columns j + k NS of both rows
+    constexpr int NS = LastPass<L>::NS, RL = LastPass<L>::R, PL = (NS + NT - 1) / NT;
+    C z[PL][RL];
+    stockham_out<L, NT, 8, 1>(s, row_tw<L>(twl), threadIdx.x, z);
+    RT pa[PL][RL], pb[PL][RL];
+    if (accumulate) {
+#pragma unroll
+      for (int q = 0; q < PL; ++q)
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+          const int c = threadIdx.x + q * NT + k * NS - col0;
+          pa[q][k] = pb[q][k] = RT(0);
+          if (threadIdx.x + q * NT < NS && c >= 0 && c < n_out) {
+            pa[q][k] = out[(size_t)ra * n_out + c];
+            pb[q][k] = out[(size_t)rb * n_out + c];
+          }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PL; ++q)
+#pragma unroll
+      for (int k = 0; k < RL; ++k) {
+        const int c = threadIdx.x + q * NT + k * NS - col0;
+        if (threadIdx.x + q * NT < NS && c >= 0 && c < n_out) {
+          const C zz = z[q][k];
+          if (accumulate) {
+            out[(size_t)ra * n_out + c] = pa[q][k] + zz.x;
+            out[(size_t)rb * n_out + c] = pb[q][k] + zz.y;
+          } else if (add) {
+            out[(size_t)ra * n_out + c] = add_scale * add[(size_t)ra * n_out + c] + zz.x;
+            out[(size_t)rb * n_out + c] = add_scale * add[(size_t)rb * n_out + c] + zz.y;
+          } else {
+            out[(size_t)ra * n_out + c] = zz.x;
+            out[(size_t)rb * n_out + c] = zz.y;
+          }
+        }
+      }
+    return;
+  }
   stockham_seq<L, NT, 1, 1, C>(s, row_tw<L>(twl), threadIdx.x);
   if (accumulate) {
     constexpr int PO = (L + NT - 1) / NT;  // n_out <= L
