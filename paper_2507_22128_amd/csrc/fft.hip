@@ -269,6 +269,28 @@ __device__ __forceinline__ void stockham_cols(C *s, const C *__restrict__ tw, in
   }
 }
 
+// Column DFTs of length 64 over CW = 32 columns with 256 threads, the two
+// radix-8 passes of stockham_cols kept in registers: group g = t / 32 owns
+// butterfly g of each pass and lane c = t % 32 its column.  On entry v[r]
+// holds row g + 8 r of column c (as the column passes load their tile), on
+// exit output row g + 8 r; one LDS round trip between the passes instead of
+// the tile's store, two round trips and reload.  The same arithmetic as
+// stockham_cols<64, 1, DIR, C, 32>.
+template <int DIR, class C>
+__device__ __forceinline__ void col64_regs(C *s, const C *__restrict__ tw, int t, C (&v)[8]) {
+  constexpr int CW = 32;
+  const int g = t / CW, c = t % CW;
+  dft<8, DIR>(v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) s[(8 * g + r) * CW + c] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = s[(g + 8 * r) * CW + c];
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], tw_get<DIR>(tw, r * g * (kTwMax / 64)));
+  dft<8, DIR>(v);
+}
+
 // stage the two tables of RowTw<L> into twl (lo then hi) from the per-length
 // tables (entry L + m of twr holds w_L^m)
 template <int L, int NT, class C>
@@ -479,8 +501,12 @@ __global__ __launch_bounds__(RowThreads<L>::v) void k_rows_plain(C *__restrict__
 template <int P, int Q, class C>
 struct ColWidth {
   static constexpr int lo = 256 / (P < Q ? P : Q);  // one element per thread
-  // FP64 elements are twice as wide: the same bytes per row segment
-  static constexpr int want = sizeof(C) > 8 ? kColWant / 2 : kColWant;
+  // FP64 elements are twice as wide: the same bytes per row segment, except
+  // for 64-point columns, whose two radix-8 passes stay in registers when
+  // each of the 256 threads holds eight elements (32 columns)
+  static constexpr int want =
+      sizeof(C) > 8 ? ((P == 64 || Q == 64) && P <= 64 && Q <= 64 ? kColWant : kColWant / 2)
+                    : kColWant;
   static constexpr int v = want > lo ? want : lo;
 };
 // Column DFT of length L = P * Q over an L x L array (row stride L):
@@ -498,33 +524,41 @@ __device__ __forceinline__ void cols_p1_body(const C *__restrict__ src, int src_
   constexpr int L = P * Q, CW = ColWidth<P, Q, C>::v;
   __shared__ C s[P * CW];
   const int t = threadIdx.x;
-  {
-    // every load of the thread goes out before the first is used
-    constexpr int PER = P * CW / 256;
-    C v[PER];
+  // every load of the thread goes out before the first is used
+  constexpr int PER = P * CW / 256;
+  C v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int i = t + q * 256, y1 = i / CW, c = i % CW;
-      const int y = Q * y1 + y2;
-      v[q] = (y >= y_lo && y < y_hi) ? src[(size_t)(y - src_row0) * L + x0 + c] : mkc<C>(0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
+  for (int q = 0; q < PER; ++q) {
+    const int i = t + q * 256, y1 = i / CW, c = i % CW;
+    const int y = Q * y1 + y2;
+    v[q] = (y >= y_lo && y < y_hi) ? src[(size_t)(y - src_row0) * L + x0 + c] : mkc<C>(0, 0);
   }
   // the twiddles of the store, loaded while the transform runs
-  constexpr int PER = P * CW / 256;
   C w[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int k1 = (t + q * 256) / CW;
     w[q] = tw_get<DIR>(tw, ((y2 * k1) & (L - 1)) * (kTwMax / L));
   }
-  __syncthreads();
-  stockham_cols<P, 1, DIR, C, CW>(s, tw, t);
+  if constexpr (P == 64 && CW == 32) {
+    // thread t holds rows t / 32 + 8 q of column t % 32: the transform runs
+    // on them, and output row k1 = t / 32 + 8 q is v[q]
+    col64_regs<DIR>(s, tw, t, v);
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int i = t + q * 256, k1 = i / CW, c = i % CW;
-    dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], w[q]);
+    for (int q = 0; q < PER; ++q) {
+      const int i = t + q * 256, k1 = i / CW, c = i % CW;
+      dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(v[q], w[q]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
+    __syncthreads();
+    stockham_cols<P, 1, DIR, C, CW>(s, tw, t);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = t + q * 256, k1 = i / CW, c = i % CW;
+      dst[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(s[i], w[q]);
+    }
   }
 }
 
@@ -543,26 +577,39 @@ __device__ __forceinline__ void cols_p2_body(const C *__restrict__ src, C *__res
   constexpr int L = P * Q, CW = ColWidth<P, Q, C>::v;
   __shared__ C s[Q * CW];
   const int t = threadIdx.x;
-  {
-    constexpr int PER = Q * CW / 256;
-    C v[PER];
+  constexpr int PER = Q * CW / 256;
+  C v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = t + q * 256, y2 = i / CW, c = i % CW;
+    v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+  }
+  if constexpr (Q == 64 && CW == 32) {
+    // output row k2 = t / 32 + 8 q of column t % 32 is v[q] after the transform
+    col64_regs<DIR>(s, tw, t, v);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int i = t + q * 256, y2 = i / CW, c = i % CW;
-      v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+      const int i = t + q * 256, k2 = i / CW, c = i % CW;
+      const int k = k1 + P * k2;
+      if (k >= k_lo && k < k_hi) {
+        C z = v[q];
+        if (modulate && ((k + x0 + c) & 1)) z = mkc<C>(-z.x, -z.y);
+        dst[(size_t)(k - dst_row0) * L + x0 + c] = z;
+      }
     }
+  } else {
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
-  }
-  __syncthreads();
-  stockham_cols<Q, 1, DIR, C, CW>(s, tw, t);
-  for (int i = t; i < Q * CW; i += 256) {
-    const int k2 = i / CW, c = i % CW;
-    const int k = k1 + P * k2;
-    if (k >= k_lo && k < k_hi) {
-      C v = s[i];
-      if (modulate && ((k + x0 + c) & 1)) v = mkc<C>(-v.x, -v.y);
-      dst[(size_t)(k - dst_row0) * L + x0 + c] = v;
+    __syncthreads();
+    stockham_cols<Q, 1, DIR, C, CW>(s, tw, t);
+    for (int i = t; i < Q * CW; i += 256) {
+      const int k2 = i / CW, c = i % CW;
+      const int k = k1 + P * k2;
+      if (k >= k_lo && k < k_hi) {
+        C z = s[i];
+        if (modulate && ((k + x0 + c) & 1)) z = mkc<C>(-z.x, -z.y);
+        dst[(size_t)(k - dst_row0) * L + x0 + c] = z;
+      }
     }
   }
 }
@@ -894,25 +941,46 @@ __device__ __forceinline__ void cols_mid_body(C *__restrict__ buf, const C *__re
         sp[q] = spec[(size_t)(k1 + P * k2) * L + x0 + c];
       }
     }
+    // the factor applied at frequency row k = k1 + P k2 of column c
+    auto filt = [&](C z, int q) {
+      const int i = t + q * 256, k2 = i / CW, c = i % CW;
+      const int k = k1 + P * k2;
+      if constexpr (MODE == FILT_GAMMA) {
+        RT g = (RT)gamma_low_at(x0 + c, k, L, ell, delta, gscale);
+        if (!(own_low & 1)) g = (RT)1 - g;
+        if (own_low & 2) g = g * g;
+        return cscale(z, g * coef);
+      } else {
+        return cscale(cmul(z, sp[q]), coef);
+      }
+    };
+    if constexpr (Q == 64 && CW == 32) {
+      // thread t holds rows t / 32 + 8 q of column t % 32 throughout: the
+      // inverse transform, the factor and the forward transform run on them
+      col64_regs<-1>(s, tw, t, v);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) v[q] = filt(v[q], q);
+      C w[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int y2 = (t + q * 256) / CW;
+        w[q] = tw_get<1>(tw, ((y2 * k1) & (L - 1)) * (kTwMax / L));
+      }
+      __syncthreads();  // the first transform's reads of s are done
+      col64_regs<1>(s, tw, t, v);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = t + q * 256, y2 = i / CW, c = i % CW;
+        buf[(size_t)(Q * k1 + y2) * L + x0 + c] = cmul(v[q], w[q]);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
-  }
-  __syncthreads();
-  stockham_cols<Q, 1, -1, C, CW>(s, tw, t);
+    __syncthreads();
+    stockham_cols<Q, 1, -1, C, CW>(s, tw, t);
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int i = t + q * 256, k2 = i / CW, c = i % CW;
-    const int k = k1 + P * k2;
-    C v = s[i];
-    if constexpr (MODE == FILT_GAMMA) {
-      RT g = (RT)gamma_low_at(x0 + c, k, L, ell, delta, gscale);
-      if (!(own_low & 1)) g = (RT)1 - g;
-      if (own_low & 2) g = g * g;
-      v = cscale(v, g * coef);
-    } else {
-      v = cscale(cmul(v, sp[q]), coef);
-    }
-    s[i] = v;
+    for (int q = 0; q < PER; ++q) s[t + q * 256] = filt(s[t + q * 256], q);
   }
   C w[PER];
 #pragma unroll
@@ -952,6 +1020,17 @@ __device__ __forceinline__ void cols_fin_body(const C *__restrict__ src, C *__re
     for (int q = 0; q < PER; ++q) {
       const int i = t + q * 256, k1 = i / CW, c = i % CW;
       v[q] = src[(size_t)(Q * k1 + y2) * L + x0 + c];
+    }
+    if constexpr (P == 64 && CW == 32) {
+      // output row y1 = t / 32 + 8 q of column t % 32 is v[q] after the transform
+      col64_regs<1>(s, tw, t, v);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = t + q * 256, y1 = i / CW, c = i % CW;
+        const int y = y2 + Q * y1;
+        if (y >= k_lo && y < k_hi) dst[(size_t)(y - k_lo) * L + x0 + c] = v[q];
+      }
+      return;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) s[t + q * 256] = v[q];
