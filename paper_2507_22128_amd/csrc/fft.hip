@@ -9,6 +9,8 @@
 //     FP32; 64 columns halve the workgroup count, which leaves much of the
 //     chip idle at these sizes, and 16 columns measured slower); in LDS each
 //     group of CW threads owns the block's columns, one lane per column.
+//     Transforms of 64 points keep both radix-8 passes in registers and
+//     exchange through LDS once (col64_regs).
 // Zero rows of a padded input are never read and rows outside a crop are
 // never written.  The centred transform of the gridder (grid cell g holds
 // frequency g - Ng/2) is the plain DFT with (-1)^index modulation on both
