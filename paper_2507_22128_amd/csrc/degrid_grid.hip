@@ -325,6 +325,9 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       s.acc[1][y * 16 + c16] = 0.f;
     }
   }
+  // the column-weight table starts clear (lane l: row l / 4, columns
+  // 4 (l % 4) ..); each batch writes its taps and takes them out again
+  *(floatx4 *)&s.kxT[(l >> 2) * kS + 4 * (l & 3)] = floatx4{0.f, 0.f, 0.f, 0.f};
   wave_sync();
 
   // row groups: group j holds the chunk's visibilities [b + rows[j-1], b + rows[j])
@@ -393,11 +396,9 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
     const int ox = min(max((int)pv.x, 0), BLK - 1);
     const float fx = pv.x - (float)ox, fy = pv.y - foy;
 
-    // tap weights phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1)); the column
-    // table is cleared by the whole wave first (lane l: row l / 4, columns
-    // 4 (l % 4) ..), then every lane writes its column taps at window
-    // columns ox + t and its row taps t (zero for t >= W)
-    *(floatx4 *)&s.kxT[(l >> 2) * kS + 4 * (l & 3)] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // tap weights phi = exp2(beta log2(e) (sqrt(1 - z^2) - 1)); every lane
+    // writes its column taps at window columns ox + t of the (clear) column
+    // table and its row taps t (zero for t >= W)
     float wy2[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -481,6 +482,13 @@ __device__ __forceinline__ void window_chunk_rows(const WinArgs &a, int chunk, R
       for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[q], kb[q], acc, 0, 0, 0);
     }
     wave_sync();  // the tables are rewritten by the next batch
+    // clear this lane's column taps again (the wave's LDS accesses execute in
+    // issue order, so the next batch's taps land after these zeros)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int t = 2 * g + q;
+      if (W == 8 || t < W) s.kxT[(ox + t) * kS + c16] = 0.f;
+    }
 
     if (group_end) {
       if constexpr (kGrid) {
