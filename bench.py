@@ -528,6 +528,80 @@ CONFIG_TEXT = {
 }
 
 
+def measure_tiny(args, with_oracle=True):
+    """The plain method's small workload (one partition: 64 antennas,
+    120,960 visibilities, 256^2 image, 512^2 grid).  Its cycle (Eq. 2) fits
+    in the caches, so it is reported as latency: the cycle time over the
+    timed steps, p50 / p99 of event-timed cycles and the per-stage times,
+    with the error of the output against the oracle's residual image."""
+    import numpy as np
+    import torch
+    from paper_2507_22128_amd import imager, synth
+
+    d = synth.make("tiny", device="cuda")
+    n = d["n_img"]
+    h = imager.Imager.create(d, n_partitions=1, weighting="uniform")
+    info = h.info
+    model = torch.tensor(np.ascontiguousarray(0.5 * d["truth"]), dtype=torch.float32,
+                         device="cuda")
+    out = torch.empty((n, n), device="cuda")
+
+    def step():
+        h.major_cycle(0, model, out=out)
+
+    # a cycle takes tens of microseconds: ten times the steps of the large
+    # workloads, so that p99 is not just the slowest of a few
+    steps, warmup = 10 * args.steps, 10 * args.warmup
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    got = out.cpu().numpy().astype(np.float64)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        step()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(a.elapsed_time(b) for a, b in ev)
+    h.set_timing(True)
+    for _ in range(steps):
+        step()
+    cycles, stage_ms = h.get_timing()
+    h.set_timing(False)
+    h.destroy()
+    res = {
+        "config": {"workload": "tiny: 64 antennas in a 2 km disk, 2016 baselines x 60 times = "
+                               "%d visibilities, 1 channel at 1.40 GHz, uniform weighting, one "
+                               "partition, 256^2 image, 2x padded grid, ES support 8; sky 20 "
+                               "points + 3 Gaussians" % len(d["vis"]),
+                   "n_vis": int(info.n_valid), "n_pix": n, "n_grid": info.n_grid},
+        "ms_per_cycle": round(ms, 4),
+        "p50_ms": round(per_step[len(per_step) // 2], 4),
+        "p99_ms": round(per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))], 4),
+        "event_timed_steps": len(per_step),
+        "stage_ms": {k: round(v / cycles, 4) for k, v in stage_ms.items()},
+        "mvis_per_s": round(info.n_valid / (ms / 1e3) / 1e6, 1),
+        "note": "cache-resident: reported as latency, not as a fraction of HBM",
+    }
+    if with_oracle:
+        from oracle import geometry, imaging
+        u, v = geometry.uv_lambda(d["uvw"], d["freq_hz"])
+        w = imaging.uniform_weights(u, v, n, d["cell"])
+        ref, _ = imaging.residual_image(u, v, d["vis"], w, 0.5 * d["truth"], d["cell"])
+        e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res["err_vs_oracle"] = {"rel_l2": e, "tolerance": 1e-5, "pass": bool(e <= 1e-5)}
+    log("tiny: %.4f ms per cycle (p50 %.4f, p99 %.4f ms)%s"
+        % (res["ms_per_cycle"], res["p50_ms"], res["p99_ms"],
+           ", error %.2e" % res["err_vs_oracle"]["rel_l2"] if with_oracle else ""))
+    return res
+
+
 def measure_cycle(name, args, workers, with_oracle=True, minor=True):
     """Times the decentralized major cycle of workload ``name``: both nodes'
     cycles (Eq. 2 then Eq. 7) with the model 0.5 x the true sky and the
@@ -698,6 +772,8 @@ def main():
                     help="skip the whole reconstructions as configured (the one-call loops)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-decentral", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true",
+                    help="skip the latency of the one-partition 120,960-visibility cycle")
     ap.add_argument("--batch-channels", type=int, default=64)
     ap.add_argument("--batch-small-channels", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -757,6 +833,8 @@ def main():
         res["decentral"] = measure_cycle("decentral", args, workers,
                                          with_oracle=not args.no_cpu_baseline,
                                          minor=not args.no_minor_cycles)
+    if not args.no_tiny:
+        res["tiny"] = measure_tiny(args, with_oracle=not args.no_cpu_baseline)
     if not args.no_batch:
         res["batched_channels"] = batched_channels(args)
         res["batched_small_channels"] = batched_channels(args, small=True)
