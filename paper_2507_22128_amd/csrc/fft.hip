@@ -951,6 +951,7 @@ __device__ __forceinline__ void cols_mid_body(C *__restrict__ buf, const C *__re
         RT g = (RT)gamma_low_at(x0 + c, k, L, ell, delta, gscale);
         if (!(own_low & 1)) g = (RT)1 - g;
         if (own_low & 2) g = g * g;
+        if (own_low & 4) g = g * ((RT)2 - g);  // 1 - (1 - Gamma_L)^2
         return cscale(z, g * coef);
       } else {
         return cscale(cmul(z, sp[q]), coef);
@@ -1185,6 +1186,9 @@ struct GammaMember {
   C *work, *tmp;
   typename Real<C>::T coef;
   int own_low, accumulate, c_hi;
+  // out = add_scale add + the filtered image (add may be null)
+  const typename Real<C>::T *add;
+  typename Real<C>::T add_scale;
 };
 template <class C>
 struct GammaPair {
@@ -1230,13 +1234,29 @@ template <int L, class C>
 __global__ __launch_bounds__(RowThreads<L>::v) void k_gamma_pair_rows_inv(GammaPair<C> g,
                                                                           const C *twr) {
   const GammaMember<C> m = pick(g, blockIdx.y);
-  rows_inv_real_body<L, C>(m.work, 0, L, m.out, m.accumulate, twr, m.c_hi, blockIdx.x);
+  rows_inv_real_body<L, C>(m.work, 0, L, m.out, m.accumulate, twr, m.c_hi, blockIdx.x, m.add,
+                           m.add_scale);
 }
 
 template <int L, class C>
 void gamma_pair_t(imgr_s *h, GammaPair<C> g, hipStream_t s) {
+  typedef typename Real<C>::T RT;
   constexpr int P = Split<L>::P, Q = Split<L>::Q, CW = ColWidth<P, Q, C>::v;
-  for (int k = 0; k < 2; ++k) g.m[k].c_hi = filter_cols<L>(h, FILT_GAMMA, g.m[k].own_low, 1.0);
+  for (int k = 0; k < 2; ++k) {
+    GammaMember<C> &m = g.m[k];
+    // a high-pass member as a minus its complement: Gamma_H a = a - Gamma_L a
+    // and Gamma_H^2 a = a - Gamma_L (2 - Gamma_L) a, whose factors vanish
+    // beyond ell + delta like Gamma_L, so the member needs only the low
+    // column blocks (the subtraction cancels at low frequencies, which the
+    // FP64 transforms of these filters absorb)
+    if (!(m.own_low & 1) && !m.accumulate && !m.add) {
+      m.add = m.a;
+      m.add_scale = m.coef * (RT)L * (RT)L;
+      m.coef = -m.coef;
+      m.own_low = 1 | ((m.own_low & 2) ? 4 : 0);
+    }
+    m.c_hi = filter_cols<L>(h, FILT_GAMMA, m.own_low, 1.0);
+  }
   const int cb = std::max(g.m[0].c_hi, g.m[1].c_hi) / CW;
   const C *tw = twiddles<C>(h);
   const C *twr = row_twiddles<C>(h);
